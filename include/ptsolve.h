@@ -1,0 +1,187 @@
+/*
+ * ptsolve.h -- C ABI of the MI355X (gfx950) solver for the implicit-Euler
+ * time-periodic nonlinear eddy-current problem.
+ *
+ * Problem 1 of the paper (eqs. (disc1)-(disc2)): find U = (u^1, ..., u^N) with
+ *     M (u^n - u^{n-1}) / tau + K(u^n) = f^n,  n = 1..N,   u^0 = u^N,
+ * where, for the 2-D model of Sec. 4 ("Test problem"),
+ *     K(u)  = -div(nu(|grad u|) grad u)  (P1 finite elements, u = 0 on the boundary),
+ *     M     = sigma-weighted consistent P1 mass (sigma may vanish: degenerate, (A2)),
+ *     f^n   = J0 w(2 pi t_n / T) b,  t_n = n tau, tau = T / N.
+ * The solver is the fixed-point iteration of Sec. 3, eqs. (iter1)-(iter2), with
+ * the linear operator Khat = nu_max * (P1 stiffness), run in correction form
+ *     U^{k+1} = U^k + P^{-1}(F - A(U^k)),  P = I (x) (M/tau + Khat) - C_N (x) M/tau,
+ * whose fixed point is A(U) = F however P^{-1} is approximated. Each P^{-1} is
+ * applied by a DFT along time (remark rem:parallel: the periodic time-invariant
+ * system is block diagonal in frequency) and one batched solve of the N/2 + 1
+ * complex-shifted systems (Khat + z_k M) X_k = R_k, z_k = (1 - exp(-2 pi i k/N))/tau,
+ * preconditioned by a geometric-multigrid V-cycle.
+ *
+ * Mesh: uniform n x n cells on the unit square, each cell split along its SW-NE
+ * diagonal; node (i, j) at (i/n, j/n) has index j (n+1) + i. Triangle ids are
+ * 2 (j n + i) + 0 for {(i,j),(i+1,j),(i+1,j+1)} and + 1 for {(i,j),(i+1,j+1),(i,j+1)}.
+ * A triangle belongs to a rectangle iff its centroid lies in the closed rectangle.
+ *
+ * Memory and ownership. Every device buffer (solution, workspace, optional
+ * tables) is allocated and owned by the caller and must stay valid until the
+ * stream-ordered work of the call has completed. The library allocates no device
+ * memory; a plan owns only small host state. All entry points are stream-ordered
+ * on the given HIP stream (hipStream_t passed as void*, NULL = default stream);
+ * pt_solve and pt_residual additionally synchronise that stream before returning
+ * because they read scalars back to the host.
+ *
+ * Errors. Every function returns a pt_status; no C++ exception crosses the ABI.
+ * Arguments are validated before anything is launched. pt_last_error() returns a
+ * thread-local description of the most recent failure on the calling thread.
+ *
+ * Layouts.
+ *   time field    double [N][n+1][n+1]: slice j holds u^{j+1} (so slice N-1 is
+ *                 u^N = u^0); boundary entries are read as 0 and written as 0.
+ *   frequency     complex [ (n+1)^2 ][N/2] interleaved (re, im), node-major, in
+ *   field         the plan's solver precision (double for PT_FP64, float for
+ *                 PT_FP32_REFINE). Slot s >= 1 holds X_s = sum_j x^{j+1} e^{-2 pi i j s/N};
+ *                 slot 0 holds (Re X_0) + i (Re X_{N/2}) (both real for real input).
+ */
+#ifndef PTSOLVE_H
+#define PTSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PT_OK = 0,
+    PT_ERR_INVALID = -1,        /* an argument or option is out of range */
+    PT_ERR_HIP = -3,            /* a HIP runtime call failed (message in pt_last_error) */
+    PT_ERR_NOT_CONVERGED = -4,  /* max_outer reached; the solution holds the last iterate */
+    PT_ERR_BREAKDOWN = -5,      /* COCG bilinear form vanished for some frequency */
+    PT_ERR_NONFINITE = -6,      /* residual norm is NaN or Inf */
+    PT_ERR_DIVERGED = -7,       /* residual grew by diverge_factor over its minimum */
+    PT_ERR_WORKSPACE = -8       /* workspace NULL, too small or not 256-byte aligned */
+} pt_status;
+
+typedef enum { PT_FP64 = 0, PT_FP32_REFINE = 1 } pt_precision;
+
+/* Inner approximation of P^{-1} per frequency k (all frequencies in one launch):
+ *  PT_INNER_GALERKIN1: one V-cycle p = B_k r, then x = alpha p with
+ *                      alpha = (p^H r) / (p^H A_k p) (Galerkin condition in the
+ *                      Hermitian inner product; p^H A_k p has positive real part).
+ *  PT_INNER_COCG:      inner_iters steps of COCG (unconjugated bilinear form
+ *                      x^T y, preconditioned by the same V-cycle) from zero.   */
+typedef enum { PT_INNER_GALERKIN1 = 0, PT_INNER_COCG = 1 } pt_inner;
+
+typedef enum { PT_WAVE_SIN = 0, PT_WAVE_COS = 1 } pt_waveform;
+
+typedef struct { double x0, y0, x1, y1; } pt_rect;   /* closed rectangle */
+
+typedef struct {
+    int32_t n;            /* cells per side, power of two, 4 <= n <= 4096 */
+    int32_t N;            /* time steps per period, power of two, 4 <= N <= 1024 */
+    double T;             /* period > 0 */
+    double sigma_in;      /* conductivity inside sigma_rect (0 outside), >= 0 */
+    pt_rect sigma_rect;
+    double nu_a, nu_b;    /* nu(s) = theta (nu_a + nu_b s^2/(1+s^2)) inside nu_rect */
+    double nu_out;        /* nu = theta nu_out outside nu_rect */
+    pt_rect nu_rect;
+    double J0;            /* source amplitude on coil_rect */
+    pt_rect coil_rect;
+    int32_t waveform;     /* pt_waveform: w = sin or cos */
+    double nu_max;        /* Khat = nu_max * stiffness; > 0 */
+    const double* d_theta; /* optional device [2 n^2] per-triangle nu scale (> 0), NULL = 1 */
+    const double* d_sigma; /* optional device [2 n^2] per-triangle conductivity (>= 0),
+                              NULL = sigma_in on sigma_rect */
+    const double* d_load;  /* optional device time field [N][n+1][n+1]: f^n given
+                              explicitly (replaces J0 w b); NULL = built-in source */
+} pt_problem;
+
+typedef struct {
+    double tol;            /* stop when ||F - A(U)||_2 <= tol ||F||_2 (absolute if F = 0) */
+    int32_t max_outer;     /* >= 1 */
+    int32_t check_every;   /* read the residual back every this many steps, >= 1 */
+    int32_t precision;     /* pt_precision */
+    int32_t inner;         /* pt_inner */
+    int32_t inner_iters;   /* COCG steps per outer step (PT_INNER_COCG), 1..64 */
+    int32_t vc_sweeps;     /* damped-Jacobi sweeps before and after coarse correction, 1..4 */
+    double vc_omega;       /* Jacobi damping, 0 < omega < 1 */
+    int32_t use_initial_guess; /* 0: U^0 = 0; 1: start from the contents of d_u */
+    double diverge_factor; /* PT_ERR_DIVERGED if rel > diverge_factor * min(rel) (0 = off) */
+    int32_t xcd_remap;     /* 1: map workgroups to contiguous node ranges per XCD */
+} pt_options;
+
+typedef struct {
+    int32_t outer_iters;        /* fixed-point updates applied */
+    double rel_residual;        /* ||F - A(U)|| / ||F|| of the returned U */
+    double f_norm;              /* ||F||_2 */
+    double time_ms;             /* device time of the whole call (HIP events) */
+    double* residual_history;   /* caller-owned host array or NULL; rel at each check */
+    int32_t history_cap;
+    int32_t history_len;
+} pt_stats;
+
+typedef struct pt_plan pt_plan;
+
+/* Fill *o with the defaults (tol 1e-8, max_outer 1000, check_every 1, FP64,
+ * PT_INNER_GALERKIN1, inner_iters 1, vc_sweeps 1, vc_omega 0.8, no initial guess,
+ * diverge_factor 1e3, xcd_remap 1). */
+void pt_options_default(pt_options* o);
+
+/* Validate the problem and options (host only, no device work) and create a plan. */
+pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan** out);
+void pt_plan_destroy(pt_plan* plan);
+
+/* Bytes of device workspace every entry point below needs (256-byte aligned base). */
+pt_status pt_plan_workspace_bytes(const pt_plan* plan, size_t* bytes);
+
+/* Solve Problem 1 by the fixed-point iteration (eqs. (iter1)-(iter2)).
+ * d_u: device time field [N][n+1][n+1], in (initial guess if use_initial_guess) and
+ * out (the periodic solution, zero boundary). stats may be NULL. Returns PT_OK on
+ * convergence; on PT_ERR_NOT_CONVERGED / _DIVERGED / _NONFINITE d_u holds the last
+ * iterate and stats are filled. Blocks until the stream has finished. */
+pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream,
+                   pt_stats* stats);
+
+/* R = F - A(U) (eq. (disc1) moved to one side, u^0 = u^N) on every slice; d_r has
+ * the time-field layout, boundary entries 0. rel_out / fnorm_out (host, may be NULL)
+ * receive ||R||_2 / ||F||_2 and ||F||_2. Blocks until the stream has finished. */
+pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
+                      double* d_r, void* stream, double* rel_out, double* fnorm_out);
+
+/* d_ku[j] = K(d_u[j]) for j < nslices (time-field layout, 1 <= nslices <= N); the
+ * nonlinear P1 operator of Sec. 4 with the plan's material law. */
+pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
+                     double* d_ku, int32_t nslices, void* stream);
+
+/* Packed real DFT along time: time field (double) -> frequency field (plan precision). */
+pt_status pt_time_rfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_x,
+                       void* d_xhat, void* stream);
+
+/* Inverse of pt_time_rfft including the 1/N factor: frequency field -> time field. */
+pt_status pt_time_irfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_xhat,
+                        double* d_x, void* stream);
+
+/* y_s = (Khat + z_s M) x_s for every slot (slot 0: the k = 0 and k = N/2 systems act
+ * on the real and imaginary parts). Frequency-field layout, plan precision. */
+pt_status pt_shifted_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_x,
+                           void* d_y, void* stream);
+
+/* x_s = B_s r_s: one V-cycle of the multigrid preconditioner for every slot. */
+pt_status pt_precond_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_r,
+                           void* d_x, void* stream);
+
+/* Approximate X = P^{-1} R for time fields R (input) and X (output) with the plan's
+ * inner method: DFT in time, the batched preconditioned solve, inverse DFT.
+ * inner_iters overrides the plan's COCG step count when > 0. */
+pt_status pt_periodic_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_r,
+                            double* d_x, int32_t inner_iters, void* stream);
+
+const char* pt_status_string(pt_status s);
+const char* pt_last_error(void);
+int32_t pt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTSOLVE_H */

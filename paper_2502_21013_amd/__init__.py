@@ -1,0 +1,231 @@
+"""MI355X-native solver for the implicit-Euler time-periodic nonlinear eddy-current problem.
+
+Python binding of the C ABI in include/ptsolve.h. Every step of the solver runs in
+the HIP kernels of libptsolve.so; this module only marshals arguments: it builds
+the problem/option structs, allocates device buffers with torch, and passes raw
+pointers and torch's current HIP stream. There is no CPU fallback: importing the
+package works without a GPU (plan creation is host-only), but every compute call
+needs the built library and a GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional
+
+from . import _lib as L
+
+__all__ = ["Plan", "SolveStats", "PTError", "library", "problem_struct"]
+
+
+class PTError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = L.load()
+        self.status = status
+        msg = lib.pt_last_error().decode()
+        name = lib.pt_status_string(status).decode()
+        super().__init__(f"{where}: {name} ({status}): {msg}")
+
+
+def library():
+    return L.load()
+
+
+def _rect(r) -> L.Rect:
+    x0, y0, x1, y1 = r.as_tuple() if hasattr(r, "as_tuple") else tuple(r)
+    return L.Rect(x0, y0, x1, y1)
+
+
+def problem_struct(p, theta=None, sigma=None, load=None) -> L.Problem:
+    """Fill the C problem struct from any object with the fields of a problem description
+    (n, N, T, sigma_in, sigma_rect, nu_a, nu_b, nu_out, nu_rect, J0, coil_rect, waveform,
+    nu_max). theta / sigma / load are optional device tensors (float64, contiguous)."""
+    s = L.Problem()
+    s.n, s.N, s.T = int(p.n), int(p.N), float(p.T)
+    s.sigma_in, s.sigma_rect = float(p.sigma_in), _rect(p.sigma_rect)
+    s.nu_a, s.nu_b, s.nu_out, s.nu_rect = float(p.nu_a), float(p.nu_b), float(p.nu_out), _rect(p.nu_rect)
+    s.J0, s.coil_rect = float(p.J0), _rect(p.coil_rect)
+    s.waveform = L.PT_WAVE_SIN if p.waveform == "sin" else L.PT_WAVE_COS
+    s.nu_max = float(p.nu_max)
+    s.d_theta = _ptr(theta, "theta", 2 * p.n * p.n)
+    s.d_sigma = _ptr(sigma, "sigma", 2 * p.n * p.n)
+    s.d_load = _ptr(load, "load", p.N * (p.n + 1) ** 2)
+    return s
+
+
+def _ptr(t, name, numel):
+    if t is None:
+        return None
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name} must be a contiguous float64 device tensor with {numel} entries")
+    return t.data_ptr()
+
+
+@dataclass
+class SolveStats:
+    status: int
+    outer_iters: int
+    rel_residual: float
+    f_norm: float
+    time_ms: float
+    history: List[float]
+
+
+class Plan:
+    """A solver plan: validated problem + options, workspace and entry points."""
+
+    def __init__(self, problem, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
+                 inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
+                 diverge_factor=1e3, xcd_remap=True, theta=None, sigma=None, load=None, device=None):
+        import torch
+        self.lib = L.load()
+        self.problem = problem
+        self.n, self.N = int(problem.n), int(problem.N)
+        self.S = self.N // 2
+        self.nodes = (self.n + 1) ** 2
+        self.precision = precision
+        self._keep = (theta, sigma, load)  # device tables must outlive the plan's calls
+        self._ps = problem_struct(problem, theta, sigma, load)
+        o = L.Options()
+        self.lib.pt_options_default(C.byref(o))
+        o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
+        o.precision = {"fp64": L.PT_FP64, "fp32": L.PT_FP32_REFINE}[precision]
+        o.inner = {"galerkin1": L.PT_INNER_GALERKIN1, "cocg": L.PT_INNER_COCG}[inner]
+        o.inner_iters, o.vc_omega = int(inner_iters), float(vc_omega)
+        o.use_initial_guess = 1 if use_initial_guess else 0
+        o.diverge_factor, o.xcd_remap = float(diverge_factor), 1 if xcd_remap else 0
+        self._opts = o
+        h = C.c_void_p()
+        st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
+        if st != L.PT_OK:
+            raise PTError(st, "pt_plan_create")
+        self._h = h
+        nb = C.c_size_t()
+        self._check(self.lib.pt_plan_workspace_bytes(self._h, C.byref(nb)), "pt_plan_workspace_bytes")
+        self.workspace_bytes = int(nb.value)
+        self.device = torch.device(device) if device is not None else None
+        self._ws = None
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+
+    # ---------------------------------------------------------------- helpers
+    def _check(self, st, where):
+        if st != L.PT_OK:
+            raise PTError(st, where)
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            dev = self.device or torch.device("cuda", torch.cuda.current_device())
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return C.c_void_p(base + off), C.c_size_t(self.workspace_bytes)
+
+    @staticmethod
+    def _stream():
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _time_field(self, t, name):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or \
+                tuple(t.shape) != (self.N, self.n + 1, self.n + 1):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of shape "
+                             f"({self.N}, {self.n + 1}, {self.n + 1})")
+        return C.c_void_p(t.data_ptr())
+
+    def _freq_field(self, t, name):
+        if t.dtype != self.cdtype or not t.is_cuda or not t.is_contiguous() or \
+                tuple(t.shape) != (self.nodes, self.S):
+            raise ValueError(f"{name} must be a contiguous {self.cdtype} device tensor of shape "
+                             f"({self.nodes}, {self.S})")
+        return C.c_void_p(t.data_ptr())
+
+    def new_time_field(self):
+        import torch
+        dev = self.device or torch.device("cuda", torch.cuda.current_device())
+        return torch.zeros((self.N, self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+
+    def new_freq_field(self):
+        import torch
+        dev = self.device or torch.device("cuda", torch.cuda.current_device())
+        return torch.zeros((self.nodes, self.S), dtype=self.cdtype, device=dev)
+
+    # ---------------------------------------------------------------- entry points
+    def solve(self, U=None, history_cap: int = 4096, raise_on_error: bool = True):
+        if U is None:
+            U = self.new_time_field()
+        ws, nb = self.workspace()
+        hist = (C.c_double * history_cap)()
+        s = L.Stats()
+        s.residual_history = C.cast(hist, C.POINTER(C.c_double))
+        s.history_cap = history_cap
+        st = self.lib.pt_solve(self._h, ws, nb, self._time_field(U, "U"), self._stream(), C.byref(s))
+        stats = SolveStats(status=st, outer_iters=s.outer_iters, rel_residual=s.rel_residual,
+                           f_norm=s.f_norm, time_ms=s.time_ms, history=list(hist[: s.history_len]))
+        if raise_on_error and st != L.PT_OK:
+            raise PTError(st, "pt_solve")
+        return U, stats
+
+    def residual(self, U):
+        R = self.new_time_field()
+        ws, nb = self.workspace()
+        rel, fn = C.c_double(), C.c_double()
+        self._check(self.lib.pt_residual(self._h, ws, nb, self._time_field(U, "U"), C.c_void_p(R.data_ptr()),
+                                         self._stream(), C.byref(rel), C.byref(fn)), "pt_residual")
+        return R, rel.value, fn.value
+
+    def apply_K(self, U, nslices=None):
+        nslices = self.N if nslices is None else int(nslices)
+        KU = self.new_time_field()
+        ws, nb = self.workspace()
+        self._check(self.lib.pt_apply_K(self._h, ws, nb, self._time_field(U, "U"), C.c_void_p(KU.data_ptr()),
+                                        nslices, self._stream()), "pt_apply_K")
+        return KU
+
+    def rfft(self, X):
+        Y = self.new_freq_field()
+        ws, nb = self.workspace()
+        self._check(self.lib.pt_time_rfft(self._h, ws, nb, self._time_field(X, "X"), C.c_void_p(Y.data_ptr()),
+                                          self._stream()), "pt_time_rfft")
+        return Y
+
+    def irfft(self, Y):
+        X = self.new_time_field()
+        ws, nb = self.workspace()
+        self._check(self.lib.pt_time_irfft(self._h, ws, nb, self._freq_field(Y, "Y"), C.c_void_p(X.data_ptr()),
+                                           self._stream()), "pt_time_irfft")
+        return X
+
+    def shifted_apply(self, Xh):
+        Yh = self.new_freq_field()
+        ws, nb = self.workspace()
+        self._check(self.lib.pt_shifted_apply(self._h, ws, nb, self._freq_field(Xh, "X"),
+                                              C.c_void_p(Yh.data_ptr()), self._stream()), "pt_shifted_apply")
+        return Yh
+
+    def precond_apply(self, Rh):
+        Xh = self.new_freq_field()
+        ws, nb = self.workspace()
+        self._check(self.lib.pt_precond_apply(self._h, ws, nb, self._freq_field(Rh, "R"),
+                                              C.c_void_p(Xh.data_ptr()), self._stream()), "pt_precond_apply")
+        return Xh
+
+    def periodic_solve(self, R, inner_iters: int = 0):
+        X = self.new_time_field()
+        ws, nb = self.workspace()
+        self._check(self.lib.pt_periodic_solve(self._h, ws, nb, self._time_field(R, "R"), C.c_void_p(X.data_ptr()),
+                                               int(inner_iters), self._stream()), "pt_periodic_solve")
+        return X
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.pt_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

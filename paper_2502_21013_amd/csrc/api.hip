@@ -1,0 +1,568 @@
+// C ABI of the solver: plan validation, workspace layout, the outer fixed-point loop
+// (Sec. 3, eqs. (iter1)-(iter2), correction form) and the component entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pt_internal.h"
+
+namespace pt {
+
+static thread_local std::string g_last_error;
+
+static pt_status fail(pt_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define PT_HIP(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(PT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Geom slot_geom(size_t nodes, int S) {
+    Geom g;
+    g.slot_chunk = S < kBlock ? S : kBlock;
+    g.per_step = kBlock / g.slot_chunk;
+    g.chunks = S / g.slot_chunk;
+    size_t groups = (nodes + g.per_step - 1) / g.per_step;
+    size_t target = (size_t)kTargetBlocks;
+    size_t steps = (groups + target - 1) / target;
+    if (steps < 1) steps = 1;
+    size_t blocks = (groups + steps - 1) / steps;
+    blocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
+    g.steps = (int)steps;
+    g.blocks = (int)blocks;
+    return g;
+}
+
+Geom team_geom(size_t nodes, int S) {
+    Geom g;
+    // S/4 threads per node: one radix-4 butterfly per thread and stage, and a fixed
+    // LDS footprint of 2 S slot values per node (32 KiB per workgroup in FP64)
+    int ts = S / 4;
+    if (ts < 1) ts = 1;
+    if (ts > kBlock) ts = kBlock;
+    g.slot_chunk = ts;
+    g.per_step = kBlock / ts;
+    g.chunks = 1;
+    size_t groups = (nodes + g.per_step - 1) / g.per_step;
+    size_t target = (size_t)kTargetBlocks;
+    size_t steps = (groups + target - 1) / target;
+    if (steps < 1) steps = 1;
+    size_t blocks = (groups + steps - 1) / steps;
+    blocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
+    g.steps = (int)steps;
+    g.blocks = (int)blocks;
+    return g;
+}
+
+static bool rect_ok(const pt_rect& r) {
+    return std::isfinite(r.x0) && std::isfinite(r.y0) && std::isfinite(r.x1) && std::isfinite(r.y1);
+}
+
+static pt_status validate(const pt_problem* pr, const pt_options* o) {
+    if (!pr || !o) return fail(PT_ERR_INVALID, "problem and options must not be NULL");
+    if (!is_pow2(pr->n) || pr->n < 4 || pr->n > 4096) return fail(PT_ERR_INVALID, "n must be a power of two in [4, 4096]");
+    if (!is_pow2(pr->N) || pr->N < 4 || pr->N > 1024) return fail(PT_ERR_INVALID, "N must be a power of two in [4, 1024]");
+    if (!(pr->T > 0) || !std::isfinite(pr->T)) return fail(PT_ERR_INVALID, "T must be positive and finite");
+    if (!(pr->sigma_in >= 0) || !std::isfinite(pr->sigma_in)) return fail(PT_ERR_INVALID, "sigma_in must be >= 0");
+    if (!(pr->nu_max > 0) || !std::isfinite(pr->nu_max)) return fail(PT_ERR_INVALID, "nu_max must be positive");
+    if (!std::isfinite(pr->nu_a) || !std::isfinite(pr->nu_b) || !std::isfinite(pr->nu_out) || !std::isfinite(pr->J0))
+        return fail(PT_ERR_INVALID, "material and source parameters must be finite");
+    if (!(pr->nu_a > 0) || !(pr->nu_a + pr->nu_b > 0) || !(pr->nu_out > 0))
+        return fail(PT_ERR_INVALID, "the reluctivity must stay positive (nu_a > 0, nu_a + nu_b > 0, nu_out > 0)");
+    if (!rect_ok(pr->sigma_rect) || !rect_ok(pr->nu_rect) || !rect_ok(pr->coil_rect))
+        return fail(PT_ERR_INVALID, "rectangles must be finite");
+    if (pr->waveform != PT_WAVE_SIN && pr->waveform != PT_WAVE_COS) return fail(PT_ERR_INVALID, "unknown waveform");
+    if (!(o->tol > 0) || !std::isfinite(o->tol)) return fail(PT_ERR_INVALID, "tol must be positive");
+    if (o->max_outer < 1) return fail(PT_ERR_INVALID, "max_outer must be >= 1");
+    if (o->check_every < 1) return fail(PT_ERR_INVALID, "check_every must be >= 1");
+    if (o->precision != PT_FP64 && o->precision != PT_FP32_REFINE) return fail(PT_ERR_INVALID, "unknown precision");
+    if (o->inner != PT_INNER_GALERKIN1 && o->inner != PT_INNER_COCG) return fail(PT_ERR_INVALID, "unknown inner method");
+    if (o->inner_iters < 1 || o->inner_iters > 64) return fail(PT_ERR_INVALID, "inner_iters must be in [1, 64]");
+    if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused V(1,1) cycle)");
+    if (!(o->vc_omega > 0 && o->vc_omega < 1)) return fail(PT_ERR_INVALID, "vc_omega must be in (0, 1)");
+    if (!(o->diverge_factor >= 0) || !std::isfinite(o->diverge_factor))
+        return fail(PT_ERR_INVALID, "diverge_factor must be >= 0");
+    return PT_OK;
+}
+
+static void layout(Plan& p) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t S = p.S;
+    p.off_U = take(p.nodes * p.N * sizeof(double));
+    p.off_F = p.prob.d_load ? take(p.nodes * p.N * sizeof(double)) : 0;
+    for (int l = 0; l < p.nlev; ++l) {
+        LevelDesc& d = p.lev[l];
+        d.off_mt = take(4 * d.nodes * sizeof(double));
+        d.off_r = take(d.nodes * S * p.elem);
+        d.off_x = take(d.nodes * S * p.elem);
+    }
+    p.off_P = p.lev[0].off_x;
+    p.has_cocg_vectors = p.opt.inner == PT_INNER_COCG;
+    if (p.has_cocg_vectors) {
+        size_t v = p.nodes * S * p.elem;
+        p.off_cx = take(v);
+        p.off_cr = take(v);
+        p.off_cq = take(v);
+        p.off_cp = take(v);
+    } else {
+        p.off_cx = p.off_cr = p.off_cq = p.off_cp = 0;
+    }
+    p.off_flags = take(2 * (size_t)p.n * p.n);
+    p.off_b = take(p.nodes * sizeof(double));
+    p.off_tw64 = take((size_t)p.N * 2 * sizeof(double));
+    p.off_tw32 = take((size_t)p.N * 2 * sizeof(float));
+    p.off_zs = take(S * 3 * sizeof(double));
+    p.off_wave = take((size_t)p.N * sizeof(double));
+    size_t part_slot = (size_t)p.g_slot0.blocks * S * 3;
+    size_t part_team = (size_t)p.g_team.blocks * 2;
+    p.part_bytes = (part_slot > part_team ? part_slot : part_team) * sizeof(double);
+    p.off_part = take(p.part_bytes);
+    p.off_scal = take(64 * sizeof(double));
+    p.off_coef = take(8 * S * 2 * sizeof(double));  // eight double2 per-slot arrays
+    p.off_coef2 = p.off_coef + 4 * S * 2 * sizeof(double);
+    p.off_hist = 0;
+    p.ws_bytes = off;
+}
+
+static void host_tables(Plan& p) {
+    const double pi = 3.14159265358979323846;
+    p.h_tw64 = new double[2 * p.N];
+    p.h_tw32 = new float[2 * p.N];
+    for (int k = 0; k < p.N; ++k) {
+        double ang = -2.0 * pi * (double)k / (double)p.N;
+        p.h_tw64[2 * k] = std::cos(ang);
+        p.h_tw64[2 * k + 1] = std::sin(ang);
+        p.h_tw32[2 * k] = (float)p.h_tw64[2 * k];
+        p.h_tw32[2 * k + 1] = (float)p.h_tw64[2 * k + 1];
+    }
+    // z_k = (1 - exp(-2 pi i k / N)) / tau: Re = (1 - cos t)/tau, Im = sin t / tau, t = 2 pi k / N
+    p.h_zs = new double[3 * p.S];
+    for (int s = 0; s < p.S; ++s) {
+        double t = 2.0 * pi * (double)s / (double)p.N;
+        double re = (1.0 - std::cos(t)) / p.tau, im = std::sin(t) / p.tau;
+        if (s == 0) {
+            p.h_zs[0] = 0.0;             // k = 0 system on the real part
+            p.h_zs[1] = 0.0;
+            p.h_zs[2] = 2.0 / p.tau;     // k = N/2 system on the imaginary part
+        } else {
+            p.h_zs[3 * s] = re;
+            p.h_zs[3 * s + 1] = im;
+            p.h_zs[3 * s + 2] = re;
+        }
+    }
+    p.h_wave = new double[p.N];
+    for (int j = 0; j < p.N; ++j) {
+        double ph = 2.0 * pi * (double)(j + 1) / (double)p.N;  // 2 pi t_{j+1} / T
+        p.h_wave[j] = (p.prob.waveform == PT_WAVE_SIN) ? std::sin(ph) : std::cos(ph);
+    }
+}
+
+static pt_status check_ws(const Plan* p, void* ws, size_t bytes) {
+    if (!ws) return fail(PT_ERR_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(PT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_bytes)
+        return fail(PT_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->ws_bytes) + " bytes");
+    return PT_OK;
+}
+
+// Upload the small tables and build the per-level operators in the workspace.
+static pt_status setup(Plan& p, char* ws, hipStream_t st) {
+    PT_HIP(hipMemcpyAsync(ws + p.off_tw64, p.h_tw64, (size_t)p.N * 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_tw32, p.h_tw32, (size_t)p.N * 2 * sizeof(float), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_zs, p.h_zs, (size_t)p.S * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_wave, p.h_wave, (size_t)p.N * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_setup_fine(p, ws, st);
+    for (int l = 0; l + 1 < p.nlev; ++l) launch_galerkin(p, ws, l, st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+// Approximate X = (Khat + z M)^{-1} Rhat for every slot. On return *X and *coef describe
+// the correction coef (x) X (coef NULL means identity).
+static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const void** X, const double** coef) {
+    double* part = (double*)(ws + p.off_part);
+    double2* cf = (double2*)(ws + p.off_coef);
+    const size_t S = p.S;
+    double* num = (double*)(cf + 0 * S);
+    double* den = (double*)(cf + 1 * S);
+    double* alpha = (double*)(cf + 2 * S);
+    double* rho = (double*)(cf + 3 * S);
+    double* rho2 = (double*)(cf + 4 * S);
+    double* beta = (double*)(cf + 5 * S);
+    int* flag = (int*)(ws + p.off_scal + 32 * sizeof(double));
+    void* R = ws + p.lev[0].off_r;
+    void* P = ws + p.off_P;
+    if (p.opt.inner == PT_INNER_GALERKIN1) {
+        launch_vcycle(p, ws, R, P, DOT_HERM, part, st);
+        launch_reduce_dots(p, part, DOT_HERM, num, st);
+        launch_matvec(p, ws, P, nullptr, DOT_HERM, part, st);
+        launch_reduce_dots(p, part, DOT_HERM, den, st);
+        launch_slot_div(p, num, den, alpha, nullptr, st);
+        *X = P;
+        *coef = alpha;
+        return PT_OK;
+    }
+    // COCG from zero: x = 0, r = Rhat, z = B r, p = z, rho = r^T z
+    void* x = ws + p.off_cx;
+    void* r = ws + p.off_cr;
+    void* q = ws + p.off_cq;
+    void* pv = ws + p.off_cp;
+    void* z = P;
+    PT_HIP(hipMemsetAsync(x, 0, p.nodes * S * p.elem, st));
+    launch_copy_slots(p, R, r, st);
+    launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
+    launch_reduce_dots(p, part, DOT_BILIN, rho, st);
+    launch_copy_slots(p, z, pv, st);
+    for (int it = 0; it < iters; ++it) {
+        launch_matvec(p, ws, pv, q, DOT_BILIN, part, st);
+        launch_reduce_dots(p, part, DOT_BILIN, den, st);
+        launch_slot_div(p, rho, den, alpha, flag, st);
+        launch_cocg_xr(p, alpha, x, r, pv, q, st);
+        if (it + 1 == iters) break;
+        launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
+        launch_reduce_dots(p, part, DOT_BILIN, rho2, st);
+        launch_slot_div(p, rho2, rho, beta, nullptr, st);
+        launch_cocg_p(p, beta, z, pv, st);
+        PT_HIP(hipMemcpyAsync(rho, rho2, S * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    }
+    *X = x;
+    *coef = nullptr;
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+}  // namespace pt
+
+using namespace pt;
+
+struct pt_plan {
+    Plan p;
+};
+
+extern "C" {
+
+int32_t pt_version(void) { return 1; }
+
+const char* pt_last_error(void) { return g_last_error.c_str(); }
+
+const char* pt_status_string(pt_status s) {
+    switch (s) {
+        case PT_OK: return "PT_OK";
+        case PT_ERR_INVALID: return "PT_ERR_INVALID";
+        case PT_ERR_HIP: return "PT_ERR_HIP";
+        case PT_ERR_NOT_CONVERGED: return "PT_ERR_NOT_CONVERGED";
+        case PT_ERR_BREAKDOWN: return "PT_ERR_BREAKDOWN";
+        case PT_ERR_NONFINITE: return "PT_ERR_NONFINITE";
+        case PT_ERR_DIVERGED: return "PT_ERR_DIVERGED";
+        case PT_ERR_WORKSPACE: return "PT_ERR_WORKSPACE";
+    }
+    return "PT_UNKNOWN_STATUS";
+}
+
+void pt_options_default(pt_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->max_outer = 1000;
+    o->check_every = 1;
+    o->precision = PT_FP64;
+    o->inner = PT_INNER_GALERKIN1;
+    o->inner_iters = 1;
+    o->vc_sweeps = 1;
+    o->vc_omega = 0.8;
+    o->use_initial_guess = 0;
+    o->diverge_factor = 1e3;
+    o->xcd_remap = 1;
+}
+
+pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan** out) {
+    if (!out) return fail(PT_ERR_INVALID, "out must not be NULL");
+    *out = nullptr;
+    pt_status s = validate(prob, opts);
+    if (s != PT_OK) return s;
+    pt_plan* h = new (std::nothrow) pt_plan();
+    if (!h) return fail(PT_ERR_INVALID, "out of host memory");
+    Plan& p = h->p;
+    p.prob = *prob;
+    p.opt = *opts;
+    p.n = prob->n;
+    p.N = prob->N;
+    p.S = prob->N / 2;
+    p.side = p.n + 1;
+    p.nodes = (size_t)p.side * p.side;
+    p.fp32 = opts->precision == PT_FP32_REFINE;
+    p.elem = p.fp32 ? 2 * sizeof(float) : 2 * sizeof(double);
+    p.tau = prob->T / prob->N;
+    p.h = 1.0 / prob->n;
+    p.nlev = 0;
+    for (int nn = p.n; nn >= 2; nn /= 2) {
+        LevelDesc& d = p.lev[p.nlev++];
+        d.n = nn;
+        d.side = nn + 1;
+        d.nodes = (size_t)d.side * d.side;
+    }
+    p.g_slot0 = slot_geom(p.nodes, p.S);
+    p.g_team = team_geom(p.nodes, p.S);
+    layout(p);
+    host_tables(p);
+    *out = h;
+    return PT_OK;
+}
+
+void pt_plan_destroy(pt_plan* plan) {
+    if (!plan) return;
+    delete[] plan->p.h_tw64;
+    delete[] plan->p.h_tw32;
+    delete[] plan->p.h_zs;
+    delete[] plan->p.h_wave;
+    delete plan;
+}
+
+pt_status pt_plan_workspace_bytes(const pt_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(PT_ERR_INVALID, "plan and bytes must not be NULL");
+    *bytes = plan->p.ws_bytes;
+    return PT_OK;
+}
+
+pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream, pt_stats* stats) {
+    if (!plan || !d_u) return fail(PT_ERR_INVALID, "plan and d_u must not be NULL");
+    Plan& p = plan->p;
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    hipEvent_t e0, e1;
+    PT_HIP(hipEventCreate(&e0));
+    PT_HIP(hipEventCreate(&e1));
+    PT_HIP(hipEventRecord(e0, st));
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    double* U = (double*)(ws + p.off_U);
+    if (p.prob.d_load) launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st);
+    if (p.opt.use_initial_guess)
+        launch_transpose_in(p, d_u, U, st);
+    else
+        PT_HIP(hipMemsetAsync(U, 0, p.nodes * p.N * sizeof(double), st));
+    double* part = (double*)(ws + p.off_part);
+    double* scal = (double*)(ws + p.off_scal);
+    int* flag = (int*)(ws + p.off_scal + 32 * sizeof(double));
+    PT_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    void* Rhat = ws + p.lev[0].off_r;
+    pt_status result = PT_ERR_NOT_CONVERGED;
+    double rel = INFINITY, fnorm = 0.0, best = INFINITY;
+    int k = 0, hist = 0;
+    for (;;) {
+        launch_forward(p, ws, TM_RESIDUAL, U, Rhat, nullptr, part, st);
+        launch_reduce_norms(p, ws, part, p.g_team.blocks, scal, st);
+        bool last = (k >= p.opt.max_outer);
+        if (last || k % p.opt.check_every == 0) {
+            double h[2];
+            int hflag = 0;
+            PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            PT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+            PT_HIP(hipStreamSynchronize(st));
+            PT_HIP(hipGetLastError());
+            fnorm = std::sqrt(h[1]);
+            rel = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+            if (stats && stats->residual_history && hist < stats->history_cap) stats->residual_history[hist] = rel;
+            ++hist;
+            if (!std::isfinite(rel)) {
+                result = fail(PT_ERR_NONFINITE, "residual norm is not finite at outer step " + std::to_string(k));
+                break;
+            }
+            if (hflag) {
+                result = fail(PT_ERR_BREAKDOWN, "COCG breakdown before outer step " + std::to_string(k));
+                break;
+            }
+            if (rel <= p.opt.tol) {
+                result = PT_OK;
+                break;
+            }
+            if (rel < best) best = rel;
+            if (p.opt.diverge_factor > 0 && rel > p.opt.diverge_factor * best) {
+                result = fail(PT_ERR_DIVERGED, "residual grew by more than diverge_factor at outer step " +
+                                                   std::to_string(k));
+                break;
+            }
+        }
+        if (last) {
+            result = fail(PT_ERR_NOT_CONVERGED, "max_outer reached");
+            break;
+        }
+        const void* X = nullptr;
+        const double* coef = nullptr;
+        s = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
+        if (s != PT_OK) return s;
+        launch_inverse(p, ws, X, coef, U, 1, st);
+        ++k;
+    }
+    launch_transpose_out(p, U, d_u, st);
+    PT_HIP(hipEventRecord(e1, st));
+    PT_HIP(hipEventSynchronize(e1));
+    PT_HIP(hipGetLastError());
+    float ms = 0.f;
+    PT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (stats) {
+        stats->outer_iters = k;
+        stats->rel_residual = rel;
+        stats->f_norm = fnorm;
+        stats->time_ms = ms;
+        stats->history_len = hist < stats->history_cap ? hist : stats->history_cap;
+    }
+    return result;
+}
+
+pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, double* d_r, void* stream,
+                      double* rel_out, double* fnorm_out) {
+    if (!plan || !d_u || !d_r) return fail(PT_ERR_INVALID, "plan, d_u and d_r must not be NULL");
+    Plan& p = plan->p;
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    double* U = (double*)(ws + p.off_U);
+    if (p.prob.d_load) launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st);
+    launch_transpose_in(p, d_u, U, st);
+    double* part = (double*)(ws + p.off_part);
+    double* scal = (double*)(ws + p.off_scal);
+    // R is first written node-major into d_r (same size), then moved through U and
+    // transposed back into d_r in the time-field layout.
+    launch_forward(p, ws, TM_RESIDUAL, U, nullptr, d_r, part, st);
+    launch_reduce_norms(p, ws, part, p.g_team.blocks, scal, st);
+    double h[2];
+    PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PT_HIP(hipStreamSynchronize(st));
+    PT_HIP(hipGetLastError());
+    PT_HIP(hipMemcpyAsync(U, d_r, p.nodes * p.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_transpose_out(p, U, d_r, st);
+    PT_HIP(hipStreamSynchronize(st));
+    PT_HIP(hipGetLastError());
+    if (fnorm_out) *fnorm_out = std::sqrt(h[1]);
+    if (rel_out) *rel_out = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+    return PT_OK;
+}
+
+pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, double* d_ku, int32_t nslices,
+                     void* stream) {
+    if (!plan || !d_u || !d_ku) return fail(PT_ERR_INVALID, "plan, d_u and d_ku must not be NULL");
+    Plan& p = plan->p;
+    if (nslices < 1 || nslices > p.N) return fail(PT_ERR_INVALID, "nslices must be in [1, N]");
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    launch_apply_K(p, ws, d_u, d_ku, nslices, st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_time_rfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_x, void* d_xhat, void* stream) {
+    if (!plan || !d_x || !d_xhat) return fail(PT_ERR_INVALID, "plan, d_x and d_xhat must not be NULL");
+    Plan& p = plan->p;
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    double* U = (double*)(ws + p.off_U);
+    launch_transpose_in(p, d_x, U, st);
+    launch_forward(p, ws, TM_SIGNAL, U, d_xhat, nullptr, (double*)(ws + p.off_part), st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_time_irfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_xhat, double* d_x, void* stream) {
+    if (!plan || !d_x || !d_xhat) return fail(PT_ERR_INVALID, "plan, d_xhat and d_x must not be NULL");
+    Plan& p = plan->p;
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    double* U = (double*)(ws + p.off_U);
+    launch_inverse(p, ws, d_xhat, nullptr, U, 0, st);
+    launch_transpose_out(p, U, d_x, st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_shifted_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_x, void* d_y, void* stream) {
+    if (!plan || !d_x || !d_y) return fail(PT_ERR_INVALID, "plan, d_x and d_y must not be NULL");
+    Plan& p = plan->p;
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    launch_matvec(p, ws, d_x, d_y, DOT_NONE, nullptr, st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_precond_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_r, void* d_x, void* stream) {
+    if (!plan || !d_r || !d_x) return fail(PT_ERR_INVALID, "plan, d_r and d_x must not be NULL");
+    Plan& p = plan->p;
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    launch_vcycle(p, ws, d_r, d_x, DOT_NONE, nullptr, st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_periodic_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_r, double* d_x,
+                            int32_t inner_iters, void* stream) {
+    if (!plan || !d_r || !d_x) return fail(PT_ERR_INVALID, "plan, d_r and d_x must not be NULL");
+    Plan& p = plan->p;
+    if (inner_iters < 0 || inner_iters > 64) return fail(PT_ERR_INVALID, "inner_iters must be in [0, 64]");
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    double* U = (double*)(ws + p.off_U);
+    launch_transpose_in(p, d_r, U, st);
+    launch_forward(p, ws, TM_SIGNAL, U, ws + p.lev[0].off_r, nullptr, (double*)(ws + p.off_part), st);
+    const void* X = nullptr;
+    const double* coef = nullptr;
+    s = inner_solve(p, ws, st, inner_iters > 0 ? inner_iters : p.opt.inner_iters, &X, &coef);
+    if (s != PT_OK) return s;
+    launch_inverse(p, ws, X, coef, U, 0, st);
+    launch_transpose_out(p, U, d_x, st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+}  // extern "C"

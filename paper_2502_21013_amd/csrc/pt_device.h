@@ -1,0 +1,114 @@
+// Device-side helpers: slot arithmetic, stencil access, workgroup mapping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pt_internal.h"
+
+namespace pt {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T> __device__ __forceinline__ typename Vec2<T>::type mk2(T x, T y) {
+    typename Vec2<T>::type r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+
+// Generic per-slot scalar in (a, b, c) form (see pt_internal.h).
+template <typename T> struct GS {
+    T a, b, c;
+};
+
+template <typename T> __device__ __forceinline__ GS<T> gs_from(double2 v, bool s0) {
+    GS<T> g;
+    g.a = (T)v.x;
+    g.b = s0 ? (T)0 : (T)v.y;
+    g.c = s0 ? (T)v.y : (T)v.x;
+    return g;
+}
+
+template <typename T, typename T2> __device__ __forceinline__ T2 gs_apply(const GS<T>& g, T2 w) {
+    T2 r;
+    r.x = g.a * w.x - g.b * w.y;
+    r.y = g.c * w.y + g.b * w.x;
+    return r;
+}
+
+// Inverse of D = dl + z (x) dm (z generic, dl and dm real), in generic form.
+template <typename T> __device__ __forceinline__ GS<T> gs_inv_diag(T dl, T dm, const GS<T>& z) {
+    T P = dl + z.a * dm;   // acts on .x
+    T Pp = dl + z.c * dm;  // acts on .y
+    T Q = z.b * dm;
+    T det = P * Pp + Q * Q;
+    T inv = (T)1 / det;
+    GS<T> g;
+    g.a = Pp * inv;
+    g.b = -Q * inv;
+    g.c = P * inv;
+    return g;
+}
+
+template <typename T2> __device__ __forceinline__ T2 add2(T2 a, T2 b) {
+    a.x += b.x;
+    a.y += b.y;
+    return a;
+}
+template <typename T2> __device__ __forceinline__ T2 sub2(T2 a, T2 b) {
+    a.x -= b.x;
+    a.y -= b.y;
+    return a;
+}
+template <typename T, typename T2> __device__ __forceinline__ T2 scale2(T s, T2 a) {
+    a.x *= s;
+    a.y *= s;
+    return a;
+}
+template <typename T, typename T2> __device__ __forceinline__ T2 fma2(T s, T2 a, T2 acc) {
+    acc.x += s * a.x;
+    acc.y += s * a.y;
+    return acc;
+}
+template <typename T2> __device__ __forceinline__ T2 cmul(T2 a, T2 b) {
+    T2 r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename T2> __device__ __forceinline__ T2 conj2(T2 a) {
+    a.y = -a.y;
+    return a;
+}
+// multiply by -i
+template <typename T2> __device__ __forceinline__ T2 mul_mi(T2 a) {
+    T2 r;
+    r.x = a.y;
+    r.y = -a.x;
+    return r;
+}
+
+// Accumulate the three partial sums of a slot dot product:
+//   s1 += u.x v.x,  s2 += u.y v.y,  s3 += u.x v.y -/+ u.y v.x
+// conj = true gives the Hermitian form u^H v, false the bilinear form u^T v.
+template <typename T2> __device__ __forceinline__ void dot3_acc(double* s, T2 u, T2 v, bool conj) {
+    s[0] += (double)u.x * (double)v.x;
+    s[1] += (double)u.y * (double)v.y;
+    double cr = (double)u.x * (double)v.y;
+    double rc = (double)u.y * (double)v.x;
+    s[2] += conj ? (cr - rc) : (cr + rc);
+}
+
+// Virtual workgroup index: workgroups are dispatched round-robin over the XCDs, so
+// this gives every XCD a contiguous range of node groups (its own L2 sees the
+// stencil neighbours of what it processes). blocks is a multiple of kNumXcd.
+__device__ __forceinline__ int virtual_block(int remap) {
+    int b = blockIdx.x;
+    if (!remap) return b;
+    int per = gridDim.x / kNumXcd;
+    return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+}  // namespace pt

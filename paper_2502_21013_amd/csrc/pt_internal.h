@@ -1,0 +1,118 @@
+// Internal declarations shared by the kernel translation units and the C ABI layer.
+//
+// Working layouts in the workspace (all node-major, so that the time axis and the
+// frequency axis are contiguous for every node):
+//   time series    double [nodes][N]        (Uw, Fw: iterate and explicit load)
+//   slot vectors   T2     [nodes][S], S=N/2 (T2 = double2 in FP64 mode, float2 in
+//                                            FP32 mode); slot 0 carries the two real
+//                                            systems k = 0 (.x) and k = N/2 (.y)
+//   M stencil      double [4][nodes] per multigrid level: centre, east (i,i+1),
+//                  north (i,i+side), north-east (i,i+side+1) couplings of the
+//                  sigma-weighted mass (symmetric, so west/south/south-west come
+//                  from the neighbour's entries)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ptsolve.h"
+
+namespace pt {
+
+constexpr int kBlock = 256;          // threads per workgroup in every kernel
+constexpr int kMaxLevels = 16;
+constexpr int kTargetBlocks = 2048;  // per slot chunk, for grid-sized loops
+constexpr int kNumXcd = 8;
+
+// Per-slot scalar in "generic" form: for slot s >= 1 a complex number (x + i y);
+// for slot 0 two reals, x acting on the real part (k = 0) and y on the imaginary
+// part (k = N/2). Applying it to a slot value w is
+//   (a w.x - b w.y,  c w.y + b w.x)
+// with (a, b, c) = (x, y, x) for s >= 1 and (x, 0, y) for s = 0.
+
+struct LevelDesc {
+    int n;          // cells per side at this level
+    int side;       // n + 1
+    size_t nodes;   // side * side
+    size_t off_mt;  // M stencil table, 4 * nodes doubles
+    size_t off_r;   // slot vector: right-hand side at this level
+    size_t off_x;   // slot vector: correction at this level
+};
+
+// Launch geometry of grid-looped kernels over a node range.
+struct Geom {
+    int per_step;   // nodes handled by one workgroup per loop step
+    int slot_chunk; // slots handled per workgroup (slot-vector kernels) or team size (time kernels)
+    int chunks;     // workgroups along y (slot chunks)
+    int steps;      // loop steps per workgroup
+    int blocks;     // workgroups along x (multiple of kNumXcd)
+};
+
+struct Plan {
+    pt_problem prob;
+    pt_options opt;
+    int n, N, S, side;
+    size_t nodes;
+    bool fp32;
+    size_t elem;        // bytes per slot value (16 or 8)
+    double tau, h;
+    int nlev;
+    LevelDesc lev[kMaxLevels];
+    // workspace offsets (bytes)
+    size_t off_U, off_F, off_P, off_cx, off_cr, off_cq, off_cp;
+    size_t off_flags, off_b, off_tw64, off_tw32, off_zs, off_wave;
+    size_t off_part, part_bytes, off_scal, off_coef, off_coef2, off_hist;
+    size_t ws_bytes;
+    bool has_cocg_vectors;
+    // host copies of the small tables uploaded at every call
+    double* h_tw64;     // N complex: exp(-2 pi i k / N)
+    float* h_tw32;      // N complex, float
+    double* h_zs;       // S x 3: generic (a, b, c) of the shift z_s
+    double* h_wave;     // N: w(2 pi t_{j+1} / T)
+    Geom g_slot0;       // slot-vector kernels on level 0
+    Geom g_team;        // per-node team kernels (time axis)
+};
+
+Geom slot_geom(size_t nodes, int S);
+Geom team_geom(size_t nodes, int S);
+
+// ---------------------------------------------------------------- launchers
+// setup (k_setup.hip)
+void launch_setup_fine(const Plan& p, char* ws, hipStream_t st);
+void launch_galerkin(const Plan& p, char* ws, int l, hipStream_t st);
+// time axis (k_time.hip)
+void launch_transpose_in(const Plan& p, const double* src, double* dst, hipStream_t st);
+void launch_transpose_out(const Plan& p, const double* src, double* dst, hipStream_t st);
+enum TimeMode { TM_RESIDUAL = 0, TM_SIGNAL = 1 };
+// forward: residual (or the field itself) per node, packed real DFT to slot vector
+// out (if non-null), real residual to rout (if non-null), norm partials to part.
+void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* out, double* rout,
+                    double* part, hipStream_t st);
+void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, double* out2,
+                         hipStream_t st);
+// inverse: Uw (+)= (1/N) irfft(coef (x) xhat), coef may be null (identity)
+void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coef, double* Uw,
+                    int accumulate, hipStream_t st);
+void launch_apply_K(const Plan& p, char* ws, const double* u, double* ku, int nslices,
+                    hipStream_t st);
+// frequency (k_freq.hip)
+void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmode, double* part,
+                   hipStream_t st);
+enum DotMode { DOT_NONE = 0, DOT_HERM = 1, DOT_BILIN = 2 };
+// y = A x (optional y), partials of x . (A x) with dotmode
+void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode, double* part,
+                   hipStream_t st);
+// reduce dot partials -> generic scalars out[S] (double2)
+void launch_reduce_dots(const Plan& p, double* part, int dotmode, double* out, hipStream_t st);
+// coef = num / den (generic division), with breakdown flag written to flag (int) if |den| tiny
+void launch_slot_div(const Plan& p, const double* num, const double* den, double* coef,
+                     int* flag, hipStream_t st);
+// x += a (x) p ; r -= a (x) q
+void launch_cocg_xr(const Plan& p, const double* coef, void* x, void* r, const void* pv,
+                    const void* q, hipStream_t st);
+// p = z + b (x) p
+void launch_cocg_p(const Plan& p, const double* coef, const void* z, void* pv, hipStream_t st);
+void launch_copy_slots(const Plan& p, const void* src, void* dst, hipStream_t st);
+
+}  // namespace pt

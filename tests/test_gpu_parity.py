@@ -1,0 +1,256 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle on seeded inputs.
+
+Tolerances (FP64 path): pointwise operators agree to rounding (relative 1e-12 in the
+max norm); transforms to 1e-12 relative; full periodic solutions to a relative L2 error
+of 1e-8 when both sides stop at a relative residual of 1e-12 (the error is at most the
+condition number of the linearised space-time operator times the residual, and the
+condition number at these sizes is below 1e3). FP32+refinement reaches the same FP64
+residual, so it meets the same solution bound; its FP32-only kernels (transforms,
+operator, preconditioner) are held to 2e-6 relative (a few float ulps times log N).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dft, fem, periodic as pp
+from tests.gpu_helpers import say, oracle_K_full, oracle_shifted, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2502_21013_amd as P
+    P.library()
+    return P
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+# ---------------------------------------------------------------- nonlinear operator
+
+@pytest.mark.parametrize("n,N,seed,scale", [(4, 4, 0, 1.0), (32, 8, 1, 0.05), (32, 8, 2, 3.0), (64, 4, 3, 0.3)])
+def test_apply_K_matches_oracle(gpu, P, n, N, seed, scale):
+    say(f"apply_K n={n} N={N} seed={seed}")
+    p = W.with_size(W.config2(seed), n, N)
+    d = fem.discretise(p)
+    U = W.random_field(N, n, seed, scale)
+    plan = P.Plan(p)
+    KU = plan.apply_K(dev(U)).cpu().numpy()
+    ref = oracle_K_full(d, U)
+    assert np.max(np.abs(KU - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_apply_K_partial_slices_and_theta(gpu, P):
+    n, N = 16, 8
+    say(f"apply_K theta n={n} N={N}")
+    p0 = W.config5(seed=3, n=n, N=N)
+    d = fem.discretise(p0)
+    U = W.random_field(N, n, 7, 0.5)
+    theta = dev(p0.theta)
+    plan = P.Plan(p0, theta=theta)
+    KU = plan.apply_K(dev(U), nslices=3).cpu().numpy()
+    ref = oracle_K_full(d, U)
+    assert np.max(np.abs(KU[:3] - ref[:3])) <= 1e-12 * np.max(np.abs(ref[:3]))
+
+
+# ---------------------------------------------------------------- residual
+
+@pytest.mark.parametrize("n,N,seed", [(32, 32, 0), (16, 64, 1), (8, 4, 2)])
+def test_residual_matches_oracle(gpu, P, n, N, seed):
+    say(f"residual n={n} N={N} seed={seed}")
+    p = W.with_size(W.config2(seed), n, N)
+    d = fem.discretise(p)
+    U = W.random_field(N, n, seed + 10, 0.1)
+    plan = P.Plan(p)
+    R, rel, fn = plan.residual(dev(U))
+    R = R.cpu().numpy()
+    F = pp.load_series(d)
+    Rref = pp.to_full(d, pp.residual(d, pp.to_free(d, U), F))
+    assert np.max(np.abs(R - Rref)) <= 1e-12 * np.max(np.abs(Rref))
+    assert abs(fn - np.linalg.norm(F)) <= 1e-12 * np.linalg.norm(F)
+    assert abs(rel - np.linalg.norm(Rref) / np.linalg.norm(F)) <= 1e-12 * rel
+
+
+def test_residual_with_explicit_load_and_sigma_table(gpu, P):
+    n, N = 16, 16
+    say(f"residual explicit load n={n} N={N}")
+    p = W.with_size(W.config1(), n, N)
+    rng = np.random.default_rng(5)
+    sigma = rng.uniform(0.0, 2.0, 2 * n * n) * (rng.uniform(size=2 * n * n) < 0.5)
+    d = fem.discretise(p)
+    # the oracle with the same per-triangle conductivity
+    d.mat.sigma = sigma.copy()
+    d.M = fem.restrict(fem.mass_full(d.mesh, sigma), d.mesh.free)
+    F = W.random_field(N, n, 11, 1.0)
+    U = W.random_field(N, n, 12, 0.3)
+    plan = P.Plan(p, sigma=dev(sigma), load=dev(F))
+    R, rel, fn = plan.residual(dev(U))
+    Ff = pp.to_free(d, F)
+    Rref = pp.to_full(d, pp.residual(d, pp.to_free(d, U), Ff))
+    assert np.max(np.abs(R.cpu().numpy() - Rref)) <= 1e-12 * np.max(np.abs(Rref))
+
+
+# ---------------------------------------------------------------- time DFT
+
+@pytest.mark.parametrize("N", [4, 8, 32, 64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_time_dft_matches_definition(gpu, P, N, precision):
+    n = 8
+    say(f"rfft/irfft N={N} {precision}")
+    p = W.with_size(W.config1(), n, N)
+    X = W.random_field(N, n, N, 1.0)
+    plan = P.Plan(p, precision=precision)
+    Xh = plan.rfft(dev(X)).cpu().numpy()
+    ref = dft.rfft_packed(X.reshape(N, -1)).T            # (nodes, S)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert rel_err(Xh, ref) <= tol
+    cd = np.complex128 if precision == "fp64" else np.complex64
+    back = plan.irfft(dev(ref.astype(cd)))
+    assert rel_err(back.cpu().numpy(), X) <= tol
+
+
+# ---------------------------------------------------------------- frequency-domain operator
+
+@pytest.mark.parametrize("n,N", [(8, 8), (32, 32), (16, 128)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_shifted_operator_matches_oracle(gpu, P, n, N, precision):
+    say(f"shifted_apply n={n} N={N} {precision}")
+    p = W.with_size(W.config2(1), n, N)
+    d = fem.discretise(p)
+    rng = np.random.default_rng(n + N)
+    nodes = (n + 1) ** 2
+    Xh = rng.standard_normal((nodes, N // 2)) + 1j * rng.standard_normal((nodes, N // 2))
+    Xh[~d.mesh.free] = 0
+    plan = P.Plan(p, precision=precision)
+    cd = np.complex128 if precision == "fp64" else np.complex64
+    Y = plan.shifted_apply(dev(Xh.astype(cd))).cpu().numpy()
+    ref = oracle_shifted(d, Xh)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert rel_err(Y, ref) <= tol
+
+
+@pytest.mark.parametrize("n,N", [(16, 16), (64, 32)])
+def test_vcycle_is_symmetric_and_contracts(gpu, P, n, N):
+    # B_s^T = B_s for the bilinear form (needed by COCG), and x <- x + B (r - A x)
+    # converges at a mesh-independent rate.
+    say(f"vcycle n={n} N={N}")
+    p = W.with_size(W.config2(2), n, N)
+    d = fem.discretise(p)
+    plan = P.Plan(p)
+    rng = np.random.default_rng(3)
+    nodes = (n + 1) ** 2
+    r1 = rng.standard_normal((nodes, N // 2)) + 1j * rng.standard_normal((nodes, N // 2))
+    r2 = rng.standard_normal((nodes, N // 2)) + 1j * rng.standard_normal((nodes, N // 2))
+    r1[~d.mesh.free] = 0
+    r2[~d.mesh.free] = 0
+    B1 = plan.precond_apply(dev(r1)).cpu().numpy()
+    B2 = plan.precond_apply(dev(r2)).cpu().numpy()
+    for s in range(1, N // 2):
+        a = np.sum(B1[:, s] * r2[:, s])
+        b = np.sum(r1[:, s] * B2[:, s])
+        assert abs(a - b) <= 1e-12 * max(abs(a), 1e-30)
+    for part in (np.real, np.imag):  # slot 0: two real symmetric operators
+        a = np.sum(part(B1[:, 0]) * part(r2[:, 0]))
+        b = np.sum(part(r1[:, 0]) * part(B2[:, 0]))
+        assert abs(a - b) <= 1e-12 * abs(a)
+    # stationary iteration with the V-cycle: error reduction per cycle
+    x = np.zeros_like(r1)
+    rn = [np.linalg.norm(r1, axis=0)]
+    for _ in range(6):
+        Ax = plan.shifted_apply(dev(x)).cpu().numpy()
+        x = x + plan.precond_apply(dev(r1 - Ax)).cpu().numpy()
+        rn.append(np.linalg.norm(r1 - plan.shifted_apply(dev(x)).cpu().numpy(), axis=0))
+    rate = (rn[-1] / rn[0]) ** (1 / 6)
+    assert np.all(rate < 0.5), rate.max()
+
+
+# ---------------------------------------------------------------- periodic linear solve
+
+@pytest.mark.parametrize("n,N", [(16, 16), (32, 8)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_periodic_solve_matches_spacetime_lu(gpu, P, n, N, precision):
+    say(f"periodic_solve n={n} N={N} {precision}")
+    p = W.with_size(W.config2(3), n, N)
+    d = fem.discretise(p)
+    R = W.random_field(N, n, 21, 1.0)
+    plan = P.Plan(p, precision=precision, inner="cocg", inner_iters=30)
+    X = plan.periodic_solve(dev(R)).cpu().numpy()
+    ref = pp.to_full(d, pp.SpaceTimeLU(d).solve(pp.to_free(d, R)))
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert rel_err(X, ref) <= tol
+
+
+# ---------------------------------------------------------------- full solve
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    d = fem.discretise(W.config1())
+    r = pp.fixed_point(d, tol=1e-12, max_iter=2000)
+    return d, r
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("inner,iters", [("galerkin1", 1), ("cocg", 2)])
+def test_config1_solution_matches_oracle(gpu, P, c1_oracle, precision, inner, iters):
+    say(f"solve config1 {precision} {inner}")
+    d, ref = c1_oracle
+    plan = P.Plan(W.config1(), tol=1e-12, precision=precision, inner=inner, inner_iters=iters, max_outer=2000)
+    U, st = plan.solve()
+    U = U.cpu().numpy()
+    assert st.rel_residual <= 1e-12
+    Uref = pp.to_full(d, ref.U)
+    assert rel_err(U, Uref) <= 1e-8
+    # the GPU residual of the returned iterate agrees with the oracle's residual of it
+    Rref = pp.residual(d, pp.to_free(d, U), ref.F)
+    assert abs(np.linalg.norm(Rref) / np.linalg.norm(ref.F) - st.rel_residual) <= 1e-3 * st.rel_residual + 1e-15
+
+
+def test_config1_tolerance_and_iteration_count(gpu, P, c1_oracle):
+    say("solve config1 tol 1e-10")
+    d, ref = c1_oracle
+    plan = P.Plan(W.config1(), tol=1e-10)
+    U, st = plan.solve()
+    oracle_iters = next(k for k, r in enumerate(ref.rel) if r <= 1e-10)
+    assert st.rel_residual <= 1e-10
+    # inexact inner solves cost only a few extra outer steps over the exact oracle
+    assert oracle_iters <= st.outer_iters <= oracle_iters + 30
+    h = np.array(st.history)
+    assert np.all(h[1:] < h[:-1])  # monotone decrease of the residual
+
+
+def test_manufactured_solution_explicit_load(gpu, P):
+    n, N = 32, 16
+    say(f"manufactured n={n} N={N}")
+    p = W.with_size(W.config2(4), n, N)
+    d = fem.discretise(p)
+    a, b, c = W.manufactured_coeffs(1)
+    t = p.tau * np.arange(1, N + 1)
+    prof = a + b * np.cos(2 * np.pi * t) + c * np.sin(4 * np.pi * t)
+    xy = d.mesh.xy[d.free_idx]
+    Ustar = prof[:, None] * (np.sin(np.pi * xy[:, 0]) * np.sin(np.pi * xy[:, 1]))[None, :] * 3.0
+    F = pp.to_full(d, pp.apply_A(d, Ustar))
+    plan = P.Plan(p, tol=1e-12, load=dev(F), max_outer=2000)
+    U, st = plan.solve()
+    assert rel_err(U.cpu().numpy(), pp.to_full(d, Ustar)) <= 1e-9
+
+
+def test_half_wave_symmetry_and_energy_balance(gpu, P):
+    n, N = 64, 32
+    say(f"symmetry/energy n={n} N={N}")
+    p = W.with_size(W.config2(0), n, N)
+    d = fem.discretise(p)
+    plan = P.Plan(p, tol=1e-12, max_outer=2000)
+    U, st = plan.solve()
+    U = U.cpu().numpy()
+    assert np.linalg.norm(U[N // 2:] + U[:N // 2]) <= 1e-10 * np.linalg.norm(U)
+    Uf = pp.to_free(d, U)
+    F = pp.load_series(d)
+    dU = (Uf - np.roll(Uf, 1, axis=0)) / p.tau
+    lhs = p.tau * np.sum(dU * (d.M @ dU.T).T)
+    rhs = 2 * np.sum((F - pp.K_free(d, Uf)) * Uf)
+    assert abs(lhs - rhs) <= 1e-8 * abs(lhs)
