@@ -104,11 +104,14 @@ typedef struct {
     int32_t precision;     /* pt_precision */
     int32_t inner;         /* pt_inner */
     int32_t inner_iters;   /* COCG steps per outer step (PT_INNER_COCG), 1..64 */
-    int32_t vc_sweeps;     /* damped-Jacobi sweeps before and after coarse correction, 1..4 */
+    int32_t vc_sweeps;     /* damped-Jacobi sweeps before and after the coarse correction;
+                              must be 1 (the fused V(1,1) cycle) */
     double vc_omega;       /* Jacobi damping, 0 < omega < 1 */
     int32_t use_initial_guess; /* 0: U^0 = 0; 1: start from the contents of d_u */
     double diverge_factor; /* PT_ERR_DIVERGED if rel > diverge_factor * min(rel) (0 = off) */
     int32_t xcd_remap;     /* 1: map workgroups to contiguous node ranges per XCD */
+    int32_t timing;        /* 1: bracket every kernel launch of pt_solve with HIP events on
+                              the solve stream and report per-kernel device time in pt_stats */
 } pt_options;
 
 typedef struct {
@@ -119,13 +122,19 @@ typedef struct {
     double* residual_history;   /* caller-owned host array or NULL; rel at each check */
     int32_t history_cap;
     int32_t history_len;
+    double* kernel_ms;          /* caller-owned host array [PT_KERNEL_CLASSES] or NULL: total
+                                   device time per kernel class (options.timing = 1) */
+    int64_t* kernel_launches;   /* caller-owned host array [PT_KERNEL_CLASSES] or NULL */
 } pt_stats;
+
+/* Kernel classes reported by the per-kernel timer; pt_kernel_class_name() names them. */
+#define PT_KERNEL_CLASSES 14
 
 typedef struct pt_plan pt_plan;
 
 /* Fill *o with the defaults (tol 1e-8, max_outer 1000, check_every 1, FP64,
  * PT_INNER_GALERKIN1, inner_iters 1, vc_sweeps 1, vc_omega 0.8, no initial guess,
- * diverge_factor 1e3, xcd_remap 1). */
+ * diverge_factor 1e3, xcd_remap 1, timing 0). */
 void pt_options_default(pt_options* o);
 
 /* Validate the problem and options (host only, no device work) and create a plan. */
@@ -176,6 +185,9 @@ pt_status pt_precond_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const voi
  * inner_iters overrides the plan's COCG step count when > 0. */
 pt_status pt_periodic_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_r,
                             double* d_x, int32_t inner_iters, void* stream);
+
+/* Name of kernel class id (0 <= id < PT_KERNEL_CLASSES), or NULL. */
+const char* pt_kernel_class_name(int32_t id);
 
 const char* pt_status_string(pt_status s);
 const char* pt_last_error(void);

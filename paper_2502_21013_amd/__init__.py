@@ -10,8 +10,8 @@ needs the built library and a GPU.
 from __future__ import annotations
 
 import ctypes as C
-from dataclasses import dataclass
-from typing import List, Optional
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
 
 from . import _lib as L
 
@@ -70,6 +70,8 @@ class SolveStats:
     f_norm: float
     time_ms: float
     history: List[float]
+    kernel_ms: Dict[str, float] = field(default_factory=dict)
+    kernel_launches: Dict[str, int] = field(default_factory=dict)
 
 
 class Plan:
@@ -77,7 +79,8 @@ class Plan:
 
     def __init__(self, problem, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
-                 diverge_factor=1e3, xcd_remap=True, theta=None, sigma=None, load=None, device=None):
+                 diverge_factor=1e3, xcd_remap=True, timing=False, theta=None, sigma=None, load=None,
+                 device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -95,6 +98,7 @@ class Plan:
         o.inner_iters, o.vc_omega = int(inner_iters), float(vc_omega)
         o.use_initial_guess = 1 if use_initial_guess else 0
         o.diverge_factor, o.xcd_remap = float(diverge_factor), 1 if xcd_remap else 0
+        o.timing = 1 if timing else 0
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -158,12 +162,19 @@ class Plan:
             U = self.new_time_field()
         ws, nb = self.workspace()
         hist = (C.c_double * history_cap)()
+        kms = (C.c_double * L.PT_KERNEL_CLASSES)()
+        kcnt = (C.c_int64 * L.PT_KERNEL_CLASSES)()
         s = L.Stats()
         s.residual_history = C.cast(hist, C.POINTER(C.c_double))
         s.history_cap = history_cap
+        s.kernel_ms = C.cast(kms, C.POINTER(C.c_double))
+        s.kernel_launches = C.cast(kcnt, C.POINTER(C.c_int64))
         st = self.lib.pt_solve(self._h, ws, nb, self._time_field(U, "U"), self._stream(), C.byref(s))
+        names = [self.lib.pt_kernel_class_name(i).decode() for i in range(L.PT_KERNEL_CLASSES)]
         stats = SolveStats(status=st, outer_iters=s.outer_iters, rel_residual=s.rel_residual,
-                           f_norm=s.f_norm, time_ms=s.time_ms, history=list(hist[: s.history_len]))
+                           f_norm=s.f_norm, time_ms=s.time_ms, history=list(hist[: s.history_len]),
+                           kernel_ms={names[i]: kms[i] for i in range(L.PT_KERNEL_CLASSES) if kcnt[i]},
+                           kernel_launches={names[i]: int(kcnt[i]) for i in range(L.PT_KERNEL_CLASSES) if kcnt[i]})
         if raise_on_error and st != L.PT_OK:
             raise PTError(st, "pt_solve")
         return U, stats

@@ -44,7 +44,7 @@ class Options(C.Structure):
         ("tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
         ("precision", C.c_int32), ("inner", C.c_int32), ("inner_iters", C.c_int32),
         ("vc_sweeps", C.c_int32), ("vc_omega", C.c_double), ("use_initial_guess", C.c_int32),
-        ("diverge_factor", C.c_double), ("xcd_remap", C.c_int32),
+        ("diverge_factor", C.c_double), ("xcd_remap", C.c_int32), ("timing", C.c_int32),
     ]
 
 
@@ -53,7 +53,11 @@ class Stats(C.Structure):
         ("outer_iters", C.c_int32), ("rel_residual", C.c_double), ("f_norm", C.c_double),
         ("time_ms", C.c_double), ("residual_history", C.POINTER(C.c_double)),
         ("history_cap", C.c_int32), ("history_len", C.c_int32),
+        ("kernel_ms", C.POINTER(C.c_double)), ("kernel_launches", C.POINTER(C.c_int64)),
     ]
+
+
+PT_KERNEL_CLASSES = 14
 
 
 _lib = None
@@ -85,6 +89,7 @@ def load():
         "pt_status_string": (C.c_char_p, [i32]),
         "pt_last_error": (C.c_char_p, []),
         "pt_version": (i32, []),
+        "pt_kernel_class_name": (C.c_char_p, [i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -28,6 +28,44 @@ static pt_status fail(pt_status s, const std::string& msg) {
             return fail(PT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
     } while (0)
 
+// ---------------------------------------------------------------- per-kernel event timer
+
+static void tm_flush(const Plan& p) {
+    Timer* t = p.tm;
+    if (!t || !t->on || t->used == 0) return;
+    hipEventSynchronize(t->ev[2 * t->used - 1]);
+    for (int i = 0; i < t->used; ++i) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t->ev[2 * i], t->ev[2 * i + 1]);
+        t->ms[t->kid[i]] += ms;
+        t->cnt[t->kid[i]] += 1;
+    }
+    t->used = 0;
+}
+
+void tm_begin(const Plan& p, int kid, hipStream_t st) {
+    (void)kid;
+    Timer* t = p.tm;
+    if (!t || !t->on) return;
+    if (t->used == Timer::kCap) tm_flush(p);
+    hipEventRecord(t->ev[2 * t->used], st);
+}
+
+void tm_end(const Plan& p, int kid, hipStream_t st) {
+    Timer* t = p.tm;
+    if (!t || !t->on) return;
+    hipEventRecord(t->ev[2 * t->used + 1], st);
+    t->kid[t->used] = kid;
+    t->used += 1;
+}
+
+#define TM(kid, stmt)              \
+    do {                           \
+        tm_begin(p, (kid), st);    \
+        stmt;                      \
+        tm_end(p, (kid), st);      \
+    } while (0)
+
 static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -184,14 +222,31 @@ static pt_status check_ws(const Plan* p, void* ws, size_t bytes) {
     return PT_OK;
 }
 
+// Per-kernel timing for one pt_solve call: events are created once per plan.
+static pt_status timer_start(Plan& p) {
+    if (!p.opt.timing) return PT_OK;
+    if (!p.tm) {
+        p.tm = new (std::nothrow) Timer();
+        if (!p.tm) return fail(PT_ERR_INVALID, "out of host memory");
+        for (int i = 0; i < 2 * Timer::kCap; ++i) PT_HIP(hipEventCreate(&p.tm->ev[i]));
+    }
+    p.tm->on = true;
+    p.tm->used = 0;
+    for (int c = 0; c < KID_COUNT; ++c) {
+        p.tm->ms[c] = 0.0;
+        p.tm->cnt[c] = 0;
+    }
+    return PT_OK;
+}
+
 // Upload the small tables and build the per-level operators in the workspace.
 static pt_status setup(Plan& p, char* ws, hipStream_t st) {
     PT_HIP(hipMemcpyAsync(ws + p.off_tw64, p.h_tw64, (size_t)p.N * 2 * sizeof(double), hipMemcpyHostToDevice, st));
     PT_HIP(hipMemcpyAsync(ws + p.off_tw32, p.h_tw32, (size_t)p.N * 2 * sizeof(float), hipMemcpyHostToDevice, st));
     PT_HIP(hipMemcpyAsync(ws + p.off_zs, p.h_zs, (size_t)p.S * 3 * sizeof(double), hipMemcpyHostToDevice, st));
     PT_HIP(hipMemcpyAsync(ws + p.off_wave, p.h_wave, (size_t)p.N * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_setup_fine(p, ws, st);
-    for (int l = 0; l + 1 < p.nlev; ++l) launch_galerkin(p, ws, l, st);
+    TM(KID_SETUP, launch_setup_fine(p, ws, st));
+    for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin(p, ws, l, st));
     PT_HIP(hipGetLastError());
     return PT_OK;
 }
@@ -213,10 +268,10 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
     void* P = ws + p.off_P;
     if (p.opt.inner == PT_INNER_GALERKIN1) {
         launch_vcycle(p, ws, R, P, DOT_HERM, part, st);
-        launch_reduce_dots(p, part, DOT_HERM, num, st);
-        launch_matvec(p, ws, P, nullptr, DOT_HERM, part, st);
-        launch_reduce_dots(p, part, DOT_HERM, den, st);
-        launch_slot_div(p, num, den, alpha, nullptr, st);
+        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_HERM, num, st));
+        TM(KID_MATVEC, launch_matvec(p, ws, P, nullptr, DOT_HERM, part, st));
+        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_HERM, den, st));
+        TM(KID_REDUCE, launch_slot_div(p, num, den, alpha, nullptr, st));
         *X = P;
         *coef = alpha;
         return PT_OK;
@@ -227,22 +282,22 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
     void* q = ws + p.off_cq;
     void* pv = ws + p.off_cp;
     void* z = P;
-    PT_HIP(hipMemsetAsync(x, 0, p.nodes * S * p.elem, st));
-    launch_copy_slots(p, R, r, st);
+    TM(KID_MEMSET, PT_HIP(hipMemsetAsync(x, 0, p.nodes * S * p.elem, st)));
+    TM(KID_COCG, launch_copy_slots(p, R, r, st));
     launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
-    launch_reduce_dots(p, part, DOT_BILIN, rho, st);
-    launch_copy_slots(p, z, pv, st);
+    TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, rho, st));
+    TM(KID_COCG, launch_copy_slots(p, z, pv, st));
     for (int it = 0; it < iters; ++it) {
-        launch_matvec(p, ws, pv, q, DOT_BILIN, part, st);
-        launch_reduce_dots(p, part, DOT_BILIN, den, st);
-        launch_slot_div(p, rho, den, alpha, flag, st);
-        launch_cocg_xr(p, alpha, x, r, pv, q, st);
+        TM(KID_MATVEC, launch_matvec(p, ws, pv, q, DOT_BILIN, part, st));
+        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, den, st));
+        TM(KID_REDUCE, launch_slot_div(p, rho, den, alpha, flag, st));
+        TM(KID_COCG, launch_cocg_xr(p, alpha, x, r, pv, q, st));
         if (it + 1 == iters) break;
         launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
-        launch_reduce_dots(p, part, DOT_BILIN, rho2, st);
-        launch_slot_div(p, rho2, rho, beta, nullptr, st);
-        launch_cocg_p(p, beta, z, pv, st);
-        PT_HIP(hipMemcpyAsync(rho, rho2, S * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, rho2, st));
+        TM(KID_REDUCE, launch_slot_div(p, rho2, rho, beta, nullptr, st));
+        TM(KID_COCG, launch_cocg_p(p, beta, z, pv, st));
+        TM(KID_COCG, PT_HIP(hipMemcpyAsync(rho, rho2, S * sizeof(double2), hipMemcpyDeviceToDevice, st)));
     }
     *X = x;
     *coef = nullptr;
@@ -263,6 +318,15 @@ extern "C" {
 int32_t pt_version(void) { return 1; }
 
 const char* pt_last_error(void) { return g_last_error.c_str(); }
+
+const char* pt_kernel_class_name(int32_t id) {
+    static const char* names[KID_COUNT] = {"setup",   "transpose", "forward_residual_rfft", "reductions",
+                                           "vcycle_down_fine", "vcycle_down_coarse", "vcycle_coarsest",
+                                           "vcycle_up_fine",   "vcycle_up_coarse",   "matvec_dot",
+                                           "inverse_rfft_update", "cocg_update", "memset", "other"};
+    if (id < 0 || id >= KID_COUNT) return nullptr;
+    return names[id];
+}
 
 const char* pt_status_string(pt_status s) {
     switch (s) {
@@ -320,6 +384,7 @@ pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan
         d.side = nn + 1;
         d.nodes = (size_t)d.side * d.side;
     }
+    p.tm = nullptr;
     p.g_slot0 = slot_geom(p.nodes, p.S);
     p.g_team = team_geom(p.nodes, p.S);
     layout(p);
@@ -330,6 +395,10 @@ pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan
 
 void pt_plan_destroy(pt_plan* plan) {
     if (!plan) return;
+    if (plan->p.tm) {
+        for (int i = 0; i < 2 * Timer::kCap; ++i) hipEventDestroy(plan->p.tm->ev[i]);
+        delete plan->p.tm;
+    }
     delete[] plan->p.h_tw64;
     delete[] plan->p.h_tw32;
     delete[] plan->p.h_zs;
@@ -353,26 +422,28 @@ pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void
     hipEvent_t e0, e1;
     PT_HIP(hipEventCreate(&e0));
     PT_HIP(hipEventCreate(&e1));
+    s = timer_start(p);
+    if (s != PT_OK) return s;
     PT_HIP(hipEventRecord(e0, st));
     s = setup(p, ws, st);
     if (s != PT_OK) return s;
     double* U = (double*)(ws + p.off_U);
-    if (p.prob.d_load) launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st);
+    if (p.prob.d_load) TM(KID_TRANSPOSE, launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st));
     if (p.opt.use_initial_guess)
-        launch_transpose_in(p, d_u, U, st);
+        TM(KID_TRANSPOSE, launch_transpose_in(p, d_u, U, st));
     else
-        PT_HIP(hipMemsetAsync(U, 0, p.nodes * p.N * sizeof(double), st));
+        TM(KID_MEMSET, PT_HIP(hipMemsetAsync(U, 0, p.nodes * p.N * sizeof(double), st)));
     double* part = (double*)(ws + p.off_part);
     double* scal = (double*)(ws + p.off_scal);
     int* flag = (int*)(ws + p.off_scal + 32 * sizeof(double));
-    PT_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    TM(KID_MEMSET, PT_HIP(hipMemsetAsync(flag, 0, sizeof(int), st)));
     void* Rhat = ws + p.lev[0].off_r;
     pt_status result = PT_ERR_NOT_CONVERGED;
     double rel = INFINITY, fnorm = 0.0, best = INFINITY;
     int k = 0, hist = 0;
     for (;;) {
-        launch_forward(p, ws, TM_RESIDUAL, U, Rhat, nullptr, part, st);
-        launch_reduce_norms(p, ws, part, p.g_team.blocks, scal, st);
+        TM(KID_FORWARD, launch_forward(p, ws, TM_RESIDUAL, U, Rhat, nullptr, part, st));
+        TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_team.blocks, scal, st));
         bool last = (k >= p.opt.max_outer);
         if (last || k % p.opt.check_every == 0) {
             double h[2];
@@ -381,6 +452,7 @@ pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void
             PT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
             PT_HIP(hipStreamSynchronize(st));
             PT_HIP(hipGetLastError());
+            tm_flush(p);
             fnorm = std::sqrt(h[1]);
             rel = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
             if (stats && stats->residual_history && hist < stats->history_cap) stats->residual_history[hist] = rel;
@@ -412,13 +484,14 @@ pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void
         const double* coef = nullptr;
         s = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
         if (s != PT_OK) return s;
-        launch_inverse(p, ws, X, coef, U, 1, st);
+        TM(KID_INVERSE, launch_inverse(p, ws, X, coef, U, 1, st));
         ++k;
     }
-    launch_transpose_out(p, U, d_u, st);
+    TM(KID_TRANSPOSE, launch_transpose_out(p, U, d_u, st));
     PT_HIP(hipEventRecord(e1, st));
     PT_HIP(hipEventSynchronize(e1));
     PT_HIP(hipGetLastError());
+    tm_flush(p);
     float ms = 0.f;
     PT_HIP(hipEventElapsedTime(&ms, e0, e1));
     hipEventDestroy(e0);
@@ -429,7 +502,12 @@ pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void
         stats->f_norm = fnorm;
         stats->time_ms = ms;
         stats->history_len = hist < stats->history_cap ? hist : stats->history_cap;
+        for (int c = 0; c < KID_COUNT; ++c) {
+            if (stats->kernel_ms) stats->kernel_ms[c] = p.tm ? p.tm->ms[c] : 0.0;
+            if (stats->kernel_launches) stats->kernel_launches[c] = p.tm ? p.tm->cnt[c] : 0;
+        }
     }
+    if (p.tm) p.tm->on = false;
     return result;
 }
 

@@ -401,12 +401,15 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         Geom g = slot_geom(p.lev[l + 1].nodes, p.S);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
+        int kid = (l == 0) ? KID_DOWN0 : KID_DOWNC;
+        tm_begin(p, kid, st);
         if (p.fp32)
             hipLaunchKernelGGL(k_vc_down<float>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l), host_lv(p, ws, l + 1),
                                rin, rout);
         else
             hipLaunchKernelGGL(k_vc_down<double>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l),
                                host_lv(p, ws, l + 1), rin, rout);
+        tm_end(p, kid, st);
     }
     {
         Geom g = slot_geom(p.lev[L - 1].nodes, p.S);
@@ -414,11 +417,13 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         const void* rin = (L == 1) ? r0 : (const void*)(ws + p.lev[L - 1].off_r);
         void* xout = (L == 1) ? x0 : (void*)(ws + p.lev[L - 1].off_x);
         int grid = (p.S + kBlock - 1) / kBlock;
+        tm_begin(p, KID_COARSEST, st);
         if (p.fp32)
             hipLaunchKernelGGL(k_vc_coarsest<float>, dim3(grid), dim3(kBlock), 0, st, sa, host_lv(p, ws, L - 1), rin, xout);
         else
             hipLaunchKernelGGL(k_vc_coarsest<double>, dim3(grid), dim3(kBlock), 0, st, sa, host_lv(p, ws, L - 1), rin,
                                xout);
+        tm_end(p, KID_COARSEST, st);
     }
     // prolongation sweep
     for (int l = L - 2; l >= 0; --l) {
@@ -429,12 +434,15 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int dm = (l == 0) ? dotmode : DOT_NONE;
+        int kid = (l == 0) ? KID_UP0 : KID_UPC;
+        tm_begin(p, kid, st);
         if (p.fp32)
             hipLaunchKernelGGL(k_vc_up<float>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l), host_lv(p, ws, l + 1),
                                rin, xc, xout, dm, part);
         else
             hipLaunchKernelGGL(k_vc_up<double>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l), host_lv(p, ws, l + 1),
                                rin, xc, xout, dm, part);
+        tm_end(p, kid, st);
     }
 }
 

@@ -49,6 +49,38 @@ struct Geom {
     int blocks;     // workgroups along x (multiple of kNumXcd)
 };
 
+// Kernel classes of the per-launch event timer (order matches pt_kernel_class_name).
+enum KernelId {
+    KID_SETUP = 0,
+    KID_TRANSPOSE,
+    KID_FORWARD,      // fused residual + packed DFT
+    KID_REDUCE,       // norm and dot-product reductions, per-slot scalar kernels
+    KID_DOWN0,        // V-cycle restriction from the finest level
+    KID_DOWNC,        // V-cycle restriction on coarser levels
+    KID_COARSEST,
+    KID_UP0,          // V-cycle prolongation + smoothing onto the finest level
+    KID_UPC,
+    KID_MATVEC,       // (Khat + z M) p with fused dot products
+    KID_INVERSE,      // inverse DFT + iterate update
+    KID_COCG,         // COCG vector updates and copies
+    KID_MEMSET,
+    KID_OTHER,
+    KID_COUNT
+};
+
+struct Timer {
+    static constexpr int kCap = 256;
+    bool on = false;
+    int used = 0;
+    hipEvent_t ev[2 * kCap];
+    int kid[kCap];
+    double ms[KID_COUNT];
+    long long cnt[KID_COUNT];
+};
+
+void tm_begin(const struct Plan& p, int kid, hipStream_t st);
+void tm_end(const struct Plan& p, int kid, hipStream_t st);
+
 struct Plan {
     pt_problem prob;
     pt_options opt;
@@ -72,6 +104,7 @@ struct Plan {
     double* h_wave;     // N: w(2 pi t_{j+1} / T)
     Geom g_slot0;       // slot-vector kernels on level 0
     Geom g_team;        // per-node team kernels (time axis)
+    Timer* tm;          // per-kernel event timer (owned by the plan)
 };
 
 Geom slot_geom(size_t nodes, int S);
