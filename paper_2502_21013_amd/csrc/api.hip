@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -69,40 +70,49 @@ void tm_end(const Plan& p, int kid, hipStream_t st) {
 static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Geom slot_geom(size_t nodes, int S) {
+static void sweep_geom(Geom& g, int side, int target_blocks) {
+    g.col_groups = (side + g.per_step - 1) / g.per_step;
+    int nch = target_blocks / (g.col_groups * g.chunks);
+    if (nch < 1) nch = 1;
+    if (nch > side) nch = side;
+    g.rows_per_chunk = (side + nch - 1) / nch;
+    nch = (side + g.rows_per_chunk - 1) / g.rows_per_chunk;
+    size_t blocks = (size_t)g.col_groups * nch;
+    blocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
+    g.blocks = (int)blocks;
+}
+
+Geom slot_geom(int side, int S, int target_blocks) {
     Geom g;
     g.slot_chunk = S < kBlock ? S : kBlock;
     g.per_step = kBlock / g.slot_chunk;
     g.chunks = S / g.slot_chunk;
-    size_t groups = (nodes + g.per_step - 1) / g.per_step;
-    size_t target = (size_t)kTargetBlocks;
-    size_t steps = (groups + target - 1) / target;
-    if (steps < 1) steps = 1;
-    size_t blocks = (groups + steps - 1) / steps;
-    blocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
-    g.steps = (int)steps;
-    g.blocks = (int)blocks;
+    sweep_geom(g, side, target_blocks);
     return g;
 }
 
-Geom team_geom(size_t nodes, int S) {
+Geom team_geom(int side, int S, int target_blocks) {
     Geom g;
-    // S/4 threads per node: one radix-4 butterfly per thread and stage, and a fixed
-    // LDS footprint of 2 S slot values per node (32 KiB per workgroup in FP64)
+    // S/4 threads per node (one radix-4 butterfly per thread and stage) and at least one
+    // wavefront per workgroup: 64 / (S/4) nodes per workgroup when S < 256, one node
+    // (one or two wavefronts) otherwise.
     int ts = S / 4;
     if (ts < 1) ts = 1;
     if (ts > kBlock) ts = kBlock;
     g.slot_chunk = ts;
+    g.per_step = ts >= 64 ? 1 : 64 / ts;
+    g.chunks = 1;
+    sweep_geom(g, side, target_blocks);
+    return g;
+}
+
+Geom fwd_geom(int side, int S, int target_blocks) {
+    Geom g;
+    int ts = S < kBlock ? S : kBlock;
+    g.slot_chunk = ts;
     g.per_step = kBlock / ts;
     g.chunks = 1;
-    size_t groups = (nodes + g.per_step - 1) / g.per_step;
-    size_t target = (size_t)kTargetBlocks;
-    size_t steps = (groups + target - 1) / target;
-    if (steps < 1) steps = 1;
-    size_t blocks = (groups + steps - 1) / steps;
-    blocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
-    g.steps = (int)steps;
-    g.blocks = (int)blocks;
+    sweep_geom(g, side, target_blocks);
     return g;
 }
 
@@ -170,8 +180,8 @@ static void layout(Plan& p) {
     p.off_tw32 = take((size_t)p.N * 2 * sizeof(float));
     p.off_zs = take(S * 3 * sizeof(double));
     p.off_wave = take((size_t)p.N * sizeof(double));
-    size_t part_slot = (size_t)p.g_slot0.blocks * S * 3;
-    size_t part_team = (size_t)p.g_team.blocks * 2;
+    size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows) * S * 3;
+    size_t part_team = (size_t)p.g_fwd.blocks * 2;
     p.part_bytes = (part_slot > part_team ? part_slot : part_team) * sizeof(double);
     p.off_part = take(p.part_bytes);
     p.off_scal = take(64 * sizeof(double));
@@ -385,8 +395,14 @@ pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan
         d.nodes = (size_t)d.side * d.side;
     }
     p.tm = nullptr;
-    p.g_slot0 = slot_geom(p.nodes, p.S);
-    p.g_team = team_geom(p.nodes, p.S);
+    // grid targets (overridable for tuning through PT_TARGET_SLOT_BLOCKS / PT_TARGET_TEAM_BLOCKS)
+    p.target_slot = 2048;
+    p.target_team = 16384;
+    if (const char* e = std::getenv("PT_TARGET_SLOT_BLOCKS")) p.target_slot = std::max(8, std::atoi(e));
+    if (const char* e = std::getenv("PT_TARGET_TEAM_BLOCKS")) p.target_team = std::max(8, std::atoi(e));
+    p.g_slot0 = slot_geom(p.side, p.S, p.target_slot);
+    p.g_team = team_geom(p.side, p.S, p.target_team);
+    p.g_fwd = fwd_geom(p.side, p.S, p.target_slot);
     layout(p);
     host_tables(p);
     *out = h;
@@ -443,7 +459,7 @@ pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void
     int k = 0, hist = 0;
     for (;;) {
         TM(KID_FORWARD, launch_forward(p, ws, TM_RESIDUAL, U, Rhat, nullptr, part, st));
-        TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_team.blocks, scal, st));
+        TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
         bool last = (k >= p.opt.max_outer);
         if (last || k % p.opt.check_every == 0) {
             double h[2];
@@ -529,7 +545,7 @@ pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* 
     // R is first written node-major into d_r (same size), then moved through U and
     // transposed back into d_r in the time-field layout.
     launch_forward(p, ws, TM_RESIDUAL, U, nullptr, d_r, part, st);
-    launch_reduce_norms(p, ws, part, p.g_team.blocks, scal, st);
+    launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st);
     double h[2];
     PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     PT_HIP(hipStreamSynchronize(st));

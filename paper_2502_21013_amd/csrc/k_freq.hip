@@ -22,19 +22,10 @@ struct LvArgs {
 };
 
 struct SlotArgs {
-    int S, steps, per_step, slot_chunk, remap;
+    int S, per_step, slot_chunk, remap, col_groups, rows_per_chunk;
     double nu, omega;
     const double* zs;  // S x 3 generic (a, b, c) of the shifts
 };
-
-__device__ __forceinline__ LvArgs mk_lv(const LevelDesc& d, char* ws) {
-    LvArgs l;
-    l.n = d.n;
-    l.side = d.side;
-    l.nodes = d.nodes;
-    l.mt = (const double*)(ws + d.off_mt);
-    return l;
-}
 
 template <typename T> __device__ __forceinline__ GS<T> load_shift(const double* zs, int s) {
     GS<T> g;
@@ -44,23 +35,42 @@ template <typename T> __device__ __forceinline__ GS<T> load_shift(const double* 
     return g;
 }
 
-// (A x)_a for interior node a, given the 7 neighbour values of x.
+// The seven mass-stencil coefficients of node a (centre, E, W, N, S, NE, SW).
+struct MRow {
+    double c, e, w, n, s, ne, sw;
+    __device__ __forceinline__ bool any() const {
+        return c != 0.0 || e != 0.0 || w != 0.0 || n != 0.0 || s != 0.0 || ne != 0.0 || sw != 0.0;
+    }
+};
+
+__device__ __forceinline__ MRow mrow(const LvArgs& L, long a) {
+    const long nd = (long)L.nodes, sd = L.side;
+    MRow m;
+    m.c = L.mt[a];
+    m.e = L.mt[nd + a];
+    m.w = L.mt[nd + a - 1];
+    m.n = L.mt[2 * nd + a];
+    m.s = L.mt[2 * nd + a - sd];
+    m.ne = L.mt[3 * nd + a];
+    m.sw = L.mt[3 * nd + a - sd - 1];
+    return m;
+}
+
+// (A x)_a for interior node a with mass row m, given the 7 neighbour values of x.
 template <typename T, typename T2>
-__device__ __forceinline__ T2 apply_A(const LvArgs& L, size_t a, T nu, const GS<T>& z, T2 xc, T2 xe, T2 xw, T2 xn,
-                                      T2 xs, T2 xne, T2 xsw) {
-    const size_t nd = L.nodes, sd = L.side;
+__device__ __forceinline__ T2 apply_A(const MRow& m, T nu, const GS<T>& z, T2 xc, T2 xe, T2 xw, T2 xn, T2 xs,
+                                      T2 xne, T2 xsw) {
     T2 Lx;
     Lx.x = nu * ((T)4 * xc.x - xe.x - xw.x - xn.x - xs.x);
     Lx.y = nu * ((T)4 * xc.y - xe.y - xw.y - xn.y - xs.y);
-    T mc = (T)L.mt[a], me = (T)L.mt[nd + a], mw = (T)L.mt[nd + a - 1], mn = (T)L.mt[2 * nd + a],
-      ms = (T)L.mt[2 * nd + a - sd], mne = (T)L.mt[3 * nd + a], msw = (T)L.mt[3 * nd + a - sd - 1];
-    T2 Mx = scale2(mc, xc);
-    Mx = fma2(me, xe, Mx);
-    Mx = fma2(mw, xw, Mx);
-    Mx = fma2(mn, xn, Mx);
-    Mx = fma2(ms, xs, Mx);
-    Mx = fma2(mne, xne, Mx);
-    Mx = fma2(msw, xsw, Mx);
+    if (!m.any()) return Lx;
+    T2 Mx = scale2((T)m.c, xc);
+    Mx = fma2((T)m.e, xe, Mx);
+    Mx = fma2((T)m.w, xw, Mx);
+    Mx = fma2((T)m.n, xn, Mx);
+    Mx = fma2((T)m.s, xs, Mx);
+    Mx = fma2((T)m.ne, xne, Mx);
+    Mx = fma2((T)m.sw, xsw, Mx);
     return add2(Lx, gs_apply(z, Mx));
 }
 
@@ -92,9 +102,13 @@ __device__ __forceinline__ void store_dot_partials(const double* acc, double* pa
 // ---------------------------------------------------------------- V-cycle: down
 
 // r_c = P^T (r - A x1) with the pre-smoothed x1 = omega D^{-1} r (one Jacobi sweep from
-// zero), evaluated per coarse node from the fine values on the 2-ring around its fine
-// twin (19 nodes).
-template <typename T>
+// zero). Thread (coarse column ci, slot) walks up the fine rows R around fine column
+// c = 2 ci with a 3-row x 5-column register window of x1 (rows R-1..R+1, columns
+// c-2..c+2), forms the fine residual s = r - A x1 at columns c-1, c, c+1 of row R and adds
+// it into the coarse rows it belongs to with the P^T weights: row 2cj-1 contributes
+// (c-1, c) x 1/2, row 2cj contributes (c-1, c, c+1) x (1/2, 1, 1/2), row 2cj+1
+// contributes (c, c+1) x 1/2 (P1 interpolation on the SW-NE split grid).
+template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_, void* rout_) {
     using T2 = typename Vec2<T>::type;
     const T2* rin = (const T2*)rin_;
@@ -104,49 +118,78 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
     const GS<T> z = load_shift<T>(sa.zs, s);
-    const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu;
-    const long sf = F.side;
-    for (int step = 0; step < sa.steps; ++step) {
-        size_t I = ((size_t)vb * sa.steps + step) * sa.per_step + ln;
-        if (I >= C.nodes) continue;
-        int ci = (int)(I % C.side), cj = (int)(I / C.side);
-        T2 out = mk2<T>(0, 0);
-        if (ci > 0 && cj > 0 && ci < C.n && cj < C.n) {
-            size_t c = (size_t)(2 * cj) * sf + 2 * ci;
-            // x1 on the 5 x 5 patch around c (only the 19 hexagonal-ring points are used)
-            T2 x1[5][5];
+    const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl;
+    const int sf = F.side, nF = F.n, sc = C.side, nc = C.n;
+    const T half = (T)0.5;
+    const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, sc);
+    int ci = sr.col0 + ln;
+    if (UNI) ci = __builtin_amdgcn_readfirstlane(ci);
+    if (ci >= sc) return;
+    const T2 zero = mk2<T>(0, 0);
+    // boundary coarse nodes of this chunk are zero
+    for (int cj = sr.row0; cj < sr.row1; ++cj)
+        if (ci == 0 || ci == nc || cj == 0 || cj == nc) rout[(size_t)(cj * sc + ci) * S + s] = zero;
+    if (ci == 0 || ci == nc) return;
+    const int cj0 = sr.row0 > 1 ? sr.row0 : 1;
+    const int cj1 = sr.row1 < nc ? sr.row1 : nc;  // interior coarse rows [cj0, cj1)
+    if (cj0 >= cj1) return;
+    const int c = 2 * ci;
+    // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
+    T2 xa[5], xb[5], xq[5], ra[3], rb[3], rq[3];
+    auto load_row = [&](int R, T2* xr, T2* rr) {
 #pragma unroll
-            for (int dy = -2; dy <= 2; ++dy) {
-#pragma unroll
-                for (int dx = -2; dx <= 2; ++dx) {
-                    int ddx = dx - dy;
-                    bool need = (ddx >= -2 && ddx <= 2) && !((dx == 2 && dy == -2) || (dx == -2 && dy == 2));
-                    // hexagonal distance in the SW-NE lattice: max(|dx|,|dy|,|dx-dy|) <= 2
-                    need = need && (dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2);
-                    if (need) {
-                        size_t b = c + (long)dy * sf + dx;
-                        T2 rb = rin[b * S + s];
-                        GS<T> di = gs_inv_diag<T>(dl, (T)F.mt[b], z);
-                        x1[dy + 2][dx + 2] = scale2(om, gs_apply(di, rb));
-                    } else {
-                        x1[dy + 2][dx + 2] = mk2<T>(0, 0);
-                    }
-                }
+        for (int d = 0; d < 5; ++d) {
+            T2 v = zero, rv = zero;
+            if (R >= 0 && R <= nF) {
+                const int b = R * sf + c - 2 + d;
+                rv = rin[(size_t)b * S + s];
+                GS<T> di = gs_inv_diag<T>(dl, idl, (T)F.mt[b], z);
+                v = scale2(om, gs_apply(di, rv));
             }
-            // supports of the coarse hat function: offset and weight
-            const int ox[7] = {0, 1, -1, 0, 0, 1, -1};
-            const int oy[7] = {0, 0, 0, 1, -1, 1, -1};
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                int X = ox[q] + 2, Y = oy[q] + 2;
-                size_t a = c + (long)oy[q] * sf + ox[q];
-                T2 Ax = apply_A<T, T2>(F, a, nu, z, x1[Y][X], x1[Y][X + 1], x1[Y][X - 1], x1[Y + 1][X], x1[Y - 1][X],
-                                       x1[Y + 1][X + 1], x1[Y - 1][X - 1]);
-                T2 res = sub2(rin[a * S + s], Ax);
-                out = fma2(q == 0 ? (T)1 : (T)0.5, res, out);
-            }
+            xr[d] = v;
+            if (d >= 1 && d <= 3) rr[d - 1] = rv;
         }
-        rout[I * S + s] = out;
+    };
+    const int Rs = 2 * cj0 - 1, Re = 2 * cj1 - 1;
+    load_row(Rs - 1, xa, ra);
+    load_row(Rs, xb, rb);
+    load_row(Rs + 1, xq, rq);
+    T2 acc = zero;
+    for (int R = Rs; R <= Re; ++R) {
+        // s = r - A x1 at (c-1+k, R), k = 0..2; window rows: xa = R-1, xb = R, xq = R+1
+        T2 sv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int a = R * sf + c - 1 + k;
+            T2 Ax = apply_A<T, T2>(mrow(F, a), nu, z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1], xa[k + 1], xq[k + 2],
+                                   xa[k]);
+            sv[k] = sub2(rb[k], Ax);
+        }
+        if (R & 1) {
+            if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
+                acc = fma2(half, sv[1], acc);
+                acc = fma2(half, sv[2], acc);
+                rout[(size_t)(((R - 1) / 2) * sc + ci) * S + s] = acc;
+            }
+            acc = scale2(half, add2(sv[0], sv[1]));  // lower row of coarse row (R+1)/2
+        } else {
+            acc = fma2(half, sv[0], acc);
+            acc = add2(acc, sv[1]);
+            acc = fma2(half, sv[2], acc);
+        }
+        if (R < Re) {
+#pragma unroll
+            for (int d = 0; d < 5; ++d) {
+                xa[d] = xb[d];
+                xb[d] = xq[d];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                ra[d] = rb[d];
+                rb[d] = rq[d];
+            }
+            load_row(R + 2, xq, rq);
+        }
     }
 }
 
@@ -165,7 +208,8 @@ __global__ void __launch_bounds__(kBlock) k_vc_coarsest(SlotArgs sa, LvArgs C, c
         for (size_t node = 0; node < C.nodes; ++node) {
             T2 v = mk2<T>(0, 0);
             if (node == (size_t)C.side + 1) {
-                GS<T> di = gs_inv_diag<T>((T)4 * (T)sa.nu, (T)C.mt[node], z);
+                T dl = (T)4 * (T)sa.nu;
+                GS<T> di = gs_inv_diag<T>(dl, (T)1 / dl, (T)C.mt[node], z);
                 v = gs_apply(di, rin[node * S + s]);
             }
             xout[node * S + s] = v;
@@ -199,8 +243,10 @@ __device__ __forceinline__ T2 prolong_at(const T2* xc, int sc, int S, int s, int
 
 // x2 = omega D^{-1} r + P x_c (pre-smoothed iterate plus coarse correction), then one
 // post-smoothing sweep x3 = x2 + omega D^{-1} (r - A x2). Optionally accumulates the
-// dot partials of (x3, r).
-template <typename T>
+// dot partials of (x3, r). Each thread walks down one column: the seven x2 values of the
+// stencil of row j are kept in registers and only the three new ones of row j+1,
+// (i-1, j+1), (i, j+2) and (i+1, j+2), are evaluated per step.
+template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
     using T2 = typename Vec2<T>::type;
@@ -212,41 +258,65 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
     const GS<T> z = load_shift<T>(sa.zs, s);
-    const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu;
-    const long sf = F.side;
+    const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl;
+    const int sf = F.side, nF = F.n;
     double acc[3] = {0, 0, 0};
-    for (int step = 0; step < sa.steps; ++step) {
-        size_t a = ((size_t)vb * sa.steps + step) * sa.per_step + ln;
-        if (a >= F.nodes) continue;
-        int ai = (int)(a % F.side), aj = (int)(a / F.side);
-        T2 out = mk2<T>(0, 0);
-        if (ai > 0 && aj > 0 && ai < F.n && aj < F.n) {
-            const int ox[7] = {0, 1, -1, 0, 0, 1, -1};
-            const int oy[7] = {0, 0, 0, 1, -1, 1, -1};
-            T2 x2[7];
-            T2 ra;
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                size_t b = a + (long)oy[q] * sf + ox[q];
-                T2 rb = rin[b * S + s];
-                if (q == 0) ra = rb;
-                GS<T> di = gs_inv_diag<T>(dl, (T)F.mt[b], z);
-                T2 v = scale2(om, gs_apply(di, rb));
-                x2[q] = add2(v, prolong_at(xc, C.side, S, s, ai + ox[q], aj + oy[q]));
-            }
-            T2 Ax = apply_A<T, T2>(F, a, nu, z, x2[0], x2[1], x2[2], x2[3], x2[4], x2[5], x2[6]);
-            GS<T> da = gs_inv_diag<T>(dl, (T)F.mt[a], z);
-            out = add2(x2[0], scale2(om, gs_apply(da, sub2(ra, Ax))));
-            if (dotmode != DOT_NONE) dot3_acc(acc, out, ra, dotmode == DOT_HERM);
+    const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
+    int ai = sr.col0 + ln;
+    if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
+    // x2 and r at fine node (bi, bj); zero outside the grid rows
+    auto eval = [&](int bi, int bj, T2& rb) -> T2 {
+        if (bj < 0 || bj > nF) {
+            rb = mk2<T>(0, 0);
+            return rb;
         }
-        xout[a * S + s] = out;
+        const int b = bj * sf + bi;
+        rb = rin[(size_t)b * S + s];
+        GS<T> di = gs_inv_diag<T>(dl, idl, (T)F.mt[b], z);
+        return add2(scale2(om, gs_apply(di, rb)), prolong_at(xc, C.side, S, s, bi, bj));
+    };
+    if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
+        T2 rdum, rc, rn;
+        const int j0 = sr.row0;
+        T2 xsw = eval(ai - 1, j0 - 1, rdum), xs = eval(ai, j0 - 1, rdum);
+        T2 xw = eval(ai - 1, j0, rdum), xcn = eval(ai, j0, rc), xe = eval(ai + 1, j0, rdum);
+        T2 xn = eval(ai, j0 + 1, rn), xne = eval(ai + 1, j0 + 1, rdum);
+        for (int aj = j0; aj < sr.row1; ++aj) {
+            const int a = aj * sf + ai;
+            T2 out = mk2<T>(0, 0);
+            if (aj > 0 && aj < nF) {
+                T2 Ax = apply_A<T, T2>(mrow(F, a), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
+                GS<T> da = gs_inv_diag<T>(dl, idl, (T)F.mt[a], z);
+                out = add2(xcn, scale2(om, gs_apply(da, sub2(rc, Ax))));
+                if (dotmode != DOT_NONE) dot3_acc(acc, out, rc, dotmode == DOT_HERM);
+            }
+            xout[(size_t)a * S + s] = out;
+            if (aj + 1 < sr.row1) {
+                T2 rn2;
+                T2 nw = eval(ai - 1, aj + 1, rdum);
+                T2 n2 = eval(ai, aj + 2, rn2);
+                T2 ne2 = eval(ai + 1, aj + 2, rdum);
+                xsw = xw;
+                xs = xcn;
+                xw = nw;
+                xcn = xn;
+                rc = rn;
+                xe = xne;
+                xn = n2;
+                rn = rn2;
+                xne = ne2;
+            }
+        }
+    } else if (ai < sf) {
+        for (int aj = sr.row0; aj < sr.row1; ++aj) xout[(size_t)(aj * sf + ai) * S + s] = mk2<T>(0, 0);
     }
     if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, S, blockIdx.y, SC);
 }
 
 // ---------------------------------------------------------------- operator apply
 
-template <typename T>
+// y = A x and the dot partials of (x, A x); rolling window along the column as in k_vc_up.
+template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const void* x_, void* y_, int dotmode,
                                                    double* part) {
     using T2 = typename Vec2<T>::type;
@@ -258,20 +328,40 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     const int vb = virtual_block(sa.remap);
     const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu;
-    const long sf = F.side;
+    const int sf = F.side, nF = F.n;
     double acc[3] = {0, 0, 0};
-    for (int step = 0; step < sa.steps; ++step) {
-        size_t a = ((size_t)vb * sa.steps + step) * sa.per_step + ln;
-        if (a >= F.nodes) continue;
-        int ai = (int)(a % F.side), aj = (int)(a / F.side);
-        T2 out = mk2<T>(0, 0);
-        if (ai > 0 && aj > 0 && ai < F.n && aj < F.n) {
-            T2 xc = x[a * S + s];
-            out = apply_A<T, T2>(F, a, nu, z, xc, x[(a + 1) * S + s], x[(a - 1) * S + s], x[(a + sf) * S + s],
-                                 x[(a - sf) * S + s], x[(a + sf + 1) * S + s], x[(a - sf - 1) * S + s]);
-            if (dotmode != DOT_NONE) dot3_acc(acc, xc, out, dotmode == DOT_HERM);
+    const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
+    int ai = sr.col0 + ln;
+    if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
+    auto ld = [&](int bi, int bj) -> T2 {
+        if (bj < 0 || bj > nF) return mk2<T>(0, 0);
+        return x[(size_t)(bj * sf + bi) * S + s];
+    };
+    if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
+        const int j0 = sr.row0;
+        T2 xsw = ld(ai - 1, j0 - 1), xs = ld(ai, j0 - 1), xw = ld(ai - 1, j0), xcn = ld(ai, j0), xe = ld(ai + 1, j0);
+        T2 xn = ld(ai, j0 + 1), xne = ld(ai + 1, j0 + 1);
+        for (int aj = j0; aj < sr.row1; ++aj) {
+            const int a = aj * sf + ai;
+            T2 out = mk2<T>(0, 0);
+            if (aj > 0 && aj < nF) {
+                out = apply_A<T, T2>(mrow(F, a), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
+                if (dotmode != DOT_NONE) dot3_acc(acc, xcn, out, dotmode == DOT_HERM);
+            }
+            if (y) y[(size_t)a * S + s] = out;
+            if (aj + 1 < sr.row1) {
+                T2 nw = ld(ai - 1, aj + 1), n2 = ld(ai, aj + 2), ne2 = ld(ai + 1, aj + 2);
+                xsw = xw;
+                xs = xcn;
+                xw = nw;
+                xcn = xn;
+                xe = xne;
+                xn = n2;
+                xne = ne2;
+            }
         }
-        if (y) y[a * S + s] = out;
+    } else if (ai < sf && y) {
+        for (int aj = sr.row0; aj < sr.row1; ++aj) y[(size_t)(aj * sf + ai) * S + s] = mk2<T>(0, 0);
     }
     if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, S, blockIdx.y, SC);
 }
@@ -281,6 +371,40 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
 // Sum the partials of every workgroup in a fixed order and combine them into a generic
 // scalar: Hermitian u^H v = (s1 + s2) + i s3, bilinear u^T v = (s1 - s2) + i s3, and for
 // slot 0 the two real dot products (s1, s2).
+// Stage 1: workgroup (x, y) sums partial rows [y nblk / RB, (y+1) nblk / RB) for SG slots
+// (threads: SG slots x 256/SG row lanes, lanes combined in a fixed order) into part2[y][s].
+__global__ void __launch_bounds__(kBlock) k_reduce_dots1(const double* part, int nblk, int S, double* part2) {
+    __shared__ double red[3][kBlock];
+    const int SG = S < 64 ? S : 64, RL = kBlock / SG;
+    const int sl = threadIdx.x % SG, rl = threadIdx.x / SG;
+    const int s = blockIdx.x * SG + sl;
+    const int RB = gridDim.y;
+    const int b0 = (int)((long)blockIdx.y * nblk / RB), b1 = (int)((long)(blockIdx.y + 1) * nblk / RB);
+    double s1 = 0, s2 = 0, s3 = 0;
+    for (int b = b0 + rl; b < b1; b += RL) {
+        const double* o = part + ((size_t)b * S + s) * 3;
+        s1 += o[0];
+        s2 += o[1];
+        s3 += o[2];
+    }
+    red[0][threadIdx.x] = s1;
+    red[1][threadIdx.x] = s2;
+    red[2][threadIdx.x] = s3;
+    __syncthreads();
+    if (rl == 0) {
+        for (int r = 1; r < RL; ++r) {
+            s1 += red[0][r * SG + sl];
+            s2 += red[1][r * SG + sl];
+            s3 += red[2][r * SG + sl];
+        }
+        double* o = part2 + ((size_t)blockIdx.y * S + s) * 3;
+        o[0] = s1;
+        o[1] = s2;
+        o[2] = s3;
+    }
+}
+
+// Stage 2: sum the RB rows of part2 in order and combine into a generic scalar.
 __global__ void __launch_bounds__(kBlock) k_reduce_dots(const double* part, int nblk, int S, int herm, double* out) {
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
         double s1 = 0, s2 = 0, s3 = 0;
@@ -366,7 +490,8 @@ __global__ void __launch_bounds__(kBlock) k_cocg_p(int S, size_t total, const do
 static SlotArgs mk_slot(const Plan& p, char* ws, const Geom& g) {
     SlotArgs sa;
     sa.S = p.S;
-    sa.steps = g.steps;
+    sa.col_groups = g.col_groups;
+    sa.rows_per_chunk = g.rows_per_chunk;
     sa.per_step = g.per_step;
     sa.slot_chunk = g.slot_chunk;
     sa.remap = p.opt.xcd_remap;
@@ -398,21 +523,28 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
     for (int l = 0; l + 1 < L; ++l) {
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* rout = ws + p.lev[l + 1].off_r;
-        Geom g = slot_geom(p.lev[l + 1].nodes, p.S);
+        Geom g = slot_geom(p.lev[l + 1].side, p.S, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int kid = (l == 0) ? KID_DOWN0 : KID_DOWNC;
         tm_begin(p, kid, st);
-        if (p.fp32)
-            hipLaunchKernelGGL(k_vc_down<float>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l), host_lv(p, ws, l + 1),
-                               rin, rout);
-        else
-            hipLaunchKernelGGL(k_vc_down<double>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l),
-                               host_lv(p, ws, l + 1), rin, rout);
+        LvArgs Fl = host_lv(p, ws, l), Cl = host_lv(p, ws, l + 1);
+        bool uni = g.slot_chunk >= 64;
+        if (p.fp32) {
+            if (uni)
+                hipLaunchKernelGGL((k_vc_down<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+            else
+                hipLaunchKernelGGL((k_vc_down<float, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+        } else {
+            if (uni)
+                hipLaunchKernelGGL((k_vc_down<double, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+            else
+                hipLaunchKernelGGL((k_vc_down<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+        }
         tm_end(p, kid, st);
     }
     {
-        Geom g = slot_geom(p.lev[L - 1].nodes, p.S);
+        Geom g = slot_geom(p.lev[L - 1].side, p.S, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         const void* rin = (L == 1) ? r0 : (const void*)(ws + p.lev[L - 1].off_r);
         void* xout = (L == 1) ? x0 : (void*)(ws + p.lev[L - 1].off_x);
@@ -430,18 +562,28 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* xout = (l == 0) ? x0 : (void*)(ws + p.lev[l].off_x);
         const void* xc = ws + p.lev[l + 1].off_x;
-        Geom g = slot_geom(p.lev[l].nodes, p.S);
+        Geom g = slot_geom(p.lev[l].side, p.S, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int dm = (l == 0) ? dotmode : DOT_NONE;
         int kid = (l == 0) ? KID_UP0 : KID_UPC;
         tm_begin(p, kid, st);
-        if (p.fp32)
-            hipLaunchKernelGGL(k_vc_up<float>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l), host_lv(p, ws, l + 1),
-                               rin, xc, xout, dm, part);
-        else
-            hipLaunchKernelGGL(k_vc_up<double>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, l), host_lv(p, ws, l + 1),
-                               rin, xc, xout, dm, part);
+        LvArgs Fl = host_lv(p, ws, l), Cl = host_lv(p, ws, l + 1);
+        bool uni = g.slot_chunk >= 64;
+        if (p.fp32) {
+            if (uni)
+                hipLaunchKernelGGL((k_vc_up<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm, part);
+            else
+                hipLaunchKernelGGL((k_vc_up<float, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
+                                   part);
+        } else {
+            if (uni)
+                hipLaunchKernelGGL((k_vc_up<double, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
+                                   part);
+            else
+                hipLaunchKernelGGL((k_vc_up<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
+                                   part);
+        }
         tm_end(p, kid, st);
     }
 }
@@ -450,15 +592,30 @@ void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode,
     const Geom& g = p.g_slot0;
     SlotArgs sa = mk_slot(p, ws, g);
     dim3 grid(g.blocks, g.chunks);
-    if (p.fp32)
-        hipLaunchKernelGGL(k_matvec<float>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, 0), x, y, dotmode, part);
-    else
-        hipLaunchKernelGGL(k_matvec<double>, grid, dim3(kBlock), 0, st, sa, host_lv(p, ws, 0), x, y, dotmode, part);
+    LvArgs Fl = host_lv(p, ws, 0);
+    bool uni = g.slot_chunk >= 64;
+    if (p.fp32) {
+        if (uni)
+            hipLaunchKernelGGL((k_matvec<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
+        else
+            hipLaunchKernelGGL((k_matvec<float, false>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
+    } else {
+        if (uni)
+            hipLaunchKernelGGL((k_matvec<double, true>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
+        else
+            hipLaunchKernelGGL((k_matvec<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
+    }
 }
 
 void launch_reduce_dots(const Plan& p, double* part, int dotmode, double* out, hipStream_t st) {
+    // stage 1 into the tail of the partial buffer, then stage 2
+    const int nblk = p.g_slot0.blocks;
+    const int RB = nblk < kReduceRows ? nblk : kReduceRows;
+    const int SG = p.S < 64 ? p.S : 64;
+    double* part2 = part + (size_t)nblk * p.S * 3;
+    hipLaunchKernelGGL(k_reduce_dots1, dim3(p.S / SG, RB), dim3(kBlock), 0, st, (const double*)part, nblk, p.S, part2);
     int grid = (p.S + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_reduce_dots, dim3(grid), dim3(kBlock), 0, st, (const double*)part, p.g_slot0.blocks, p.S,
+    hipLaunchKernelGGL(k_reduce_dots, dim3(grid), dim3(kBlock), 0, st, (const double*)part2, RB, p.S,
                        dotmode == DOT_HERM ? 1 : 0, out);
 }
 

@@ -74,7 +74,7 @@ __device__ T2* fft_team(T2* a, T2* b, int S, int lt, int TS, const T2* __restric
 // ---------------------------------------------------------------- forward kernel
 
 struct FwdArgs {
-    int n, side, N, S, ts, nb, steps, remap, mode;
+    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, mode;
     size_t nodes;
     double inv_tau, n2;
     double nu_a, nu_b, nu_out;
@@ -91,105 +91,251 @@ struct FwdArgs {
     double* part;          // [gridDim.x][2]
 };
 
+// 1 / x for x >= 1 to full double precision: hardware reciprocal estimate refined by two
+// Newton steps r <- r + r (1 - x r) (each step squares the relative error).
+__device__ __forceinline__ double rcp_ge1(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// Reluctivity of one triangle from its scaled gradient G = h grad u: nu_a + nu_b s^2/(1+s^2)
+// = (nu_a + nu_b) - nu_b / (1 + s^2) with s^2 = n^2 |G|^2, times theta; nu_out outside iron.
 __device__ __forceinline__ double nu_tri(double gx, double gy, const FwdArgs& a, bool iron, double th) {
     if (!iron) return th * a.nu_out;
     double s2 = a.n2 * (gx * gx + gy * gy);
-    return th * (a.nu_a + a.nu_b * s2 / (1.0 + s2));
+    return th * ((a.nu_a + a.nu_b) - a.nu_b * rcp_ge1(1.0 + s2));
 }
 
-template <typename T>
+// K(u)_i at an interior node from the values of u at the node and its six neighbours
+// (triangles T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i,j-1), T_a(i-1,j-1), T_b(i-1,j-1);
+// the node is vertex 0, 0, 1, 2, 2, 1 of them, with scaled basis gradients (-1,0),
+// (0,-1), (1,-1), (-1,1), (0,1), (1,0)).
+struct NodeMat {
+    bool ir[6];
+    double th[6];
+};
+
+__device__ __forceinline__ double k_node(const FwdArgs& a, const NodeMat& m, double uc, double ue, double uw,
+                                         double un, double us, double une, double usw) {
+    double g1x = ue - uc, g1y = une - ue;   // T_a(i,j)
+    double g2x = une - un, g2y = un - uc;   // T_b(i,j)
+    double g3x = uc - uw, g3y = un - uc;    // T_a(i-1,j)
+    double g4x = ue - uc, g4y = uc - us;    // T_b(i,j-1)
+    double g5x = us - usw, g5y = uc - us;   // T_a(i-1,j-1)
+    double g6x = uc - uw, g6y = uw - usw;   // T_b(i-1,j-1)
+    double K = nu_tri(g1x, g1y, a, m.ir[0], m.th[0]) * (-g1x) + nu_tri(g2x, g2y, a, m.ir[1], m.th[1]) * (-g2y) +
+               nu_tri(g3x, g3y, a, m.ir[2], m.th[2]) * (g3x - g3y) +
+               nu_tri(g4x, g4y, a, m.ir[3], m.th[3]) * (g4y - g4x) + nu_tri(g5x, g5y, a, m.ir[4], m.th[4]) * g5y +
+               nu_tri(g6x, g6y, a, m.ir[5], m.th[5]) * g6x;
+    return 0.5 * K;
+}
+
+__device__ __forceinline__ NodeMat node_materials(const FwdArgs& a, int i, int j) {
+    NodeMat m;
+    size_t c_ij = (size_t)j * a.n + i, c_w = c_ij - 1, c_s = c_ij - a.n, c_sw = c_ij - a.n - 1;
+    m.ir[0] = a.flags[2 * c_ij] & 1;
+    m.ir[1] = a.flags[2 * c_ij + 1] & 1;
+    m.ir[2] = a.flags[2 * c_w] & 1;
+    m.ir[3] = a.flags[2 * c_s + 1] & 1;
+    m.ir[4] = a.flags[2 * c_sw] & 1;
+    m.ir[5] = a.flags[2 * c_sw + 1] & 1;
+    if (a.theta) {
+        m.th[0] = a.theta[2 * c_ij];
+        m.th[1] = a.theta[2 * c_ij + 1];
+        m.th[2] = a.theta[2 * c_w];
+        m.th[3] = a.theta[2 * c_s + 1];
+        m.th[4] = a.theta[2 * c_sw];
+        m.th[5] = a.theta[2 * c_sw + 1];
+    } else {
+        for (int t = 0; t < 6; ++t) m.th[t] = 1.0;
+    }
+    return m;
+}
+
+// Material flags and scales of the two triangles T_a (t = 0) and T_b (t = 1) of cell (ci, cj).
+__device__ __forceinline__ void cell_mat(const FwdArgs& a, int ci, int cj, bool ir[2], double th[2]) {
+    size_t c = (size_t)cj * a.n + ci;
+    ir[0] = a.flags[2 * c] & 1;
+    ir[1] = a.flags[2 * c + 1] & 1;
+    th[0] = a.theta ? a.theta[2 * c] : 1.0;
+    th[1] = a.theta ? a.theta[2 * c + 1] : 1.0;
+}
+
+// Per-lane state of the column walk for one time value: u on the rows j-1 (s, sw), j
+// (w, c, e) and j+1 (nw, n, ne), and the contribution of the three triangles of the cells
+// of row j-1 to K at node (i, j).
+struct Win {
+    double sw, s, w, c, e, nw, n, ne, carry;
+};
+
+// The three triangles of the cells of row j-1 that touch node (i, j): T_b(i,j-1),
+// T_a(i-1,j-1), T_b(i-1,j-1) (node = vertex 2, 2, 1; scaled gradients (-1,1), (0,1), (1,0)).
+__device__ __forceinline__ double lower_three(const FwdArgs& a, const Win& v, const bool ir_s[2], const double th_s[2],
+                                              const bool ir_sw[2], const double th_sw[2]) {
+    double g4x = v.e - v.c, g4y = v.c - v.s;
+    double g5x = v.s - v.sw, g5y = v.c - v.s;
+    double g6x = v.c - v.w, g6y = v.w - v.sw;
+    return 0.5 * (nu_tri(g4x, g4y, a, ir_s[1], th_s[1]) * (g4y - g4x) + nu_tri(g5x, g5y, a, ir_sw[0], th_sw[0]) * g5y +
+                  nu_tri(g6x, g6y, a, ir_sw[1], th_sw[1]) * g6x);
+}
+
+// K at node (i, j) from the four triangles of the cells of row j (T_a(i,j), T_b(i,j),
+// T_a(i-1,j), T_b(i-1,j)) plus the carried lower part; also returns the carried part
+// for node (i, j+1): T_b(i,j) (vertex 2, (-1,1)), T_a(i-1,j) (vertex 2, (0,1)),
+// T_b(i-1,j) (vertex 1, (1,0)).
+__device__ __forceinline__ double upper_four(const FwdArgs& a, const Win& v, const bool ir_c[2], const double th_c[2],
+                                             const bool ir_w[2], const double th_w[2], double& carry_up) {
+    double g1x = v.e - v.c, g1y = v.ne - v.e;    // T_a(i,j)
+    double g2x = v.ne - v.n, g2y = v.n - v.c;    // T_b(i,j)
+    double g3x = v.c - v.w, g3y = v.n - v.c;     // T_a(i-1,j)
+    double g4x = v.n - v.nw, g4y = v.nw - v.w;   // T_b(i-1,j)
+    double nu1 = nu_tri(g1x, g1y, a, ir_c[0], th_c[0]);
+    double nu2 = nu_tri(g2x, g2y, a, ir_c[1], th_c[1]);
+    double nu3 = nu_tri(g3x, g3y, a, ir_w[0], th_w[0]);
+    double nu4 = nu_tri(g4x, g4y, a, ir_w[1], th_w[1]);
+    carry_up = 0.5 * (nu2 * (g2y - g2x) + nu3 * g3y + nu4 * g4x);
+    return 0.5 * (nu1 * (-g1x) + nu2 * (-g2y) + nu3 * (g3x - g3y)) + v.carry;
+}
+
+// Team of TS = S / KP threads per grid column (KP = 1 or 2 time pairs per lane). Lane lt
+// owns the time pairs (2m, 2m+1), m = lt + TS k, i.e. the complex inputs z_m = R_{2m} +
+// i R_{2m+1} of the half-length FFT. The team walks down its column keeping u on rows
+// j-1..j+1 in registers (three new neighbour series per row) and carrying the lower
+// triangles' part of K. UNI: one column per wavefront, per-column data wave-uniform.
+template <typename T, bool UNI, int KP>
 __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs a) {
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T2* smem = (T2*)smem_raw;
-    const int TS = a.ts, S = a.S, N = a.N;
+    const int TS = a.ts, S = a.S;
     const int lt = threadIdx.x % TS, team = threadIdx.x / TS;
-    T2* buf0 = smem + (size_t)team * 2 * S;
+    T2* buf0 = (T2*)(smem_raw + (size_t)team * S * 2 * sizeof(T2));
     T2* buf1 = buf0 + S;
-    T* rb = (T*)buf0;
+    double* xo = (double*)buf1;  // odd-time mass products, exchanged to form M u^{n-1}
     const T2* tw = (const T2*)a.tw;
+    const double2* U2 = (const double2*)a.U;
     const int vb = virtual_block(a.remap);
+    const int side = a.side, n = a.n;
+    const long S_ = S;
     double rr = 0.0, ff = 0.0;
-    for (int step = 0; step < a.steps; ++step) {
-        size_t node = ((size_t)vb * a.steps + step) * a.nb + team;
-        bool valid = node < a.nodes;
-        int i = valid ? (int)(node % a.side) : 0, j = valid ? (int)(node / a.side) : 0;
-        bool interior = valid && i > 0 && j > 0 && i < a.n && j < a.n;
-        if (interior) {
-            const size_t nodes = a.nodes;
-            const size_t sd = (size_t)a.side;
-            const double* U = a.U + node * N;
-            const long sN = (long)sd * N;
-            double mc = 0, me = 0, mw = 0, mn = 0, ms = 0, mne = 0, msw = 0;
-            bool mass = false;
-            if (a.mode == TM_RESIDUAL) {
-                mc = a.mt[node];
-                me = a.mt[nodes + node];
-                mw = a.mt[nodes + node - 1];
-                mn = a.mt[2 * nodes + node];
-                ms = a.mt[2 * nodes + node - sd];
-                mne = a.mt[3 * nodes + node];
-                msw = a.mt[3 * nodes + node - sd - 1];
-                mass = (mc != 0.0) || (me != 0.0) || (mw != 0.0) || (mn != 0.0) || (ms != 0.0) || (mne != 0.0) ||
-                       (msw != 0.0);
-            }
-            // the six triangles around node (i, j)
-            size_t c_ij = (size_t)j * a.n + i, c_w = c_ij - 1, c_s = c_ij - a.n, c_sw = c_ij - a.n - 1;
-            bool ir1 = a.flags[2 * c_ij] & 1, ir2 = a.flags[2 * c_ij + 1] & 1, ir3 = a.flags[2 * c_w] & 1,
-                 ir4 = a.flags[2 * c_s + 1] & 1, ir5 = a.flags[2 * c_sw] & 1, ir6 = a.flags[2 * c_sw + 1] & 1;
-            double th1 = 1, th2 = 1, th3 = 1, th4 = 1, th5 = 1, th6 = 1;
-            if (a.theta) {
-                th1 = a.theta[2 * c_ij];
-                th2 = a.theta[2 * c_ij + 1];
-                th3 = a.theta[2 * c_w];
-                th4 = a.theta[2 * c_s + 1];
-                th5 = a.theta[2 * c_sw];
-                th6 = a.theta[2 * c_sw + 1];
-            }
-            double bl = a.bload[node];
-            for (int q = lt; q < N; q += TS) {
-                double R;
-                if (a.mode == TM_RESIDUAL) {
-                    double uc = U[q], ue = U[N + q], uw = U[q - N], un = U[sN + q], us = U[q - sN];
-                    double une = U[sN + N + q], usw = U[q - sN - N];
-                    double g1x = ue - uc, g1y = une - ue;      // T_a(i,j)
-                    double g2x = une - un, g2y = un - uc;      // T_b(i,j)
-                    double g3x = uc - uw, g3y = un - uc;       // T_a(i-1,j)
-                    double g4x = ue - uc, g4y = uc - us;       // T_b(i,j-1)
-                    double g5x = us - usw, g5y = uc - us;      // T_a(i-1,j-1)
-                    double g6x = uc - uw, g6y = uw - usw;      // T_b(i-1,j-1)
-                    double K = nu_tri(g1x, g1y, a, ir1, th1) * (-g1x) + nu_tri(g2x, g2y, a, ir2, th2) * (-g2y) +
-                               nu_tri(g3x, g3y, a, ir3, th3) * (g3x - g3y) +
-                               nu_tri(g4x, g4y, a, ir4, th4) * (g4y - g4x) + nu_tri(g5x, g5y, a, ir5, th5) * g5y +
-                               nu_tri(g6x, g6y, a, ir6, th6) * g6x;
-                    K *= 0.5;
-                    double f = a.F ? a.F[node * N + q] : bl * a.wave[q];
-                    double Md = 0.0;
-                    if (mass) {
-                        int qm = (q == 0) ? N - 1 : q - 1;
-                        Md = mc * (uc - U[qm]) + me * (ue - U[N + qm]) + mw * (uw - U[qm - N]) +
-                             mn * (un - U[sN + qm]) + ms * (us - U[qm - sN]) + mne * (une - U[sN + N + qm]) +
-                             msw * (usw - U[qm - sN - N]);
-                    }
-                    R = f - Md * a.inv_tau - K;
-                    ff += f * f;
-                } else {
-                    R = U[q];
-                }
-                rr += R * R;
-                rb[q] = (T)R;
-                if (a.rout) a.rout[node * N + q] = R;
-            }
-        } else {
-            for (int q = lt; q < N; q += TS) rb[q] = (T)0;
-            if (valid && a.rout)
-                for (int q = lt; q < N; q += TS) a.rout[node * N + q] = 0.0;
+    const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, side);
+    int i = sr.col0 + team;
+    if (UNI) i = __builtin_amdgcn_readfirstlane(i);
+    const bool colvalid = i < side, colint = i > 0 && i < n;
+    Win v[KP][2];   // [k][0] even time, [k][1] odd time
+    auto ld = [&](int ci, int cj, int k) -> double2 {
+        if (cj < 0 || cj > n) return make_double2(0.0, 0.0);
+        return U2[(long)(cj * side + ci) * S_ + lt + TS * k];
+    };
+    bool inited = false;
+    for (int j = sr.row0; j < sr.row1; ++j) {
+        const bool interior = colint && j > 0 && j < n;
+        const int node = colvalid ? j * side + i : 0;
+        double2 r[KP];
+        double mue[KP], muo[KP];
+        bool mass = false;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            r[k] = make_double2(0.0, 0.0);
+            mue[k] = muo[k] = 0.0;
         }
+        if (interior && a.mode == TM_RESIDUAL) {
+            bool ir_c[2], ir_w[2];
+            double th_c[2], th_w[2];
+            cell_mat(a, i, j, ir_c, th_c);
+            cell_mat(a, i - 1, j, ir_w, th_w);
+            if (!inited) {
+                bool ir_s[2], ir_sw[2];
+                double th_s[2], th_sw[2];
+                cell_mat(a, i, j - 1, ir_s, th_s);
+                cell_mat(a, i - 1, j - 1, ir_sw, th_sw);
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    double2 sw = ld(i - 1, j - 1, k), s_ = ld(i, j - 1, k), w = ld(i - 1, j, k), c = ld(i, j, k),
+                            e = ld(i + 1, j, k), nw = ld(i - 1, j + 1, k), nn = ld(i, j + 1, k),
+                            ne = ld(i + 1, j + 1, k);
+                    v[k][0] = Win{sw.x, s_.x, w.x, c.x, e.x, nw.x, nn.x, ne.x, 0.0};
+                    v[k][1] = Win{sw.y, s_.y, w.y, c.y, e.y, nw.y, nn.y, ne.y, 0.0};
+                    v[k][0].carry = lower_three(a, v[k][0], ir_s, th_s, ir_sw, th_sw);
+                    v[k][1].carry = lower_three(a, v[k][1], ir_s, th_s, ir_sw, th_sw);
+                }
+                inited = true;
+            }
+            const size_t nodes = a.nodes;
+            const long sd = side;
+            const double mc = a.mt[node], mE = a.mt[nodes + node], mW = a.mt[nodes + node - 1],
+                         mN = a.mt[2 * nodes + node], mS = a.mt[2 * nodes + node - sd],
+                         mNE = a.mt[3 * nodes + node], mSW = a.mt[3 * nodes + node - sd - 1];
+            mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) || (mNE != 0.0) ||
+                   (mSW != 0.0);
+            const double bl = a.bload[node];
+            const double2* w2 = (const double2*)a.wave;
+            const double2* F2 = (const double2*)a.F;
+            double cu[KP][2];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                const int m = lt + TS * k;
+                double K0 = upper_four(a, v[k][0], ir_c, th_c, ir_w, th_w, cu[k][0]);
+                double K1 = upper_four(a, v[k][1], ir_c, th_c, ir_w, th_w, cu[k][1]);
+                double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * w2[m].x, bl * w2[m].y);
+                ff += f.x * f.x + f.y * f.y;
+                r[k] = make_double2(f.x - K0, f.y - K1);
+                if (mass) {
+                    const Win& p = v[k][0];
+                    const Win& q = v[k][1];
+                    mue[k] = mc * p.c + mE * p.e + mW * p.w + mN * p.n + mS * p.s + mNE * p.ne + mSW * p.sw;
+                    muo[k] = mc * q.c + mE * q.e + mW * q.w + mN * q.n + mS * q.s + mNE * q.ne + mSW * q.sw;
+                }
+            }
+            // advance the window to row j+1
+            if (j + 1 < sr.row1 && j + 1 < n) {
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    double2 nw = ld(i - 1, j + 2, k), nn = ld(i, j + 2, k), ne = ld(i + 1, j + 2, k);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        Win& p = v[k][h];
+                        p.sw = p.w;
+                        p.s = p.c;
+                        p.w = p.nw;
+                        p.c = p.n;
+                        p.e = p.ne;
+                        p.nw = h ? nw.y : nw.x;
+                        p.n = h ? nn.y : nn.x;
+                        p.ne = h ? ne.y : ne.x;
+                        p.carry = cu[k][h];
+                    }
+                }
+            }
+        } else if (interior) {  // TM_SIGNAL: the field itself
+#pragma unroll
+            for (int k = 0; k < KP; ++k) r[k] = U2[(long)node * S_ + lt + TS * k];
+        }
+        // M (u^n - u^{n-1}) = M u^n - M u^{n-1}: the odd-time product of pair m-1 (cyclic)
+#pragma unroll
+        for (int k = 0; k < KP; ++k) xo[lt + TS * k] = muo[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int m = lt + TS * k;
+            if (mass) {
+                double prev = xo[m == 0 ? S - 1 : m - 1];
+                r[k].x -= (mue[k] - prev) * a.inv_tau;
+                r[k].y -= (muo[k] - mue[k]) * a.inv_tau;
+            }
+            if (interior) rr += r[k].x * r[k].x + r[k].y * r[k].y;
+            if (colvalid && a.rout) ((double2*)a.rout)[(long)node * S_ + m] = r[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KP; ++k) buf0[lt + TS * k] = mk2<T>((T)r[k].x, (T)r[k].y);
         __syncthreads();
         if (a.out) {
             T2* res = fft_team<T2>(buf0, buf1, S, lt, TS, tw);
-            if (valid) {
-                T2* out = (T2*)a.out + node * S;
+            if (colvalid) {
+                T2* out = (T2*)a.out + (size_t)node * S;
                 for (int k = lt; k < S; k += TS) {
                     T2 X;
                     if (k == 0) {
@@ -213,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs a) {
     red[1][threadIdx.x] = ff;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
+        if ((int)threadIdx.x < w && (int)(threadIdx.x + w) < (int)blockDim.x) {
             red[0][threadIdx.x] += red[0][threadIdx.x + w];
             red[1][threadIdx.x] += red[1][threadIdx.x + w];
         }
@@ -235,7 +381,8 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.S = p.S;
     a.ts = g.slot_chunk;
     a.nb = g.per_step;
-    a.steps = g.steps;
+    a.col_groups = g.col_groups;
+    a.rows_per_chunk = g.rows_per_chunk;
     a.remap = p.opt.xcd_remap;
     a.mode = mode;
     a.nodes = p.nodes;
@@ -255,11 +402,29 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.out = out;
     a.rout = rout;
     a.part = part;
-    size_t shm = (size_t)g.per_step * 2 * p.S * p.elem;
-    if (p.fp32)
-        hipLaunchKernelGGL(k_forward<float>, dim3(g.blocks), dim3(kBlock), shm, st, a);
-    else
-        hipLaunchKernelGGL(k_forward<double>, dim3(g.blocks), dim3(kBlock), shm, st, a);
+    // forward team: TS = min(S, 256) threads per column, KP = S / TS pairs per lane
+    const int TS = p.S < kBlock ? p.S : kBlock;
+    const int KP = p.S / TS;
+    const int nb = kBlock / TS;
+    const Geom& gf = p.g_fwd;
+    a.ts = TS;
+    a.nb = nb;
+    a.col_groups = gf.col_groups;
+    a.rows_per_chunk = gf.rows_per_chunk;
+    size_t shm = (size_t)nb * p.S * 2 * p.elem;
+    dim3 blk(nb * TS);
+    bool uni = TS >= 64;
+#define PT_FWD(TT, U, K) hipLaunchKernelGGL((k_forward<TT, U, K>), dim3(gf.blocks), blk, shm, st, a)
+    if (p.fp32) {
+        if (KP == 2) PT_FWD(float, true, 2);
+        else if (uni) PT_FWD(float, true, 1);
+        else PT_FWD(float, false, 1);
+    } else {
+        if (KP == 2) PT_FWD(double, true, 2);
+        else if (uni) PT_FWD(double, true, 1);
+        else PT_FWD(double, false, 1);
+    }
+#undef PT_FWD
 }
 
 // ---------------------------------------------------------------- norm reduction
@@ -296,7 +461,7 @@ void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, doub
 // ---------------------------------------------------------------- inverse kernel
 
 struct InvArgs {
-    int n, side, N, S, ts, nb, steps, remap, accumulate;
+    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, accumulate;
     size_t nodes;
     const void* xhat;     // T2 [nodes][S]
     const double* coef;   // double2 [S] generic scalars or null
@@ -316,10 +481,11 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
     const T2* tw = (const T2*)a.tw;
     const T invS = (T)1 / (T)S;
     const int vb = virtual_block(a.remap);
-    for (int step = 0; step < a.steps; ++step) {
-        size_t node = ((size_t)vb * a.steps + step) * a.nb + team;
-        bool valid = node < a.nodes;
-        int i = valid ? (int)(node % a.side) : 0, j = valid ? (int)(node / a.side) : 0;
+    const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, a.side);
+    const int i = sr.col0 + team;
+    for (int j = sr.row0; j < sr.row1; ++j) {
+        bool valid = i < a.side;
+        size_t node = valid ? (size_t)j * a.side + i : 0;
         bool interior = valid && i > 0 && j > 0 && i < a.n && j < a.n;
         const T2* x = (const T2*)a.xhat + node * S;
         for (int k = lt; k < S; k += TS) {
@@ -383,7 +549,8 @@ void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coe
     a.S = p.S;
     a.ts = g.slot_chunk;
     a.nb = g.per_step;
-    a.steps = g.steps;
+    a.col_groups = g.col_groups;
+    a.rows_per_chunk = g.rows_per_chunk;
     a.remap = p.opt.xcd_remap;
     a.accumulate = accumulate;
     a.nodes = p.nodes;
@@ -392,10 +559,11 @@ void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coe
     a.tw = ws + (p.fp32 ? p.off_tw32 : p.off_tw64);
     a.U = Uw;
     size_t shm = (size_t)g.per_step * 2 * p.S * p.elem;
+    dim3 blk(g.per_step * g.slot_chunk);
     if (p.fp32)
-        hipLaunchKernelGGL(k_inverse<float>, dim3(g.blocks), dim3(kBlock), shm, st, a);
+        hipLaunchKernelGGL(k_inverse<float>, dim3(g.blocks), blk, shm, st, a);
     else
-        hipLaunchKernelGGL(k_inverse<double>, dim3(g.blocks), dim3(kBlock), shm, st, a);
+        hipLaunchKernelGGL(k_inverse<double>, dim3(g.blocks), blk, shm, st, a);
 }
 
 // ---------------------------------------------------------------- transposes

@@ -38,14 +38,32 @@ template <typename T, typename T2> __device__ __forceinline__ T2 gs_apply(const 
     return r;
 }
 
-// Inverse of D = dl + z (x) dm (z generic, dl and dm real), in generic form.
-template <typename T> __device__ __forceinline__ GS<T> gs_inv_diag(T dl, T dm, const GS<T>& z) {
+// Reciprocal of a positive number: hardware estimate (float), or the estimate refined by
+// two Newton steps r <- r + r (1 - x r) (double, full precision).
+template <typename T> __device__ __forceinline__ T fast_rcp(T x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// Inverse of D = dl + z (x) dm (z generic, dl > 0 and dm >= 0 real), in generic form;
+// idl = 1/dl is the inverse where dm = 0 (no conductivity near the node).
+template <typename T> __device__ __forceinline__ GS<T> gs_inv_diag(T dl, T idl, T dm, const GS<T>& z) {
+    GS<T> g;
+    if (dm == (T)0) {
+        g.a = idl;
+        g.b = (T)0;
+        g.c = idl;
+        return g;
+    }
     T P = dl + z.a * dm;   // acts on .x
     T Pp = dl + z.c * dm;  // acts on .y
     T Q = z.b * dm;
-    T det = P * Pp + Q * Q;
-    T inv = (T)1 / det;
-    GS<T> g;
+    T inv = fast_rcp<T>(P * Pp + Q * Q);
     g.a = Pp * inv;
     g.b = -Q * inv;
     g.c = P * inv;
@@ -109,6 +127,21 @@ __device__ __forceinline__ int virtual_block(int remap) {
     if (!remap) return b;
     int per = gridDim.x / kNumXcd;
     return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+// Column and row range of this workgroup in a sweeping kernel (see Geom).
+struct SweepRange {
+    int col0, row0, row1;
+};
+
+__device__ __forceinline__ SweepRange sweep_range(int vb, int col_groups, int per_step, int rows_per_chunk, int side) {
+    SweepRange r;
+    int g = vb % col_groups, c = vb / col_groups;
+    r.col0 = g * per_step;
+    r.row0 = c * rows_per_chunk;
+    r.row1 = min(r.row0 + rows_per_chunk, side);
+    if (r.row0 > side) r.row0 = side;
+    return r;
 }
 
 }  // namespace pt

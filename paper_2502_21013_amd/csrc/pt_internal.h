@@ -22,8 +22,8 @@ namespace pt {
 
 constexpr int kBlock = 256;          // threads per workgroup in every kernel
 constexpr int kMaxLevels = 16;
-constexpr int kTargetBlocks = 2048;  // per slot chunk, for grid-sized loops
 constexpr int kNumXcd = 8;
+constexpr int kReduceRows = 64;      // first-stage row groups of the dot-product reduction
 
 // Per-slot scalar in "generic" form: for slot s >= 1 a complex number (x + i y);
 // for slot 0 two reals, x acting on the real part (k = 0) and y on the imaginary
@@ -40,13 +40,19 @@ struct LevelDesc {
     size_t off_x;   // slot vector: correction at this level
 };
 
-// Launch geometry of grid-looped kernels over a node range.
+// Launch geometry of the node-sweeping kernels. A workgroup owns per_step adjacent grid
+// columns and walks down one chunk of rows_per_chunk rows, one row per loop step, so
+// the stencil neighbours in the rows above and below are the rows it has just touched
+// (and that the workgroups of the adjacent columns, scheduled on the same XCD at the
+// same time, are touching). Workgroup vb -> column group vb % col_groups, row chunk
+// vb / col_groups.
 struct Geom {
-    int per_step;   // nodes handled by one workgroup per loop step
-    int slot_chunk; // slots handled per workgroup (slot-vector kernels) or team size (time kernels)
-    int chunks;     // workgroups along y (slot chunks)
-    int steps;      // loop steps per workgroup
-    int blocks;     // workgroups along x (multiple of kNumXcd)
+    int per_step;        // columns (nodes per row step) per workgroup
+    int slot_chunk;      // slots per workgroup (slot-vector kernels) or team size (time kernels)
+    int chunks;          // workgroups along y (slot chunks)
+    int col_groups;      // ceil(side / per_step)
+    int rows_per_chunk;  // rows per workgroup
+    int blocks;          // workgroups along x (multiple of kNumXcd)
 };
 
 // Kernel classes of the per-launch event timer (order matches pt_kernel_class_name).
@@ -102,13 +108,17 @@ struct Plan {
     float* h_tw32;      // N complex, float
     double* h_zs;       // S x 3: generic (a, b, c) of the shift z_s
     double* h_wave;     // N: w(2 pi t_{j+1} / T)
+    int target_slot, target_team;  // grid targets of the slot-vector and per-node kernels
     Geom g_slot0;       // slot-vector kernels on level 0
-    Geom g_team;        // per-node team kernels (time axis)
+    Geom g_team;        // per-node team kernels (inverse DFT)
+    Geom g_fwd;         // residual + DFT kernel (team of min(S, 256) threads per column)
     Timer* tm;          // per-kernel event timer (owned by the plan)
 };
 
-Geom slot_geom(size_t nodes, int S);
-Geom team_geom(size_t nodes, int S);
+// target = number of workgroups (per slot chunk) the sweeping kernels aim for
+Geom slot_geom(int side, int S, int target);
+Geom team_geom(int side, int S, int target);
+Geom fwd_geom(int side, int S, int target);
 
 // ---------------------------------------------------------------- launchers
 // setup (k_setup.hip)
