@@ -51,7 +51,8 @@ def workload(name, seed):
 def algorithmic_bytes(p, elem):
     """Bytes each dominant kernel must move per launch (all (n+1)^2 grid nodes).
 
-    forward (residual + DFT): read U (8 B per node-time), write R^ (elem per node-slot)
+    residual_sweep:           read U (8 B per node-time), write R (elem/2 per node-time)
+    rfft (packed DFT):        read R, write R^ (elem per node-slot each)
     vcycle_down_fine:         read r (fine), write r_c (coarse)
     vcycle_up_fine:           read r (fine), read x_c (coarse), write x (fine)
     matvec_dot:               read p (fine)
@@ -65,7 +66,8 @@ def algorithmic_bytes(p, elem):
     cslot = nc * S * elem
     tfield = nodes * N * 8
     return {
-        "forward_residual_rfft": tfield + slot,
+        "residual_sweep": tfield + slot,
+        "rfft": 2 * slot,
         "vcycle_down_fine": slot + cslot,
         "vcycle_up_fine": 2 * slot + cslot,
         "matvec_dot": slot,

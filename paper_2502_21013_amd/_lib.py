@@ -57,7 +57,7 @@ class Stats(C.Structure):
     ]
 
 
-PT_KERNEL_CLASSES = 14
+PT_KERNEL_CLASSES = 15
 
 
 _lib = None

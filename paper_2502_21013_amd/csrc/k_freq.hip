@@ -136,19 +136,31 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     const int c = 2 * ci;
     // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
     T2 xa[5], xb[5], xq[5], ra[3], rb[3], rq[3];
-    auto load_row = [&](int R, T2* xr, T2* rr) {
+    auto fetch_row = [&](int R, T2* rv, double* mv) {
 #pragma unroll
         for (int d = 0; d < 5; ++d) {
-            T2 v = zero, rv = zero;
+            rv[d] = zero;
+            mv[d] = 0.0;
             if (R >= 0 && R <= nF) {
                 const int b = R * sf + c - 2 + d;
-                rv = rin[(size_t)b * S + s];
-                GS<T> di = gs_inv_diag<T>(dl, idl, (T)F.mt[b], z);
-                v = scale2(om, gs_apply(di, rv));
+                rv[d] = rin[(size_t)b * S + s];
+                mv[d] = F.mt[b];
             }
-            xr[d] = v;
-            if (d >= 1 && d <= 3) rr[d - 1] = rv;
         }
+    };
+    auto eval_row = [&](const T2* rv, const double* mv, T2* xr, T2* rr) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            GS<T> di = gs_inv_diag<T>(dl, idl, (T)mv[d], z);
+            xr[d] = scale2(om, gs_apply(di, rv[d]));
+            if (d >= 1 && d <= 3) rr[d - 1] = rv[d];
+        }
+    };
+    auto load_row = [&](int R, T2* xr, T2* rr) {
+        T2 rv[5];
+        double mv[5];
+        fetch_row(R, rv, mv);
+        eval_row(rv, mv, xr, rr);
     };
     const int Rs = 2 * cj0 - 1, Re = 2 * cj1 - 1;
     load_row(Rs - 1, xa, ra);
@@ -156,6 +168,9 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     load_row(Rs + 1, xq, rq);
     T2 acc = zero;
     for (int R = Rs; R <= Re; ++R) {
+        T2 nr[5];
+        double nm[5];
+        if (R < Re) fetch_row(R + 2, nr, nm);  // next row's inputs, loaded before this row is computed
         // s = r - A x1 at (c-1+k, R), k = 0..2; window rows: xa = R-1, xb = R, xq = R+1
         T2 sv[3];
 #pragma unroll
@@ -188,7 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
                 ra[d] = rb[d];
                 rb[d] = rq[d];
             }
-            load_row(R + 2, xq, rq);
+            eval_row(nr, nm, xq, rq);
         }
     }
 }
@@ -241,11 +256,56 @@ __device__ __forceinline__ T2 prolong_at(const T2* xc, int sc, int S, int s, int
     return r;
 }
 
+// Raw inputs of the pre-smoothed, coarse-corrected value x2 at one fine node: r, the
+// diagonal mass entry and the (one or two) coarse values its P1 interpolation uses.
+template <typename T2> struct UpIn {
+    T2 r, c0, c1;
+    double mc;
+    int kind;  // 0: outside the grid rows, 1: coincides with a coarse node, 2: edge midpoint
+};
+
+template <typename T, typename T2>
+__device__ __forceinline__ UpIn<T2> up_load(const T2* rin, const T2* xc, const LvArgs& F, int sc, int S, int s, int bi,
+                                            int bj) {
+    UpIn<T2> u;
+    if (bj < 0 || bj > F.n) {
+        u.kind = 0;
+        u.r = u.c0 = u.c1 = mk2<T>(0, 0);
+        u.mc = 0.0;
+        return u;
+    }
+    const int b = bj * F.side + bi;
+    u.r = rin[(size_t)b * S + s];
+    u.mc = F.mt[b];
+    const int hi = bi >> 1, hj = bj >> 1;
+    const bool oi = bi & 1, oj = bj & 1;
+    u.c0 = xc[((size_t)hj * sc + hi) * S + s];
+    if (!oi && !oj) {
+        u.kind = 1;
+        u.c1 = mk2<T>(0, 0);
+    } else {
+        u.kind = 2;
+        const int qi = hi + (oi ? 1 : 0), qj = hj + (oj ? 1 : 0);
+        u.c1 = xc[((size_t)qj * sc + qi) * S + s];
+    }
+    return u;
+}
+
+template <typename T, typename T2>
+__device__ __forceinline__ T2 up_eval(const UpIn<T2>& u, T dl, T idl, T om, const GS<T>& z) {
+    if (u.kind == 0) return mk2<T>(0, 0);
+    GS<T> di = gs_inv_diag<T>(dl, idl, (T)u.mc, z);
+    T2 v = scale2(om, gs_apply(di, u.r));
+    if (u.kind == 1) return add2(v, u.c0);
+    return fma2((T)0.5, add2(u.c0, u.c1), v);
+}
+
 // x2 = omega D^{-1} r + P x_c (pre-smoothed iterate plus coarse correction), then one
 // post-smoothing sweep x3 = x2 + omega D^{-1} (r - A x2). Optionally accumulates the
 // dot partials of (x3, r). Each thread walks down one column: the seven x2 values of the
 // stencil of row j are kept in registers and only the three new ones of row j+1,
-// (i-1, j+1), (i, j+2) and (i+1, j+2), are evaluated per step.
+// (i-1, j+1), (i, j+2) and (i+1, j+2), are evaluated per step; their inputs are loaded
+// before the current row is computed so that the loads overlap the arithmetic.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
@@ -259,29 +319,32 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
     const int vb = virtual_block(sa.remap);
     const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl;
-    const int sf = F.side, nF = F.n;
+    const int sf = F.side, nF = F.n, sc = C.side;
     double acc[3] = {0, 0, 0};
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
     int ai = sr.col0 + ln;
     if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
-    // x2 and r at fine node (bi, bj); zero outside the grid rows
-    auto eval = [&](int bi, int bj, T2& rb) -> T2 {
-        if (bj < 0 || bj > nF) {
-            rb = mk2<T>(0, 0);
-            return rb;
-        }
-        const int b = bj * sf + bi;
-        rb = rin[(size_t)b * S + s];
-        GS<T> di = gs_inv_diag<T>(dl, idl, (T)F.mt[b], z);
-        return add2(scale2(om, gs_apply(di, rb)), prolong_at(xc, C.side, S, s, bi, bj));
-    };
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
-        T2 rdum, rc, rn;
         const int j0 = sr.row0;
-        T2 xsw = eval(ai - 1, j0 - 1, rdum), xs = eval(ai, j0 - 1, rdum);
-        T2 xw = eval(ai - 1, j0, rdum), xcn = eval(ai, j0, rc), xe = eval(ai + 1, j0, rdum);
-        T2 xn = eval(ai, j0 + 1, rn), xne = eval(ai + 1, j0 + 1, rdum);
+        UpIn<T2> q0 = up_load<T, T2>(rin, xc, F, sc, S, s, ai - 1, j0 - 1);
+        UpIn<T2> q1 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, j0 - 1);
+        UpIn<T2> q2 = up_load<T, T2>(rin, xc, F, sc, S, s, ai - 1, j0);
+        UpIn<T2> q3 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, j0);
+        UpIn<T2> q4 = up_load<T, T2>(rin, xc, F, sc, S, s, ai + 1, j0);
+        UpIn<T2> q5 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, j0 + 1);
+        UpIn<T2> q6 = up_load<T, T2>(rin, xc, F, sc, S, s, ai + 1, j0 + 1);
+        T2 xsw = up_eval(q0, dl, idl, om, z), xs = up_eval(q1, dl, idl, om, z);
+        T2 xw = up_eval(q2, dl, idl, om, z), xcn = up_eval(q3, dl, idl, om, z), xe = up_eval(q4, dl, idl, om, z);
+        T2 xn = up_eval(q5, dl, idl, om, z), xne = up_eval(q6, dl, idl, om, z);
+        T2 rc = q3.r, rn = q5.r;
         for (int aj = j0; aj < sr.row1; ++aj) {
+            const bool more = aj + 1 < sr.row1;
+            UpIn<T2> p0, p1, p2;
+            if (more) {
+                p0 = up_load<T, T2>(rin, xc, F, sc, S, s, ai - 1, aj + 1);
+                p1 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, aj + 2);
+                p2 = up_load<T, T2>(rin, xc, F, sc, S, s, ai + 1, aj + 2);
+            }
             const int a = aj * sf + ai;
             T2 out = mk2<T>(0, 0);
             if (aj > 0 && aj < nF) {
@@ -291,20 +354,16 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
                 if (dotmode != DOT_NONE) dot3_acc(acc, out, rc, dotmode == DOT_HERM);
             }
             xout[(size_t)a * S + s] = out;
-            if (aj + 1 < sr.row1) {
-                T2 rn2;
-                T2 nw = eval(ai - 1, aj + 1, rdum);
-                T2 n2 = eval(ai, aj + 2, rn2);
-                T2 ne2 = eval(ai + 1, aj + 2, rdum);
+            if (more) {
                 xsw = xw;
                 xs = xcn;
-                xw = nw;
+                xw = up_eval(p0, dl, idl, om, z);
                 xcn = xn;
                 rc = rn;
                 xe = xne;
-                xn = n2;
-                rn = rn2;
-                xne = ne2;
+                xn = up_eval(p1, dl, idl, om, z);
+                rn = p1.r;
+                xne = up_eval(p2, dl, idl, om, z);
             }
         }
     } else if (ai < sf) {
@@ -342,6 +401,13 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
         T2 xsw = ld(ai - 1, j0 - 1), xs = ld(ai, j0 - 1), xw = ld(ai - 1, j0), xcn = ld(ai, j0), xe = ld(ai + 1, j0);
         T2 xn = ld(ai, j0 + 1), xne = ld(ai + 1, j0 + 1);
         for (int aj = j0; aj < sr.row1; ++aj) {
+            const bool more = aj + 1 < sr.row1;
+            T2 nw, n2, ne2;
+            if (more) {  // next row's new points, loaded before this row is computed
+                nw = ld(ai - 1, aj + 1);
+                n2 = ld(ai, aj + 2);
+                ne2 = ld(ai + 1, aj + 2);
+            }
             const int a = aj * sf + ai;
             T2 out = mk2<T>(0, 0);
             if (aj > 0 && aj < nF) {
@@ -349,8 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
                 if (dotmode != DOT_NONE) dot3_acc(acc, xcn, out, dotmode == DOT_HERM);
             }
             if (y) y[(size_t)a * S + s] = out;
-            if (aj + 1 < sr.row1) {
-                T2 nw = ld(ai - 1, aj + 1), n2 = ld(ai, aj + 2), ne2 = ld(ai + 1, aj + 2);
+            if (more) {
                 xsw = xw;
                 xs = xcn;
                 xw = nw;

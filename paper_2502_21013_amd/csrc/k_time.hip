@@ -200,21 +200,28 @@ __device__ __forceinline__ double upper_four(const FwdArgs& a, const Win& v, con
     return 0.5 * (nu1 * (-g1x) + nu2 * (-g2y) + nu3 * (g3x - g3y)) + v.carry;
 }
 
-// Team of TS = S / KP threads per grid column (KP = 1 or 2 time pairs per lane). Lane lt
-// owns the time pairs (2m, 2m+1), m = lt + TS k, i.e. the complex inputs z_m = R_{2m} +
-// i R_{2m+1} of the half-length FFT. The team walks down its column keeping u on rows
-// j-1..j+1 in registers (three new neighbour series per row) and carrying the lower
-// triangles' part of K. UNI: one column per wavefront, per-column data wave-uniform.
+// Residual sweep: team of TS = S / KP threads per grid column (KP = 1 or 2 time pairs per
+// lane); lane lt owns the time pairs (2m, 2m+1), m = lt + TS k. The team walks down its
+// column keeping u on rows j-1..j+1 in registers (three new neighbour series per row) and
+// carrying the lower triangles' part of K. Rows are processed in batches of kRowBatch so
+// that one LDS exchange per batch forms M u^{n-1} from the neighbouring lane's M u^n.
+// Writes R in the solver precision (node-major, [node][N]) for the DFT, and/or in double
+// (rout), plus the FP64 norm partials. UNI: one column per wavefront.
+constexpr int kRowBatch = 4;
+
 template <typename T, bool UNI, int KP>
-__global__ void __launch_bounds__(kBlock) k_forward(FwdArgs a) {
+__global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int RB = kRowBatch;
     const int TS = a.ts, S = a.S;
     const int lt = threadIdx.x % TS, team = threadIdx.x / TS;
-    T2* buf0 = (T2*)(smem_raw + (size_t)team * S * 2 * sizeof(T2));
-    T2* buf1 = buf0 + S;
-    double* xo = (double*)buf1;  // odd-time mass products, exchanged to form M u^{n-1}
-    const T2* tw = (const T2*)a.tw;
+    // per team: rs [RB][S] double2 (residual without the mass term), me / xo [RB][S] double
+    // (even / odd time mass products)
+    double2* rs = (double2*)smem_raw + (size_t)team * RB * S * 2;
+    double* me = (double*)(rs + RB * S);
+    double* xo = me + RB * S;
+    T2* rt = (T2*)rt_;
     const double2* U2 = (const double2*)a.U;
     const int vb = virtual_block(a.remap);
     const int side = a.side, n = a.n;
@@ -224,131 +231,139 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs a) {
     int i = sr.col0 + team;
     if (UNI) i = __builtin_amdgcn_readfirstlane(i);
     const bool colvalid = i < side, colint = i > 0 && i < n;
-    Win v[KP][2];   // [k][0] even time, [k][1] odd time
+    Win v[KP][2];
     auto ld = [&](int ci, int cj, int k) -> double2 {
         if (cj < 0 || cj > n) return make_double2(0.0, 0.0);
         return U2[(long)(cj * side + ci) * S_ + lt + TS * k];
     };
-    bool inited = false;
-    for (int j = sr.row0; j < sr.row1; ++j) {
-        const bool interior = colint && j > 0 && j < n;
-        const int node = colvalid ? j * side + i : 0;
-        double2 r[KP];
-        double mue[KP], muo[KP];
-        bool mass = false;
+    // window at the first interior row of the chunk
+    const int jin = sr.row0 > 1 ? sr.row0 : 1;
+    if (a.mode == TM_RESIDUAL && colint && jin < sr.row1 && jin < n) {
+        bool ir_s[2], ir_sw[2];
+        double th_s[2], th_sw[2];
+        cell_mat(a, i, jin - 1, ir_s, th_s);
+        cell_mat(a, i - 1, jin - 1, ir_sw, th_sw);
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-            r[k] = make_double2(0.0, 0.0);
-            mue[k] = muo[k] = 0.0;
+            double2 sw = ld(i - 1, jin - 1, k), s_ = ld(i, jin - 1, k), w = ld(i - 1, jin, k), c = ld(i, jin, k),
+                    e = ld(i + 1, jin, k), nw = ld(i - 1, jin + 1, k), nn = ld(i, jin + 1, k),
+                    ne = ld(i + 1, jin + 1, k);
+            v[k][0] = Win{sw.x, s_.x, w.x, c.x, e.x, nw.x, nn.x, ne.x, 0.0};
+            v[k][1] = Win{sw.y, s_.y, w.y, c.y, e.y, nw.y, nn.y, ne.y, 0.0};
+            v[k][0].carry = lower_three(a, v[k][0], ir_s, th_s, ir_sw, th_sw);
+            v[k][1].carry = lower_three(a, v[k][1], ir_s, th_s, ir_sw, th_sw);
         }
-        if (interior && a.mode == TM_RESIDUAL) {
-            bool ir_c[2], ir_w[2];
-            double th_c[2], th_w[2];
-            cell_mat(a, i, j, ir_c, th_c);
-            cell_mat(a, i - 1, j, ir_w, th_w);
-            if (!inited) {
-                bool ir_s[2], ir_sw[2];
-                double th_s[2], th_sw[2];
-                cell_mat(a, i, j - 1, ir_s, th_s);
-                cell_mat(a, i - 1, j - 1, ir_sw, th_sw);
+    }
+    for (int jb = sr.row0; jb < sr.row1; jb += RB) {
+        unsigned mass_bits = 0;
+#pragma unroll 1
+        for (int q = 0; q < RB; ++q) {
+            const int j = jb + q;
+            const bool interior = colint && j < sr.row1 && j > 0 && j < n;
+            const int node = colvalid ? j * side + i : 0;
+            double2 r[KP];
+            double mue[KP], muo[KP];
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                r[k] = make_double2(0.0, 0.0);
+                mue[k] = muo[k] = 0.0;
+            }
+            if (interior && a.mode == TM_RESIDUAL) {
+                // the next row's three new neighbour series, loaded before this row is computed
+                const bool adv = j + 1 < sr.row1 && j + 1 < n;
+                double2 pnw[KP], pnn[KP], pne[KP];
+                if (adv) {
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) {
+                        pnw[k] = ld(i - 1, j + 2, k);
+                        pnn[k] = ld(i, j + 2, k);
+                        pne[k] = ld(i + 1, j + 2, k);
+                    }
+                }
+                bool ir_c[2], ir_w[2];
+                double th_c[2], th_w[2];
+                cell_mat(a, i, j, ir_c, th_c);
+                cell_mat(a, i - 1, j, ir_w, th_w);
+                const size_t nodes = a.nodes;
+                const long sd = side;
+                const double mc = a.mt[node], mE = a.mt[nodes + node], mW = a.mt[nodes + node - 1],
+                             mN = a.mt[2 * nodes + node], mS = a.mt[2 * nodes + node - sd],
+                             mNE = a.mt[3 * nodes + node], mSW = a.mt[3 * nodes + node - sd - 1];
+                const bool mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) ||
+                                  (mNE != 0.0) || (mSW != 0.0);
+                if (mass) mass_bits |= 1u << q;
+                const double bl = a.bload[node];
+                const double2* w2 = (const double2*)a.wave;
+                const double2* F2 = (const double2*)a.F;
+                double cu[KP][2];
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
-                    double2 sw = ld(i - 1, j - 1, k), s_ = ld(i, j - 1, k), w = ld(i - 1, j, k), c = ld(i, j, k),
-                            e = ld(i + 1, j, k), nw = ld(i - 1, j + 1, k), nn = ld(i, j + 1, k),
-                            ne = ld(i + 1, j + 1, k);
-                    v[k][0] = Win{sw.x, s_.x, w.x, c.x, e.x, nw.x, nn.x, ne.x, 0.0};
-                    v[k][1] = Win{sw.y, s_.y, w.y, c.y, e.y, nw.y, nn.y, ne.y, 0.0};
-                    v[k][0].carry = lower_three(a, v[k][0], ir_s, th_s, ir_sw, th_sw);
-                    v[k][1].carry = lower_three(a, v[k][1], ir_s, th_s, ir_sw, th_sw);
+                    const int m = lt + TS * k;
+                    double K0 = upper_four(a, v[k][0], ir_c, th_c, ir_w, th_w, cu[k][0]);
+                    double K1 = upper_four(a, v[k][1], ir_c, th_c, ir_w, th_w, cu[k][1]);
+                    double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * w2[m].x, bl * w2[m].y);
+                    ff += f.x * f.x + f.y * f.y;
+                    r[k] = make_double2(f.x - K0, f.y - K1);
+                    if (mass) {
+                        const Win& p = v[k][0];
+                        const Win& o = v[k][1];
+                        mue[k] = mc * p.c + mE * p.e + mW * p.w + mN * p.n + mS * p.s + mNE * p.ne + mSW * p.sw;
+                        muo[k] = mc * o.c + mE * o.e + mW * o.w + mN * o.n + mS * o.s + mNE * o.ne + mSW * o.sw;
+                    }
                 }
-                inited = true;
+                if (adv) {  // advance the window to row j+1
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) {
+                        const double2 nw = pnw[k], nn = pnn[k], ne = pne[k];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            Win& p = v[k][h];
+                            p.sw = p.w;
+                            p.s = p.c;
+                            p.w = p.nw;
+                            p.c = p.n;
+                            p.e = p.ne;
+                            p.nw = h ? nw.y : nw.x;
+                            p.n = h ? nn.y : nn.x;
+                            p.ne = h ? ne.y : ne.x;
+                            p.carry = cu[k][h];
+                        }
+                    }
+                }
+            } else if (interior) {  // TM_SIGNAL: the field itself
+#pragma unroll
+                for (int k = 0; k < KP; ++k) r[k] = U2[(long)node * S_ + lt + TS * k];
             }
-            const size_t nodes = a.nodes;
-            const long sd = side;
-            const double mc = a.mt[node], mE = a.mt[nodes + node], mW = a.mt[nodes + node - 1],
-                         mN = a.mt[2 * nodes + node], mS = a.mt[2 * nodes + node - sd],
-                         mNE = a.mt[3 * nodes + node], mSW = a.mt[3 * nodes + node - sd - 1];
-            mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) || (mNE != 0.0) ||
-                   (mSW != 0.0);
-            const double bl = a.bload[node];
-            const double2* w2 = (const double2*)a.wave;
-            const double2* F2 = (const double2*)a.F;
-            double cu[KP][2];
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
                 const int m = lt + TS * k;
-                double K0 = upper_four(a, v[k][0], ir_c, th_c, ir_w, th_w, cu[k][0]);
-                double K1 = upper_four(a, v[k][1], ir_c, th_c, ir_w, th_w, cu[k][1]);
-                double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * w2[m].x, bl * w2[m].y);
-                ff += f.x * f.x + f.y * f.y;
-                r[k] = make_double2(f.x - K0, f.y - K1);
-                if (mass) {
-                    const Win& p = v[k][0];
-                    const Win& q = v[k][1];
-                    mue[k] = mc * p.c + mE * p.e + mW * p.w + mN * p.n + mS * p.s + mNE * p.ne + mSW * p.sw;
-                    muo[k] = mc * q.c + mE * q.e + mW * q.w + mN * q.n + mS * q.s + mNE * q.ne + mSW * q.sw;
-                }
+                rs[q * S + m] = r[k];
+                me[q * S + m] = mue[k];
+                xo[q * S + m] = muo[k];
             }
-            // advance the window to row j+1
-            if (j + 1 < sr.row1 && j + 1 < n) {
-#pragma unroll
-                for (int k = 0; k < KP; ++k) {
-                    double2 nw = ld(i - 1, j + 2, k), nn = ld(i, j + 2, k), ne = ld(i + 1, j + 2, k);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        Win& p = v[k][h];
-                        p.sw = p.w;
-                        p.s = p.c;
-                        p.w = p.nw;
-                        p.c = p.n;
-                        p.e = p.ne;
-                        p.nw = h ? nw.y : nw.x;
-                        p.n = h ? nn.y : nn.x;
-                        p.ne = h ? ne.y : ne.x;
-                        p.carry = cu[k][h];
-                    }
-                }
-            }
-        } else if (interior) {  // TM_SIGNAL: the field itself
-#pragma unroll
-            for (int k = 0; k < KP; ++k) r[k] = U2[(long)node * S_ + lt + TS * k];
         }
+        __syncthreads();
         // M (u^n - u^{n-1}) = M u^n - M u^{n-1}: the odd-time product of pair m-1 (cyclic)
+#pragma unroll 1
+        for (int q = 0; q < RB; ++q) {
+            const int j = jb + q;
+            if (!colvalid || j >= sr.row1) continue;
+            const int node = j * side + i;
+            const bool interior = colint && j > 0 && j < n;
+            const bool mass = (mass_bits >> q) & 1u;
 #pragma unroll
-        for (int k = 0; k < KP; ++k) xo[lt + TS * k] = muo[k];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            const int m = lt + TS * k;
-            if (mass) {
-                double prev = xo[m == 0 ? S - 1 : m - 1];
-                r[k].x -= (mue[k] - prev) * a.inv_tau;
-                r[k].y -= (muo[k] - mue[k]) * a.inv_tau;
-            }
-            if (interior) rr += r[k].x * r[k].x + r[k].y * r[k].y;
-            if (colvalid && a.rout) ((double2*)a.rout)[(long)node * S_ + m] = r[k];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KP; ++k) buf0[lt + TS * k] = mk2<T>((T)r[k].x, (T)r[k].y);
-        __syncthreads();
-        if (a.out) {
-            T2* res = fft_team<T2>(buf0, buf1, S, lt, TS, tw);
-            if (colvalid) {
-                T2* out = (T2*)a.out + (size_t)node * S;
-                for (int k = lt; k < S; k += TS) {
-                    T2 X;
-                    if (k == 0) {
-                        T2 z0 = res[0];
-                        X = mk2<T>(z0.x + z0.y, z0.x - z0.y);
-                    } else {
-                        T2 zk = res[k], zc = conj2(res[S - k]);
-                        T2 E = scale2((T)0.5, add2(zk, zc));
-                        T2 O = scale2((T)0.5, mul_mi(sub2(zk, zc)));
-                        X = add2(E, cmul(tw[k], O));
-                    }
-                    out[k] = X;
+            for (int k = 0; k < KP; ++k) {
+                const int m = lt + TS * k;
+                double2 rv = rs[q * S + m];
+                if (mass) {
+                    double mue = me[q * S + m], muo = xo[q * S + m];
+                    double prev = xo[q * S + (m == 0 ? S - 1 : m - 1)];
+                    rv.x -= (mue - prev) * a.inv_tau;
+                    rv.y -= (muo - mue) * a.inv_tau;
                 }
+                if (interior) rr += rv.x * rv.x + rv.y * rv.y;
+                if (a.rout) ((double2*)a.rout)[(long)node * S_ + m] = rv;
+                if (rt) rt[(long)node * S_ + m] = mk2<T>((T)rv.x, (T)rv.y);
             }
         }
         __syncthreads();
@@ -371,18 +386,63 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs a) {
     }
 }
 
+// Packed real DFT along time of node-major real series rt ([node][N], solver precision):
+// the half-length complex FFT of z_m = x_{2m} + i x_{2m+1} and the split into X_k
+// (remark rem:parallel). Team of S/4 threads per node.
+struct RfftArgs {
+    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap;
+    const void* rt;   // T2 [nodes][S]
+    const void* tw;   // T2 [N]
+    void* out;        // T2 [nodes][S]
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_rfft(RfftArgs a) {
+    using T2 = typename Vec2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T2* smem = (T2*)smem_raw;
+    const int TS = a.ts, S = a.S;
+    const int lt = threadIdx.x % TS, team = threadIdx.x / TS;
+    T2* buf0 = smem + (size_t)team * 2 * S;
+    T2* buf1 = buf0 + S;
+    const T2* tw = (const T2*)a.tw;
+    const T2* rt = (const T2*)a.rt;
+    const int vb = virtual_block(a.remap);
+    const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, a.side);
+    const int i = sr.col0 + team;
+    const bool colvalid = i < a.side;
+    for (int j = sr.row0; j < sr.row1; ++j) {
+        const size_t node = colvalid ? (size_t)j * a.side + i : 0;
+        for (int m = lt; m < S; m += TS) buf0[m] = colvalid ? rt[node * S + m] : mk2<T>(0, 0);
+        __syncthreads();
+        T2* res = fft_team<T2>(buf0, buf1, S, lt, TS, tw);
+        if (colvalid) {
+            T2* out = (T2*)a.out + node * S;
+            for (int k = lt; k < S; k += TS) {
+                T2 X;
+                if (k == 0) {
+                    T2 z0 = res[0];
+                    X = mk2<T>(z0.x + z0.y, z0.x - z0.y);
+                } else {
+                    T2 zk = res[k], zc = conj2(res[S - k]);
+                    T2 E = scale2((T)0.5, add2(zk, zc));
+                    T2 O = scale2((T)0.5, mul_mi(sub2(zk, zc)));
+                    X = add2(E, cmul(tw[k], O));
+                }
+                out[k] = X;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* out, double* rout, double* part,
                     hipStream_t st) {
     FwdArgs a;
-    const Geom& g = p.g_team;
     a.n = p.n;
     a.side = p.side;
     a.N = p.N;
     a.S = p.S;
-    a.ts = g.slot_chunk;
-    a.nb = g.per_step;
-    a.col_groups = g.col_groups;
-    a.rows_per_chunk = g.rows_per_chunk;
     a.remap = p.opt.xcd_remap;
     a.mode = mode;
     a.nodes = p.nodes;
@@ -399,10 +459,10 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.flags = (const uint8_t*)(ws + p.off_flags);
     a.theta = p.prob.d_theta;
     a.tw = ws + (p.fp32 ? p.off_tw32 : p.off_tw64);
-    a.out = out;
+    a.out = nullptr;
     a.rout = rout;
     a.part = part;
-    // forward team: TS = min(S, 256) threads per column, KP = S / TS pairs per lane
+    // residual sweep: TS = min(S, 256) threads per column, KP = S / TS pairs per lane
     const int TS = p.S < kBlock ? p.S : kBlock;
     const int KP = p.S / TS;
     const int nb = kBlock / TS;
@@ -411,20 +471,46 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.nb = nb;
     a.col_groups = gf.col_groups;
     a.rows_per_chunk = gf.rows_per_chunk;
-    size_t shm = (size_t)nb * p.S * 2 * p.elem;
+    size_t shm = (size_t)nb * kRowBatch * p.S * 4 * sizeof(double);
     dim3 blk(nb * TS);
     bool uni = TS >= 64;
-#define PT_FWD(TT, U, K) hipLaunchKernelGGL((k_forward<TT, U, K>), dim3(gf.blocks), blk, shm, st, a)
+    void* rt = out ? (void*)(ws + p.off_P) : nullptr;  // R in solver precision, node-major
+    tm_begin(p, KID_RESIDUAL, st);
+#define PT_RES(TT, U, K) hipLaunchKernelGGL((k_residual<TT, U, K>), dim3(gf.blocks), blk, shm, st, a, rt)
     if (p.fp32) {
-        if (KP == 2) PT_FWD(float, true, 2);
-        else if (uni) PT_FWD(float, true, 1);
-        else PT_FWD(float, false, 1);
+        if (KP == 2) PT_RES(float, true, 2);
+        else if (uni) PT_RES(float, true, 1);
+        else PT_RES(float, false, 1);
     } else {
-        if (KP == 2) PT_FWD(double, true, 2);
-        else if (uni) PT_FWD(double, true, 1);
-        else PT_FWD(double, false, 1);
+        if (KP == 2) PT_RES(double, true, 2);
+        else if (uni) PT_RES(double, true, 1);
+        else PT_RES(double, false, 1);
     }
-#undef PT_FWD
+#undef PT_RES
+    tm_end(p, KID_RESIDUAL, st);
+    if (!out) return;
+    RfftArgs b;
+    const Geom& g = p.g_team;
+    b.n = p.n;
+    b.side = p.side;
+    b.N = p.N;
+    b.S = p.S;
+    b.ts = g.slot_chunk;
+    b.nb = g.per_step;
+    b.col_groups = g.col_groups;
+    b.rows_per_chunk = g.rows_per_chunk;
+    b.remap = p.opt.xcd_remap;
+    b.rt = rt;
+    b.tw = a.tw;
+    b.out = out;
+    size_t shm2 = (size_t)g.per_step * 2 * p.S * p.elem;
+    dim3 blk2(g.per_step * g.slot_chunk);
+    tm_begin(p, KID_RFFT, st);
+    if (p.fp32)
+        hipLaunchKernelGGL(k_rfft<float>, dim3(g.blocks), blk2, shm2, st, b);
+    else
+        hipLaunchKernelGGL(k_rfft<double>, dim3(g.blocks), blk2, shm2, st, b);
+    tm_end(p, KID_RFFT, st);
 }
 
 // ---------------------------------------------------------------- norm reduction

@@ -59,7 +59,8 @@ struct Geom {
 enum KernelId {
     KID_SETUP = 0,
     KID_TRANSPOSE,
-    KID_FORWARD,      // fused residual + packed DFT
+    KID_RESIDUAL,     // residual sweep F - A(U)
+    KID_RFFT,         // packed real DFT along time
     KID_REDUCE,       // norm and dot-product reductions, per-slot scalar kernels
     KID_DOWN0,        // V-cycle restriction from the finest level
     KID_DOWNC,        // V-cycle restriction on coarser levels
@@ -111,7 +112,7 @@ struct Plan {
     int target_slot, target_team;  // grid targets of the slot-vector and per-node kernels
     Geom g_slot0;       // slot-vector kernels on level 0
     Geom g_team;        // per-node team kernels (inverse DFT)
-    Geom g_fwd;         // residual + DFT kernel (team of min(S, 256) threads per column)
+    Geom g_fwd;         // residual sweep (team of min(S, 256) threads per column)
     Timer* tm;          // per-kernel event timer (owned by the plan)
 };
 

