@@ -22,7 +22,7 @@ struct LvArgs {
 };
 
 struct SlotArgs {
-    int S, per_step, slot_chunk, remap, col_groups, rows_per_chunk;
+    int S, lgS, per_step, slot_chunk, remap, col_groups, rows_per_chunk;
     double nu, omega;
     const double* zs;  // S x 3 generic (a, b, c) of the shifts
 };
@@ -33,6 +33,19 @@ template <typename T> __device__ __forceinline__ GS<T> load_shift(const double* 
     g.b = (T)zs[3 * s + 1];
     g.c = (T)zs[3 * s + 2];
     return g;
+}
+
+// Addressing: a workgroup walks the same grid row in all its threads, so row base
+// pointers are uniform; per-lane positions inside a row are loop-invariant 32-bit byte
+// offsets (a row holds at most 4097 x 512 slot values).
+template <typename P> __device__ __forceinline__ const P* cboff(const P* base, unsigned bytes) {
+    return reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + bytes);
+}
+template <typename P> __device__ __forceinline__ P* boff(P* base, unsigned bytes) {
+    return reinterpret_cast<P*>(reinterpret_cast<char*>(base) + bytes);
+}
+template <typename P> __device__ __forceinline__ P* row_of(P* base, int row, int side, int lgS) {
+    return base + ((size_t)(row * side) << lgS);
 }
 
 // The seven mass-stencil coefficients of node a (centre, E, W, N, S, NE, SW).
@@ -107,44 +120,56 @@ __device__ __forceinline__ void store_dot_partials(const double* acc, double* pa
 // c-2..c+2), forms the fine residual s = r - A x1 at columns c-1, c, c+1 of row R and adds
 // it into the coarse rows it belongs to with the P^T weights: row 2cj-1 contributes
 // (c-1, c) x 1/2, row 2cj contributes (c-1, c, c+1) x (1/2, 1, 1/2), row 2cj+1
-// contributes (c, c+1) x 1/2 (P1 interpolation on the SW-NE split grid).
+// contributes (c, c+1) x 1/2 (P1 interpolation on the SW-NE split grid). The inputs of
+// row R+2 are loaded before row R is computed.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_, void* rout_) {
     using T2 = typename Vec2<T>::type;
     const T2* rin = (const T2*)rin_;
     T2* rout = (T2*)rout_;
-    const int S = sa.S, SC = sa.slot_chunk;
+    const int S = sa.S, lgS = sa.lgS, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
     const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl;
     const int sf = F.side, nF = F.n, sc = C.side, nc = C.n;
+    const long nd = (long)F.nodes;
     const T half = (T)0.5;
+    const unsigned E = sizeof(T2);
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, sc);
     int ci = sr.col0 + ln;
     if (UNI) ci = __builtin_amdgcn_readfirstlane(ci);
     if (ci >= sc) return;
     const T2 zero = mk2<T>(0, 0);
+    const unsigned oco = (((unsigned)ci << lgS) + s) * E;
     // boundary coarse nodes of this chunk are zero
     for (int cj = sr.row0; cj < sr.row1; ++cj)
-        if (ci == 0 || ci == nc || cj == 0 || cj == nc) rout[(size_t)(cj * sc + ci) * S + s] = zero;
+        if (ci == 0 || ci == nc || cj == 0 || cj == nc) *boff(row_of(rout, cj, sc, lgS), oco) = zero;
     if (ci == 0 || ci == nc) return;
     const int cj0 = sr.row0 > 1 ? sr.row0 : 1;
     const int cj1 = sr.row1 < nc ? sr.row1 : nc;  // interior coarse rows [cj0, cj1)
     if (cj0 >= cj1) return;
     const int c = 2 * ci;
-    // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
-    T2 xa[5], xb[5], xq[5], ra[3], rb[3], rq[3];
-    auto fetch_row = [&](int R, T2* rv, double* mv) {
+    unsigned of[5];
 #pragma unroll
-        for (int d = 0; d < 5; ++d) {
-            rv[d] = zero;
-            mv[d] = 0.0;
-            if (R >= 0 && R <= nF) {
-                const int b = R * sf + c - 2 + d;
-                rv[d] = rin[(size_t)b * S + s];
-                mv[d] = F.mt[b];
+    for (int d = 0; d < 5; ++d) of[d] = ((((unsigned)(c - 2 + d)) << lgS) + s) * E;
+    // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
+    T2 xa[5], xb[5], xq[5], rb[3], rq[3];
+    auto fetch_row = [&](int R, T2* rv, double* mv) {
+        if (R >= 0 && R <= nF) {
+            const T2* fr = row_of(rin, R, sf, lgS);
+            const double* mr = F.mt + (long)R * sf + (c - 2);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) {
+                rv[d] = *cboff(fr, of[d]);
+                mv[d] = mr[d];
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < 5; ++d) {
+                rv[d] = zero;
+                mv[d] = 0.0;
             }
         }
     };
@@ -156,35 +181,44 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             if (d >= 1 && d <= 3) rr[d - 1] = rv[d];
         }
     };
-    auto load_row = [&](int R, T2* xr, T2* rr) {
-        T2 rv[5];
-        double mv[5];
-        fetch_row(R, rv, mv);
-        eval_row(rv, mv, xr, rr);
-    };
     const int Rs = 2 * cj0 - 1, Re = 2 * cj1 - 1;
-    load_row(Rs - 1, xa, ra);
-    load_row(Rs, xb, rb);
-    load_row(Rs + 1, xq, rq);
+    {
+        T2 rv[5], dummy[3];
+        double mv[5];
+        fetch_row(Rs - 1, rv, mv);
+        eval_row(rv, mv, xa, dummy);
+        fetch_row(Rs, rv, mv);
+        eval_row(rv, mv, xb, rb);
+        fetch_row(Rs + 1, rv, mv);
+        eval_row(rv, mv, xq, rq);
+    }
     T2 acc = zero;
     for (int R = Rs; R <= Re; ++R) {
         T2 nr[5];
         double nm[5];
         if (R < Re) fetch_row(R + 2, nr, nm);  // next row's inputs, loaded before this row is computed
         // s = r - A x1 at (c-1+k, R), k = 0..2; window rows: xa = R-1, xb = R, xq = R+1
+        const double* m0 = F.mt + (long)R * sf + (c - 1);
         T2 sv[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const int a = R * sf + c - 1 + k;
-            T2 Ax = apply_A<T, T2>(mrow(F, a), nu, z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1], xa[k + 1], xq[k + 2],
-                                   xa[k]);
+            const double* mp = m0 + k;
+            MRow m;
+            m.c = mp[0];
+            m.e = mp[nd];
+            m.w = mp[nd - 1];
+            m.n = mp[2 * nd];
+            m.s = mp[2 * nd - sf];
+            m.ne = mp[3 * nd];
+            m.sw = mp[3 * nd - sf - 1];
+            T2 Ax = apply_A<T, T2>(m, nu, z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1], xa[k + 1], xq[k + 2], xa[k]);
             sv[k] = sub2(rb[k], Ax);
         }
         if (R & 1) {
             if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
                 acc = fma2(half, sv[1], acc);
                 acc = fma2(half, sv[2], acc);
-                rout[(size_t)(((R - 1) / 2) * sc + ci) * S + s] = acc;
+                *boff(row_of(rout, (R - 1) / 2, sc, lgS), oco) = acc;
             }
             acc = scale2(half, add2(sv[0], sv[1]));  // lower row of coarse row (R+1)/2
         } else {
@@ -199,10 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
                 xb[d] = xq[d];
             }
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                ra[d] = rb[d];
-                rb[d] = rq[d];
-            }
+            for (int d = 0; d < 3; ++d) rb[d] = rq[d];
             eval_row(nr, nm, xq, rq);
         }
     }
@@ -265,33 +296,6 @@ template <typename T2> struct UpIn {
 };
 
 template <typename T, typename T2>
-__device__ __forceinline__ UpIn<T2> up_load(const T2* rin, const T2* xc, const LvArgs& F, int sc, int S, int s, int bi,
-                                            int bj) {
-    UpIn<T2> u;
-    if (bj < 0 || bj > F.n) {
-        u.kind = 0;
-        u.r = u.c0 = u.c1 = mk2<T>(0, 0);
-        u.mc = 0.0;
-        return u;
-    }
-    const int b = bj * F.side + bi;
-    u.r = rin[(size_t)b * S + s];
-    u.mc = F.mt[b];
-    const int hi = bi >> 1, hj = bj >> 1;
-    const bool oi = bi & 1, oj = bj & 1;
-    u.c0 = xc[((size_t)hj * sc + hi) * S + s];
-    if (!oi && !oj) {
-        u.kind = 1;
-        u.c1 = mk2<T>(0, 0);
-    } else {
-        u.kind = 2;
-        const int qi = hi + (oi ? 1 : 0), qj = hj + (oj ? 1 : 0);
-        u.c1 = xc[((size_t)qj * sc + qi) * S + s];
-    }
-    return u;
-}
-
-template <typename T, typename T2>
 __device__ __forceinline__ T2 up_eval(const UpIn<T2>& u, T dl, T idl, T om, const GS<T>& z) {
     if (u.kind == 0) return mk2<T>(0, 0);
     GS<T> di = gs_inv_diag<T>(dl, idl, (T)u.mc, z);
@@ -313,26 +317,54 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
     const T2* rin = (const T2*)rin_;
     const T2* xc = (const T2*)xc_;
     T2* xout = (T2*)xout_;
-    const int S = sa.S, SC = sa.slot_chunk;
+    const int S = sa.S, lgS = sa.lgS, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
     const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl;
     const int sf = F.side, nF = F.n, sc = C.side;
+    const unsigned E = sizeof(T2);
     double acc[3] = {0, 0, 0};
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
     int ai = sr.col0 + ln;
     if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
+        // per-lane byte offsets: fine columns ai-1, ai, ai+1; their coarse columns hi and hi + (bi & 1)
+        unsigned ofn[3], och[3], ocq[3];
+        bool odd[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int bi = ai - 1 + d, hi = bi >> 1;
+            odd[d] = bi & 1;
+            ofn[d] = (((unsigned)bi << lgS) + s) * E;
+            och[d] = (((unsigned)hi << lgS) + s) * E;
+            ocq[d] = (((unsigned)(hi + (bi & 1)) << lgS) + s) * E;
+        }
+        auto load = [&](int d, int bj) -> UpIn<T2> {
+            UpIn<T2> u;
+            if (bj < 0 || bj > nF) {
+                u.kind = 0;
+                u.r = u.c0 = u.c1 = mk2<T>(0, 0);
+                u.mc = 0.0;
+                return u;
+            }
+            u.r = *cboff(row_of(rin, bj, sf, lgS), ofn[d]);
+            u.mc = F.mt[(long)bj * sf + ai - 1 + d];
+            const int hj = bj >> 1, oj = bj & 1;
+            u.c0 = *cboff(row_of(xc, hj, sc, lgS), och[d]);
+            if (!odd[d] && !oj) {
+                u.kind = 1;
+                u.c1 = mk2<T>(0, 0);
+            } else {
+                u.kind = 2;
+                u.c1 = *cboff(row_of(xc, hj + oj, sc, lgS), ocq[d]);
+            }
+            return u;
+        };
         const int j0 = sr.row0;
-        UpIn<T2> q0 = up_load<T, T2>(rin, xc, F, sc, S, s, ai - 1, j0 - 1);
-        UpIn<T2> q1 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, j0 - 1);
-        UpIn<T2> q2 = up_load<T, T2>(rin, xc, F, sc, S, s, ai - 1, j0);
-        UpIn<T2> q3 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, j0);
-        UpIn<T2> q4 = up_load<T, T2>(rin, xc, F, sc, S, s, ai + 1, j0);
-        UpIn<T2> q5 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, j0 + 1);
-        UpIn<T2> q6 = up_load<T, T2>(rin, xc, F, sc, S, s, ai + 1, j0 + 1);
+        UpIn<T2> q0 = load(0, j0 - 1), q1 = load(1, j0 - 1), q2 = load(0, j0), q3 = load(1, j0), q4 = load(2, j0);
+        UpIn<T2> q5 = load(1, j0 + 1), q6 = load(2, j0 + 1);
         T2 xsw = up_eval(q0, dl, idl, om, z), xs = up_eval(q1, dl, idl, om, z);
         T2 xw = up_eval(q2, dl, idl, om, z), xcn = up_eval(q3, dl, idl, om, z), xe = up_eval(q4, dl, idl, om, z);
         T2 xn = up_eval(q5, dl, idl, om, z), xne = up_eval(q6, dl, idl, om, z);
@@ -341,19 +373,19 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
             const bool more = aj + 1 < sr.row1;
             UpIn<T2> p0, p1, p2;
             if (more) {
-                p0 = up_load<T, T2>(rin, xc, F, sc, S, s, ai - 1, aj + 1);
-                p1 = up_load<T, T2>(rin, xc, F, sc, S, s, ai, aj + 2);
-                p2 = up_load<T, T2>(rin, xc, F, sc, S, s, ai + 1, aj + 2);
+                p0 = load(0, aj + 1);
+                p1 = load(1, aj + 2);
+                p2 = load(2, aj + 2);
             }
-            const int a = aj * sf + ai;
             T2 out = mk2<T>(0, 0);
             if (aj > 0 && aj < nF) {
+                const long a = (long)aj * sf + ai;
                 T2 Ax = apply_A<T, T2>(mrow(F, a), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
                 GS<T> da = gs_inv_diag<T>(dl, idl, (T)F.mt[a], z);
                 out = add2(xcn, scale2(om, gs_apply(da, sub2(rc, Ax))));
                 if (dotmode != DOT_NONE) dot3_acc(acc, out, rc, dotmode == DOT_HERM);
             }
-            xout[(size_t)a * S + s] = out;
+            *boff(row_of(xout, aj, sf, lgS), ofn[1]) = out;
             if (more) {
                 xsw = xw;
                 xs = xcn;
@@ -367,7 +399,8 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
             }
         }
     } else if (ai < sf) {
-        for (int aj = sr.row0; aj < sr.row1; ++aj) xout[(size_t)(aj * sf + ai) * S + s] = mk2<T>(0, 0);
+        const unsigned oc = (((unsigned)ai << lgS) + s) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, lgS), oc) = mk2<T>(0, 0);
     }
     if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, S, blockIdx.y, SC);
 }
@@ -381,40 +414,42 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     using T2 = typename Vec2<T>::type;
     const T2* x = (const T2*)x_;
     T2* y = (T2*)y_;
-    const int S = sa.S, SC = sa.slot_chunk;
+    const int S = sa.S, lgS = sa.lgS, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
     const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu;
     const int sf = F.side, nF = F.n;
+    const unsigned E = sizeof(T2);
     double acc[3] = {0, 0, 0};
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
     int ai = sr.col0 + ln;
     if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
-    auto ld = [&](int bi, int bj) -> T2 {
-        if (bj < 0 || bj > nF) return mk2<T>(0, 0);
-        return x[(size_t)(bj * sf + bi) * S + s];
-    };
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
+        const unsigned ow = ((((unsigned)(ai - 1)) << lgS) + s) * E, oc = ow + (unsigned)S * E,
+                       oe = oc + (unsigned)S * E;
+        auto ld = [&](unsigned o, int bj) -> T2 {
+            if (bj < 0 || bj > nF) return mk2<T>(0, 0);
+            return *cboff(row_of(x, bj, sf, lgS), o);
+        };
         const int j0 = sr.row0;
-        T2 xsw = ld(ai - 1, j0 - 1), xs = ld(ai, j0 - 1), xw = ld(ai - 1, j0), xcn = ld(ai, j0), xe = ld(ai + 1, j0);
-        T2 xn = ld(ai, j0 + 1), xne = ld(ai + 1, j0 + 1);
+        T2 xsw = ld(ow, j0 - 1), xs = ld(oc, j0 - 1), xw = ld(ow, j0), xcn = ld(oc, j0), xe = ld(oe, j0);
+        T2 xn = ld(oc, j0 + 1), xne = ld(oe, j0 + 1);
         for (int aj = j0; aj < sr.row1; ++aj) {
             const bool more = aj + 1 < sr.row1;
             T2 nw, n2, ne2;
             if (more) {  // next row's new points, loaded before this row is computed
-                nw = ld(ai - 1, aj + 1);
-                n2 = ld(ai, aj + 2);
-                ne2 = ld(ai + 1, aj + 2);
+                nw = ld(ow, aj + 1);
+                n2 = ld(oc, aj + 2);
+                ne2 = ld(oe, aj + 2);
             }
-            const int a = aj * sf + ai;
             T2 out = mk2<T>(0, 0);
             if (aj > 0 && aj < nF) {
-                out = apply_A<T, T2>(mrow(F, a), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
+                out = apply_A<T, T2>(mrow(F, (long)aj * sf + ai), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
                 if (dotmode != DOT_NONE) dot3_acc(acc, xcn, out, dotmode == DOT_HERM);
             }
-            if (y) y[(size_t)a * S + s] = out;
+            if (y) *boff(row_of(y, aj, sf, lgS), oc) = out;
             if (more) {
                 xsw = xw;
                 xs = xcn;
@@ -426,7 +461,8 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
             }
         }
     } else if (ai < sf && y) {
-        for (int aj = sr.row0; aj < sr.row1; ++aj) y[(size_t)(aj * sf + ai) * S + s] = mk2<T>(0, 0);
+        const unsigned oc = (((unsigned)ai << lgS) + s) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, lgS), oc) = mk2<T>(0, 0);
     }
     if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, S, blockIdx.y, SC);
 }
@@ -555,6 +591,8 @@ __global__ void __launch_bounds__(kBlock) k_cocg_p(int S, size_t total, const do
 static SlotArgs mk_slot(const Plan& p, char* ws, const Geom& g) {
     SlotArgs sa;
     sa.S = p.S;
+    sa.lgS = 0;
+    while ((1 << sa.lgS) < p.S) ++sa.lgS;
     sa.col_groups = g.col_groups;
     sa.rows_per_chunk = g.rows_per_chunk;
     sa.per_step = g.per_step;

@@ -74,7 +74,7 @@ __device__ T2* fft_team(T2* a, T2* b, int S, int lt, int TS, const T2* __restric
 // ---------------------------------------------------------------- forward kernel
 
 struct FwdArgs {
-    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, mode;
+    int n, side, N, S, lgS, ts, nb, col_groups, rows_per_chunk, remap, mode;
     size_t nodes;
     double inv_tau, n2;
     double nu_a, nu_b, nu_out;
@@ -232,10 +232,20 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
     if (UNI) i = __builtin_amdgcn_readfirstlane(i);
     const bool colvalid = i < side, colint = i > 0 && i < n;
     Win v[KP][2];
-    auto ld = [&](int ci, int cj, int k) -> double2 {
+    // uniform row base + per-lane byte offset of (column i-1+d, pair lt + TS k)
+    const int lgS = a.lgS;
+    unsigned ofs[3][KP];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+            ofs[d][k] = ((((unsigned)(i - 1 + d)) << lgS) + (unsigned)(lt + TS * k)) * (unsigned)sizeof(double2);
+    auto rowU = [&](int cj) { return U2 + ((size_t)(cj * side) << lgS); };
+    auto ldd = [&](int d, int cj, int k) -> double2 {
         if (cj < 0 || cj > n) return make_double2(0.0, 0.0);
-        return U2[(long)(cj * side + ci) * S_ + lt + TS * k];
+        return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(rowU(cj)) + ofs[d][k]);
     };
+    auto ld = [&](int ci, int cj, int k) -> double2 { return ldd(ci - i + 1, cj, k); };
     // window at the first interior row of the chunk
     const int jin = sr.row0 > 1 ? sr.row0 : 1;
     if (a.mode == TM_RESIDUAL && colint && jin < sr.row1 && jin < n) {
@@ -443,6 +453,8 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.side = p.side;
     a.N = p.N;
     a.S = p.S;
+    a.lgS = 0;
+    while ((1 << a.lgS) < p.S) ++a.lgS;
     a.remap = p.opt.xcd_remap;
     a.mode = mode;
     a.nodes = p.nodes;
