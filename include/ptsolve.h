@@ -112,6 +112,9 @@ typedef struct {
     int32_t xcd_remap;     /* 1: map workgroups to contiguous node ranges per XCD */
     int32_t timing;        /* 1: bracket every kernel launch of pt_solve with HIP events on
                               the solve stream and report per-kernel device time in pt_stats */
+    int32_t graph;         /* 1: capture the kernels of check_every outer steps into a HIP
+                              graph on the first call (per plan and workspace address) and
+                              replay it; same iterates as 0. Cannot be combined with timing. */
 } pt_options;
 
 typedef struct {
@@ -125,10 +128,11 @@ typedef struct {
     double* kernel_ms;          /* caller-owned host array [PT_KERNEL_CLASSES] or NULL: total
                                    device time per kernel class (options.timing = 1) */
     int64_t* kernel_launches;   /* caller-owned host array [PT_KERNEL_CLASSES] or NULL */
+    int32_t converged_at;       /* outer step at whose check rel <= tol first held, -1 if never */
 } pt_stats;
 
 /* Kernel classes reported by the per-kernel timer; pt_kernel_class_name() names them. */
-#define PT_KERNEL_CLASSES 14
+#define PT_KERNEL_CLASSES 15
 
 typedef struct pt_plan pt_plan;
 
@@ -151,6 +155,29 @@ pt_status pt_plan_workspace_bytes(const pt_plan* plan, size_t* bytes);
  * iterate and stats are filled. Blocks until the stream has finished. */
 pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream,
                    pt_stats* stats);
+
+/* Batching: count independent instances of Problem 1 that share the grid (n), the
+ * period (N, T), the conductivity (sigma_in, sigma_rect) and nu_max -- hence M, Khat and
+ * the multigrid hierarchy -- but may differ in the reluctivity law and region (nu_a,
+ * nu_b, nu_out, nu_rect), the source (J0, coil_rect, waveform). The instances are
+ * stacked along the frequency axis, so each kernel of the outer step treats all of
+ * them in one launch (the DFT diagonalisation of Remark rem:parallel applied per
+ * instance). count is a power of two, 1 <= count <= 1024, count N / 2 <= 65536;
+ * d_theta, d_sigma and d_load must be NULL when count > 1. probs is copied. */
+pt_status pt_plan_create_batch(const pt_problem* probs, int32_t count, const pt_options* opts,
+                               pt_plan** out);
+
+/* Number of instances of a plan (1 for pt_plan_create). */
+pt_status pt_plan_batch_size(const pt_plan* plan, int32_t* count);
+
+/* pt_solve for a batch plan: d_u is [count][N][n+1][n+1] (instance-major), stats NULL
+ * or a caller-owned array of count entries (each with its own history buffer). The
+ * iteration runs until every instance meets tol; an instance's converged_at gives the
+ * step at which it first did. The status is the first failure over the instances
+ * (non-finite, breakdown, divergence of any instance; max_outer). Every other entry
+ * point below requires a single-problem plan. Blocks until the stream has finished. */
+pt_status pt_solve_batch(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream,
+                         pt_stats* stats);
 
 /* R = F - A(U) (eq. (disc1) moved to one side, u^0 = u^N) on every slice; d_r has
  * the time-field layout, boundary entries 0. rel_out / fnorm_out (host, may be NULL)

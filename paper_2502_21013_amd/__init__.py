@@ -15,7 +15,7 @@ from typing import Dict, List, Optional
 
 from . import _lib as L
 
-__all__ = ["Plan", "SolveStats", "PTError", "library", "problem_struct"]
+__all__ = ["Plan", "BatchPlan", "SolveStats", "PTError", "library", "problem_struct"]
 
 
 class PTError(RuntimeError):
@@ -72,6 +72,47 @@ class SolveStats:
     history: List[float]
     kernel_ms: Dict[str, float] = field(default_factory=dict)
     kernel_launches: Dict[str, int] = field(default_factory=dict)
+    converged_at: int = -1
+
+
+def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega, use_initial_guess,
+             diverge_factor, xcd_remap, timing, graph) -> L.Options:
+    o = L.Options()
+    lib.pt_options_default(C.byref(o))
+    o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
+    o.precision = {"fp64": L.PT_FP64, "fp32": L.PT_FP32_REFINE}[precision]
+    o.inner = {"galerkin1": L.PT_INNER_GALERKIN1, "cocg": L.PT_INNER_COCG}[inner]
+    o.inner_iters, o.vc_omega = int(inner_iters), float(vc_omega)
+    o.use_initial_guess = 1 if use_initial_guess else 0
+    o.diverge_factor, o.xcd_remap = float(diverge_factor), 1 if xcd_remap else 0
+    o.timing = 1 if timing else 0
+    o.graph = 1 if graph else 0
+    return o
+
+
+class _StatsBuf:
+    """Host buffers behind one pt_stats struct."""
+
+    def __init__(self, history_cap):
+        self.hist = (C.c_double * history_cap)()
+        self.kms = (C.c_double * L.PT_KERNEL_CLASSES)()
+        self.kcnt = (C.c_int64 * L.PT_KERNEL_CLASSES)()
+        self.cap = history_cap
+
+    def fill(self, s: L.Stats):
+        s.residual_history = C.cast(self.hist, C.POINTER(C.c_double))
+        s.history_cap = self.cap
+        s.kernel_ms = C.cast(self.kms, C.POINTER(C.c_double))
+        s.kernel_launches = C.cast(self.kcnt, C.POINTER(C.c_int64))
+
+    def result(self, lib, st, s: L.Stats) -> SolveStats:
+        names = [lib.pt_kernel_class_name(i).decode() for i in range(L.PT_KERNEL_CLASSES)]
+        n = L.PT_KERNEL_CLASSES
+        return SolveStats(status=st, outer_iters=s.outer_iters, rel_residual=s.rel_residual, f_norm=s.f_norm,
+                          time_ms=s.time_ms, history=list(self.hist[: s.history_len]),
+                          kernel_ms={names[i]: self.kms[i] for i in range(n) if self.kcnt[i]},
+                          kernel_launches={names[i]: int(self.kcnt[i]) for i in range(n) if self.kcnt[i]},
+                          converged_at=s.converged_at)
 
 
 class Plan:
@@ -79,8 +120,8 @@ class Plan:
 
     def __init__(self, problem, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
-                 diverge_factor=1e3, xcd_remap=True, timing=False, theta=None, sigma=None, load=None,
-                 device=None):
+                 diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, theta=None, sigma=None,
+                 load=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -90,15 +131,8 @@ class Plan:
         self.precision = precision
         self._keep = (theta, sigma, load)  # device tables must outlive the plan's calls
         self._ps = problem_struct(problem, theta, sigma, load)
-        o = L.Options()
-        self.lib.pt_options_default(C.byref(o))
-        o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
-        o.precision = {"fp64": L.PT_FP64, "fp32": L.PT_FP32_REFINE}[precision]
-        o.inner = {"galerkin1": L.PT_INNER_GALERKIN1, "cocg": L.PT_INNER_COCG}[inner]
-        o.inner_iters, o.vc_omega = int(inner_iters), float(vc_omega)
-        o.use_initial_guess = 1 if use_initial_guess else 0
-        o.diverge_factor, o.xcd_remap = float(diverge_factor), 1 if xcd_remap else 0
-        o.timing = 1 if timing else 0
+        o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -161,20 +195,11 @@ class Plan:
         if U is None:
             U = self.new_time_field()
         ws, nb = self.workspace()
-        hist = (C.c_double * history_cap)()
-        kms = (C.c_double * L.PT_KERNEL_CLASSES)()
-        kcnt = (C.c_int64 * L.PT_KERNEL_CLASSES)()
+        buf = _StatsBuf(history_cap)
         s = L.Stats()
-        s.residual_history = C.cast(hist, C.POINTER(C.c_double))
-        s.history_cap = history_cap
-        s.kernel_ms = C.cast(kms, C.POINTER(C.c_double))
-        s.kernel_launches = C.cast(kcnt, C.POINTER(C.c_int64))
+        buf.fill(s)
         st = self.lib.pt_solve(self._h, ws, nb, self._time_field(U, "U"), self._stream(), C.byref(s))
-        names = [self.lib.pt_kernel_class_name(i).decode() for i in range(L.PT_KERNEL_CLASSES)]
-        stats = SolveStats(status=st, outer_iters=s.outer_iters, rel_residual=s.rel_residual,
-                           f_norm=s.f_norm, time_ms=s.time_ms, history=list(hist[: s.history_len]),
-                           kernel_ms={names[i]: kms[i] for i in range(L.PT_KERNEL_CLASSES) if kcnt[i]},
-                           kernel_launches={names[i]: int(kcnt[i]) for i in range(L.PT_KERNEL_CLASSES) if kcnt[i]})
+        stats = buf.result(self.lib, st, s)
         if raise_on_error and st != L.PT_OK:
             raise PTError(st, "pt_solve")
         return U, stats
@@ -240,3 +265,71 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class BatchPlan(Plan):
+    """count instances of one grid and period (shared conductivity and nu_max) solved
+    together: pt_plan_create_batch / pt_solve_batch. count must be a power of two."""
+
+    def __init__(self, problems, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
+                 inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
+                 diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, device=None):
+        import torch
+        problems = list(problems)
+        self.lib = L.load()
+        self.problems = problems
+        self.problem = problems[0]
+        self.count = len(problems)
+        self.n, self.N = int(self.problem.n), int(self.problem.N)
+        self.S = self.N // 2
+        self.nodes = (self.n + 1) ** 2
+        self.precision = precision
+        self._keep = ()
+        self._pa = (L.Problem * self.count)(*[problem_struct(p) for p in problems])
+        o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph)
+        self._opts = o
+        h = C.c_void_p()
+        st = self.lib.pt_plan_create_batch(self._pa, self.count, C.byref(o), C.byref(h))
+        if st != L.PT_OK:
+            raise PTError(st, "pt_plan_create_batch")
+        self._h = h
+        nb = C.c_size_t()
+        self._check(self.lib.pt_plan_workspace_bytes(self._h, C.byref(nb)), "pt_plan_workspace_bytes")
+        self.workspace_bytes = int(nb.value)
+        self.device = torch.device(device) if device is not None else None
+        self._ws = None
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+
+    def new_time_field(self):
+        import torch
+        dev = self.device or torch.device("cuda", torch.cuda.current_device())
+        return torch.zeros((self.count, self.N, self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+
+    def _batch_field(self, t, name):
+        import torch
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or \
+                tuple(t.shape) != (self.count, self.N, self.n + 1, self.n + 1):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of shape "
+                             f"({self.count}, {self.N}, {self.n + 1}, {self.n + 1})")
+        return C.c_void_p(t.data_ptr())
+
+    def solve(self, U=None, history_cap: int = 4096, raise_on_error: bool = True):
+        """Returns U [count, N, n+1, n+1] and one SolveStats per instance."""
+        if U is None:
+            U = self.new_time_field()
+        ws, nb = self.workspace()
+        bufs = [_StatsBuf(history_cap) for _ in range(self.count)]
+        sa = (L.Stats * self.count)()
+        for b, buf in zip(bufs, sa):
+            b.fill(buf)
+        st = self.lib.pt_solve_batch(self._h, ws, nb, self._batch_field(U, "U"), self._stream(), sa)
+        stats = [b.result(self.lib, st, s) for b, s in zip(bufs, sa)]
+        if raise_on_error and st != L.PT_OK:
+            raise PTError(st, "pt_solve_batch")
+        return U, stats
+
+    def _single(self, *a, **k):
+        raise TypeError("component entry points take a single-problem plan")
+
+    residual = apply_K = rfft = irfft = shifted_apply = precond_apply = periodic_solve = _single

@@ -45,6 +45,7 @@ class Options(C.Structure):
         ("precision", C.c_int32), ("inner", C.c_int32), ("inner_iters", C.c_int32),
         ("vc_sweeps", C.c_int32), ("vc_omega", C.c_double), ("use_initial_guess", C.c_int32),
         ("diverge_factor", C.c_double), ("xcd_remap", C.c_int32), ("timing", C.c_int32),
+        ("graph", C.c_int32),
     ]
 
 
@@ -54,6 +55,7 @@ class Stats(C.Structure):
         ("time_ms", C.c_double), ("residual_history", C.POINTER(C.c_double)),
         ("history_cap", C.c_int32), ("history_len", C.c_int32),
         ("kernel_ms", C.POINTER(C.c_double)), ("kernel_launches", C.POINTER(C.c_int64)),
+        ("converged_at", C.c_int32),
     ]
 
 
@@ -79,6 +81,9 @@ def load():
         "pt_plan_destroy": (None, [vp]),
         "pt_plan_workspace_bytes": (i32, [vp, C.POINTER(C.c_size_t)]),
         "pt_solve": (i32, [vp, vp, sz, vp, vp, C.POINTER(Stats)]),
+        "pt_plan_create_batch": (i32, [C.POINTER(Problem), i32, C.POINTER(Options), pplan]),
+        "pt_plan_batch_size": (i32, [vp, C.POINTER(C.c_int32)]),
+        "pt_solve_batch": (i32, [vp, vp, sz, vp, vp, C.POINTER(Stats)]),
         "pt_residual": (i32, [vp, vp, sz, vp, vp, vp, dp, dp]),
         "pt_apply_K": (i32, [vp, vp, sz, vp, vp, i32, vp]),
         "pt_time_rfft": (i32, [vp, vp, sz, vp, vp, vp]),

@@ -70,8 +70,9 @@ void tm_end(const Plan& p, int kid, hipStream_t st) {
 static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static void sweep_geom(Geom& g, int side, int target_blocks) {
-    g.col_groups = (side + g.per_step - 1) / g.per_step;
+static void sweep_geom(Geom& g, int side, int target_blocks, int cols = 0) {
+    if (cols <= 0) cols = side;
+    g.col_groups = (cols + g.per_step - 1) / g.per_step;
     int nch = target_blocks / (g.col_groups * g.chunks);
     if (nch < 1) nch = 1;
     if (nch > side) nch = side;
@@ -91,7 +92,7 @@ Geom slot_geom(int side, int S, int target_blocks) {
     return g;
 }
 
-Geom team_geom(int side, int S, int target_blocks) {
+Geom team_geom(int side, int S, int B, int target_blocks) {
     Geom g;
     // S/4 threads per node (one radix-4 butterfly per thread and stage) and at least one
     // wavefront per workgroup: 64 / (S/4) nodes per workgroup when S < 256, one node
@@ -102,17 +103,17 @@ Geom team_geom(int side, int S, int target_blocks) {
     g.slot_chunk = ts;
     g.per_step = ts >= 64 ? 1 : 64 / ts;
     g.chunks = 1;
-    sweep_geom(g, side, target_blocks);
+    sweep_geom(g, side, target_blocks, side * B);
     return g;
 }
 
-Geom fwd_geom(int side, int S, int target_blocks) {
+Geom fwd_geom(int side, int S, int B, int target_blocks) {
     Geom g;
     int ts = S < kBlock ? S : kBlock;
     g.slot_chunk = ts;
     g.per_step = kBlock / ts;
     g.chunks = 1;
-    sweep_geom(g, side, target_blocks);
+    sweep_geom(g, side, target_blocks, side * B);
     return g;
 }
 
@@ -147,6 +148,35 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     return PT_OK;
 }
 
+// A batch shares the grid, the period, the conductivity (so M and the multigrid
+// hierarchy) and nu_max (so Khat); the reluctivity law, the iron region and the source
+// may differ per instance.
+static pt_status validate_batch(const pt_problem* pr, int count, const pt_options* o) {
+    if (!pr) return fail(PT_ERR_INVALID, "problems must not be NULL");
+    if (!is_pow2(count) || count > 1024) return fail(PT_ERR_INVALID, "count must be a power of two in [1, 1024]");
+    for (int b = 0; b < count; ++b) {
+        pt_status s = validate(&pr[b], o);
+        if (s != PT_OK) return fail(s, "instance " + std::to_string(b) + ": " + g_last_error);
+    }
+    if (count == 1) return PT_OK;
+    const pt_problem& a = pr[0];
+    auto same_rect = [](const pt_rect& x, const pt_rect& y) {
+        return x.x0 == y.x0 && x.y0 == y.y0 && x.x1 == y.x1 && x.y1 == y.y1;
+    };
+    for (int b = 1; b < count; ++b) {
+        const pt_problem& q = pr[b];
+        if (q.n != a.n || q.N != a.N || q.T != a.T)
+            return fail(PT_ERR_INVALID, "batch instances must share n, N and T");
+        if (q.sigma_in != a.sigma_in || !same_rect(q.sigma_rect, a.sigma_rect) || q.nu_max != a.nu_max)
+            return fail(PT_ERR_INVALID, "batch instances must share sigma_in, sigma_rect and nu_max");
+    }
+    for (int b = 0; b < count; ++b)
+        if (pr[b].d_theta || pr[b].d_sigma || pr[b].d_load)
+            return fail(PT_ERR_INVALID, "d_theta, d_sigma and d_load must be NULL in a batch of more than one");
+    if ((long)count * (a.N / 2) > 65536) return fail(PT_ERR_INVALID, "count * N / 2 must not exceed 65536");
+    return PT_OK;
+}
+
 static void layout(Plan& p) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -154,8 +184,9 @@ static void layout(Plan& p) {
         off = align256(off + bytes);
         return o;
     };
-    const size_t S = p.S;
-    p.off_U = take(p.nodes * p.N * sizeof(double));
+    const size_t S = p.ST;  // slots per node over the batch
+    const size_t B = p.B;
+    p.off_U = take(p.nodes * B * p.N * sizeof(double));
     p.off_F = p.prob.d_load ? take(p.nodes * p.N * sizeof(double)) : 0;
     for (int l = 0; l < p.nlev; ++l) {
         LevelDesc& d = p.lev[l];
@@ -174,17 +205,19 @@ static void layout(Plan& p) {
     } else {
         p.off_cx = p.off_cr = p.off_cq = p.off_cp = 0;
     }
-    p.off_flags = take(2 * (size_t)p.n * p.n);
-    p.off_b = take(p.nodes * sizeof(double));
+    p.off_flags = take(B * 2 * (size_t)p.n * p.n);
+    p.off_b = take(B * p.nodes * sizeof(double));
     p.off_tw64 = take((size_t)p.N * 2 * sizeof(double));
     p.off_tw32 = take((size_t)p.N * 2 * sizeof(float));
     p.off_zs = take(S * 3 * sizeof(double));
-    p.off_wave = take((size_t)p.N * sizeof(double));
+    p.off_wave = take(B * (size_t)p.N * sizeof(double));
+    p.off_inst = take(B * 4 * sizeof(double));
     size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows) * S * 3;
-    size_t part_team = (size_t)p.g_fwd.blocks * 2;
+    size_t part_team = (size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2;
     p.part_bytes = (part_slot > part_team ? part_slot : part_team) * sizeof(double);
     p.off_part = take(p.part_bytes);
-    p.off_scal = take(64 * sizeof(double));
+    p.off_scal = take(2 * B * sizeof(double));
+    p.off_flag = take(sizeof(int));
     p.off_coef = take(8 * S * 2 * sizeof(double));  // eight double2 per-slot arrays
     p.off_coef2 = p.off_coef + 4 * S * 2 * sizeof(double);
     p.off_hist = 0;
@@ -203,7 +236,7 @@ static void host_tables(Plan& p) {
         p.h_tw32[2 * k + 1] = (float)p.h_tw64[2 * k + 1];
     }
     // z_k = (1 - exp(-2 pi i k / N)) / tau: Re = (1 - cos t)/tau, Im = sin t / tau, t = 2 pi k / N
-    p.h_zs = new double[3 * p.S];
+    p.h_zs = new double[3 * (size_t)p.ST];
     for (int s = 0; s < p.S; ++s) {
         double t = 2.0 * pi * (double)s / (double)p.N;
         double re = (1.0 - std::cos(t)) / p.tau, im = std::sin(t) / p.tau;
@@ -217,10 +250,19 @@ static void host_tables(Plan& p) {
             p.h_zs[3 * s + 2] = re;
         }
     }
-    p.h_wave = new double[p.N];
-    for (int j = 0; j < p.N; ++j) {
-        double ph = 2.0 * pi * (double)(j + 1) / (double)p.N;  // 2 pi t_{j+1} / T
-        p.h_wave[j] = (p.prob.waveform == PT_WAVE_SIN) ? std::sin(ph) : std::cos(ph);
+    for (int b = 1; b < p.B; ++b) std::memcpy(p.h_zs + 3 * (size_t)b * p.S, p.h_zs, 3 * (size_t)p.S * sizeof(double));
+    p.h_wave = new double[(size_t)p.B * p.N];
+    p.h_inst = new double[4 * (size_t)p.B];
+    for (int b = 0; b < p.B; ++b) {
+        const pt_problem& q = p.probs[b];
+        for (int j = 0; j < p.N; ++j) {
+            double ph = 2.0 * pi * (double)(j + 1) / (double)p.N;  // 2 pi t_{j+1} / T
+            p.h_wave[(size_t)b * p.N + j] = (q.waveform == PT_WAVE_SIN) ? std::sin(ph) : std::cos(ph);
+        }
+        p.h_inst[4 * b] = q.nu_a;
+        p.h_inst[4 * b + 1] = q.nu_b;
+        p.h_inst[4 * b + 2] = q.nu_out;
+        p.h_inst[4 * b + 3] = 0.0;
     }
 }
 
@@ -253,8 +295,9 @@ static pt_status timer_start(Plan& p) {
 static pt_status setup(Plan& p, char* ws, hipStream_t st) {
     PT_HIP(hipMemcpyAsync(ws + p.off_tw64, p.h_tw64, (size_t)p.N * 2 * sizeof(double), hipMemcpyHostToDevice, st));
     PT_HIP(hipMemcpyAsync(ws + p.off_tw32, p.h_tw32, (size_t)p.N * 2 * sizeof(float), hipMemcpyHostToDevice, st));
-    PT_HIP(hipMemcpyAsync(ws + p.off_zs, p.h_zs, (size_t)p.S * 3 * sizeof(double), hipMemcpyHostToDevice, st));
-    PT_HIP(hipMemcpyAsync(ws + p.off_wave, p.h_wave, (size_t)p.N * sizeof(double), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_zs, p.h_zs, (size_t)p.ST * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_wave, p.h_wave, (size_t)p.B * p.N * sizeof(double), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_inst, p.h_inst, (size_t)p.B * 4 * sizeof(double), hipMemcpyHostToDevice, st));
     TM(KID_SETUP, launch_setup_fine(p, ws, st));
     for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin(p, ws, l, st));
     PT_HIP(hipGetLastError());
@@ -266,14 +309,14 @@ static pt_status setup(Plan& p, char* ws, hipStream_t st) {
 static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const void** X, const double** coef) {
     double* part = (double*)(ws + p.off_part);
     double2* cf = (double2*)(ws + p.off_coef);
-    const size_t S = p.S;
+    const size_t S = p.ST;
     double* num = (double*)(cf + 0 * S);
     double* den = (double*)(cf + 1 * S);
     double* alpha = (double*)(cf + 2 * S);
     double* rho = (double*)(cf + 3 * S);
     double* rho2 = (double*)(cf + 4 * S);
     double* beta = (double*)(cf + 5 * S);
-    int* flag = (int*)(ws + p.off_scal + 32 * sizeof(double));
+    int* flag = (int*)(ws + p.off_flag);
     void* R = ws + p.lev[0].off_r;
     void* P = ws + p.off_P;
     if (p.opt.inner == PT_INNER_GALERKIN1) {
@@ -292,7 +335,7 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
     void* q = ws + p.off_cq;
     void* pv = ws + p.off_cp;
     void* z = P;
-    TM(KID_MEMSET, PT_HIP(hipMemsetAsync(x, 0, p.nodes * S * p.elem, st)));
+    TM(KID_MEMSET, launch_zero16(x, p.nodes * S * p.elem, st));
     TM(KID_COCG, launch_copy_slots(p, R, r, st));
     launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
     TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, rho, st));
@@ -307,12 +350,219 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
         TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, rho2, st));
         TM(KID_REDUCE, launch_slot_div(p, rho2, rho, beta, nullptr, st));
         TM(KID_COCG, launch_cocg_p(p, beta, z, pv, st));
-        TM(KID_COCG, PT_HIP(hipMemcpyAsync(rho, rho2, S * sizeof(double2), hipMemcpyDeviceToDevice, st)));
+        TM(KID_COCG, launch_copy16(rho2, rho, S * sizeof(double2), st));
     }
     *X = x;
     *coef = nullptr;
     PT_HIP(hipGetLastError());
     return PT_OK;
+}
+
+// ---------------------------------------------------------------- outer loop
+
+// Graph of check_every outer steps, captured once per plan and workspace.
+struct GraphCache {
+    hipStream_t cap = nullptr;  // capture stream (default priority)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    char* ws = nullptr;  // workspace the graph's kernel arguments point into
+    int steps = 0;
+};
+
+void graph_release(Plan& p) {
+    GraphCache* g = p.gr;
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->cap) hipStreamDestroy(g->cap);
+    delete g;
+    p.gr = nullptr;
+}
+
+// One fixed-point update once the residual of U^k is in Rhat (eq. (iter2) in correction
+// form, U^{k+1} = U^k + P^{-1} R^k), followed by the residual of U^{k+1} and its norm
+// partials.
+static pt_status outer_segment(Plan& p, char* ws, hipStream_t st) {
+    double* U = (double*)(ws + p.off_U);
+    double* part = (double*)(ws + p.off_part);
+    double* scal = (double*)(ws + p.off_scal);
+    const void* X = nullptr;
+    const double* coef = nullptr;
+    pt_status s = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
+    if (s != PT_OK) return s;
+    TM(KID_INVERSE, launch_inverse(p, ws, X, coef, U, 1, st));
+    launch_forward(p, ws, TM_RESIDUAL, U, ws + p.lev[0].off_r, nullptr, part, st);
+    TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
+    return PT_OK;
+}
+
+static pt_status graph_get(Plan& p, char* ws, int steps, hipGraphExec_t* exec) {
+    if (!p.gr) {
+        p.gr = new (std::nothrow) GraphCache();
+        if (!p.gr) return fail(PT_ERR_INVALID, "out of host memory");
+        PT_HIP(hipStreamCreateWithFlags(&p.gr->cap, hipStreamNonBlocking));
+    }
+    GraphCache* g = p.gr;
+    if (g->exec && g->ws == ws && g->steps == steps) {
+        *exec = g->exec;
+        return PT_OK;
+    }
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    g->exec = nullptr;
+    g->graph = nullptr;
+    PT_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    pt_status s = PT_OK;
+    for (int i = 0; i < steps && s == PT_OK; ++i) s = outer_segment(p, ws, g->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g->cap, &graph);
+    if (s != PT_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return fail(PT_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return fail(PT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    g->graph = graph;
+    g->ws = ws;
+    g->steps = steps;
+    *exec = g->exec;
+    return PT_OK;
+}
+
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair() {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+    }
+};
+
+// The fixed-point iteration (eqs. (iter1)-(iter2)) for the B instances of a plan, stopped
+// when every instance's relative residual is at most tol. d_u: [B][N][n+1][n+1];
+// stats: NULL or an array of B.
+static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, hipStream_t st, pt_stats* stats) {
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    char* ws = (char*)d_ws;
+    const int B = p.B;
+    EventPair ev;
+    PT_HIP(hipEventCreate(&ev.e0));
+    PT_HIP(hipEventCreate(&ev.e1));
+    s = timer_start(p);
+    if (s != PT_OK) return s;
+    PT_HIP(hipEventRecord(ev.e0, st));
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    double* U = (double*)(ws + p.off_U);
+    if (p.prob.d_load) TM(KID_TRANSPOSE, launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st));
+    if (p.opt.use_initial_guess)
+        TM(KID_TRANSPOSE, launch_transpose_in(p, d_u, U, st));
+    else
+        TM(KID_MEMSET, launch_zero16(U, (size_t)B * p.nodes * p.N * sizeof(double), st));
+    double* part = (double*)(ws + p.off_part);
+    double* scal = (double*)(ws + p.off_scal);
+    int* flag = (int*)(ws + p.off_flag);
+    TM(KID_MEMSET, launch_zero16(flag, 16, st));
+    launch_forward(p, ws, TM_RESIDUAL, U, ws + p.lev[0].off_r, nullptr, part, st);
+    TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
+    std::vector<double> h(2 * (size_t)B), rel(B, INFINITY), fnorm(B, 0.0), best(B, INFINITY);
+    std::vector<int> conv(B, -1);
+    pt_status result = PT_ERR_NOT_CONVERGED;
+    const int ce = p.opt.check_every;
+    int k = 0, hist = 0;
+    for (;;) {
+        bool last = (k >= p.opt.max_outer);
+        if (last || k % ce == 0) {
+            int hflag = 0;
+            PT_HIP(hipMemcpyAsync(h.data(), scal, 2 * (size_t)B * sizeof(double), hipMemcpyDeviceToHost, st));
+            PT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+            PT_HIP(hipStreamSynchronize(st));
+            PT_HIP(hipGetLastError());
+            tm_flush(p);
+            bool all = true;
+            int bad = -1;
+            for (int b = 0; b < B; ++b) {
+                const double r2 = h[2 * b], f2 = h[2 * b + 1];
+                fnorm[b] = std::sqrt(f2);
+                rel[b] = (f2 > 0) ? std::sqrt(r2 / f2) : std::sqrt(r2);
+                if (stats && stats[b].residual_history && hist < stats[b].history_cap)
+                    stats[b].residual_history[hist] = rel[b];
+                if (!std::isfinite(rel[b]) && bad < 0) bad = b;
+                if (rel[b] <= p.opt.tol) {
+                    if (conv[b] < 0) conv[b] = k;
+                } else {
+                    all = false;
+                }
+            }
+            ++hist;
+            auto inst = [&](int b) { return B > 1 ? " (instance " + std::to_string(b) + ")" : std::string(); };
+            if (bad >= 0) {
+                result = fail(PT_ERR_NONFINITE, "residual norm is not finite at outer step " + std::to_string(k) + inst(bad));
+                break;
+            }
+            if (hflag) {
+                result = fail(PT_ERR_BREAKDOWN, "COCG breakdown before outer step " + std::to_string(k));
+                break;
+            }
+            if (all) {
+                result = PT_OK;
+                break;
+            }
+            int grew = -1;
+            for (int b = 0; b < B; ++b) {
+                if (rel[b] < best[b]) best[b] = rel[b];
+                if (grew < 0 && p.opt.diverge_factor > 0 && rel[b] > p.opt.diverge_factor * best[b]) grew = b;
+            }
+            if (grew >= 0) {
+                result = fail(PT_ERR_DIVERGED, "residual grew by more than diverge_factor at outer step " +
+                                                   std::to_string(k) + inst(grew));
+                break;
+            }
+        }
+        if (last) {
+            result = fail(PT_ERR_NOT_CONVERGED, "max_outer reached");
+            break;
+        }
+        if (p.opt.graph && k % ce == 0 && k + ce <= p.opt.max_outer) {
+            hipGraphExec_t exec = nullptr;
+            s = graph_get(p, ws, ce, &exec);
+            if (s != PT_OK) return s;
+            PT_HIP(hipGraphLaunch(exec, st));
+            k += ce;
+        } else {
+            s = outer_segment(p, ws, st);
+            if (s != PT_OK) return s;
+            ++k;
+        }
+    }
+    TM(KID_TRANSPOSE, launch_transpose_out(p, U, d_u, st));
+    PT_HIP(hipEventRecord(ev.e1, st));
+    PT_HIP(hipEventSynchronize(ev.e1));
+    PT_HIP(hipGetLastError());
+    tm_flush(p);
+    float ms = 0.f;
+    PT_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    if (stats) {
+        for (int b = 0; b < B; ++b) {
+            pt_stats& o = stats[b];
+            o.outer_iters = k;
+            o.rel_residual = rel[b];
+            o.f_norm = fnorm[b];
+            o.time_ms = ms;
+            o.history_len = hist < o.history_cap ? hist : o.history_cap;
+            o.converged_at = conv[b];
+            for (int c = 0; c < KID_COUNT; ++c) {
+                if (o.kernel_ms) o.kernel_ms[c] = p.tm ? p.tm->ms[c] : 0.0;
+                if (o.kernel_launches) o.kernel_launches[c] = p.tm ? p.tm->cnt[c] : 0;
+            }
+        }
+    }
+    if (p.tm) p.tm->on = false;
+    return result;
 }
 
 }  // namespace pt
@@ -368,19 +618,26 @@ void pt_options_default(pt_options* o) {
     o->xcd_remap = 1;
 }
 
-pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan** out) {
+static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_options* opts, pt_plan** out) {
     if (!out) return fail(PT_ERR_INVALID, "out must not be NULL");
     *out = nullptr;
-    pt_status s = validate(prob, opts);
+    pt_status s = validate_batch(probs, count, opts);
     if (s != PT_OK) return s;
+    if (opts->graph && opts->timing)
+        return fail(PT_ERR_INVALID, "graph replay and per-kernel timing cannot be combined");
     pt_plan* h = new (std::nothrow) pt_plan();
     if (!h) return fail(PT_ERR_INVALID, "out of host memory");
     Plan& p = h->p;
+    const pt_problem* prob = &probs[0];
     p.prob = *prob;
     p.opt = *opts;
+    p.B = count;
+    p.probs = new pt_problem[count];
+    for (int b = 0; b < count; ++b) p.probs[b] = probs[b];
     p.n = prob->n;
     p.N = prob->N;
     p.S = prob->N / 2;
+    p.ST = p.B * p.S;
     p.side = p.n + 1;
     p.nodes = (size_t)p.side * p.side;
     p.fp32 = opts->precision == PT_FP32_REFINE;
@@ -395,17 +652,36 @@ pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan
         d.nodes = (size_t)d.side * d.side;
     }
     p.tm = nullptr;
+    p.gr = nullptr;
     // grid targets (overridable for tuning through PT_TARGET_SLOT_BLOCKS / PT_TARGET_TEAM_BLOCKS)
     p.target_slot = 2048;
     p.target_team = 16384;
     if (const char* e = std::getenv("PT_TARGET_SLOT_BLOCKS")) p.target_slot = std::max(8, std::atoi(e));
     if (const char* e = std::getenv("PT_TARGET_TEAM_BLOCKS")) p.target_team = std::max(8, std::atoi(e));
-    p.g_slot0 = slot_geom(p.side, p.S, p.target_slot);
-    p.g_team = team_geom(p.side, p.S, p.target_team);
-    p.g_fwd = fwd_geom(p.side, p.S, p.target_slot);
+    p.g_slot0 = slot_geom(p.side, p.ST, p.target_slot);
+    p.g_team = team_geom(p.side, p.S, p.B, p.target_team);
+    p.g_fwd = fwd_geom(p.side, p.S, p.B, p.target_slot);
     layout(p);
     host_tables(p);
     *out = h;
+    return PT_OK;
+}
+
+pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan** out) {
+    if (!prob) {
+        if (out) *out = nullptr;
+        return fail(PT_ERR_INVALID, "problem and options must not be NULL");
+    }
+    return plan_create_impl(prob, 1, opts, out);
+}
+
+pt_status pt_plan_create_batch(const pt_problem* probs, int32_t count, const pt_options* opts, pt_plan** out) {
+    return plan_create_impl(probs, count, opts, out);
+}
+
+pt_status pt_plan_batch_size(const pt_plan* plan, int32_t* count) {
+    if (!plan || !count) return fail(PT_ERR_INVALID, "plan and count must not be NULL");
+    *count = plan->p.B;
     return PT_OK;
 }
 
@@ -415,10 +691,13 @@ void pt_plan_destroy(pt_plan* plan) {
         for (int i = 0; i < 2 * Timer::kCap; ++i) hipEventDestroy(plan->p.tm->ev[i]);
         delete plan->p.tm;
     }
+    graph_release(plan->p);
     delete[] plan->p.h_tw64;
     delete[] plan->p.h_tw32;
     delete[] plan->p.h_zs;
     delete[] plan->p.h_wave;
+    delete[] plan->p.h_inst;
+    delete[] plan->p.probs;
     delete plan;
 }
 
@@ -430,107 +709,20 @@ pt_status pt_plan_workspace_bytes(const pt_plan* plan, size_t* bytes) {
 
 pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream, pt_stats* stats) {
     if (!plan || !d_u) return fail(PT_ERR_INVALID, "plan and d_u must not be NULL");
-    Plan& p = plan->p;
-    pt_status s = check_ws(&p, d_ws, ws_bytes);
-    if (s != PT_OK) return s;
-    hipStream_t st = (hipStream_t)stream;
-    char* ws = (char*)d_ws;
-    hipEvent_t e0, e1;
-    PT_HIP(hipEventCreate(&e0));
-    PT_HIP(hipEventCreate(&e1));
-    s = timer_start(p);
-    if (s != PT_OK) return s;
-    PT_HIP(hipEventRecord(e0, st));
-    s = setup(p, ws, st);
-    if (s != PT_OK) return s;
-    double* U = (double*)(ws + p.off_U);
-    if (p.prob.d_load) TM(KID_TRANSPOSE, launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st));
-    if (p.opt.use_initial_guess)
-        TM(KID_TRANSPOSE, launch_transpose_in(p, d_u, U, st));
-    else
-        TM(KID_MEMSET, PT_HIP(hipMemsetAsync(U, 0, p.nodes * p.N * sizeof(double), st)));
-    double* part = (double*)(ws + p.off_part);
-    double* scal = (double*)(ws + p.off_scal);
-    int* flag = (int*)(ws + p.off_scal + 32 * sizeof(double));
-    TM(KID_MEMSET, PT_HIP(hipMemsetAsync(flag, 0, sizeof(int), st)));
-    void* Rhat = ws + p.lev[0].off_r;
-    pt_status result = PT_ERR_NOT_CONVERGED;
-    double rel = INFINITY, fnorm = 0.0, best = INFINITY;
-    int k = 0, hist = 0;
-    for (;;) {
-        launch_forward(p, ws, TM_RESIDUAL, U, Rhat, nullptr, part, st);
-        TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
-        bool last = (k >= p.opt.max_outer);
-        if (last || k % p.opt.check_every == 0) {
-            double h[2];
-            int hflag = 0;
-            PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-            PT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-            PT_HIP(hipStreamSynchronize(st));
-            PT_HIP(hipGetLastError());
-            tm_flush(p);
-            fnorm = std::sqrt(h[1]);
-            rel = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
-            if (stats && stats->residual_history && hist < stats->history_cap) stats->residual_history[hist] = rel;
-            ++hist;
-            if (!std::isfinite(rel)) {
-                result = fail(PT_ERR_NONFINITE, "residual norm is not finite at outer step " + std::to_string(k));
-                break;
-            }
-            if (hflag) {
-                result = fail(PT_ERR_BREAKDOWN, "COCG breakdown before outer step " + std::to_string(k));
-                break;
-            }
-            if (rel <= p.opt.tol) {
-                result = PT_OK;
-                break;
-            }
-            if (rel < best) best = rel;
-            if (p.opt.diverge_factor > 0 && rel > p.opt.diverge_factor * best) {
-                result = fail(PT_ERR_DIVERGED, "residual grew by more than diverge_factor at outer step " +
-                                                   std::to_string(k));
-                break;
-            }
-        }
-        if (last) {
-            result = fail(PT_ERR_NOT_CONVERGED, "max_outer reached");
-            break;
-        }
-        const void* X = nullptr;
-        const double* coef = nullptr;
-        s = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
-        if (s != PT_OK) return s;
-        TM(KID_INVERSE, launch_inverse(p, ws, X, coef, U, 1, st));
-        ++k;
-    }
-    TM(KID_TRANSPOSE, launch_transpose_out(p, U, d_u, st));
-    PT_HIP(hipEventRecord(e1, st));
-    PT_HIP(hipEventSynchronize(e1));
-    PT_HIP(hipGetLastError());
-    tm_flush(p);
-    float ms = 0.f;
-    PT_HIP(hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (stats) {
-        stats->outer_iters = k;
-        stats->rel_residual = rel;
-        stats->f_norm = fnorm;
-        stats->time_ms = ms;
-        stats->history_len = hist < stats->history_cap ? hist : stats->history_cap;
-        for (int c = 0; c < KID_COUNT; ++c) {
-            if (stats->kernel_ms) stats->kernel_ms[c] = p.tm ? p.tm->ms[c] : 0.0;
-            if (stats->kernel_launches) stats->kernel_launches[c] = p.tm ? p.tm->cnt[c] : 0;
-        }
-    }
-    if (p.tm) p.tm->on = false;
-    return result;
+    if (plan->p.B != 1) return fail(PT_ERR_INVALID, "pt_solve takes a single-problem plan; use pt_solve_batch");
+    return solve_impl(plan->p, d_ws, ws_bytes, d_u, (hipStream_t)stream, stats);
+}
+
+pt_status pt_solve_batch(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream, pt_stats* stats) {
+    if (!plan || !d_u) return fail(PT_ERR_INVALID, "plan and d_u must not be NULL");
+    return solve_impl(plan->p, d_ws, ws_bytes, d_u, (hipStream_t)stream, stats);
 }
 
 pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, double* d_r, void* stream,
                       double* rel_out, double* fnorm_out) {
     if (!plan || !d_u || !d_r) return fail(PT_ERR_INVALID, "plan, d_u and d_r must not be NULL");
     Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -563,6 +755,7 @@ pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d
                      void* stream) {
     if (!plan || !d_u || !d_ku) return fail(PT_ERR_INVALID, "plan, d_u and d_ku must not be NULL");
     Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
     if (nslices < 1 || nslices > p.N) return fail(PT_ERR_INVALID, "nslices must be in [1, N]");
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
@@ -578,6 +771,7 @@ pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d
 pt_status pt_time_rfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_x, void* d_xhat, void* stream) {
     if (!plan || !d_x || !d_xhat) return fail(PT_ERR_INVALID, "plan, d_x and d_xhat must not be NULL");
     Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -594,6 +788,7 @@ pt_status pt_time_rfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const double*
 pt_status pt_time_irfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_xhat, double* d_x, void* stream) {
     if (!plan || !d_x || !d_xhat) return fail(PT_ERR_INVALID, "plan, d_xhat and d_x must not be NULL");
     Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -610,6 +805,7 @@ pt_status pt_time_irfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* 
 pt_status pt_shifted_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_x, void* d_y, void* stream) {
     if (!plan || !d_x || !d_y) return fail(PT_ERR_INVALID, "plan, d_x and d_y must not be NULL");
     Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -624,6 +820,7 @@ pt_status pt_shifted_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const voi
 pt_status pt_precond_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_r, void* d_x, void* stream) {
     if (!plan || !d_r || !d_x) return fail(PT_ERR_INVALID, "plan, d_r and d_x must not be NULL");
     Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -639,6 +836,7 @@ pt_status pt_periodic_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const do
                             int32_t inner_iters, void* stream) {
     if (!plan || !d_r || !d_x) return fail(PT_ERR_INVALID, "plan, d_r and d_x must not be NULL");
     Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
     if (inner_iters < 0 || inner_iters > 64) return fail(PT_ERR_INVALID, "inner_iters must be in [0, 64]");
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;

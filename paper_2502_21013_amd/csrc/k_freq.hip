@@ -21,8 +21,10 @@ struct LvArgs {
     const double* mt;
 };
 
+// S: slots per instance (a power of two; slot s with s % S == 0 packs k = 0 and k = N/2),
+// ST = B S: slots per node over the B instances of a batch (the row stride).
 struct SlotArgs {
-    int S, lgS, per_step, slot_chunk, remap, col_groups, rows_per_chunk;
+    int S, ST, per_step, slot_chunk, remap, col_groups, rows_per_chunk;
     double nu, omega;
     const double* zs;  // S x 3 generic (a, b, c) of the shifts
 };
@@ -44,8 +46,8 @@ template <typename P> __device__ __forceinline__ const P* cboff(const P* base, u
 template <typename P> __device__ __forceinline__ P* boff(P* base, unsigned bytes) {
     return reinterpret_cast<P*>(reinterpret_cast<char*>(base) + bytes);
 }
-template <typename P> __device__ __forceinline__ P* row_of(P* base, int row, int side, int lgS) {
-    return base + ((size_t)(row * side) << lgS);
+template <typename P> __device__ __forceinline__ P* row_of(P* base, int row, int side, int ST) {
+    return base + (size_t)(row * side) * (size_t)ST;
 }
 
 // The seven mass-stencil coefficients of node a (centre, E, W, N, S, NE, SW).
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     using T2 = typename Vec2<T>::type;
     const T2* rin = (const T2*)rin_;
     T2* rout = (T2*)rout_;
-    const int S = sa.S, lgS = sa.lgS, SC = sa.slot_chunk;
+    const int ST = sa.ST, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
@@ -142,10 +144,10 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     if (UNI) ci = __builtin_amdgcn_readfirstlane(ci);
     if (ci >= sc) return;
     const T2 zero = mk2<T>(0, 0);
-    const unsigned oco = (((unsigned)ci << lgS) + s) * E;
+    const unsigned oco = ((unsigned)ci * ST + s) * E;
     // boundary coarse nodes of this chunk are zero
     for (int cj = sr.row0; cj < sr.row1; ++cj)
-        if (ci == 0 || ci == nc || cj == 0 || cj == nc) *boff(row_of(rout, cj, sc, lgS), oco) = zero;
+        if (ci == 0 || ci == nc || cj == 0 || cj == nc) *boff(row_of(rout, cj, sc, ST), oco) = zero;
     if (ci == 0 || ci == nc) return;
     const int cj0 = sr.row0 > 1 ? sr.row0 : 1;
     const int cj1 = sr.row1 < nc ? sr.row1 : nc;  // interior coarse rows [cj0, cj1)
@@ -153,12 +155,12 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     const int c = 2 * ci;
     unsigned of[5];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) of[d] = ((((unsigned)(c - 2 + d)) << lgS) + s) * E;
+    for (int d = 0; d < 5; ++d) of[d] = ((unsigned)(c - 2 + d) * ST + s) * E;
     // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
     T2 xa[5], xb[5], xq[5], rb[3], rq[3];
     auto fetch_row = [&](int R, T2* rv, double* mv) {
         if (R >= 0 && R <= nF) {
-            const T2* fr = row_of(rin, R, sf, lgS);
+            const T2* fr = row_of(rin, R, sf, ST);
             const double* mr = F.mt + (long)R * sf + (c - 2);
 #pragma unroll
             for (int d = 0; d < 5; ++d) {
@@ -218,7 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
                 acc = fma2(half, sv[1], acc);
                 acc = fma2(half, sv[2], acc);
-                *boff(row_of(rout, (R - 1) / 2, sc, lgS), oco) = acc;
+                *boff(row_of(rout, (R - 1) / 2, sc, ST), oco) = acc;
             }
             acc = scale2(half, add2(sv[0], sv[1]));  // lower row of coarse row (R+1)/2
         } else {
@@ -248,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_coarsest(SlotArgs sa, LvArgs C, c
     using T2 = typename Vec2<T>::type;
     const T2* rin = (const T2*)rin_;
     T2* xout = (T2*)xout_;
-    const int S = sa.S;
+    const int S = sa.ST;
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
         const GS<T> z = load_shift<T>(sa.zs, s);
         for (size_t node = 0; node < C.nodes; ++node) {
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
     const T2* rin = (const T2*)rin_;
     const T2* xc = (const T2*)xc_;
     T2* xout = (T2*)xout_;
-    const int S = sa.S, lgS = sa.lgS, SC = sa.slot_chunk;
+    const int ST = sa.ST, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
@@ -337,9 +339,9 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
         for (int d = 0; d < 3; ++d) {
             const int bi = ai - 1 + d, hi = bi >> 1;
             odd[d] = bi & 1;
-            ofn[d] = (((unsigned)bi << lgS) + s) * E;
-            och[d] = (((unsigned)hi << lgS) + s) * E;
-            ocq[d] = (((unsigned)(hi + (bi & 1)) << lgS) + s) * E;
+            ofn[d] = ((unsigned)bi * ST + s) * E;
+            och[d] = ((unsigned)hi * ST + s) * E;
+            ocq[d] = ((unsigned)(hi + (bi & 1)) * ST + s) * E;
         }
         auto load = [&](int d, int bj) -> UpIn<T2> {
             UpIn<T2> u;
@@ -349,16 +351,16 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
                 u.mc = 0.0;
                 return u;
             }
-            u.r = *cboff(row_of(rin, bj, sf, lgS), ofn[d]);
+            u.r = *cboff(row_of(rin, bj, sf, ST), ofn[d]);
             u.mc = F.mt[(long)bj * sf + ai - 1 + d];
             const int hj = bj >> 1, oj = bj & 1;
-            u.c0 = *cboff(row_of(xc, hj, sc, lgS), och[d]);
+            u.c0 = *cboff(row_of(xc, hj, sc, ST), och[d]);
             if (!odd[d] && !oj) {
                 u.kind = 1;
                 u.c1 = mk2<T>(0, 0);
             } else {
                 u.kind = 2;
-                u.c1 = *cboff(row_of(xc, hj + oj, sc, lgS), ocq[d]);
+                u.c1 = *cboff(row_of(xc, hj + oj, sc, ST), ocq[d]);
             }
             return u;
         };
@@ -385,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
                 out = add2(xcn, scale2(om, gs_apply(da, sub2(rc, Ax))));
                 if (dotmode != DOT_NONE) dot3_acc(acc, out, rc, dotmode == DOT_HERM);
             }
-            *boff(row_of(xout, aj, sf, lgS), ofn[1]) = out;
+            *boff(row_of(xout, aj, sf, ST), ofn[1]) = out;
             if (more) {
                 xsw = xw;
                 xs = xcn;
@@ -399,10 +401,10 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
             }
         }
     } else if (ai < sf) {
-        const unsigned oc = (((unsigned)ai << lgS) + s) * E;
-        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, lgS), oc) = mk2<T>(0, 0);
+        const unsigned oc = ((unsigned)ai * ST + s) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, ST), oc) = mk2<T>(0, 0);
     }
-    if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, S, blockIdx.y, SC);
+    if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, ST, blockIdx.y, SC);
 }
 
 // ---------------------------------------------------------------- operator apply
@@ -414,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     using T2 = typename Vec2<T>::type;
     const T2* x = (const T2*)x_;
     T2* y = (T2*)y_;
-    const int S = sa.S, lgS = sa.lgS, SC = sa.slot_chunk;
+    const int ST = sa.ST, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
@@ -427,11 +429,11 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     int ai = sr.col0 + ln;
     if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
-        const unsigned ow = ((((unsigned)(ai - 1)) << lgS) + s) * E, oc = ow + (unsigned)S * E,
-                       oe = oc + (unsigned)S * E;
+        const unsigned ow = ((unsigned)(ai - 1) * ST + s) * E, oc = ow + (unsigned)ST * E,
+                       oe = oc + (unsigned)ST * E;
         auto ld = [&](unsigned o, int bj) -> T2 {
             if (bj < 0 || bj > nF) return mk2<T>(0, 0);
-            return *cboff(row_of(x, bj, sf, lgS), o);
+            return *cboff(row_of(x, bj, sf, ST), o);
         };
         const int j0 = sr.row0;
         T2 xsw = ld(ow, j0 - 1), xs = ld(oc, j0 - 1), xw = ld(ow, j0), xcn = ld(oc, j0), xe = ld(oe, j0);
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
                 out = apply_A<T, T2>(mrow(F, (long)aj * sf + ai), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
                 if (dotmode != DOT_NONE) dot3_acc(acc, xcn, out, dotmode == DOT_HERM);
             }
-            if (y) *boff(row_of(y, aj, sf, lgS), oc) = out;
+            if (y) *boff(row_of(y, aj, sf, ST), oc) = out;
             if (more) {
                 xsw = xw;
                 xs = xcn;
@@ -461,10 +463,10 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
             }
         }
     } else if (ai < sf && y) {
-        const unsigned oc = (((unsigned)ai << lgS) + s) * E;
-        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, lgS), oc) = mk2<T>(0, 0);
+        const unsigned oc = ((unsigned)ai * ST + s) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, ST), oc) = mk2<T>(0, 0);
     }
-    if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, S, blockIdx.y, SC);
+    if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, ST, blockIdx.y, SC);
 }
 
 // ---------------------------------------------------------------- per-slot scalars
@@ -505,8 +507,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce_dots1(const double* part, int
     }
 }
 
-// Stage 2: sum the RB rows of part2 in order and combine into a generic scalar.
-__global__ void __launch_bounds__(kBlock) k_reduce_dots(const double* part, int nblk, int S, int herm, double* out) {
+// Stage 2: sum the RB rows of part2 in order and combine into a generic scalar
+// (S = total slots, Si = slots per instance).
+__global__ void __launch_bounds__(kBlock) k_reduce_dots(const double* part, int nblk, int S, int Si, int herm,
+                                                        double* out) {
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
         double s1 = 0, s2 = 0, s3 = 0;
         for (int b = 0; b < nblk; ++b) {
@@ -516,7 +520,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_dots(const double* part, int 
             s3 += o[2];
         }
         double2 r;
-        if (s == 0) {
+        if ((s & (Si - 1)) == 0) {
             r.x = s1;
             r.y = s2;
         } else {
@@ -531,13 +535,13 @@ __global__ void __launch_bounds__(kBlock) k_reduce_dots(const double* part, int 
 // frequency whose right-hand side vanishes) gives 0; a vanishing denominator with a
 // nonzero numerator sets *flag (COCG breakdown) and gives 0.
 __global__ void __launch_bounds__(kBlock) k_slot_div(const double* num_, const double* den_, double* coef_, int S,
-                                                     int* flag) {
+                                                     int Si, int* flag) {
     const double2* num = (const double2*)num_;
     const double2* den = (const double2*)den_;
     double2* coef = (double2*)coef_;
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
         double2 a = num[s], b = den[s], r;
-        if (s == 0) {
+        if ((s & (Si - 1)) == 0) {
             r.x = (b.x != 0.0) ? a.x / b.x : 0.0;
             r.y = (b.y != 0.0) ? a.y / b.y : 0.0;
             if (flag && ((b.x == 0.0 && a.x != 0.0) || (b.y == 0.0 && a.y != 0.0))) *flag = 1;
@@ -559,8 +563,8 @@ __global__ void __launch_bounds__(kBlock) k_slot_div(const double* num_, const d
 // ---------------------------------------------------------------- COCG vector updates
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cocg_xr(int S, size_t total, const double* coef, void* x_, void* r_,
-                                                    const void* p_, const void* q_) {
+__global__ void __launch_bounds__(kBlock) k_cocg_xr(int S, int Si, size_t total, const double* coef, void* x_,
+                                                    void* r_, const void* p_, const void* q_) {
     using T2 = typename Vec2<T>::type;
     T2* x = (T2*)x_;
     T2* r = (T2*)r_;
@@ -568,20 +572,21 @@ __global__ void __launch_bounds__(kBlock) k_cocg_xr(int S, size_t total, const d
     const T2* q = (const T2*)q_;
     for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
         int s = (int)(id % S);
-        GS<T> g = gs_from<T>(((const double2*)coef)[s], s == 0);
+        GS<T> g = gs_from<T>(((const double2*)coef)[s], (s & (Si - 1)) == 0);
         x[id] = add2(x[id], gs_apply(g, p[id]));
         r[id] = sub2(r[id], gs_apply(g, q[id]));
     }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cocg_p(int S, size_t total, const double* coef, const void* z_, void* p_) {
+__global__ void __launch_bounds__(kBlock) k_cocg_p(int S, int Si, size_t total, const double* coef, const void* z_,
+                                                   void* p_) {
     using T2 = typename Vec2<T>::type;
     const T2* z = (const T2*)z_;
     T2* p = (T2*)p_;
     for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
         int s = (int)(id % S);
-        GS<T> g = gs_from<T>(((const double2*)coef)[s], s == 0);
+        GS<T> g = gs_from<T>(((const double2*)coef)[s], (s & (Si - 1)) == 0);
         p[id] = add2(z[id], gs_apply(g, p[id]));
     }
 }
@@ -591,8 +596,7 @@ __global__ void __launch_bounds__(kBlock) k_cocg_p(int S, size_t total, const do
 static SlotArgs mk_slot(const Plan& p, char* ws, const Geom& g) {
     SlotArgs sa;
     sa.S = p.S;
-    sa.lgS = 0;
-    while ((1 << sa.lgS) < p.S) ++sa.lgS;
+    sa.ST = p.ST;
     sa.col_groups = g.col_groups;
     sa.rows_per_chunk = g.rows_per_chunk;
     sa.per_step = g.per_step;
@@ -626,7 +630,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
     for (int l = 0; l + 1 < L; ++l) {
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* rout = ws + p.lev[l + 1].off_r;
-        Geom g = slot_geom(p.lev[l + 1].side, p.S, p.target_slot);
+        Geom g = slot_geom(p.lev[l + 1].side, p.ST, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int kid = (l == 0) ? KID_DOWN0 : KID_DOWNC;
@@ -647,11 +651,11 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         tm_end(p, kid, st);
     }
     {
-        Geom g = slot_geom(p.lev[L - 1].side, p.S, p.target_slot);
+        Geom g = slot_geom(p.lev[L - 1].side, p.ST, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         const void* rin = (L == 1) ? r0 : (const void*)(ws + p.lev[L - 1].off_r);
         void* xout = (L == 1) ? x0 : (void*)(ws + p.lev[L - 1].off_x);
-        int grid = (p.S + kBlock - 1) / kBlock;
+        int grid = (p.ST + kBlock - 1) / kBlock;
         tm_begin(p, KID_COARSEST, st);
         if (p.fp32)
             hipLaunchKernelGGL(k_vc_coarsest<float>, dim3(grid), dim3(kBlock), 0, st, sa, host_lv(p, ws, L - 1), rin, xout);
@@ -665,7 +669,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* xout = (l == 0) ? x0 : (void*)(ws + p.lev[l].off_x);
         const void* xc = ws + p.lev[l + 1].off_x;
-        Geom g = slot_geom(p.lev[l].side, p.S, p.target_slot);
+        Geom g = slot_geom(p.lev[l].side, p.ST, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int dm = (l == 0) ? dotmode : DOT_NONE;
@@ -714,39 +718,64 @@ void launch_reduce_dots(const Plan& p, double* part, int dotmode, double* out, h
     // stage 1 into the tail of the partial buffer, then stage 2
     const int nblk = p.g_slot0.blocks;
     const int RB = nblk < kReduceRows ? nblk : kReduceRows;
-    const int SG = p.S < 64 ? p.S : 64;
-    double* part2 = part + (size_t)nblk * p.S * 3;
-    hipLaunchKernelGGL(k_reduce_dots1, dim3(p.S / SG, RB), dim3(kBlock), 0, st, (const double*)part, nblk, p.S, part2);
-    int grid = (p.S + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_reduce_dots, dim3(grid), dim3(kBlock), 0, st, (const double*)part2, RB, p.S,
+    const int SG = p.ST < 64 ? p.ST : 64;
+    double* part2 = part + (size_t)nblk * p.ST * 3;
+    hipLaunchKernelGGL(k_reduce_dots1, dim3((p.ST + SG - 1) / SG, RB), dim3(kBlock), 0, st, (const double*)part, nblk,
+                       p.ST, part2);
+    int grid = (p.ST + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_reduce_dots, dim3(grid), dim3(kBlock), 0, st, (const double*)part2, RB, p.ST, p.S,
                        dotmode == DOT_HERM ? 1 : 0, out);
 }
 
 void launch_slot_div(const Plan& p, const double* num, const double* den, double* coef, int* flag, hipStream_t st) {
-    int grid = (p.S + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_slot_div, dim3(grid), dim3(kBlock), 0, st, num, den, coef, p.S, flag);
+    int grid = (p.ST + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_slot_div, dim3(grid), dim3(kBlock), 0, st, num, den, coef, p.ST, p.S, flag);
 }
 
 void launch_cocg_xr(const Plan& p, const double* coef, void* x, void* r, const void* pv, const void* q,
                     hipStream_t st) {
-    size_t total = p.nodes * (size_t)p.S;
+    size_t total = p.nodes * (size_t)p.ST;
     if (p.fp32)
-        hipLaunchKernelGGL(k_cocg_xr<float>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.S, total, coef, x, r, pv, q);
+        hipLaunchKernelGGL(k_cocg_xr<float>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.ST, p.S, total, coef, x, r,
+                           pv, q);
     else
-        hipLaunchKernelGGL(k_cocg_xr<double>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.S, total, coef, x, r, pv,
-                           q);
+        hipLaunchKernelGGL(k_cocg_xr<double>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.ST, p.S, total, coef, x,
+                           r, pv, q);
 }
 
 void launch_cocg_p(const Plan& p, const double* coef, const void* z, void* pv, hipStream_t st) {
-    size_t total = p.nodes * (size_t)p.S;
+    size_t total = p.nodes * (size_t)p.ST;
     if (p.fp32)
-        hipLaunchKernelGGL(k_cocg_p<float>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.S, total, coef, z, pv);
+        hipLaunchKernelGGL(k_cocg_p<float>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.ST, p.S, total, coef, z, pv);
     else
-        hipLaunchKernelGGL(k_cocg_p<double>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.S, total, coef, z, pv);
+        hipLaunchKernelGGL(k_cocg_p<double>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.ST, p.S, total, coef, z,
+                           pv);
+}
+
+// Plain 16-byte copies and fills as kernels (rather than hipMemcpyAsync / hipMemsetAsync),
+// so that the outer step can be captured into a HIP graph.
+__global__ void __launch_bounds__(kBlock) k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
+    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < n16; id += (size_t)gridDim.x * kBlock)
+        dst[id] = src[id];
+}
+
+__global__ void __launch_bounds__(kBlock) k_zero16(uint4* __restrict__ dst, size_t n16) {
+    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < n16; id += (size_t)gridDim.x * kBlock)
+        dst[id] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+void launch_copy16(const void* src, void* dst, size_t bytes, hipStream_t st) {
+    size_t n16 = bytes / 16;
+    hipLaunchKernelGGL(k_copy16, dim3(flat_grid(n16)), dim3(kBlock), 0, st, (const uint4*)src, (uint4*)dst, n16);
+}
+
+void launch_zero16(void* dst, size_t bytes, hipStream_t st) {
+    size_t n16 = bytes / 16;
+    hipLaunchKernelGGL(k_zero16, dim3(flat_grid(n16)), dim3(kBlock), 0, st, (uint4*)dst, n16);
 }
 
 void launch_copy_slots(const Plan& p, const void* src, void* dst, hipStream_t st) {
-    hipMemcpyAsync(dst, src, p.nodes * (size_t)p.S * p.elem, hipMemcpyDeviceToDevice, st);
+    launch_copy16(src, dst, p.nodes * (size_t)p.ST * p.elem, st);
 }
 
 }  // namespace pt

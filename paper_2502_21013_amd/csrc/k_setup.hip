@@ -144,21 +144,26 @@ static int grid_for(size_t items) {
 }
 
 void launch_setup_fine(const Plan& p, char* ws, hipStream_t st) {
-    SetupArgs a;
-    a.n = p.n;
-    a.side = p.side;
-    a.h = p.h;
-    a.sig = p.prob.sigma_rect;
-    a.nu = p.prob.nu_rect;
-    a.coil = p.prob.coil_rect;
-    a.sigma_in = p.prob.sigma_in;
-    a.J0 = p.prob.J0;
-    a.d_sigma = p.prob.d_sigma;
-    a.flags = (uint8_t*)(ws + p.off_flags);
-    a.mt = (double*)(ws + p.lev[0].off_mt);
-    a.b = (double*)(ws + p.off_b);
-    hipLaunchKernelGGL(k_tri_flags, dim3(grid_for(2 * (size_t)p.n * p.n)), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_fine_node, dim3(grid_for(p.nodes)), dim3(kBlock), 0, st, a);
+    // one pass per batch instance: the iron flags and the load are the instance's own, the
+    // mass stencil (shared conductivity) is the same for all and rewritten each time
+    for (int inst = 0; inst < p.B; ++inst) {
+        const pt_problem& q = p.probs[inst];
+        SetupArgs a;
+        a.n = p.n;
+        a.side = p.side;
+        a.h = p.h;
+        a.sig = q.sigma_rect;
+        a.nu = q.nu_rect;
+        a.coil = q.coil_rect;
+        a.sigma_in = q.sigma_in;
+        a.J0 = q.J0;
+        a.d_sigma = q.d_sigma;
+        a.flags = (uint8_t*)(ws + p.off_flags) + (size_t)inst * 2 * p.n * p.n;
+        a.mt = (double*)(ws + p.lev[0].off_mt);
+        a.b = (double*)(ws + p.off_b) + (size_t)inst * p.nodes;
+        hipLaunchKernelGGL(k_tri_flags, dim3(grid_for(2 * (size_t)p.n * p.n)), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_fine_node, dim3(grid_for(p.nodes)), dim3(kBlock), 0, st, a);
+    }
 }
 
 void launch_galerkin(const Plan& p, char* ws, int l, hipStream_t st) {

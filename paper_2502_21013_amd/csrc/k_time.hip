@@ -75,9 +75,11 @@ __device__ T2* fft_team(T2* a, T2* b, int S, int lt, int TS, const T2* __restric
 
 struct FwdArgs {
     int n, side, N, S, lgS, ts, nb, col_groups, rows_per_chunk, remap, mode;
+    int B, ST;             // instances in the batch, slots per node over all instances
     size_t nodes;
     double inv_tau, n2;
     double nu_a, nu_b, nu_out;
+    const double* inst;    // [B][4] per-instance nu_a, nu_b, nu_out (batch); null for one instance
     const double* U;       // [nodes][N]
     const double* F;       // [nodes][N] explicit load or null
     const double* bload;   // [nodes]
@@ -228,19 +230,31 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
     const long S_ = S;
     double rr = 0.0, ff = 0.0;
     const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, side);
-    int i = sr.col0 + team;
-    if (UNI) i = __builtin_amdgcn_readfirstlane(i);
-    const bool colvalid = i < side, colint = i > 0 && i < n;
+    // virtual column vcol = b (n+1) + i: grid column i of batch instance b
+    int vcol = sr.col0 + team;
+    if (UNI) vcol = __builtin_amdgcn_readfirstlane(vcol);
+    const int bi = vcol / side;
+    const int i = vcol - bi * side;
+    const bool colvalid = vcol < side * a.B, colint = colvalid && i > 0 && i < n;
+    FwdArgs ai = a;   // this instance's material parameters
+    if (a.inst && colvalid) {
+        ai.nu_a = a.inst[4 * bi];
+        ai.nu_b = a.inst[4 * bi + 1];
+        ai.nu_out = a.inst[4 * bi + 2];
+        ai.flags = a.flags + (size_t)bi * 2 * a.n * a.n;
+        ai.bload = a.bload + (size_t)bi * a.nodes;
+        ai.wave = a.wave + (size_t)bi * a.N;
+    }
     Win v[KP][2];
-    // uniform row base + per-lane byte offset of (column i-1+d, pair lt + TS k)
-    const int lgS = a.lgS;
+    // uniform row base + per-lane byte offset of (column i-1+d, instance bi, pair lt + TS k)
+    const int STp = a.ST;  // time pairs per node over all instances (= slots per node)
     unsigned ofs[3][KP];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int k = 0; k < KP; ++k)
-            ofs[d][k] = ((((unsigned)(i - 1 + d)) << lgS) + (unsigned)(lt + TS * k)) * (unsigned)sizeof(double2);
-    auto rowU = [&](int cj) { return U2 + ((size_t)(cj * side) << lgS); };
+            ofs[d][k] = ((unsigned)(i - 1 + d) * STp + (unsigned)(bi * S + lt + TS * k)) * (unsigned)sizeof(double2);
+    auto rowU = [&](int cj) { return U2 + (size_t)(cj * side) * STp; };
     auto ldd = [&](int d, int cj, int k) -> double2 {
         if (cj < 0 || cj > n) return make_double2(0.0, 0.0);
         return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(rowU(cj)) + ofs[d][k]);
@@ -251,8 +265,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
     if (a.mode == TM_RESIDUAL && colint && jin < sr.row1 && jin < n) {
         bool ir_s[2], ir_sw[2];
         double th_s[2], th_sw[2];
-        cell_mat(a, i, jin - 1, ir_s, th_s);
-        cell_mat(a, i - 1, jin - 1, ir_sw, th_sw);
+        cell_mat(ai, i, jin - 1, ir_s, th_s);
+        cell_mat(ai, i - 1, jin - 1, ir_sw, th_sw);
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             double2 sw = ld(i - 1, jin - 1, k), s_ = ld(i, jin - 1, k), w = ld(i - 1, jin, k), c = ld(i, jin, k),
@@ -260,8 +274,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                     ne = ld(i + 1, jin + 1, k);
             v[k][0] = Win{sw.x, s_.x, w.x, c.x, e.x, nw.x, nn.x, ne.x, 0.0};
             v[k][1] = Win{sw.y, s_.y, w.y, c.y, e.y, nw.y, nn.y, ne.y, 0.0};
-            v[k][0].carry = lower_three(a, v[k][0], ir_s, th_s, ir_sw, th_sw);
-            v[k][1].carry = lower_three(a, v[k][1], ir_s, th_s, ir_sw, th_sw);
+            v[k][0].carry = lower_three(ai, v[k][0], ir_s, th_s, ir_sw, th_sw);
+            v[k][1].carry = lower_three(ai, v[k][1], ir_s, th_s, ir_sw, th_sw);
         }
     }
     for (int jb = sr.row0; jb < sr.row1; jb += RB) {
@@ -292,8 +306,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                 }
                 bool ir_c[2], ir_w[2];
                 double th_c[2], th_w[2];
-                cell_mat(a, i, j, ir_c, th_c);
-                cell_mat(a, i - 1, j, ir_w, th_w);
+                cell_mat(ai, i, j, ir_c, th_c);
+                cell_mat(ai, i - 1, j, ir_w, th_w);
                 const size_t nodes = a.nodes;
                 const long sd = side;
                 const double mc = a.mt[node], mE = a.mt[nodes + node], mW = a.mt[nodes + node - 1],
@@ -302,15 +316,15 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                 const bool mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) ||
                                   (mNE != 0.0) || (mSW != 0.0);
                 if (mass) mass_bits |= 1u << q;
-                const double bl = a.bload[node];
-                const double2* w2 = (const double2*)a.wave;
+                const double bl = ai.bload[node];
+                const double2* w2 = (const double2*)ai.wave;
                 const double2* F2 = (const double2*)a.F;
                 double cu[KP][2];
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     const int m = lt + TS * k;
-                    double K0 = upper_four(a, v[k][0], ir_c, th_c, ir_w, th_w, cu[k][0]);
-                    double K1 = upper_four(a, v[k][1], ir_c, th_c, ir_w, th_w, cu[k][1]);
+                    double K0 = upper_four(ai, v[k][0], ir_c, th_c, ir_w, th_w, cu[k][0]);
+                    double K1 = upper_four(ai, v[k][1], ir_c, th_c, ir_w, th_w, cu[k][1]);
                     double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * w2[m].x, bl * w2[m].y);
                     ff += f.x * f.x + f.y * f.y;
                     r[k] = make_double2(f.x - K0, f.y - K1);
@@ -342,7 +356,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                 }
             } else if (interior) {  // TM_SIGNAL: the field itself
 #pragma unroll
-                for (int k = 0; k < KP; ++k) r[k] = U2[(long)node * S_ + lt + TS * k];
+                for (int k = 0; k < KP; ++k) r[k] = U2[(long)node * STp + bi * S + lt + TS * k];
             }
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
@@ -372,27 +386,29 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                     rv.y -= (muo - mue) * a.inv_tau;
                 }
                 if (interior) rr += rv.x * rv.x + rv.y * rv.y;
-                if (a.rout) ((double2*)a.rout)[(long)node * S_ + m] = rv;
-                if (rt) rt[(long)node * S_ + m] = mk2<T>((T)rv.x, (T)rv.y);
+                if (a.rout) ((double2*)a.rout)[(long)node * STp + bi * S + m] = rv;
+                if (rt) rt[(long)node * STp + bi * S + m] = mk2<T>((T)rv.x, (T)rv.y);
             }
         }
         __syncthreads();
     }
-    // workgroup reduction of the norm partials (fixed order)
+    // per-team reduction of the norm partials (fixed order): part[(vb nb + team) 2 + {0, 1}]
+    // with vb the virtual workgroup index (column group vb % col_groups)
     __shared__ double red[2][kBlock];
     red[0][threadIdx.x] = rr;
     red[1][threadIdx.x] = ff;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w && (int)(threadIdx.x + w) < (int)blockDim.x) {
+    for (int w = TS / 2; w > 0; w >>= 1) {
+        if (lt < w) {
             red[0][threadIdx.x] += red[0][threadIdx.x + w];
             red[1][threadIdx.x] += red[1][threadIdx.x + w];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && a.part) {
-        a.part[2 * blockIdx.x] = red[0][0];
-        a.part[2 * blockIdx.x + 1] = red[1][0];
+    if (lt == 0 && a.part) {
+        const size_t o = ((size_t)vb * a.nb + team) * 2;
+        a.part[o] = red[0][threadIdx.x];
+        a.part[o + 1] = red[1][threadIdx.x];
     }
 }
 
@@ -400,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
 // the half-length complex FFT of z_m = x_{2m} + i x_{2m+1} and the split into X_k
 // (remark rem:parallel). Team of S/4 threads per node.
 struct RfftArgs {
-    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap;
+    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, B, ST;
     const void* rt;   // T2 [nodes][S]
     const void* tw;   // T2 [N]
     void* out;        // T2 [nodes][S]
@@ -419,15 +435,16 @@ __global__ void __launch_bounds__(kBlock) k_rfft(RfftArgs a) {
     const T2* rt = (const T2*)a.rt;
     const int vb = virtual_block(a.remap);
     const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, a.side);
-    const int i = sr.col0 + team;
-    const bool colvalid = i < a.side;
+    const int vcol = sr.col0 + team;  // b (n+1) + i
+    const bool colvalid = vcol < a.side * a.B;
+    const int bi = vcol / a.side, i = vcol - bi * a.side;
     for (int j = sr.row0; j < sr.row1; ++j) {
-        const size_t node = colvalid ? (size_t)j * a.side + i : 0;
-        for (int m = lt; m < S; m += TS) buf0[m] = colvalid ? rt[node * S + m] : mk2<T>(0, 0);
+        const size_t chunk = colvalid ? ((size_t)j * a.side + i) * a.ST + (size_t)bi * S : 0;
+        for (int m = lt; m < S; m += TS) buf0[m] = colvalid ? rt[chunk + m] : mk2<T>(0, 0);
         __syncthreads();
         T2* res = fft_team<T2>(buf0, buf1, S, lt, TS, tw);
         if (colvalid) {
-            T2* out = (T2*)a.out + node * S;
+            T2* out = (T2*)a.out + chunk;
             for (int k = lt; k < S; k += TS) {
                 T2 X;
                 if (k == 0) {
@@ -455,6 +472,9 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.S = p.S;
     a.lgS = 0;
     while ((1 << a.lgS) < p.S) ++a.lgS;
+    a.B = p.B;
+    a.ST = p.ST;
+    a.inst = p.B > 1 ? (const double*)(ws + p.off_inst) : nullptr;
     a.remap = p.opt.xcd_remap;
     a.mode = mode;
     a.nodes = p.nodes;
@@ -512,6 +532,8 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     b.col_groups = g.col_groups;
     b.rows_per_chunk = g.rows_per_chunk;
     b.remap = p.opt.xcd_remap;
+    b.B = p.B;
+    b.ST = p.ST;
     b.rt = rt;
     b.tw = a.tw;
     b.out = out;
@@ -527,12 +549,19 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
 
 // ---------------------------------------------------------------- norm reduction
 
-__global__ void __launch_bounds__(kBlock) k_reduce_norms(const double* part, int nparts, double* out2) {
+// Norm partials of the residual sweep: partial p belongs to virtual workgroup p / nb, team
+// p % nb, i.e. virtual column ((p / nb) % col_groups) nb + p % nb; workgroup x = instance b sums
+// the partials of its columns in a fixed order into out2[2 b], out2[2 b + 1].
+__global__ void __launch_bounds__(kBlock) k_reduce_norms(const double* part, int nparts, int nb, int col_groups,
+                                                         int side, double* out2) {
     __shared__ double red[2][kBlock];
+    const int b = blockIdx.x;
     double s0 = 0, s1 = 0;
-    for (int b = threadIdx.x; b < nparts; b += kBlock) {
-        s0 += part[2 * b];
-        s1 += part[2 * b + 1];
+    for (int q = threadIdx.x; q < nparts; q += kBlock) {
+        const int vcol = ((q / nb) % col_groups) * nb + q % nb;
+        if (vcol / side != b) continue;
+        s0 += part[2 * q];
+        s1 += part[2 * q + 1];
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;
@@ -545,21 +574,22 @@ __global__ void __launch_bounds__(kBlock) k_reduce_norms(const double* part, int
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out2[0] = red[0][0];
-        out2[1] = red[1][0];
+        out2[2 * b] = red[0][0];
+        out2[2 * b + 1] = red[1][0];
     }
 }
 
 void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, double* out2, hipStream_t st) {
-    (void)p;
     (void)ws;
-    hipLaunchKernelGGL(k_reduce_norms, dim3(1), dim3(kBlock), 0, st, (const double*)part, nparts, out2);
+    const Geom& g = p.g_fwd;
+    hipLaunchKernelGGL(k_reduce_norms, dim3(p.B), dim3(kBlock), 0, st, (const double*)part, nparts * g.per_step,
+                       g.per_step, g.col_groups, p.side, out2);
 }
 
 // ---------------------------------------------------------------- inverse kernel
 
 struct InvArgs {
-    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, accumulate;
+    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, accumulate, B, ST;
     size_t nodes;
     const void* xhat;     // T2 [nodes][S]
     const double* coef;   // double2 [S] generic scalars or null
@@ -580,18 +610,20 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
     const T invS = (T)1 / (T)S;
     const int vb = virtual_block(a.remap);
     const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, a.side);
-    const int i = sr.col0 + team;
+    const int vcol = sr.col0 + team;  // b (n+1) + i
+    const bool valid = vcol < a.side * a.B;
+    const int bi = vcol / a.side, i = vcol - bi * a.side;
     for (int j = sr.row0; j < sr.row1; ++j) {
-        bool valid = i < a.side;
         size_t node = valid ? (size_t)j * a.side + i : 0;
         bool interior = valid && i > 0 && j > 0 && i < a.n && j < a.n;
-        const T2* x = (const T2*)a.xhat + node * S;
+        const size_t chunk = node * a.ST + (size_t)bi * S;  // slot / time-pair offset of (node, instance)
+        const T2* x = (const T2*)a.xhat + chunk;
         for (int k = lt; k < S; k += TS) {
             T2 v = mk2<T>(0, 0);
             if (interior) {
                 v = x[k];
                 if (a.coef) {
-                    double2 c = ((const double2*)a.coef)[k];
+                    double2 c = ((const double2*)a.coef)[bi * S + k];
                     v = gs_apply(gs_from<T>(c, k == 0), v);
                 }
             }
@@ -614,7 +646,7 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
         __syncthreads();
         T2* res = fft_team<T2>(buf1, buf0, S, lt, TS, tw);
         if (interior) {
-            double2* u2 = (double2*)(a.U + node * N);
+            double2* u2 = (double2*)a.U + chunk;
             for (int m = lt; m < S; m += TS) {
                 T2 z = res[m];
                 double x0 = (double)(z.x * invS), x1 = (double)(-z.y * invS);
@@ -630,7 +662,7 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
                 u2[m] = o;
             }
         } else if (valid && !a.accumulate) {
-            double2* u2 = (double2*)(a.U + node * N);
+            double2* u2 = (double2*)a.U + chunk;
             for (int m = lt; m < S; m += TS) u2[m] = make_double2(0.0, 0.0);
         }
         __syncthreads();
@@ -651,6 +683,8 @@ void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coe
     a.rows_per_chunk = g.rows_per_chunk;
     a.remap = p.opt.xcd_remap;
     a.accumulate = accumulate;
+    a.B = p.B;
+    a.ST = p.ST;
     a.nodes = p.nodes;
     a.xhat = xhat;
     a.coef = coef;
@@ -698,13 +732,13 @@ static unsigned transpose_grid(size_t rows, size_t cols) {
 }
 
 void launch_transpose_in(const Plan& p, const double* src, double* dst, hipStream_t st) {
-    size_t rows = p.N, cols = p.nodes;
+    size_t rows = (size_t)p.B * p.N, cols = p.nodes;
     hipLaunchKernelGGL(k_transpose, dim3(transpose_grid(rows, cols)), dim3(kBlock), 0, st, src, dst, rows, cols,
                        p.n, 0);
 }
 
 void launch_transpose_out(const Plan& p, const double* src, double* dst, hipStream_t st) {
-    size_t rows = p.nodes, cols = p.N;
+    size_t rows = p.nodes, cols = (size_t)p.B * p.N;
     hipLaunchKernelGGL(k_transpose, dim3(transpose_grid(rows, cols)), dim3(kBlock), 0, st, src, dst, rows, cols,
                        p.n, 1);
 }

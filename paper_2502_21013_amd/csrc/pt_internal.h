@@ -89,9 +89,12 @@ void tm_begin(const struct Plan& p, int kid, hipStream_t st);
 void tm_end(const struct Plan& p, int kid, hipStream_t st);
 
 struct Plan {
-    pt_problem prob;
+    pt_problem prob;     // instance 0 (the shared grid, period, conductivity and nu_max)
     pt_options opt;
+    int B;               // instances in the batch (power of two; 1 for a single problem)
+    pt_problem* probs;   // host copy of the B instances
     int n, N, S, side;
+    int ST;              // slots (and time pairs) per node over all instances: B S
     size_t nodes;
     bool fp32;
     size_t elem;        // bytes per slot value (16 or 8)
@@ -101,25 +104,31 @@ struct Plan {
     // workspace offsets (bytes)
     size_t off_U, off_F, off_P, off_cx, off_cr, off_cq, off_cp;
     size_t off_flags, off_b, off_tw64, off_tw32, off_zs, off_wave;
-    size_t off_part, part_bytes, off_scal, off_coef, off_coef2, off_hist;
+    size_t off_part, part_bytes, off_scal, off_flag, off_coef, off_coef2, off_hist, off_inst;
     size_t ws_bytes;
     bool has_cocg_vectors;
     // host copies of the small tables uploaded at every call
     double* h_tw64;     // N complex: exp(-2 pi i k / N)
     float* h_tw32;      // N complex, float
-    double* h_zs;       // S x 3: generic (a, b, c) of the shift z_s
-    double* h_wave;     // N: w(2 pi t_{j+1} / T)
+    double* h_zs;       // ST x 3: generic (a, b, c) of the shift z_s, repeated per instance
+    double* h_wave;     // B x N: w(2 pi t_{j+1} / T) of each instance
+    double* h_inst;     // B x 4: nu_a, nu_b, nu_out, 0 of each instance
     int target_slot, target_team;  // grid targets of the slot-vector and per-node kernels
     Geom g_slot0;       // slot-vector kernels on level 0
     Geom g_team;        // per-node team kernels (inverse DFT)
     Geom g_fwd;         // residual sweep (team of min(S, 256) threads per column)
     Timer* tm;          // per-kernel event timer (owned by the plan)
+    struct GraphCache* gr;  // captured outer steps (owned by the plan)
 };
 
-// target = number of workgroups (per slot chunk) the sweeping kernels aim for
+void graph_release(Plan& p);
+
+// target = number of workgroups (per slot chunk) the sweeping kernels aim for. The
+// per-node team kernels sweep B (n+1) virtual columns (instance b, grid column i at
+// b (n+1) + i) over n+1 rows.
 Geom slot_geom(int side, int S, int target);
-Geom team_geom(int side, int S, int target);
-Geom fwd_geom(int side, int S, int target);
+Geom team_geom(int side, int S, int B, int target);
+Geom fwd_geom(int side, int S, int B, int target);
 
 // ---------------------------------------------------------------- launchers
 // setup (k_setup.hip)
@@ -158,5 +167,8 @@ void launch_cocg_xr(const Plan& p, const double* coef, void* x, void* r, const v
 // p = z + b (x) p
 void launch_cocg_p(const Plan& p, const double* coef, const void* z, void* pv, hipStream_t st);
 void launch_copy_slots(const Plan& p, const void* src, void* dst, hipStream_t st);
+// byte counts are multiples of 16, pointers 16-byte aligned
+void launch_copy16(const void* src, void* dst, size_t bytes, hipStream_t st);
+void launch_zero16(void* dst, size_t bytes, hipStream_t st);
 
 }  // namespace pt

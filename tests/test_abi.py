@@ -111,3 +111,59 @@ def test_workspace_checks_happen_before_any_launch(P):
     st = lib.pt_solve(plan._h, C.c_void_p(0x1000), plan.workspace_bytes - 1, dummy, None, None)
     assert st == L.PT_ERR_WORKSPACE
     assert b"too small" in lib.pt_last_error()
+
+
+def _batch_structs(P, ps):
+    from paper_2502_21013_amd import _lib as L
+    return (L.Problem * len(ps))(*[P.problem_struct(p) for p in ps])
+
+
+def test_batch_plan_validation(P):
+    import dataclasses
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    o = L.Options()
+    lib.pt_options_default(C.byref(o))
+    h = C.c_void_p()
+    base = [W.with_size(p, 16, 16) for p in W.config4(0, 4)]
+    assert lib.pt_plan_create_batch(_batch_structs(P, base), 4, C.byref(o), C.byref(h)) == L.PT_OK
+    cnt = C.c_int32()
+    assert lib.pt_plan_batch_size(h, C.byref(cnt)) == L.PT_OK and cnt.value == 4
+    nb4 = C.c_size_t()
+    lib.pt_plan_workspace_bytes(h, C.byref(nb4))
+    lib.pt_plan_destroy(h)
+    one = P.Plan(base[0]).workspace_bytes
+    assert 3 * one < nb4.value < 5 * one
+    # count not a power of two
+    assert lib.pt_plan_create_batch(_batch_structs(P, base[:3]), 3, C.byref(o), C.byref(h)) == L.PT_ERR_INVALID
+    # grid, period and conductivity must be shared
+    for change in [dict(n=32), dict(N=32), dict(T=2.0), dict(sigma_in=2.0), dict(nu_max=12.0)]:
+        bad = list(base)
+        bad[3] = dataclasses.replace(bad[3], **change)
+        assert lib.pt_plan_create_batch(_batch_structs(P, bad), 4, C.byref(o), C.byref(h)) == L.PT_ERR_INVALID
+        assert b"share" in lib.pt_last_error()
+    # device tables are single-problem only
+    s = _batch_structs(P, base[:2])
+    s[1].d_load = 0x1000
+    assert lib.pt_plan_create_batch(s, 2, C.byref(o), C.byref(h)) == L.PT_ERR_INVALID
+    # one invalid member names its index
+    bad = list(base[:2])
+    bad[1] = dataclasses.replace(bad[1], nu_a=-1.0)
+    assert lib.pt_plan_create_batch(_batch_structs(P, bad), 2, C.byref(o), C.byref(h)) == L.PT_ERR_INVALID
+    assert b"instance 1" in lib.pt_last_error()
+
+
+def test_batch_plan_rejects_single_entry_points(P):
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    bp = P.BatchPlan([W.with_size(p, 8, 8) for p in W.config4(1, 2)])
+    dummy = C.c_void_p(0x1000)
+    assert lib.pt_solve(bp._h, dummy, bp.workspace_bytes, dummy, None, None) == L.PT_ERR_INVALID
+    assert lib.pt_residual(bp._h, dummy, bp.workspace_bytes, dummy, dummy, None, None, None) == L.PT_ERR_INVALID
+    with pytest.raises(TypeError):
+        bp.apply_K(None)
+
+
+def test_graph_and_timing_are_exclusive(P):
+    with pytest.raises(P.PTError):
+        P.Plan(W.config1(), graph=True, timing=True)
