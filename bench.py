@@ -16,7 +16,13 @@ Per-kernel durations come from HIP events that the library records around every 
 the solve stream over the timed region; the roofline entry uses the dominant kernel.
 The CPU baseline is the FP64 oracle on a bounded sample of the same workload family.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1]
+Batching workload (--workload c4): the 64 seeded instances of uneven grid and period
+(n in {64,128,256,512}, N in {64,128,256}, J0 and iron corners seeded), grouped into batch
+plans and solved by the concurrent work-list runner with graph replay; one step solves
+all 64 to 1e-8. It is compared with the plain FP64 path (each instance alone, one after
+the other, eager launches).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c4]
 """
 from __future__ import annotations
 
@@ -46,6 +52,84 @@ def workload(name, seed):
     if name == "c1":
         return W.config1(), "32x32 cells, N=32"
     raise SystemExit(f"unknown workload {name}")
+
+
+def run_many(P, problems, mode, steps, warmup, tol, nstreams, graph, tuning):
+    import torch
+    from paper_2502_21013_amd.batch import ManySolver
+    ms = ManySolver(problems, precision=mode, tol=tol, max_outer=2000, graph=graph, nstreams=nstreams,
+                    tuning=tuning)
+    for w in range(warmup):
+        r = ms.solve()
+        log(f"{mode} many warmup {w}: {len(ms.plans)} plans, max outer "
+            f"{max(s.outer_iters for s in r.stats)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        r = ms.solve()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"ms_per_step": 1e3 * wall / steps, "plans": len(ms.plans),
+           "batch_sizes": [len(b) for b in ms.batches],
+           "outer_iters_max": max(s.outer_iters for s in r.stats),
+           "rel_residual_max": max(s.rel_residual for s in r.stats)}
+    ms.close()
+    del ms
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_plain_each(P, problems, tol):
+    """The plain FP64 path: each instance alone, eager launches, one after the other."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outer = []
+    for p in problems:
+        plan = P.Plan(p, tol=tol, precision="fp64", max_outer=2000)
+        _, st = plan.solve()
+        outer.append(st.outer_iters)
+        plan.close()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    return {"ms_per_step": 1e3 * wall, "outer_iters_max": max(outer)}
+
+
+def main_many(args, P):
+    import workloads as W
+    from paper_2502_21013_amd import autotune as AT
+    problems = W.config4(args.seed)
+    total = sum(p.st_dofs for p in problems)
+    log(f"workload c4: {len(problems)} instances, {total} space-time DoFs in total")
+    tuning = AT.load_table(args.tuning) if args.tuning else None
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    res = {m: run_many(P, problems, m, args.steps, args.warmup, args.tol, args.streams, not args.no_graph, tuning)
+           for m in modes}
+    for m in modes:
+        log(f"{m}: {res[m]['ms_per_step']:.1f} ms for all instances")
+    plain = None
+    if not args.no_plain:
+        log("plain FP64 path, instance by instance")
+        plain = run_plain_each(P, problems, args.tol)
+        log(f"plain fp64: {plain['ms_per_step']:.1f} ms")
+    r0 = res[modes[0]]
+    out = {
+        "metric": "space-time DoFs/s to rel. residual 1e-8 (FP32+refine vs FP64); % HBM peak",
+        "value": total / (r0["ms_per_step"] * 1e-3),
+        "unit": "space-time DoFs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r0["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if modes[0] == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "batching: 64 seeded instances, n in {64,128,256,512}, N in {64,128,256}",
+                   "seed": args.seed, "st_dofs": total, "tol": args.tol, "streams": args.streams,
+                   "graph": not args.no_graph, "tuned": bool(tuning)},
+        "roofline": None,
+        "cpu_baseline": None,
+        "modes": {m: dict(res[m], value=total / (res[m]["ms_per_step"] * 1e-3)) for m in modes},
+        "plain_fp64_each": None if plain is None else dict(plain, value=total / (plain["ms_per_step"] * 1e-3)),
+    }
+    print(json.dumps(out), flush=True)
 
 
 def algorithmic_bytes(p, elem):
@@ -156,6 +240,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--modes", default="fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--streams", type=int, default=4, help="c4: host threads / HIP streams of the work list")
+    ap.add_argument("--no-graph", action="store_true", help="c4: eager launches instead of graph replay")
+    ap.add_argument("--no-plain", action="store_true", help="c4: skip the instance-by-instance FP64 run")
+    ap.add_argument("--tuning", default="", help="c4: autotuner table (JSON) to apply")
     ap.add_argument("--max-outer", type=int, default=2000,
                     help="cap on outer steps per solve; below the count needed for 1e-8 the run is a "
                          "profiling run (marked in the output), not a metric measurement")
@@ -170,6 +258,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     P.library()
+    if args.workload == "c4":
+        main_many(args, P)
+        return
     prob, desc = workload(args.workload, args.seed)
     log(f"workload {args.workload}: {desc}, {prob.st_dofs} space-time DoFs")
 

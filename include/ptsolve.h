@@ -112,6 +112,10 @@ typedef struct {
     int32_t xcd_remap;     /* 1: map workgroups to contiguous node ranges per XCD */
     int32_t timing;        /* 1: bracket every kernel launch of pt_solve with HIP events on
                               the solve stream and report per-kernel device time in pt_stats */
+    int32_t grid_slot;     /* workgroups the slot-vector sweeps (V-cycle, operator) aim for
+                              per slot chunk; 0 = 2048. Performance only (>= 8). */
+    int32_t grid_team;     /* workgroups the per-node time-axis sweeps (DFT, inverse DFT)
+                              aim for; 0 = 16384. Performance only (>= 8). */
     int32_t graph;         /* 1: capture the kernels of check_every outer steps into a HIP
                               graph on the first call (per plan and workspace address) and
                               replay it; same iterates as 0. Cannot be combined with timing. */
@@ -138,7 +142,7 @@ typedef struct pt_plan pt_plan;
 
 /* Fill *o with the defaults (tol 1e-8, max_outer 1000, check_every 1, FP64,
  * PT_INNER_GALERKIN1, inner_iters 1, vc_sweeps 1, vc_omega 0.8, no initial guess,
- * diverge_factor 1e3, xcd_remap 1, timing 0). */
+ * diverge_factor 1e3, xcd_remap 1, timing 0, default grid targets, graph 0). */
 void pt_options_default(pt_options* o);
 
 /* Validate the problem and options (host only, no device work) and create a plan. */
@@ -178,6 +182,18 @@ pt_status pt_plan_batch_size(const pt_plan* plan, int32_t* count);
  * point below requires a single-problem plan. Blocks until the stream has finished. */
 pt_status pt_solve_batch(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream,
                          pt_stats* stats);
+
+/* Work-list solve of several plans (single or batch) at once, for many problems of
+ * uneven size: nstreams host threads each own streams[w] (NULL: all on the null
+ * stream) and repeatedly take the next unclaimed plan, in the order given, and run
+ * pt_solve_batch on it, so that the kernels of different plans overlap on the device.
+ * Plan i uses d_ws[i] (ws_bytes[i]) and d_u[i]; stats[i] is NULL or its stats array;
+ * status[i] receives its status. A plan may appear only once. Returns PT_OK if every
+ * plan returned PT_OK, else the status of the first failing item (pt_last_error names
+ * it). Blocks until all are done. 1 <= nstreams <= 64. */
+pt_status pt_solve_many(int32_t count, pt_plan* const* plans, void* const* d_ws,
+                        const size_t* ws_bytes, double* const* d_u, pt_stats* const* stats,
+                        pt_status* status, void* const* streams, int32_t nstreams);
 
 /* R = F - A(U) (eq. (disc1) moved to one side, u^0 = u^N) on every slice; d_r has
  * the time-field layout, boundary entries 0. rel_out / fnorm_out (host, may be NULL)

@@ -76,7 +76,7 @@ class SolveStats:
 
 
 def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega, use_initial_guess,
-             diverge_factor, xcd_remap, timing, graph) -> L.Options:
+             diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0) -> L.Options:
     o = L.Options()
     lib.pt_options_default(C.byref(o))
     o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
@@ -87,6 +87,7 @@ def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc
     o.diverge_factor, o.xcd_remap = float(diverge_factor), 1 if xcd_remap else 0
     o.timing = 1 if timing else 0
     o.graph = 1 if graph else 0
+    o.grid_slot, o.grid_team = int(grid_slot), int(grid_team)
     return o
 
 
@@ -120,8 +121,8 @@ class Plan:
 
     def __init__(self, problem, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
-                 diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, theta=None, sigma=None,
-                 load=None, device=None):
+                 diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
+                 theta=None, sigma=None, load=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -132,7 +133,7 @@ class Plan:
         self._keep = (theta, sigma, load)  # device tables must outlive the plan's calls
         self._ps = problem_struct(problem, theta, sigma, load)
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
-                     use_initial_guess, diverge_factor, xcd_remap, timing, graph)
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -273,7 +274,8 @@ class BatchPlan(Plan):
 
     def __init__(self, problems, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
-                 diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, device=None):
+                 diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
+                 device=None):
         import torch
         problems = list(problems)
         self.lib = L.load()
@@ -287,7 +289,7 @@ class BatchPlan(Plan):
         self._keep = ()
         self._pa = (L.Problem * self.count)(*[problem_struct(p) for p in problems])
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
-                     use_initial_guess, diverge_factor, xcd_remap, timing, graph)
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create_batch(self._pa, self.count, C.byref(o), C.byref(h))

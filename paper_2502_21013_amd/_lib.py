@@ -45,7 +45,7 @@ class Options(C.Structure):
         ("precision", C.c_int32), ("inner", C.c_int32), ("inner_iters", C.c_int32),
         ("vc_sweeps", C.c_int32), ("vc_omega", C.c_double), ("use_initial_guess", C.c_int32),
         ("diverge_factor", C.c_double), ("xcd_remap", C.c_int32), ("timing", C.c_int32),
-        ("graph", C.c_int32),
+        ("grid_slot", C.c_int32), ("grid_team", C.c_int32), ("graph", C.c_int32),
     ]
 
 
@@ -84,6 +84,9 @@ def load():
         "pt_plan_create_batch": (i32, [C.POINTER(Problem), i32, C.POINTER(Options), pplan]),
         "pt_plan_batch_size": (i32, [vp, C.POINTER(C.c_int32)]),
         "pt_solve_batch": (i32, [vp, vp, sz, vp, vp, C.POINTER(Stats)]),
+        "pt_solve_many": (i32, [i32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_size_t),
+                                C.POINTER(C.c_void_p), C.POINTER(C.POINTER(Stats)), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_void_p), i32]),
         "pt_residual": (i32, [vp, vp, sz, vp, vp, vp, dp, dp]),
         "pt_apply_K": (i32, [vp, vp, sz, vp, vp, i32, vp]),
         "pt_time_rfft": (i32, [vp, vp, sz, vp, vp, vp]),

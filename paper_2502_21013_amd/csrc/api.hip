@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cstring>
 #include <new>
 #include <string>
@@ -143,6 +145,9 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (o->inner_iters < 1 || o->inner_iters > 64) return fail(PT_ERR_INVALID, "inner_iters must be in [1, 64]");
     if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused V(1,1) cycle)");
     if (!(o->vc_omega > 0 && o->vc_omega < 1)) return fail(PT_ERR_INVALID, "vc_omega must be in (0, 1)");
+    if (o->grid_slot < 0 || (o->grid_slot > 0 && o->grid_slot < 8) || o->grid_slot > (1 << 22) || o->grid_team < 0 ||
+        (o->grid_team > 0 && o->grid_team < 8) || o->grid_team > (1 << 22))
+        return fail(PT_ERR_INVALID, "grid_slot and grid_team must be 0 or in [8, 4194304]");
     if (!(o->diverge_factor >= 0) || !std::isfinite(o->diverge_factor))
         return fail(PT_ERR_INVALID, "diverge_factor must be >= 0");
     return PT_OK;
@@ -653,11 +658,8 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     }
     p.tm = nullptr;
     p.gr = nullptr;
-    // grid targets (overridable for tuning through PT_TARGET_SLOT_BLOCKS / PT_TARGET_TEAM_BLOCKS)
-    p.target_slot = 2048;
-    p.target_team = 16384;
-    if (const char* e = std::getenv("PT_TARGET_SLOT_BLOCKS")) p.target_slot = std::max(8, std::atoi(e));
-    if (const char* e = std::getenv("PT_TARGET_TEAM_BLOCKS")) p.target_team = std::max(8, std::atoi(e));
+    p.target_slot = opts->grid_slot > 0 ? opts->grid_slot : 2048;
+    p.target_team = opts->grid_team > 0 ? opts->grid_team : 16384;
     p.g_slot0 = slot_geom(p.side, p.ST, p.target_slot);
     p.g_team = team_geom(p.side, p.S, p.B, p.target_team);
     p.g_fwd = fwd_geom(p.side, p.S, p.B, p.target_slot);
@@ -854,6 +856,43 @@ pt_status pt_periodic_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const do
     launch_inverse(p, ws, X, coef, U, 0, st);
     launch_transpose_out(p, U, d_x, st);
     PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_solve_many(int32_t count, pt_plan* const* plans, void* const* d_ws, const size_t* ws_bytes,
+                        double* const* d_u, pt_stats* const* stats, pt_status* status, void* const* streams,
+                        int32_t nstreams) {
+    if (count < 0 || (count > 0 && (!plans || !d_ws || !ws_bytes || !d_u || !status)))
+        return fail(PT_ERR_INVALID, "plans, d_ws, ws_bytes, d_u and status must not be NULL");
+    if (nstreams < 1 || nstreams > 64) return fail(PT_ERR_INVALID, "nstreams must be in [1, 64]");
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !d_u[i]) return fail(PT_ERR_INVALID, "plan " + std::to_string(i) + " or its d_u is NULL");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(PT_ERR_INVALID, "a plan appears twice in the work list");
+    }
+    int device = 0;
+    PT_HIP(hipGetDevice(&device));
+    // work list: worker w takes the next unclaimed plan (in the given order) on streams[w]
+    std::atomic<int> next{0};
+    std::vector<std::string> errors(count);
+    auto worker = [&](int w) {
+        if (hipSetDevice(device) != hipSuccess) return;
+        hipStream_t st = streams ? (hipStream_t)streams[w] : nullptr;
+        for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
+            Plan& p = plans[i]->p;
+            status[i] = solve_impl(p, d_ws[i], ws_bytes[i], d_u[i], st, stats ? stats[i] : nullptr);
+            if (status[i] != PT_OK) errors[i] = g_last_error;
+        }
+    };
+    for (int i = 0; i < count; ++i) status[i] = PT_ERR_INVALID;
+    const int nw = std::min<int>(nstreams, std::max(count, 1));
+    std::vector<std::thread> pool;
+    pool.reserve(nw);
+    for (int w = 0; w < nw; ++w) pool.emplace_back(worker, w);
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < count; ++i)
+        if (status[i] != PT_OK)
+            return fail(status[i], "work item " + std::to_string(i) + ": " + errors[i]);
     return PT_OK;
 }
 

@@ -133,3 +133,49 @@ def test_graph_respects_max_outer(gpu, P):
     Ug, sg = P.Plan(p, max_outer=7, check_every=3, graph=True).solve(raise_on_error=False)
     assert se.status == sg.status == -4 and se.outer_iters == sg.outer_iters == 7
     assert torch.equal(Ue, Ug)
+
+
+def test_work_list_solver_matches_oracle(gpu, P):
+    # problems of uneven size: two grids, two periods, group sizes 3 (-> 2 + 1) and 1 and 2
+    say("work list")
+    from paper_2502_21013_amd.batch import ManySolver
+    base = W.config4(21, 6)
+    sizes = [(16, 16), (16, 16), (16, 16), (32, 8), (16, 8), (16, 8)]
+    ps = [W.with_size(p, n, N) for p, (n, N) in zip(base, sizes)]
+    ms = ManySolver(ps, tol=1e-12, max_outer=2000, nstreams=3, graph=True)
+    assert sorted(len(b) for b in ms.batches) == [1, 1, 2, 2]
+    for rep in range(2):
+        r = ms.solve()
+        assert r.status == 0
+        for i, p in enumerate(ps):
+            assert r.stats[i].rel_residual <= 1e-12
+            assert tuple(r.U[i].shape) == (p.N, p.n + 1, p.n + 1)
+            assert rel_err(r.U[i].cpu().numpy(), oracle_solution(p)) <= 1e-8, (rep, i)
+    ms.close()
+
+
+def test_work_list_reports_the_failing_item(gpu, P):
+    say("work list failure")
+    from paper_2502_21013_amd.batch import ManySolver
+    ps = [W.with_size(p, 16, 16) for p in W.config4(22, 2)] + [W.with_size(W.config4(23, 1)[0], 32, 8)]
+    ms = ManySolver(ps, tol=1e-12, max_outer=3, nstreams=2)
+    r = ms.solve(raise_on_error=False)
+    assert r.status == -4
+    assert all(s.status == -4 and s.outer_iters == 3 for s in r.stats)
+    assert b"work item" in P.library().pt_last_error()
+    ms.close()
+
+
+def test_autotuner_picks_a_valid_setting(gpu, P):
+    say("autotune")
+    from paper_2502_21013_amd import autotune as AT
+    ps = instances(31, 32, 16, 2)
+    mk = lambda max_outer, **kw: P.BatchPlan(ps, tol=1e-10, max_outer=max_outer, **kw)
+    r = AT.tune(mk, tol=1e-10, steps=8, omegas=(0.7, 0.8), grid_slot=(256, 2048), grid_team=(1024, 16384))
+    best = r["best"]
+    assert best["vc_omega"] in (0.7, 0.8) and best["grid_slot"] in (256, 2048) and best["grid_team"] in (1024, 16384)
+    assert all(0 < t["rate"] < 1 and t["step_ms"] > 0 for t in r["trials"])
+    # the tuned plan reaches the same solution
+    U, st = P.BatchPlan(ps, tol=1e-12, max_outer=2000, **best).solve()
+    for b, p in enumerate(ps):
+        assert rel_err(U[b].cpu().numpy(), oracle_solution(p)) <= 1e-8
