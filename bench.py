@@ -184,9 +184,9 @@ def load_traffic(kernel, mode, wl):
     return ent.get("hbm_bytes_per_launch")
 
 
-def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000):
+def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None):
     import torch
-    plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer)
+    plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer, **(tuned or {}))
     U = plan.new_time_field()
     plan.workspace()
     for w in range(warmup):
@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--streams", type=int, default=4, help="c4: host threads / HIP streams of the work list")
     ap.add_argument("--no-graph", action="store_true", help="c4: eager launches instead of graph replay")
     ap.add_argument("--no-plain", action="store_true", help="c4: skip the instance-by-instance FP64 run")
-    ap.add_argument("--tuning", default="", help="c4: autotuner table (JSON) to apply")
+    ap.add_argument("--tuning", default="", help="autotuner table (JSON) to apply")
     ap.add_argument("--max-outer", type=int, default=2000,
                     help="cap on outer steps per solve; below the count needed for 1e-8 the run is a "
                          "profiling run (marked in the output), not a metric measurement")
@@ -265,9 +265,16 @@ def main():
     log(f"workload {args.workload}: {desc}, {prob.st_dofs} space-time DoFs")
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    from paper_2502_21013_amd import autotune as AT
+    from paper_2502_21013_amd.batch import tune_key
+    table = AT.load_table(args.tuning) if args.tuning else {}
     res = {}
     for m in modes:
-        res[m] = run_mode(P, prob, m, args.steps, args.warmup, args.tol, args.max_outer)
+        tuned = table.get(tune_key(prob, 1, m))
+        if tuned:
+            log(f"{m}: tuned setting {tuned}")
+        res[m] = run_mode(P, prob, m, args.steps, args.warmup, args.tol, args.max_outer, tuned)
+        res[m]["tuned"] = tuned
         log(f"{m}: {res[m]['ms_per_step']:.1f} ms per solve")
 
     primary = modes[0]
@@ -312,7 +319,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": {m: {"value": prob.st_dofs / (res[m]["ms_per_step"] * 1e-3), "ms_per_step": res[m]["ms_per_step"],
-                      "outer_iters": res[m]["outer_iters"], "rel_residual": res[m]["rel_residual"]} for m in modes},
+                      "outer_iters": res[m]["outer_iters"], "rel_residual": res[m]["rel_residual"],
+                      "tuned": res[m]["tuned"]} for m in modes},
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "kernel_ms_all": {k: round(v, 3) for k, v in r0["kernel_ms"].items()},

@@ -24,7 +24,7 @@ struct LvArgs {
 // S: slots per instance (a power of two; slot s with s % S == 0 packs k = 0 and k = N/2),
 // ST = B S: slots per node over the B instances of a batch (the row stride).
 struct SlotArgs {
-    int S, ST, per_step, slot_chunk, remap, col_groups, rows_per_chunk;
+    int S, ST, lgST, per_step, slot_chunk, remap, col_groups, rows_per_chunk;
     double nu, omega;
     const double* zs;  // S x 3 generic (a, b, c) of the shifts
 };
@@ -46,8 +46,9 @@ template <typename P> __device__ __forceinline__ const P* cboff(const P* base, u
 template <typename P> __device__ __forceinline__ P* boff(P* base, unsigned bytes) {
     return reinterpret_cast<P*>(reinterpret_cast<char*>(base) + bytes);
 }
-template <typename P> __device__ __forceinline__ P* row_of(P* base, int row, int side, int ST) {
-    return base + (size_t)(row * side) * (size_t)ST;
+// Row `row` of a slot vector with `side` nodes per row and 2^lgST slots per node.
+template <typename P> __device__ __forceinline__ P* row_of(P* base, int row, int side, int lgST) {
+    return base + ((size_t)(row * side) << lgST);
 }
 
 // The seven mass-stencil coefficients of node a (centre, E, W, N, S, NE, SW).
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     using T2 = typename Vec2<T>::type;
     const T2* rin = (const T2*)rin_;
     T2* rout = (T2*)rout_;
-    const int ST = sa.ST, SC = sa.slot_chunk;
+    const int ST = sa.ST, lgST = sa.lgST, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
@@ -144,10 +145,10 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     if (UNI) ci = __builtin_amdgcn_readfirstlane(ci);
     if (ci >= sc) return;
     const T2 zero = mk2<T>(0, 0);
-    const unsigned oco = ((unsigned)ci * ST + s) * E;
+    const unsigned oco = (((unsigned)ci << lgST) + s) * E;
     // boundary coarse nodes of this chunk are zero
     for (int cj = sr.row0; cj < sr.row1; ++cj)
-        if (ci == 0 || ci == nc || cj == 0 || cj == nc) *boff(row_of(rout, cj, sc, ST), oco) = zero;
+        if (ci == 0 || ci == nc || cj == 0 || cj == nc) *boff(row_of(rout, cj, sc, lgST), oco) = zero;
     if (ci == 0 || ci == nc) return;
     const int cj0 = sr.row0 > 1 ? sr.row0 : 1;
     const int cj1 = sr.row1 < nc ? sr.row1 : nc;  // interior coarse rows [cj0, cj1)
@@ -155,12 +156,12 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     const int c = 2 * ci;
     unsigned of[5];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) of[d] = ((unsigned)(c - 2 + d) * ST + s) * E;
+    for (int d = 0; d < 5; ++d) of[d] = (((unsigned)(c - 2 + d) << lgST) + s) * E;
     // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
     T2 xa[5], xb[5], xq[5], rb[3], rq[3];
     auto fetch_row = [&](int R, T2* rv, double* mv) {
         if (R >= 0 && R <= nF) {
-            const T2* fr = row_of(rin, R, sf, ST);
+            const T2* fr = row_of(rin, R, sf, lgST);
             const double* mr = F.mt + (long)R * sf + (c - 2);
 #pragma unroll
             for (int d = 0; d < 5; ++d) {
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
                 acc = fma2(half, sv[1], acc);
                 acc = fma2(half, sv[2], acc);
-                *boff(row_of(rout, (R - 1) / 2, sc, ST), oco) = acc;
+                *boff(row_of(rout, (R - 1) / 2, sc, lgST), oco) = acc;
             }
             acc = scale2(half, add2(sv[0], sv[1]));  // lower row of coarse row (R+1)/2
         } else {
@@ -319,7 +320,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
     const T2* rin = (const T2*)rin_;
     const T2* xc = (const T2*)xc_;
     T2* xout = (T2*)xout_;
-    const int ST = sa.ST, SC = sa.slot_chunk;
+    const int ST = sa.ST, lgST = sa.lgST, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
@@ -339,9 +340,9 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
         for (int d = 0; d < 3; ++d) {
             const int bi = ai - 1 + d, hi = bi >> 1;
             odd[d] = bi & 1;
-            ofn[d] = ((unsigned)bi * ST + s) * E;
-            och[d] = ((unsigned)hi * ST + s) * E;
-            ocq[d] = ((unsigned)(hi + (bi & 1)) * ST + s) * E;
+            ofn[d] = (((unsigned)bi << lgST) + s) * E;
+            och[d] = (((unsigned)hi << lgST) + s) * E;
+            ocq[d] = (((unsigned)(hi + (bi & 1)) << lgST) + s) * E;
         }
         auto load = [&](int d, int bj) -> UpIn<T2> {
             UpIn<T2> u;
@@ -351,16 +352,16 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
                 u.mc = 0.0;
                 return u;
             }
-            u.r = *cboff(row_of(rin, bj, sf, ST), ofn[d]);
+            u.r = *cboff(row_of(rin, bj, sf, lgST), ofn[d]);
             u.mc = F.mt[(long)bj * sf + ai - 1 + d];
             const int hj = bj >> 1, oj = bj & 1;
-            u.c0 = *cboff(row_of(xc, hj, sc, ST), och[d]);
+            u.c0 = *cboff(row_of(xc, hj, sc, lgST), och[d]);
             if (!odd[d] && !oj) {
                 u.kind = 1;
                 u.c1 = mk2<T>(0, 0);
             } else {
                 u.kind = 2;
-                u.c1 = *cboff(row_of(xc, hj + oj, sc, ST), ocq[d]);
+                u.c1 = *cboff(row_of(xc, hj + oj, sc, lgST), ocq[d]);
             }
             return u;
         };
@@ -387,7 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
                 out = add2(xcn, scale2(om, gs_apply(da, sub2(rc, Ax))));
                 if (dotmode != DOT_NONE) dot3_acc(acc, out, rc, dotmode == DOT_HERM);
             }
-            *boff(row_of(xout, aj, sf, ST), ofn[1]) = out;
+            *boff(row_of(xout, aj, sf, lgST), ofn[1]) = out;
             if (more) {
                 xsw = xw;
                 xs = xcn;
@@ -401,8 +402,8 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
             }
         }
     } else if (ai < sf) {
-        const unsigned oc = ((unsigned)ai * ST + s) * E;
-        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, ST), oc) = mk2<T>(0, 0);
+        const unsigned oc = (((unsigned)ai << lgST) + s) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, lgST), oc) = mk2<T>(0, 0);
     }
     if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, ST, blockIdx.y, SC);
 }
@@ -416,7 +417,7 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     using T2 = typename Vec2<T>::type;
     const T2* x = (const T2*)x_;
     T2* y = (T2*)y_;
-    const int ST = sa.ST, SC = sa.slot_chunk;
+    const int ST = sa.ST, lgST = sa.lgST, SC = sa.slot_chunk;
     const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
     const int s = blockIdx.y * SC + ls;
     const int vb = virtual_block(sa.remap);
@@ -429,11 +430,11 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     int ai = sr.col0 + ln;
     if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
-        const unsigned ow = ((unsigned)(ai - 1) * ST + s) * E, oc = ow + (unsigned)ST * E,
+        const unsigned ow = (((unsigned)(ai - 1) << lgST) + s) * E, oc = ow + (unsigned)ST * E,
                        oe = oc + (unsigned)ST * E;
         auto ld = [&](unsigned o, int bj) -> T2 {
             if (bj < 0 || bj > nF) return mk2<T>(0, 0);
-            return *cboff(row_of(x, bj, sf, ST), o);
+            return *cboff(row_of(x, bj, sf, lgST), o);
         };
         const int j0 = sr.row0;
         T2 xsw = ld(ow, j0 - 1), xs = ld(oc, j0 - 1), xw = ld(ow, j0), xcn = ld(oc, j0), xe = ld(oe, j0);
@@ -451,7 +452,7 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
                 out = apply_A<T, T2>(mrow(F, (long)aj * sf + ai), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
                 if (dotmode != DOT_NONE) dot3_acc(acc, xcn, out, dotmode == DOT_HERM);
             }
-            if (y) *boff(row_of(y, aj, sf, ST), oc) = out;
+            if (y) *boff(row_of(y, aj, sf, lgST), oc) = out;
             if (more) {
                 xsw = xw;
                 xs = xcn;
@@ -463,8 +464,8 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
             }
         }
     } else if (ai < sf && y) {
-        const unsigned oc = ((unsigned)ai * ST + s) * E;
-        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, ST), oc) = mk2<T>(0, 0);
+        const unsigned oc = (((unsigned)ai << lgST) + s) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, lgST), oc) = mk2<T>(0, 0);
     }
     if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, ST, blockIdx.y, SC);
 }
@@ -597,6 +598,8 @@ static SlotArgs mk_slot(const Plan& p, char* ws, const Geom& g) {
     SlotArgs sa;
     sa.S = p.S;
     sa.ST = p.ST;
+    sa.lgST = 0;
+    while ((1 << sa.lgST) < p.ST) ++sa.lgST;
     sa.col_groups = g.col_groups;
     sa.rows_per_chunk = g.rows_per_chunk;
     sa.per_step = g.per_step;

@@ -75,7 +75,7 @@ __device__ T2* fft_team(T2* a, T2* b, int S, int lt, int TS, const T2* __restric
 
 struct FwdArgs {
     int n, side, N, S, lgS, ts, nb, col_groups, rows_per_chunk, remap, mode;
-    int B, ST;             // instances in the batch, slots per node over all instances
+    int B, ST, lgST;       // instances in the batch, slots per node over all instances (2^lgST)
     size_t nodes;
     double inv_tau, n2;
     double nu_a, nu_b, nu_out;
@@ -247,14 +247,15 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
     }
     Win v[KP][2];
     // uniform row base + per-lane byte offset of (column i-1+d, instance bi, pair lt + TS k)
-    const int STp = a.ST;  // time pairs per node over all instances (= slots per node)
+    const int lgST = a.lgST;  // 2^lgST time pairs per node over all instances (= slots per node)
+    const long STp = a.ST;
     unsigned ofs[3][KP];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int k = 0; k < KP; ++k)
-            ofs[d][k] = ((unsigned)(i - 1 + d) * STp + (unsigned)(bi * S + lt + TS * k)) * (unsigned)sizeof(double2);
-    auto rowU = [&](int cj) { return U2 + (size_t)(cj * side) * STp; };
+            ofs[d][k] = ((((unsigned)(i - 1 + d)) << lgST) + (unsigned)(bi * S + lt + TS * k)) * (unsigned)sizeof(double2);
+    auto rowU = [&](int cj) { return U2 + ((size_t)(cj * side) << lgST); };
     auto ldd = [&](int d, int cj, int k) -> double2 {
         if (cj < 0 || cj > n) return make_double2(0.0, 0.0);
         return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(rowU(cj)) + ofs[d][k]);
@@ -474,6 +475,8 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     while ((1 << a.lgS) < p.S) ++a.lgS;
     a.B = p.B;
     a.ST = p.ST;
+    a.lgST = 0;
+    while ((1 << a.lgST) < p.ST) ++a.lgST;
     a.inst = p.B > 1 ? (const double*)(ws + p.off_inst) : nullptr;
     a.remap = p.opt.xcd_remap;
     a.mode = mode;
