@@ -19,7 +19,12 @@ What it computes (all in float64, numpy + scipy.sparse):
                 M/tau + Khat with period sweeps (oracle B), an all-at-once Newton
                 solve (method (M2) without multigrid in time) and sequential
                 nonlinear time stepping (method (M3)).
+* ``adjoint``   the cycle-averaged eddy-current loss tau sum_n d u^T M d u, the
+                Jacobian dA/dU, the adjoint state of the transposed (backward in
+                time, periodic) linearised system by sparse LU, and the gradients of
+                the loss with respect to the per-triangle nu scale and conductivity.
 
-Conventions where the paper is silent are listed in DESIGN.md ("Readings").
+Where the paper leaves a convention open, the docstring of the function that uses it
+states the reading taken.
 """
-from . import fem, periodic  # noqa: F401
+from . import adjoint, fem, periodic  # noqa: F401
