@@ -116,6 +116,9 @@ typedef struct {
                               per slot chunk; 0 = 2048. Performance only (>= 8). */
     int32_t grid_team;     /* workgroups the per-node time-axis sweeps (DFT, inverse DFT)
                               aim for; 0 = 16384. Performance only (>= 8). */
+    int32_t adjoint;       /* 1: reserve the workspace of pt_adjoint_solve / pt_loss_gradients
+                              (two more time fields and a per-triangle table); single-problem
+                              plans only */
     int32_t graph;         /* 1: capture the kernels of check_every outer steps into a HIP
                               graph on the first call (per plan and workspace address) and
                               replay it; same iterates as 0. Cannot be combined with timing. */
@@ -142,7 +145,7 @@ typedef struct pt_plan pt_plan;
 
 /* Fill *o with the defaults (tol 1e-8, max_outer 1000, check_every 1, FP64,
  * PT_INNER_GALERKIN1, inner_iters 1, vc_sweeps 1, vc_omega 0.8, no initial guess,
- * diverge_factor 1e3, xcd_remap 1, timing 0, default grid targets, graph 0). */
+ * diverge_factor 1e3, xcd_remap 1, timing 0, default grid targets, adjoint 0, graph 0). */
 void pt_options_default(pt_options* o);
 
 /* Validate the problem and options (host only, no device work) and create a plan. */
@@ -228,6 +231,38 @@ pt_status pt_precond_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const voi
  * inner_iters overrides the plan's COCG step count when > 0. */
 pt_status pt_periodic_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_r,
                             double* d_x, int32_t inner_iters, void* stream);
+
+/* Adjoint of the cycle-averaged eddy-current loss
+ *     l(U) = tau sum_n (d u^n)^T M (d u^n),   d u^n = (u^n - u^{n-1}) / tau,  u^0 = u^N,
+ * (the time integral over one period of int sigma |du/dt|^2 with the implicit-Euler
+ * difference quotient and the consistent mass; Sec. 4 model, Problem 1). For the state U
+ * with A(U) = F the adjoint state lambda solves J^T lambda = dl/dU, J = dA/dU (eqs.
+ * (disc1)-(disc2) linearised):
+ *     (M/tau)(lambda^n - lambda^{n+1}) + K'(u^n) lambda^n = (dl/dU)^n,  lambda^{N+1} = lambda^1,
+ * a periodic system running backward in time. It is solved by the same fixed-point
+ * correction as the forward problem (eqs. (iter1)-(iter2) with Khat = nu_max S), whose
+ * periodic linear part is now I (x) (M/tau + Khat) - C_N^T (x) (M/tau): in the time-DFT
+ * basis the systems (Khat + conj(z_k) M), solved as the conjugates of the forward ones.
+ * The plan must have been created with options.adjoint = 1 (single problem).
+ *
+ * pt_adjoint_solve: d_u is the state (time field [N][n+1][n+1], e.g. from pt_solve);
+ * d_lambda receives lambda in the same layout (and holds the initial guess when
+ * use_initial_guess = 1). Stops when ||dl/dU - J^T lambda|| <= tol ||dl/dU|| (absolute if
+ * dl/dU = 0); statuses and stats as pt_solve. Blocks until the stream has finished. */
+pt_status pt_adjoint_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
+                           double* d_lambda, void* stream, pt_stats* stats);
+
+/* Loss and gradients at the state d_u with the adjoint state d_lambda (may be NULL: then
+ * only the loss and the direct part tau sum du^T M_T du of dl/dsigma_T are formed):
+ *     dl/dtheta_T = - sum_n |T| nuhat_T(|grad u^n|^2) grad u^n . grad lambda^n
+ *     dl/dsigma_T = tau sum_n du^T M_T du - sum_n (lambda^n)^T M_T du
+ * with theta_T the nu scale (nu = theta nuhat) and M_T the unit-conductivity element mass
+ * of triangle T. d_gtheta / d_gsigma: device arrays (may be NULL) of 2 n^2 entries (per
+ * triangle, id 2 (j n + i) + {0, 1}) or, with per_cell = 1, of n^2 entries (sum over the
+ * two triangles of cell (i, j)). loss_out (host, may be NULL) receives l. Blocks. */
+pt_status pt_loss_gradients(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
+                            const double* d_lambda, double* d_gtheta, double* d_gsigma,
+                            int32_t per_cell, double* loss_out, void* stream);
 
 /* Name of kernel class id (0 <= id < PT_KERNEL_CLASSES), or NULL. */
 const char* pt_kernel_class_name(int32_t id);

@@ -76,7 +76,7 @@ class SolveStats:
 
 
 def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega, use_initial_guess,
-             diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0) -> L.Options:
+             diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0, adjoint=False) -> L.Options:
     o = L.Options()
     lib.pt_options_default(C.byref(o))
     o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
@@ -88,6 +88,7 @@ def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc
     o.timing = 1 if timing else 0
     o.graph = 1 if graph else 0
     o.grid_slot, o.grid_team = int(grid_slot), int(grid_team)
+    o.adjoint = 1 if adjoint else 0
     return o
 
 
@@ -122,7 +123,7 @@ class Plan:
     def __init__(self, problem, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
-                 theta=None, sigma=None, load=None, device=None):
+                 adjoint=False, theta=None, sigma=None, load=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -133,7 +134,7 @@ class Plan:
         self._keep = (theta, sigma, load)  # device tables must outlive the plan's calls
         self._ps = problem_struct(problem, theta, sigma, load)
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
-                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team)
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -205,6 +206,39 @@ class Plan:
             raise PTError(st, "pt_solve")
         return U, stats
 
+    def adjoint_solve(self, U, Lam=None, history_cap: int = 4096, raise_on_error: bool = True):
+        """Adjoint state lambda of the eddy-current loss at the state U (pt_adjoint_solve);
+        Lam is the output (and the initial guess if the plan uses one)."""
+        if Lam is None:
+            Lam = self.new_time_field()
+        ws, nb = self.workspace()
+        buf = _StatsBuf(history_cap)
+        s = L.Stats()
+        buf.fill(s)
+        st = self.lib.pt_adjoint_solve(self._h, ws, nb, self._time_field(U, "U"), self._time_field(Lam, "Lam"),
+                                       self._stream(), C.byref(s))
+        stats = buf.result(self.lib, st, s)
+        if raise_on_error and st != L.PT_OK:
+            raise PTError(st, "pt_adjoint_solve")
+        return Lam, stats
+
+    def loss_gradients(self, U, Lam=None, per_cell: bool = False):
+        """(loss, dl/dtheta, dl/dsigma) at the state U with adjoint state Lam (pt_loss_gradients);
+        per triangle (2 n^2) or per cell (n^2)."""
+        import torch
+        dev = U.device
+        m = self.n * self.n * (1 if per_cell else 2)
+        gt = torch.zeros(m, dtype=torch.float64, device=dev)
+        gs = torch.zeros(m, dtype=torch.float64, device=dev)
+        ws, nb = self.workspace()
+        loss = C.c_double()
+        lam = None if Lam is None else self._time_field(Lam, "Lam")
+        self._check(self.lib.pt_loss_gradients(self._h, ws, nb, self._time_field(U, "U"), lam,
+                                               C.c_void_p(gt.data_ptr()), C.c_void_p(gs.data_ptr()),
+                                               1 if per_cell else 0, C.byref(loss), self._stream()),
+                    "pt_loss_gradients")
+        return loss.value, gt, gs
+
     def residual(self, U):
         R = self.new_time_field()
         ws, nb = self.workspace()
@@ -275,7 +309,7 @@ class BatchPlan(Plan):
     def __init__(self, problems, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
-                 device=None):
+                 adjoint=False, device=None):
         import torch
         problems = list(problems)
         self.lib = L.load()
@@ -289,7 +323,7 @@ class BatchPlan(Plan):
         self._keep = ()
         self._pa = (L.Problem * self.count)(*[problem_struct(p) for p in problems])
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
-                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team)
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create_batch(self._pa, self.count, C.byref(o), C.byref(h))
@@ -335,3 +369,4 @@ class BatchPlan(Plan):
         raise TypeError("component entry points take a single-problem plan")
 
     residual = apply_K = rfft = irfft = shifted_apply = precond_apply = periodic_solve = _single
+    adjoint_solve = loss_gradients = _single

@@ -45,7 +45,7 @@ class Options(C.Structure):
         ("precision", C.c_int32), ("inner", C.c_int32), ("inner_iters", C.c_int32),
         ("vc_sweeps", C.c_int32), ("vc_omega", C.c_double), ("use_initial_guess", C.c_int32),
         ("diverge_factor", C.c_double), ("xcd_remap", C.c_int32), ("timing", C.c_int32),
-        ("grid_slot", C.c_int32), ("grid_team", C.c_int32), ("graph", C.c_int32),
+        ("grid_slot", C.c_int32), ("grid_team", C.c_int32), ("adjoint", C.c_int32), ("graph", C.c_int32),
     ]
 
 
@@ -94,6 +94,8 @@ def load():
         "pt_shifted_apply": (i32, [vp, vp, sz, vp, vp, vp]),
         "pt_precond_apply": (i32, [vp, vp, sz, vp, vp, vp]),
         "pt_periodic_solve": (i32, [vp, vp, sz, vp, vp, i32, vp]),
+        "pt_adjoint_solve": (i32, [vp, vp, sz, vp, vp, vp, C.POINTER(Stats)]),
+        "pt_loss_gradients": (i32, [vp, vp, sz, vp, vp, vp, vp, i32, dp, vp]),
         "pt_status_string": (C.c_char_p, [i32]),
         "pt_last_error": (C.c_char_p, []),
         "pt_version": (i32, []),

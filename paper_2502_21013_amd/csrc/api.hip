@@ -145,6 +145,7 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (o->inner_iters < 1 || o->inner_iters > 64) return fail(PT_ERR_INVALID, "inner_iters must be in [1, 64]");
     if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused V(1,1) cycle)");
     if (!(o->vc_omega > 0 && o->vc_omega < 1)) return fail(PT_ERR_INVALID, "vc_omega must be in (0, 1)");
+    if (o->adjoint != 0 && o->adjoint != 1) return fail(PT_ERR_INVALID, "adjoint must be 0 or 1");
     if (o->grid_slot < 0 || (o->grid_slot > 0 && o->grid_slot < 8) || o->grid_slot > (1 << 22) || o->grid_team < 0 ||
         (o->grid_team > 0 && o->grid_team < 8) || o->grid_team > (1 << 22))
         return fail(PT_ERR_INVALID, "grid_slot and grid_team must be 0 or in [8, 4194304]");
@@ -175,6 +176,7 @@ static pt_status validate_batch(const pt_problem* pr, int count, const pt_option
         if (q.sigma_in != a.sigma_in || !same_rect(q.sigma_rect, a.sigma_rect) || q.nu_max != a.nu_max)
             return fail(PT_ERR_INVALID, "batch instances must share sigma_in, sigma_rect and nu_max");
     }
+    if (o->adjoint) return fail(PT_ERR_INVALID, "adjoint plans take a single problem");
     for (int b = 0; b < count; ++b)
         if (pr[b].d_theta || pr[b].d_sigma || pr[b].d_load)
             return fail(PT_ERR_INVALID, "d_theta, d_sigma and d_load must be NULL in a batch of more than one");
@@ -219,10 +221,18 @@ static void layout(Plan& p) {
     p.off_inst = take(B * 4 * sizeof(double));
     size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows) * S * 3;
     size_t part_team = (size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2;
-    p.part_bytes = (part_slot > part_team ? part_slot : part_team) * sizeof(double);
+    size_t part_adj = p.opt.adjoint ? std::max<size_t>((size_t)kAdjBlocks * 2, (size_t)p.n * p.n * 2) : 0;
+    p.part_bytes = std::max(std::max(part_slot, part_team), part_adj) * sizeof(double);
     p.off_part = take(p.part_bytes);
     p.off_scal = take(2 * B * sizeof(double));
     p.off_flag = take(sizeof(int));
+    if (p.opt.adjoint) {
+        p.off_L = take(p.nodes * p.N * sizeof(double));
+        p.off_G = take(p.nodes * p.N * sizeof(double));
+        p.off_sig = take(2 * (size_t)p.n * p.n * sizeof(double));
+    } else {
+        p.off_L = p.off_G = p.off_sig = 0;
+    }
     p.off_coef = take(8 * S * 2 * sizeof(double));  // eight double2 per-slot arrays
     p.off_coef2 = p.off_coef + 4 * S * 2 * sizeof(double);
     p.off_hist = 0;
@@ -372,6 +382,7 @@ struct GraphCache {
     hipGraphExec_t exec = nullptr;
     char* ws = nullptr;  // workspace the graph's kernel arguments point into
     int steps = 0;
+    bool adjoint = false;
 };
 
 void graph_release(Plan& p) {
@@ -384,31 +395,45 @@ void graph_release(Plan& p) {
     p.gr = nullptr;
 }
 
-// One fixed-point update once the residual of U^k is in Rhat (eq. (iter2) in correction
-// form, U^{k+1} = U^k + P^{-1} R^k), followed by the residual of U^{k+1} and its norm
-// partials.
-static pt_status outer_segment(Plan& p, char* ws, hipStream_t st) {
-    double* U = (double*)(ws + p.off_U);
+// Residual of the current iterate into Rhat (frequency domain, solver precision) and its
+// norm partials reduced into scal. Forward: R = F - A(U). Adjoint: R = dl/dU - J^T lambda,
+// transformed with conjugated shifts (the DFT of the backward-in-time coupling).
+static void residual_step(Plan& p, char* ws, bool adjoint, hipStream_t st) {
     double* part = (double*)(ws + p.off_part);
     double* scal = (double*)(ws + p.off_scal);
+    if (!adjoint) {
+        launch_forward(p, ws, TM_RESIDUAL, (double*)(ws + p.off_U), ws + p.lev[0].off_r, nullptr, part, st);
+        TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
+        return;
+    }
+    int nparts = 0;
+    TM(KID_RESIDUAL, nparts = launch_adj_residual(p, ws, ws + p.off_P, st));
+    TM(KID_REDUCE, launch_reduce_pairs(p, part, nparts, scal, st));
+    launch_rfft(p, ws, ws + p.off_P, ws + p.lev[0].off_r, 1, st);
+}
+
+// One fixed-point update once the residual of the iterate is in Rhat (eq. (iter2) in
+// correction form, U^{k+1} = U^k + P^{-1} R^k; for the adjoint with the transposed P),
+// followed by the residual of the new iterate and its norm partials.
+static pt_status outer_segment(Plan& p, char* ws, bool adjoint, hipStream_t st) {
+    double* X0 = (double*)(ws + (adjoint ? p.off_L : p.off_U));
     const void* X = nullptr;
     const double* coef = nullptr;
     pt_status s = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
     if (s != PT_OK) return s;
-    TM(KID_INVERSE, launch_inverse(p, ws, X, coef, U, 1, st));
-    launch_forward(p, ws, TM_RESIDUAL, U, ws + p.lev[0].off_r, nullptr, part, st);
-    TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
+    TM(KID_INVERSE, launch_inverse(p, ws, X, coef, X0, 1, st, adjoint ? 1 : 0));
+    residual_step(p, ws, adjoint, st);
     return PT_OK;
 }
 
-static pt_status graph_get(Plan& p, char* ws, int steps, hipGraphExec_t* exec) {
+static pt_status graph_get(Plan& p, char* ws, int steps, bool adjoint, hipGraphExec_t* exec) {
     if (!p.gr) {
         p.gr = new (std::nothrow) GraphCache();
         if (!p.gr) return fail(PT_ERR_INVALID, "out of host memory");
         PT_HIP(hipStreamCreateWithFlags(&p.gr->cap, hipStreamNonBlocking));
     }
     GraphCache* g = p.gr;
-    if (g->exec && g->ws == ws && g->steps == steps) {
+    if (g->exec && g->ws == ws && g->steps == steps && g->adjoint == adjoint) {
         *exec = g->exec;
         return PT_OK;
     }
@@ -418,7 +443,7 @@ static pt_status graph_get(Plan& p, char* ws, int steps, hipGraphExec_t* exec) {
     g->graph = nullptr;
     PT_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
     pt_status s = PT_OK;
-    for (int i = 0; i < steps && s == PT_OK; ++i) s = outer_segment(p, ws, g->cap);
+    for (int i = 0; i < steps && s == PT_OK; ++i) s = outer_segment(p, ws, adjoint, g->cap);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(g->cap, &graph);
     if (s != PT_OK) {
@@ -434,6 +459,7 @@ static pt_status graph_get(Plan& p, char* ws, int steps, hipGraphExec_t* exec) {
     g->graph = graph;
     g->ws = ws;
     g->steps = steps;
+    g->adjoint = adjoint;
     *exec = g->exec;
     return PT_OK;
 }
@@ -448,8 +474,10 @@ struct EventPair {
 
 // The fixed-point iteration (eqs. (iter1)-(iter2)) for the B instances of a plan, stopped
 // when every instance's relative residual is at most tol. d_u: [B][N][n+1][n+1];
-// stats: NULL or an array of B.
-static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, hipStream_t st, pt_stats* stats) {
+// stats: NULL or an array of B. Adjoint (B = 1): the same iteration for J^T lambda = dl/dU
+// at the state d_u, lambda in and out through d_lambda.
+static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, hipStream_t st, pt_stats* stats,
+                            bool adjoint = false, double* d_lambda = nullptr) {
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
     char* ws = (char*)d_ws;
@@ -463,17 +491,19 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
     s = setup(p, ws, st);
     if (s != PT_OK) return s;
     double* U = (double*)(ws + p.off_U);
+    double* X0 = adjoint ? (double*)(ws + p.off_L) : U;   // the iterate
+    double* d_x = adjoint ? d_lambda : d_u;
     if (p.prob.d_load) TM(KID_TRANSPOSE, launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st));
+    if (adjoint) TM(KID_TRANSPOSE, launch_transpose_in(p, d_u, U, st));
     if (p.opt.use_initial_guess)
-        TM(KID_TRANSPOSE, launch_transpose_in(p, d_u, U, st));
+        TM(KID_TRANSPOSE, launch_transpose_in(p, d_x, X0, st));
     else
-        TM(KID_MEMSET, launch_zero16(U, (size_t)B * p.nodes * p.N * sizeof(double), st));
-    double* part = (double*)(ws + p.off_part);
+        TM(KID_MEMSET, launch_zero16(X0, (size_t)B * p.nodes * p.N * sizeof(double), st));
+    if (adjoint) TM(KID_OTHER, launch_adj_source(p, ws, st));
     double* scal = (double*)(ws + p.off_scal);
     int* flag = (int*)(ws + p.off_flag);
     TM(KID_MEMSET, launch_zero16(flag, 16, st));
-    launch_forward(p, ws, TM_RESIDUAL, U, ws + p.lev[0].off_r, nullptr, part, st);
-    TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
+    residual_step(p, ws, adjoint, st);
     std::vector<double> h(2 * (size_t)B), rel(B, INFINITY), fnorm(B, 0.0), best(B, INFINITY);
     std::vector<int> conv(B, -1);
     pt_status result = PT_ERR_NOT_CONVERGED;
@@ -534,17 +564,17 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
         }
         if (p.opt.graph && k % ce == 0 && k + ce <= p.opt.max_outer) {
             hipGraphExec_t exec = nullptr;
-            s = graph_get(p, ws, ce, &exec);
+            s = graph_get(p, ws, ce, adjoint, &exec);
             if (s != PT_OK) return s;
             PT_HIP(hipGraphLaunch(exec, st));
             k += ce;
         } else {
-            s = outer_segment(p, ws, st);
+            s = outer_segment(p, ws, adjoint, st);
             if (s != PT_OK) return s;
             ++k;
         }
     }
-    TM(KID_TRANSPOSE, launch_transpose_out(p, U, d_u, st));
+    TM(KID_TRANSPOSE, launch_transpose_out(p, X0, d_x, st));
     PT_HIP(hipEventRecord(ev.e1, st));
     PT_HIP(hipEventSynchronize(ev.e1));
     PT_HIP(hipGetLastError());
@@ -893,6 +923,39 @@ pt_status pt_solve_many(int32_t count, pt_plan* const* plans, void* const* d_ws,
     for (int i = 0; i < count; ++i)
         if (status[i] != PT_OK)
             return fail(status[i], "work item " + std::to_string(i) + ": " + errors[i]);
+    return PT_OK;
+}
+
+pt_status pt_adjoint_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, double* d_lambda,
+                           void* stream, pt_stats* stats) {
+    if (!plan || !d_u || !d_lambda) return fail(PT_ERR_INVALID, "plan, d_u and d_lambda must not be NULL");
+    Plan& p = plan->p;
+    if (p.B != 1 || !p.opt.adjoint) return fail(PT_ERR_INVALID, "the plan was not created with options.adjoint = 1");
+    return solve_impl(p, d_ws, ws_bytes, const_cast<double*>(d_u), (hipStream_t)stream, stats, true, d_lambda);
+}
+
+pt_status pt_loss_gradients(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, const double* d_lambda,
+                            double* d_gtheta, double* d_gsigma, int32_t per_cell, double* loss_out, void* stream) {
+    if (!plan || !d_u) return fail(PT_ERR_INVALID, "plan and d_u must not be NULL");
+    Plan& p = plan->p;
+    if (p.B != 1 || !p.opt.adjoint) return fail(PT_ERR_INVALID, "the plan was not created with options.adjoint = 1");
+    if (per_cell != 0 && per_cell != 1) return fail(PT_ERR_INVALID, "per_cell must be 0 or 1");
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    launch_transpose_in(p, d_u, (double*)(ws + p.off_U), st);
+    if (d_lambda) launch_transpose_in(p, d_lambda, (double*)(ws + p.off_L), st);
+    launch_adj_grad(p, ws, d_lambda != nullptr, d_gtheta, d_gsigma, per_cell, st);
+    double* scal = (double*)(ws + p.off_scal);
+    launch_reduce_pairs(p, (const double*)(ws + p.off_part), p.n * p.n, scal, st);
+    double h[2];
+    PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PT_HIP(hipStreamSynchronize(st));
+    PT_HIP(hipGetLastError());
+    if (loss_out) *loss_out = h[0];
     return PT_OK;
 }
 

@@ -17,6 +17,7 @@ struct SetupArgs {
     double sigma_in, J0;
     const double* d_sigma;  // optional per-triangle conductivity
     uint8_t* flags;         // [2 n^2] bit 0: nonlinear (iron) law applies
+    double* sig_out;        // [2 n^2] per-triangle conductivity (written if non-null)
     double* mt;             // [4][nodes] fine mass stencil
     double* b;              // [nodes] load amplitude
 };
@@ -56,6 +57,7 @@ __global__ void __launch_bounds__(kBlock) k_tri_flags(SetupArgs a) {
         double cx, cy;
         centroid(a.n, i, j, typ, cx, cy);
         a.flags[t] = in_rect(a.nu, cx, cy) ? 1 : 0;
+        if (a.sig_out) a.sig_out[t] = tri_sigma(a, i, j, typ);
     }
 }
 
@@ -161,6 +163,7 @@ void launch_setup_fine(const Plan& p, char* ws, hipStream_t st) {
         a.flags = (uint8_t*)(ws + p.off_flags) + (size_t)inst * 2 * p.n * p.n;
         a.mt = (double*)(ws + p.lev[0].off_mt);
         a.b = (double*)(ws + p.off_b) + (size_t)inst * p.nodes;
+        a.sig_out = (p.opt.adjoint && inst == 0) ? (double*)(ws + p.off_sig) : nullptr;
         hipLaunchKernelGGL(k_tri_flags, dim3(grid_for(2 * (size_t)p.n * p.n)), dim3(kBlock), 0, st, a);
         hipLaunchKernelGGL(k_fine_node, dim3(grid_for(p.nodes)), dim3(kBlock), 0, st, a);
     }

@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
 // the half-length complex FFT of z_m = x_{2m} + i x_{2m+1} and the split into X_k
 // (remark rem:parallel). Team of S/4 threads per node.
 struct RfftArgs {
-    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, B, ST;
+    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, B, ST, conj;
     const void* rt;   // T2 [nodes][S]
     const void* tw;   // T2 [N]
     void* out;        // T2 [nodes][S]
@@ -456,6 +456,7 @@ __global__ void __launch_bounds__(kBlock) k_rfft(RfftArgs a) {
                     T2 E = scale2((T)0.5, add2(zk, zc));
                     T2 O = scale2((T)0.5, mul_mi(sub2(zk, zc)));
                     X = add2(E, cmul(tw[k], O));
+                    if (a.conj) X = conj2(X);
                 }
                 out[k] = X;
             }
@@ -524,6 +525,10 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
 #undef PT_RES
     tm_end(p, KID_RESIDUAL, st);
     if (!out) return;
+    launch_rfft(p, ws, rt, out, 0, st);
+}
+
+void launch_rfft(const Plan& p, char* ws, const void* rt, void* out, int conj, hipStream_t st) {
     RfftArgs b;
     const Geom& g = p.g_team;
     b.n = p.n;
@@ -537,8 +542,9 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     b.remap = p.opt.xcd_remap;
     b.B = p.B;
     b.ST = p.ST;
+    b.conj = conj;
     b.rt = rt;
-    b.tw = a.tw;
+    b.tw = ws + (p.fp32 ? p.off_tw32 : p.off_tw64);
     b.out = out;
     size_t shm2 = (size_t)g.per_step * 2 * p.S * p.elem;
     dim3 blk2(g.per_step * g.slot_chunk);
@@ -582,6 +588,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce_norms(const double* part, int
     }
 }
 
+void launch_reduce_pairs(const Plan& p, const double* part, int nparts, double* out2, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_norms, dim3(1), dim3(kBlock), 0, st, part, nparts, 1, 1, p.side, out2);
+}
+
 void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, double* out2, hipStream_t st) {
     (void)ws;
     const Geom& g = p.g_fwd;
@@ -592,7 +602,7 @@ void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, doub
 // ---------------------------------------------------------------- inverse kernel
 
 struct InvArgs {
-    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, accumulate, B, ST;
+    int n, side, N, S, ts, nb, col_groups, rows_per_chunk, remap, accumulate, B, ST, conj;
     size_t nodes;
     const void* xhat;     // T2 [nodes][S]
     const double* coef;   // double2 [S] generic scalars or null
@@ -629,6 +639,7 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
                     double2 c = ((const double2*)a.coef)[bi * S + k];
                     v = gs_apply(gs_from<T>(c, k == 0), v);
                 }
+                if (a.conj && k != 0) v = conj2(v);
             }
             buf0[k] = v;
         }
@@ -673,7 +684,7 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
 }
 
 void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coef, double* Uw, int accumulate,
-                    hipStream_t st) {
+                    hipStream_t st, int conj) {
     InvArgs a;
     const Geom& g = p.g_team;
     a.n = p.n;
@@ -688,6 +699,7 @@ void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coe
     a.accumulate = accumulate;
     a.B = p.B;
     a.ST = p.ST;
+    a.conj = conj;
     a.nodes = p.nodes;
     a.xhat = xhat;
     a.coef = coef;

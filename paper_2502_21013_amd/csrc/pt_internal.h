@@ -24,6 +24,7 @@ constexpr int kBlock = 256;          // threads per workgroup in every kernel
 constexpr int kMaxLevels = 16;
 constexpr int kNumXcd = 8;
 constexpr int kReduceRows = 64;      // first-stage row groups of the dot-product reduction
+constexpr int kAdjBlocks = 8192;     // workgroups of the grid-stride adjoint kernels
 
 // Per-slot scalar in "generic" form: for slot s >= 1 a complex number (x + i y);
 // for slot 0 two reals, x acting on the real part (k = 0) and y on the imaginary
@@ -105,6 +106,7 @@ struct Plan {
     size_t off_U, off_F, off_P, off_cx, off_cr, off_cq, off_cp;
     size_t off_flags, off_b, off_tw64, off_tw32, off_zs, off_wave;
     size_t off_part, part_bytes, off_scal, off_flag, off_coef, off_coef2, off_hist, off_inst;
+    size_t off_L, off_G, off_sig;   // adjoint plans: adjoint iterate, dl/dU, per-triangle sigma
     size_t ws_bytes;
     bool has_cocg_vectors;
     // host copies of the small tables uploaded at every call
@@ -144,9 +146,20 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
                     double* part, hipStream_t st);
 void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, double* out2,
                          hipStream_t st);
-// inverse: Uw (+)= (1/N) irfft(coef (x) xhat), coef may be null (identity)
+// packed real DFT of rt (T2 [nodes][ST], solver precision) into out; conj: conjugate the
+// result (every slot but the packed real slot 0)
+void launch_rfft(const Plan& p, char* ws, const void* rt, void* out, int conj, hipStream_t st);
+// inverse: Uw (+)= (1/N) irfft(c(coef (x) xhat)), coef may be null (identity), c the
+// conjugation (conj = 1) or the identity
 void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coef, double* Uw,
-                    int accumulate, hipStream_t st);
+                    int accumulate, hipStream_t st, int conj = 0);
+// sum nparts pairs of partials in a fixed order into out2[0], out2[1]
+void launch_reduce_pairs(const Plan& p, const double* part, int nparts, double* out2, hipStream_t st);
+// adjoint (k_adjoint.hip)
+void launch_adj_source(const Plan& p, char* ws, hipStream_t st);
+int launch_adj_residual(const Plan& p, char* ws, void* rt, hipStream_t st);  // returns the partial count
+void launch_adj_grad(const Plan& p, char* ws, bool with_lambda, double* gth, double* gsg, int per_cell,
+                     hipStream_t st);
 void launch_apply_K(const Plan& p, char* ws, const double* u, double* ku, int nslices,
                     hipStream_t st);
 // frequency (k_freq.hip)

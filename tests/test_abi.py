@@ -167,3 +167,20 @@ def test_batch_plan_rejects_single_entry_points(P):
 def test_graph_and_timing_are_exclusive(P):
     with pytest.raises(P.PTError):
         P.Plan(W.config1(), graph=True, timing=True)
+
+
+def test_adjoint_entry_points_need_an_adjoint_plan(P):
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    plan = P.Plan(W.with_size(W.config1(), 8, 8))
+    dummy = C.c_void_p(0x1000)
+    assert lib.pt_adjoint_solve(plan._h, dummy, plan.workspace_bytes, dummy, dummy, None, None) == L.PT_ERR_INVALID
+    assert b"adjoint" in lib.pt_last_error()
+    assert lib.pt_loss_gradients(plan._h, dummy, plan.workspace_bytes, dummy, None, None, None, 0, None,
+                                 None) == L.PT_ERR_INVALID
+    adj = P.Plan(W.with_size(W.config1(), 8, 8), adjoint=True)
+    assert adj.workspace_bytes > plan.workspace_bytes
+    assert lib.pt_loss_gradients(adj._h, dummy, adj.workspace_bytes, dummy, None, None, None, 2, None,
+                                 None) == L.PT_ERR_INVALID
+    with pytest.raises(P.PTError):
+        P.BatchPlan([W.with_size(p, 8, 8) for p in W.config4(0, 2)], adjoint=True)
