@@ -112,10 +112,11 @@ typedef struct {
     int32_t xcd_remap;     /* 1: map workgroups to contiguous node ranges per XCD */
     int32_t timing;        /* 1: bracket every kernel launch of pt_solve with HIP events on
                               the solve stream and report per-kernel device time in pt_stats */
-    int32_t grid_slot;     /* workgroups the slot-vector sweeps (V-cycle, operator) aim for
-                              per slot chunk; 0 = 2048. Performance only (>= 8). */
+    int32_t grid_slot;     /* workgroups the slot-vector sweeps (V-cycle, operator) and the
+                              residual sweep aim for per slot chunk; 0 = 8192. Performance
+                              only (>= 8). */
     int32_t grid_team;     /* workgroups the per-node time-axis sweeps (DFT, inverse DFT)
-                              aim for; 0 = 16384. Performance only (>= 8). */
+                              aim for; 0 = 65536. Performance only (>= 8). */
     int32_t adjoint;       /* 1: reserve the workspace of pt_adjoint_solve / pt_loss_gradients
                               (two more time fields and a per-triangle table); single-problem
                               plans only */

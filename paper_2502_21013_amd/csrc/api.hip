@@ -85,11 +85,14 @@ static void sweep_geom(Geom& g, int side, int target_blocks, int cols = 0) {
     g.blocks = (int)blocks;
 }
 
-Geom slot_geom(int side, int S, int target_blocks) {
+Geom slot_geom(int side, int S, int V, int target_blocks) {
+    // S slots per node, V slots per lane: a workgroup row of slot_chunk lanes covers
+    // slot_chunk V slots; per_step columns per workgroup
     Geom g;
-    g.slot_chunk = S < kBlock ? S : kBlock;
+    const int lanes = S / V;
+    g.slot_chunk = lanes < kBlock ? lanes : kBlock;
     g.per_step = kBlock / g.slot_chunk;
-    g.chunks = S / g.slot_chunk;
+    g.chunks = lanes / g.slot_chunk;
     sweep_geom(g, side, target_blocks);
     return g;
 }
@@ -688,9 +691,9 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     }
     p.tm = nullptr;
     p.gr = nullptr;
-    p.target_slot = opts->grid_slot > 0 ? opts->grid_slot : 2048;
-    p.target_team = opts->grid_team > 0 ? opts->grid_team : 16384;
-    p.g_slot0 = slot_geom(p.side, p.ST, p.target_slot);
+    p.target_slot = opts->grid_slot > 0 ? opts->grid_slot : 8192;
+    p.target_team = opts->grid_team > 0 ? opts->grid_team : 65536;
+    p.g_slot0 = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
     p.g_team = team_geom(p.side, p.S, p.B, p.target_team);
     p.g_fwd = fwd_geom(p.side, p.S, p.B, p.target_slot);
     layout(p);

@@ -11,6 +11,8 @@
 // Multigrid: damped Jacobi smoothing with D = 4 nu_max + z diag(M), P1 interpolation P
 // between nested grids, restriction P^T, Galerkin coarse mass (k_setup.hip), exact solve
 // on the 2 x 2-cell grid (one unknown). One V(1,1) cycle is symmetric (B^T = B).
+#include <type_traits>
+
 #include "pt_device.h"
 
 namespace pt {
@@ -72,43 +74,137 @@ __device__ __forceinline__ MRow mrow(const LvArgs& L, long a) {
     return m;
 }
 
-// (A x)_a for interior node a with mass row m, given the 7 neighbour values of x.
-template <typename T, typename T2>
-__device__ __forceinline__ T2 apply_A(const MRow& m, T nu, const GS<T>& z, T2 xc, T2 xe, T2 xw, T2 xn, T2 xs,
-                                      T2 xne, T2 xsw) {
-    T2 Lx;
-    Lx.x = nu * ((T)4 * xc.x - xe.x - xw.x - xn.x - xs.x);
-    Lx.y = nu * ((T)4 * xc.y - xe.y - xw.y - xn.y - xs.y);
-    if (!m.any()) return Lx;
-    T2 Mx = scale2((T)m.c, xc);
-    Mx = fma2((T)m.e, xe, Mx);
-    Mx = fma2((T)m.w, xw, Mx);
-    Mx = fma2((T)m.n, xn, Mx);
-    Mx = fma2((T)m.s, xs, Mx);
-    Mx = fma2((T)m.ne, xne, Mx);
-    Mx = fma2((T)m.sw, xsw, Mx);
-    return add2(Lx, gs_apply(z, Mx));
+// V consecutive slots of one node held by one lane: V = 2 in FP32 mode (one 16-byte
+// access), V = 1 in FP64 mode (a double2). Slot vectors are read and written in these
+// units, which halves the memory instructions of the FP32 sweeps.
+template <typename T> struct LaneW;
+template <> struct LaneW<float> { static constexpr int V = 2; };
+template <> struct LaneW<double> { static constexpr int V = 1; };
+
+template <typename T> struct alignas(16) SV {
+    static constexpr int V = LaneW<T>::V;
+    typename Vec2<T>::type v[V];
+};
+
+template <typename T> __device__ __forceinline__ SV<T> sv_zero() {
+    SV<T> r;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) r.v[k] = mk2<T>(0, 0);
+    return r;
+}
+template <typename T> __device__ __forceinline__ SV<T> sv_add(const SV<T>& a, const SV<T>& b) {
+    SV<T> r;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) r.v[k] = add2(a.v[k], b.v[k]);
+    return r;
+}
+template <typename T> __device__ __forceinline__ SV<T> sv_sub(const SV<T>& a, const SV<T>& b) {
+    SV<T> r;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) r.v[k] = sub2(a.v[k], b.v[k]);
+    return r;
+}
+template <typename T> __device__ __forceinline__ SV<T> sv_scale(T s, const SV<T>& a) {
+    SV<T> r;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) r.v[k] = scale2(s, a.v[k]);
+    return r;
+}
+// acc + s a
+template <typename T> __device__ __forceinline__ SV<T> sv_fma(T s, const SV<T>& a, const SV<T>& acc) {
+    SV<T> r;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) r.v[k] = fma2(s, a.v[k], acc.v[k]);
+    return r;
+}
+
+// (A x)_a for interior node a with mass row m, given the 7 neighbour values of x; z[k] is
+// the shift of the lane's slot k.
+template <typename T>
+__device__ __forceinline__ SV<T> apply_A(const MRow& m, T nu, const GS<T>* z, const SV<T>& xc, const SV<T>& xe,
+                                         const SV<T>& xw, const SV<T>& xn, const SV<T>& xs, const SV<T>& xne,
+                                         const SV<T>& xsw) {
+    SV<T> out;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) {
+        out.v[k].x = nu * ((T)4 * xc.v[k].x - xe.v[k].x - xw.v[k].x - xn.v[k].x - xs.v[k].x);
+        out.v[k].y = nu * ((T)4 * xc.v[k].y - xe.v[k].y - xw.v[k].y - xn.v[k].y - xs.v[k].y);
+    }
+    if (!m.any()) return out;
+    const T mc = (T)m.c, me = (T)m.e, mw = (T)m.w, mn = (T)m.n, ms = (T)m.s, mne = (T)m.ne, msw = (T)m.sw;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) {
+        auto Mx = scale2(mc, xc.v[k]);
+        Mx = fma2(me, xe.v[k], Mx);
+        Mx = fma2(mw, xw.v[k], Mx);
+        Mx = fma2(mn, xn.v[k], Mx);
+        Mx = fma2(ms, xs.v[k], Mx);
+        Mx = fma2(mne, xne.v[k], Mx);
+        Mx = fma2(msw, xsw.v[k], Mx);
+        out.v[k] = add2(out.v[k], gs_apply(z[k], Mx));
+    }
+    return out;
+}
+
+// omega D^{-1} r with D = dl + z diag(M) (dm the node's diagonal mass entry)
+template <typename T>
+__device__ __forceinline__ SV<T> jacobi(T dl, T idl, T om, double dm, const GS<T>* z, const SV<T>& r) {
+    SV<T> out;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) {
+        GS<T> di = gs_inv_diag<T>(dl, idl, (T)dm, z[k]);
+        out.v[k] = scale2(om, gs_apply(di, r.v[k]));
+    }
+    return out;
+}
+
+template <typename T> __device__ __forceinline__ void sv_dot_acc(double (*acc)[3], const SV<T>& u, const SV<T>& v,
+                                                                bool conj) {
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) dot3_acc(acc[k], u.v[k], v.v[k], conj);
+}
+
+// Lane geometry of the slot-vector kernels: a workgroup row of SC lanes covers SC V
+// consecutive slots; lane ls of slot chunk blockIdx.y starts at slot s0.
+template <typename T> struct SlotLane {
+    int ls, ln, s0;
+    GS<T> z[SV<T>::V];
+};
+
+template <typename T> __device__ __forceinline__ SlotLane<T> slot_lane(const SlotArgs& sa) {
+    SlotLane<T> L;
+    constexpr int V = SV<T>::V;
+    L.ls = threadIdx.x % sa.slot_chunk;
+    L.ln = threadIdx.x / sa.slot_chunk;
+    L.s0 = (blockIdx.y * sa.slot_chunk + L.ls) * V;
+#pragma unroll
+    for (int k = 0; k < V; ++k) L.z[k] = load_shift<T>(sa.zs, L.s0 + k);
+    return L;
 }
 
 // ---------------------------------------------------------------- dot-product partials
 
 // Reduce the per-thread partial sums of a workgroup over threads sharing a slot and
-// store them at part[(vb * S + s) * 3 + c].
-__device__ __forceinline__ void store_dot_partials(const double* acc, double* part, int vb, int S, int chunk, int SC) {
-    __shared__ double red[3][kBlock];
-    red[0][threadIdx.x] = acc[0];
-    red[1][threadIdx.x] = acc[1];
-    red[2][threadIdx.x] = acc[2];
+// store them at part[(vb * ST + s) * 3 + c].
+template <int V>
+__device__ __forceinline__ void store_dot_partials(const double (*acc)[3], double* part, int vb, int ST, int chunk,
+                                                   int SC) {
+    __shared__ double red[3][kBlock * V];
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) red[c][threadIdx.x * V + k] = acc[k][c];
     __syncthreads();
-    if ((int)threadIdx.x < SC) {
+    const int SL = SC * V;  // slots per workgroup row
+    for (int q = threadIdx.x; q < SL; q += kBlock) {
         double s0 = 0, s1 = 0, s2 = 0;
-        for (int t = threadIdx.x; t < kBlock; t += SC) {
+        for (int t = q; t < kBlock * V; t += SL) {
             s0 += red[0][t];
             s1 += red[1][t];
             s2 += red[2][t];
         }
-        size_t s = (size_t)chunk * SC + threadIdx.x;
-        double* o = part + ((size_t)vb * S + s) * 3;
+        const size_t s = (size_t)chunk * SL + q;
+        double* o = part + ((size_t)vb * ST + s) * 3;
         o[0] = s0;
         o[1] = s1;
         o[2] = s2;
@@ -118,7 +214,7 @@ __device__ __forceinline__ void store_dot_partials(const double* acc, double* pa
 // ---------------------------------------------------------------- V-cycle: down
 
 // r_c = P^T (r - A x1) with the pre-smoothed x1 = omega D^{-1} r (one Jacobi sweep from
-// zero). Thread (coarse column ci, slot) walks up the fine rows R around fine column
+// zero). Thread (coarse column ci, slots) walks up the fine rows R around fine column
 // c = 2 ci with a 3-row x 5-column register window of x1 (rows R-1..R+1, columns
 // c-2..c+2), forms the fine residual s = r - A x1 at columns c-1, c, c+1 of row R and adds
 // it into the coarse rows it belongs to with the P^T weights: row 2cj-1 contributes
@@ -127,41 +223,40 @@ __device__ __forceinline__ void store_dot_partials(const double* acc, double* pa
 // row R+2 are loaded before row R is computed.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_, void* rout_) {
-    using T2 = typename Vec2<T>::type;
-    const T2* rin = (const T2*)rin_;
-    T2* rout = (T2*)rout_;
-    const int ST = sa.ST, lgST = sa.lgST, SC = sa.slot_chunk;
-    const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
-    const int s = blockIdx.y * SC + ls;
+    using W = SV<T>;
+    const W* rin = (const W*)rin_;
+    W* rout = (W*)rout_;
+    const int lgST = sa.lgST;
+    const SlotLane<T> L = slot_lane<T>(sa);
     const int vb = virtual_block(sa.remap);
-    const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl;
     const int sf = F.side, nF = F.n, sc = C.side, nc = C.n;
     const long nd = (long)F.nodes;
     const T half = (T)0.5;
-    const unsigned E = sizeof(T2);
+    const unsigned E = sizeof(typename Vec2<T>::type);
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, sc);
-    int ci = sr.col0 + ln;
+    int ci = sr.col0 + L.ln;
     if (UNI) ci = __builtin_amdgcn_readfirstlane(ci);
     if (ci >= sc) return;
-    const T2 zero = mk2<T>(0, 0);
-    const unsigned oco = (((unsigned)ci << lgST) + s) * E;
+    const W zero = sv_zero<T>();
+    const unsigned oco = (((unsigned)ci << lgST) + L.s0) * E;
     // boundary coarse nodes of this chunk are zero
     for (int cj = sr.row0; cj < sr.row1; ++cj)
-        if (ci == 0 || ci == nc || cj == 0 || cj == nc) *boff(row_of(rout, cj, sc, lgST), oco) = zero;
+        if (ci == 0 || ci == nc || cj == 0 || cj == nc) *boff(row_of(rout, cj, sc, lgST - (W::V - 1)), oco) = zero;
     if (ci == 0 || ci == nc) return;
     const int cj0 = sr.row0 > 1 ? sr.row0 : 1;
     const int cj1 = sr.row1 < nc ? sr.row1 : nc;  // interior coarse rows [cj0, cj1)
     if (cj0 >= cj1) return;
     const int c = 2 * ci;
+    const int lgR = lgST - (W::V - 1);  // row stride in lane units: 2^lgST slots = 2^lgR units
     unsigned of[5];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) of[d] = (((unsigned)(c - 2 + d) << lgST) + s) * E;
+    for (int d = 0; d < 5; ++d) of[d] = (((unsigned)(c - 2 + d) << lgST) + L.s0) * E;
     // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
-    T2 xa[5], xb[5], xq[5], rb[3], rq[3];
-    auto fetch_row = [&](int R, T2* rv, double* mv) {
+    W xa[5], xb[5], xq[5], rb[3], rq[3];
+    auto fetch_row = [&](int R, W* rv, double* mv) {
         if (R >= 0 && R <= nF) {
-            const T2* fr = row_of(rin, R, sf, lgST);
+            const W* fr = row_of(rin, R, sf, lgR);
             const double* mr = F.mt + (long)R * sf + (c - 2);
 #pragma unroll
             for (int d = 0; d < 5; ++d) {
@@ -176,17 +271,16 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             }
         }
     };
-    auto eval_row = [&](const T2* rv, const double* mv, T2* xr, T2* rr) {
+    auto eval_row = [&](const W* rv, const double* mv, W* xr, W* rr) {
 #pragma unroll
         for (int d = 0; d < 5; ++d) {
-            GS<T> di = gs_inv_diag<T>(dl, idl, (T)mv[d], z);
-            xr[d] = scale2(om, gs_apply(di, rv[d]));
+            xr[d] = jacobi<T>(dl, idl, om, mv[d], L.z, rv[d]);
             if (d >= 1 && d <= 3) rr[d - 1] = rv[d];
         }
     };
     const int Rs = 2 * cj0 - 1, Re = 2 * cj1 - 1;
     {
-        T2 rv[5], dummy[3];
+        W rv[5], dummy[3];
         double mv[5];
         fetch_row(Rs - 1, rv, mv);
         eval_row(rv, mv, xa, dummy);
@@ -195,14 +289,14 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
         fetch_row(Rs + 1, rv, mv);
         eval_row(rv, mv, xq, rq);
     }
-    T2 acc = zero;
+    W acc = zero;
     for (int R = Rs; R <= Re; ++R) {
-        T2 nr[5];
+        W nr[5];
         double nm[5];
         if (R < Re) fetch_row(R + 2, nr, nm);  // next row's inputs, loaded before this row is computed
         // s = r - A x1 at (c-1+k, R), k = 0..2; window rows: xa = R-1, xb = R, xq = R+1
         const double* m0 = F.mt + (long)R * sf + (c - 1);
-        T2 sv[3];
+        W sv[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double* mp = m0 + k;
@@ -214,20 +308,20 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             m.s = mp[2 * nd - sf];
             m.ne = mp[3 * nd];
             m.sw = mp[3 * nd - sf - 1];
-            T2 Ax = apply_A<T, T2>(m, nu, z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1], xa[k + 1], xq[k + 2], xa[k]);
-            sv[k] = sub2(rb[k], Ax);
+            W Ax = apply_A<T>(m, nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1], xa[k + 1], xq[k + 2], xa[k]);
+            sv[k] = sv_sub(rb[k], Ax);
         }
         if (R & 1) {
             if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
-                acc = fma2(half, sv[1], acc);
-                acc = fma2(half, sv[2], acc);
-                *boff(row_of(rout, (R - 1) / 2, sc, lgST), oco) = acc;
+                acc = sv_fma(half, sv[1], acc);
+                acc = sv_fma(half, sv[2], acc);
+                *boff(row_of(rout, (R - 1) / 2, sc, lgR), oco) = acc;
             }
-            acc = scale2(half, add2(sv[0], sv[1]));  // lower row of coarse row (R+1)/2
+            acc = sv_scale(half, sv_add(sv[0], sv[1]));  // lower row of coarse row (R+1)/2
         } else {
-            acc = fma2(half, sv[0], acc);
-            acc = add2(acc, sv[1]);
-            acc = fma2(half, sv[2], acc);
+            acc = sv_fma(half, sv[0], acc);
+            acc = sv_add(acc, sv[1]);
+            acc = sv_fma(half, sv[2], acc);
         }
         if (R < Re) {
 #pragma unroll
@@ -268,43 +362,20 @@ __global__ void __launch_bounds__(kBlock) k_vc_coarsest(SlotArgs sa, LvArgs C, c
 
 // ---------------------------------------------------------------- V-cycle: up
 
-template <typename T2>
-__device__ __forceinline__ T2 prolong_at(const T2* xc, int sc, int S, int s, int bi, int bj) {
-    int hi = bi >> 1, hj = bj >> 1;
-    bool oi = bi & 1, oj = bj & 1;
-    if (!oi && !oj) return xc[((size_t)hj * sc + hi) * S + s];
-    T2 p, q;
-    if (oi && !oj) {
-        p = xc[((size_t)hj * sc + hi) * S + s];
-        q = xc[((size_t)hj * sc + hi + 1) * S + s];
-    } else if (!oi && oj) {
-        p = xc[((size_t)hj * sc + hi) * S + s];
-        q = xc[((size_t)(hj + 1) * sc + hi) * S + s];
-    } else {
-        p = xc[((size_t)hj * sc + hi) * S + s];
-        q = xc[((size_t)(hj + 1) * sc + hi + 1) * S + s];
-    }
-    T2 r;
-    r.x = (p.x + q.x) * 0.5f;
-    r.y = (p.y + q.y) * 0.5f;
-    return r;
-}
-
 // Raw inputs of the pre-smoothed, coarse-corrected value x2 at one fine node: r, the
 // diagonal mass entry and the (one or two) coarse values its P1 interpolation uses.
-template <typename T2> struct UpIn {
-    T2 r, c0, c1;
+template <typename W> struct UpIn {
+    W r, c0, c1;
     double mc;
     int kind;  // 0: outside the grid rows, 1: coincides with a coarse node, 2: edge midpoint
 };
 
-template <typename T, typename T2>
-__device__ __forceinline__ T2 up_eval(const UpIn<T2>& u, T dl, T idl, T om, const GS<T>& z) {
-    if (u.kind == 0) return mk2<T>(0, 0);
-    GS<T> di = gs_inv_diag<T>(dl, idl, (T)u.mc, z);
-    T2 v = scale2(om, gs_apply(di, u.r));
-    if (u.kind == 1) return add2(v, u.c0);
-    return fma2((T)0.5, add2(u.c0, u.c1), v);
+template <typename T>
+__device__ __forceinline__ SV<T> up_eval(const UpIn<SV<T>>& u, T dl, T idl, T om, const GS<T>* z) {
+    if (u.kind == 0) return sv_zero<T>();
+    SV<T> v = jacobi<T>(dl, idl, om, u.mc, z, u.r);
+    if (u.kind == 1) return sv_add(v, u.c0);
+    return sv_fma((T)0.5, sv_add(u.c0, u.c1), v);
 }
 
 // x2 = omega D^{-1} r + P x_c (pre-smoothed iterate plus coarse correction), then one
@@ -316,21 +387,20 @@ __device__ __forceinline__ T2 up_eval(const UpIn<T2>& u, T dl, T idl, T om, cons
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
-    using T2 = typename Vec2<T>::type;
-    const T2* rin = (const T2*)rin_;
-    const T2* xc = (const T2*)xc_;
-    T2* xout = (T2*)xout_;
-    const int ST = sa.ST, lgST = sa.lgST, SC = sa.slot_chunk;
-    const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
-    const int s = blockIdx.y * SC + ls;
+    using W = SV<T>;
+    constexpr int V = W::V;
+    const W* rin = (const W*)rin_;
+    const W* xc = (const W*)xc_;
+    W* xout = (W*)xout_;
+    const int ST = sa.ST, lgST = sa.lgST, lgR = lgST - (V - 1), SC = sa.slot_chunk;
+    const SlotLane<T> L = slot_lane<T>(sa);
     const int vb = virtual_block(sa.remap);
-    const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl;
     const int sf = F.side, nF = F.n, sc = C.side;
-    const unsigned E = sizeof(T2);
-    double acc[3] = {0, 0, 0};
+    const unsigned E = sizeof(typename Vec2<T>::type);
+    double acc[V][3] = {};
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
-    int ai = sr.col0 + ln;
+    int ai = sr.col0 + L.ln;
     if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
         // per-lane byte offsets: fine columns ai-1, ai, ai+1; their coarse columns hi and hi + (bi & 1)
@@ -340,134 +410,146 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
         for (int d = 0; d < 3; ++d) {
             const int bi = ai - 1 + d, hi = bi >> 1;
             odd[d] = bi & 1;
-            ofn[d] = (((unsigned)bi << lgST) + s) * E;
-            och[d] = (((unsigned)hi << lgST) + s) * E;
-            ocq[d] = (((unsigned)(hi + (bi & 1)) << lgST) + s) * E;
+            ofn[d] = (((unsigned)bi << lgST) + L.s0) * E;
+            och[d] = (((unsigned)hi << lgST) + L.s0) * E;
+            ocq[d] = (((unsigned)(hi + (bi & 1)) << lgST) + L.s0) * E;
         }
-        auto load = [&](int d, int bj) -> UpIn<T2> {
-            UpIn<T2> u;
+        auto load = [&](int d, int bj) -> UpIn<W> {
+            UpIn<W> u;
             if (bj < 0 || bj > nF) {
                 u.kind = 0;
-                u.r = u.c0 = u.c1 = mk2<T>(0, 0);
+                u.r = u.c0 = u.c1 = sv_zero<T>();
                 u.mc = 0.0;
                 return u;
             }
-            u.r = *cboff(row_of(rin, bj, sf, lgST), ofn[d]);
+            u.r = *cboff(row_of(rin, bj, sf, lgR), ofn[d]);
             u.mc = F.mt[(long)bj * sf + ai - 1 + d];
             const int hj = bj >> 1, oj = bj & 1;
-            u.c0 = *cboff(row_of(xc, hj, sc, lgST), och[d]);
+            u.c0 = *cboff(row_of(xc, hj, sc, lgR), och[d]);
             if (!odd[d] && !oj) {
                 u.kind = 1;
-                u.c1 = mk2<T>(0, 0);
+                u.c1 = sv_zero<T>();
             } else {
                 u.kind = 2;
-                u.c1 = *cboff(row_of(xc, hj + oj, sc, lgST), ocq[d]);
+                u.c1 = *cboff(row_of(xc, hj + oj, sc, lgR), ocq[d]);
             }
             return u;
         };
         const int j0 = sr.row0;
-        UpIn<T2> q0 = load(0, j0 - 1), q1 = load(1, j0 - 1), q2 = load(0, j0), q3 = load(1, j0), q4 = load(2, j0);
-        UpIn<T2> q5 = load(1, j0 + 1), q6 = load(2, j0 + 1);
-        T2 xsw = up_eval(q0, dl, idl, om, z), xs = up_eval(q1, dl, idl, om, z);
-        T2 xw = up_eval(q2, dl, idl, om, z), xcn = up_eval(q3, dl, idl, om, z), xe = up_eval(q4, dl, idl, om, z);
-        T2 xn = up_eval(q5, dl, idl, om, z), xne = up_eval(q6, dl, idl, om, z);
-        T2 rc = q3.r, rn = q5.r;
+        W xsw, xs, xw, xcn, xe, xn, xne, rc, rn;
+        {
+            const UpIn<W> q0 = load(0, j0 - 1), q1 = load(1, j0 - 1), q2 = load(0, j0), q3 = load(1, j0),
+                          q4 = load(2, j0), q5 = load(1, j0 + 1), q6 = load(2, j0 + 1);
+            xsw = up_eval(q0, dl, idl, om, L.z);
+            xs = up_eval(q1, dl, idl, om, L.z);
+            xw = up_eval(q2, dl, idl, om, L.z);
+            xcn = up_eval(q3, dl, idl, om, L.z);
+            xe = up_eval(q4, dl, idl, om, L.z);
+            xn = up_eval(q5, dl, idl, om, L.z);
+            xne = up_eval(q6, dl, idl, om, L.z);
+            rc = q3.r;
+            rn = q5.r;
+        }
         for (int aj = j0; aj < sr.row1; ++aj) {
             const bool more = aj + 1 < sr.row1;
-            UpIn<T2> p0, p1, p2;
+            UpIn<W> p0, p1, p2;
             if (more) {
                 p0 = load(0, aj + 1);
                 p1 = load(1, aj + 2);
                 p2 = load(2, aj + 2);
             }
-            T2 out = mk2<T>(0, 0);
+            W out = sv_zero<T>();
             if (aj > 0 && aj < nF) {
                 const long a = (long)aj * sf + ai;
-                T2 Ax = apply_A<T, T2>(mrow(F, a), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
-                GS<T> da = gs_inv_diag<T>(dl, idl, (T)F.mt[a], z);
-                out = add2(xcn, scale2(om, gs_apply(da, sub2(rc, Ax))));
-                if (dotmode != DOT_NONE) dot3_acc(acc, out, rc, dotmode == DOT_HERM);
+                W Ax = apply_A<T>(mrow(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
+                out = sv_add(xcn, jacobi<T>(dl, idl, om, F.mt[a], L.z, sv_sub(rc, Ax)));
+                if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
             }
-            *boff(row_of(xout, aj, sf, lgST), ofn[1]) = out;
+            *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
             if (more) {
                 xsw = xw;
                 xs = xcn;
-                xw = up_eval(p0, dl, idl, om, z);
+                xw = up_eval(p0, dl, idl, om, L.z);
                 xcn = xn;
                 rc = rn;
                 xe = xne;
-                xn = up_eval(p1, dl, idl, om, z);
+                xn = up_eval(p1, dl, idl, om, L.z);
                 rn = p1.r;
-                xne = up_eval(p2, dl, idl, om, z);
+                xne = up_eval(p2, dl, idl, om, L.z);
             }
         }
     } else if (ai < sf) {
-        const unsigned oc = (((unsigned)ai << lgST) + s) * E;
-        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, lgST), oc) = mk2<T>(0, 0);
+        const unsigned oc = (((unsigned)ai << lgST) + L.s0) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, lgR), oc) = sv_zero<T>();
     }
-    if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, ST, blockIdx.y, SC);
+    if (dotmode != DOT_NONE) store_dot_partials<V>(acc, part, vb, ST, blockIdx.y, SC);
 }
 
 // ---------------------------------------------------------------- operator apply
 
-// y = A x and the dot partials of (x, A x); rolling window along the column as in k_vc_up.
+// y = A x and the dot partials of (x, A x); rolling window along the column as in k_vc_up,
+// kept in row slots modulo 4 (row aj in slot (aj - j0 + 1) & 3) with the row loop unrolled
+// by 4, so that the window is addressed with compile-time slots and never moved.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const void* x_, void* y_, int dotmode,
                                                    double* part) {
-    using T2 = typename Vec2<T>::type;
-    const T2* x = (const T2*)x_;
-    T2* y = (T2*)y_;
-    const int ST = sa.ST, lgST = sa.lgST, SC = sa.slot_chunk;
-    const int ls = threadIdx.x % SC, ln = threadIdx.x / SC;
-    const int s = blockIdx.y * SC + ls;
+    using W = SV<T>;
+    constexpr int V = W::V;
+    const W* x = (const W*)x_;
+    W* y = (W*)y_;
+    const int ST = sa.ST, lgST = sa.lgST, lgR = lgST - (V - 1), SC = sa.slot_chunk;
+    const SlotLane<T> L = slot_lane<T>(sa);
     const int vb = virtual_block(sa.remap);
-    const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu;
     const int sf = F.side, nF = F.n;
-    const unsigned E = sizeof(T2);
-    double acc[3] = {0, 0, 0};
+    const unsigned E = sizeof(typename Vec2<T>::type);
+    double acc[V][3] = {};
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
-    int ai = sr.col0 + ln;
+    int ai = sr.col0 + L.ln;
     if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
-        const unsigned ow = (((unsigned)(ai - 1) << lgST) + s) * E, oc = ow + (unsigned)ST * E,
+        const unsigned ow = (((unsigned)(ai - 1) << lgST) + L.s0) * E, oc = ow + (unsigned)ST * E,
                        oe = oc + (unsigned)ST * E;
-        auto ld = [&](unsigned o, int bj) -> T2 {
-            if (bj < 0 || bj > nF) return mk2<T>(0, 0);
-            return *cboff(row_of(x, bj, sf, lgST), o);
+        auto ld = [&](unsigned o, int bj) -> W {
+            if (bj < 0 || bj > nF) return sv_zero<T>();
+            return *cboff(row_of(x, bj, sf, lgR), o);
         };
         const int j0 = sr.row0;
-        T2 xsw = ld(ow, j0 - 1), xs = ld(oc, j0 - 1), xw = ld(ow, j0), xcn = ld(oc, j0), xe = ld(oe, j0);
-        T2 xn = ld(oc, j0 + 1), xne = ld(oe, j0 + 1);
-        for (int aj = j0; aj < sr.row1; ++aj) {
-            const bool more = aj + 1 < sr.row1;
-            T2 nw, n2, ne2;
-            if (more) {  // next row's new points, loaded before this row is computed
-                nw = ld(ow, aj + 1);
-                n2 = ld(oc, aj + 2);
-                ne2 = ld(oe, aj + 2);
+        W Wc[4], Cc[4], Ec[4];
+        Wc[0] = ld(ow, j0 - 1);
+        Cc[0] = ld(oc, j0 - 1);
+        Wc[1] = ld(ow, j0);
+        Cc[1] = ld(oc, j0);
+        Ec[1] = ld(oe, j0);
+        Cc[2] = ld(oc, j0 + 1);
+        Ec[2] = ld(oe, j0 + 1);
+        auto row = [&](int aj, auto r_) {
+            constexpr int r = decltype(r_)::value;  // slot of row aj - 1
+            constexpr int s0 = r, s1 = (r + 1) & 3, s2 = (r + 2) & 3, s3 = (r + 3) & 3;
+            if (aj + 1 < sr.row1) {  // next row's new points, loaded before this row is computed
+                Wc[s2] = ld(ow, aj + 1);
+                Cc[s3] = ld(oc, aj + 2);
+                Ec[s3] = ld(oe, aj + 2);
             }
-            T2 out = mk2<T>(0, 0);
+            W out = sv_zero<T>();
             if (aj > 0 && aj < nF) {
-                out = apply_A<T, T2>(mrow(F, (long)aj * sf + ai), nu, z, xcn, xe, xw, xn, xs, xne, xsw);
-                if (dotmode != DOT_NONE) dot3_acc(acc, xcn, out, dotmode == DOT_HERM);
+                out = apply_A<T>(mrow(F, (long)aj * sf + ai), nu, L.z, Cc[s1], Ec[s1], Wc[s1], Cc[s2], Cc[s0], Ec[s2],
+                                 Wc[s0]);
+                if (dotmode != DOT_NONE) sv_dot_acc(acc, Cc[s1], out, dotmode == DOT_HERM);
             }
-            if (y) *boff(row_of(y, aj, sf, lgST), oc) = out;
-            if (more) {
-                xsw = xw;
-                xs = xcn;
-                xw = nw;
-                xcn = xn;
-                xe = xne;
-                xn = n2;
-                xne = ne2;
-            }
+            if (y) *boff(row_of(y, aj, sf, lgR), oc) = out;
+        };
+        for (int aj = j0; aj < sr.row1; aj += 4) {
+            row(aj, std::integral_constant<int, 0>());
+            if (aj + 1 < sr.row1) row(aj + 1, std::integral_constant<int, 1>());
+            if (aj + 2 < sr.row1) row(aj + 2, std::integral_constant<int, 2>());
+            if (aj + 3 < sr.row1) row(aj + 3, std::integral_constant<int, 3>());
         }
     } else if (ai < sf && y) {
-        const unsigned oc = (((unsigned)ai << lgST) + s) * E;
-        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, lgST), oc) = mk2<T>(0, 0);
+        const unsigned oc = (((unsigned)ai << lgST) + L.s0) * E;
+        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, lgR), oc) = sv_zero<T>();
     }
-    if (dotmode != DOT_NONE) store_dot_partials(acc, part, vb, ST, blockIdx.y, SC);
+    if (dotmode != DOT_NONE) store_dot_partials<V>(acc, part, vb, ST, blockIdx.y, SC);
 }
 
 // ---------------------------------------------------------------- per-slot scalars
@@ -633,7 +715,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
     for (int l = 0; l + 1 < L; ++l) {
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* rout = ws + p.lev[l + 1].off_r;
-        Geom g = slot_geom(p.lev[l + 1].side, p.ST, p.target_slot);
+        Geom g = slot_geom(p.lev[l + 1].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int kid = (l == 0) ? KID_DOWN0 : KID_DOWNC;
@@ -654,7 +736,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         tm_end(p, kid, st);
     }
     {
-        Geom g = slot_geom(p.lev[L - 1].side, p.ST, p.target_slot);
+        Geom g = slot_geom(p.lev[L - 1].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         const void* rin = (L == 1) ? r0 : (const void*)(ws + p.lev[L - 1].off_r);
         void* xout = (L == 1) ? x0 : (void*)(ws + p.lev[L - 1].off_x);
@@ -672,7 +754,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* xout = (l == 0) ? x0 : (void*)(ws + p.lev[l].off_x);
         const void* xc = ws + p.lev[l + 1].off_x;
-        Geom g = slot_geom(p.lev[l].side, p.ST, p.target_slot);
+        Geom g = slot_geom(p.lev[l].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int dm = (l == 0) ? dotmode : DOT_NONE;
