@@ -22,26 +22,58 @@ namespace pt {
 
 // ---------------------------------------------------------------- in-LDS complex FFT
 
-// Forward (unnormalised) complex DFT of length S of the team's buffer a, Stockham
+// Forward (unnormalised) complex DFT of length S of the team's buffer a in LDS, Stockham
 // radix-4 stages and one radix-2 stage when log2 S is odd; b is scratch. tw[k] =
 // exp(-2 pi i k / N) for k < N (so exp(-2 pi i m / S) = tw[2 m]). Every thread of the
 // workgroup must call it (it synchronises the workgroup). Returns the result buffer.
+// Every lane of the team (S/4 lanes) owns exactly one butterfly of each radix-4 stage and
+// two of the radix-2 stage: the twiddles of a lane do not change from one node to the
+// next, so they are read from the table once per kernel and kept in registers (LaneFft)
+// instead of being fetched for every transform.
+constexpr int kFftMaxR4 = 5;  // radix-4 stages for S <= 1024
+
+template <typename T2> struct LaneFft {
+    T2 w[kFftMaxR4][3];
+    T2 w2[2];
+};
+
+template <typename T2> __device__ __forceinline__ LaneFft<T2> lane_fft_twiddles(const T2* tw, int S, int lt, int TS) {
+    LaneFft<T2> L;
+    int Ns = 1;
+#pragma unroll
+    for (int st = 0; st < kFftMaxR4; ++st) {
+        const bool on = Ns * 4 <= S;
+        const int k = lt & (Ns - 1), stp = on ? S / (2 * Ns) : 0;
+        L.w[st][0] = tw[k * stp];
+        L.w[st][1] = tw[2 * k * stp];
+        L.w[st][2] = tw[3 * k * stp];
+        if (on) Ns *= 4;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = lt + h * TS, k = j & (Ns - 1);
+        L.w2[h] = (Ns < S) ? tw[(k * (S / Ns)) & (2 * S - 1)] : tw[0];
+    }
+    return L;
+}
+
 template <typename T2>
-__device__ T2* fft_team(T2* a, T2* b, int S, int lt, int TS, const T2* __restrict__ tw) {
+__device__ __forceinline__ T2* fft_lane(T2* a, T2* b, int S, int lt, int TS, const LaneFft<T2>& L) {
     int Ns = 1;
     const int Q = S >> 2;
-    while (Ns * 4 <= S) {
-        for (int j = lt; j < Q; j += TS) {
-            int k = j & (Ns - 1);
+#pragma unroll
+    for (int st = 0; st < kFftMaxR4; ++st) {
+        if (Ns * 4 > S) break;
+        if (lt < Q) {
+            const int j = lt, k = j & (Ns - 1);
             T2 v0 = a[j], v1 = a[j + Q], v2 = a[j + 2 * Q], v3 = a[j + 3 * Q];
-            if (Ns > 1) {
-                int st = S / (2 * Ns);
-                v1 = cmul(v1, tw[k * st]);
-                v2 = cmul(v2, tw[2 * k * st]);
-                v3 = cmul(v3, tw[3 * k * st]);
+            if (st > 0) {
+                v1 = cmul(v1, L.w[st][0]);
+                v2 = cmul(v2, L.w[st][1]);
+                v3 = cmul(v3, L.w[st][2]);
             }
             T2 t0 = add2(v0, v2), t1 = sub2(v0, v2), t2 = add2(v1, v3), t3 = mul_mi(sub2(v1, v3));
-            int idx = (j / Ns) * Ns * 4 + k;
+            const int idx = (j / Ns) * Ns * 4 + k;
             b[idx] = add2(t0, t2);
             b[idx + Ns] = add2(t1, t3);
             b[idx + 2 * Ns] = sub2(t0, t2);
@@ -55,13 +87,17 @@ __device__ T2* fft_team(T2* a, T2* b, int S, int lt, int TS, const T2* __restric
     }
     if (Ns < S) {
         const int H = S >> 1;
-        for (int j = lt; j < H; j += TS) {
-            int k = j & (Ns - 1);
-            T2 v0 = a[j];
-            T2 v1 = cmul(a[j + H], tw[k * S / Ns]);
-            int idx = (j / Ns) * Ns * 2 + k;
-            b[idx] = add2(v0, v1);
-            b[idx + Ns] = sub2(v0, v1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lt + h * TS;
+            if (j < H) {
+                const int k = j & (Ns - 1);
+                T2 v0 = a[j];
+                T2 v1 = cmul(a[j + H], L.w2[h]);
+                const int idx = (j / Ns) * Ns * 2 + k;
+                b[idx] = add2(v0, v1);
+                b[idx + Ns] = sub2(v0, v1);
+            }
         }
         __syncthreads();
         T2* t = a;
@@ -70,6 +106,11 @@ __device__ T2* fft_team(T2* a, T2* b, int S, int lt, int TS, const T2* __restric
     }
     return a;
 }
+
+// Two consecutive slot values (one 16-byte access in FP32).
+template <typename T2> struct alignas(16) Pair {
+    T2 a, b;
+};
 
 // ---------------------------------------------------------------- forward kernel
 
@@ -428,37 +469,71 @@ __global__ void __launch_bounds__(kBlock) k_rfft(RfftArgs a) {
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T2* smem = (T2*)smem_raw;
-    const int TS = a.ts, S = a.S;
+    const int TS = a.ts, S = a.S, H = S / 2;
     const int lt = threadIdx.x % TS, team = threadIdx.x / TS;
     T2* buf0 = smem + (size_t)team * 2 * S;
     T2* buf1 = buf0 + S;
     const T2* tw = (const T2*)a.tw;
-    const T2* rt = (const T2*)a.rt;
+    const Pair<T2>* rtp = (const Pair<T2>*)a.rt;
+    Pair<T2>* outp = (Pair<T2>*)a.out;
+    const LaneFft<T2> LF = lane_fft_twiddles<T2>(tw, S, lt, TS);
+    // the lane owns the slot pairs q = lt + h TS (h = 0, 1): slots 2q, 2q + 1
+    T2 pw[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = (lt + h * TS) < H ? lt + h * TS : 0;
+        pw[h][0] = tw[2 * q];
+        pw[h][1] = tw[2 * q + 1];
+    }
     const int vb = virtual_block(a.remap);
     const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, a.side);
     const int vcol = sr.col0 + team;  // b (n+1) + i
     const bool colvalid = vcol < a.side * a.B;
     const int bi = vcol / a.side, i = vcol - bi * a.side;
     for (int j = sr.row0; j < sr.row1; ++j) {
-        const size_t chunk = colvalid ? ((size_t)j * a.side + i) * a.ST + (size_t)bi * S : 0;
-        for (int m = lt; m < S; m += TS) buf0[m] = colvalid ? rt[chunk + m] : mk2<T>(0, 0);
-        __syncthreads();
-        T2* res = fft_team<T2>(buf0, buf1, S, lt, TS, tw);
-        if (colvalid) {
-            T2* out = (T2*)a.out + chunk;
-            for (int k = lt; k < S; k += TS) {
-                T2 X;
-                if (k == 0) {
-                    T2 z0 = res[0];
-                    X = mk2<T>(z0.x + z0.y, z0.x - z0.y);
+        const size_t chunk = colvalid ? ((size_t)j * a.side + i) * a.ST + (size_t)bi * S : 0;  // even
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = lt + h * TS;
+            if (q < H) {
+                Pair<T2> v;
+                if (colvalid) {
+                    v = rtp[chunk / 2 + q];
                 } else {
-                    T2 zk = res[k], zc = conj2(res[S - k]);
-                    T2 E = scale2((T)0.5, add2(zk, zc));
-                    T2 O = scale2((T)0.5, mul_mi(sub2(zk, zc)));
-                    X = add2(E, cmul(tw[k], O));
-                    if (a.conj) X = conj2(X);
+                    v.a = mk2<T>(0, 0);
+                    v.b = v.a;
                 }
-                out[k] = X;
+                buf0[2 * q] = v.a;
+                buf0[2 * q + 1] = v.b;
+            }
+        }
+        __syncthreads();
+        T2* res = fft_lane<T2>(buf0, buf1, S, lt, TS, LF);
+        if (colvalid) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = lt + h * TS;
+                if (q < H) {
+                    T2 X[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int k = 2 * q + e;
+                        if (k == 0) {
+                            T2 z0 = res[0];
+                            X[e] = mk2<T>(z0.x + z0.y, z0.x - z0.y);
+                        } else {
+                            T2 zk = res[k], zc = conj2(res[S - k]);
+                            T2 E = scale2((T)0.5, add2(zk, zc));
+                            T2 O = scale2((T)0.5, mul_mi(sub2(zk, zc)));
+                            X[e] = add2(E, cmul(pw[h][e], O));
+                            if (a.conj) X[e] = conj2(X[e]);
+                        }
+                    }
+                    Pair<T2> o;
+                    o.a = X[0];
+                    o.b = X[1];
+                    outp[chunk / 2 + q] = o;
+                }
             }
         }
         __syncthreads();
@@ -615,50 +690,85 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T2* smem = (T2*)smem_raw;
-    const int TS = a.ts, S = a.S, N = a.N;
+    const int TS = a.ts, S = a.S, H = S / 2;
     const int lt = threadIdx.x % TS, team = threadIdx.x / TS;
     T2* buf0 = smem + (size_t)team * 2 * S;
     T2* buf1 = buf0 + S;
     const T2* tw = (const T2*)a.tw;
     const T invS = (T)1 / (T)S;
+    const LaneFft<T2> LF = lane_fft_twiddles<T2>(tw, S, lt, TS);
     const int vb = virtual_block(a.remap);
     const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, a.side);
     const int vcol = sr.col0 + team;  // b (n+1) + i
     const bool valid = vcol < a.side * a.B;
-    const int bi = vcol / a.side, i = vcol - bi * a.side;
+    const int bi = valid ? vcol / a.side : 0, i = vcol - bi * a.side;
+    // per-lane constants of the slot pairs q = lt + h TS: twiddles and coefficients of slots 2q, 2q+1
+    T2 pw[2][2];
+    GS<T> cf[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = (lt + h * TS) < H ? lt + h * TS : 0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int k = 2 * q + e;
+            pw[h][e] = conj2(tw[k]);
+            if (a.coef) {
+                cf[h][e] = gs_from<T>(((const double2*)a.coef)[bi * S + k], k == 0);
+            } else {
+                cf[h][e].a = (T)1;
+                cf[h][e].b = (T)0;
+                cf[h][e].c = (T)1;
+            }
+        }
+    }
     for (int j = sr.row0; j < sr.row1; ++j) {
         size_t node = valid ? (size_t)j * a.side + i : 0;
         bool interior = valid && i > 0 && j > 0 && i < a.n && j < a.n;
-        const size_t chunk = node * a.ST + (size_t)bi * S;  // slot / time-pair offset of (node, instance)
-        const T2* x = (const T2*)a.xhat + chunk;
-        for (int k = lt; k < S; k += TS) {
-            T2 v = mk2<T>(0, 0);
-            if (interior) {
-                v = x[k];
-                if (a.coef) {
-                    double2 c = ((const double2*)a.coef)[bi * S + k];
-                    v = gs_apply(gs_from<T>(c, k == 0), v);
+        const size_t chunk = node * a.ST + (size_t)bi * S;  // slot / time-pair offset of (node, instance), even
+        const Pair<T2>* xp = (const Pair<T2>*)a.xhat + chunk / 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = lt + h * TS;
+            if (q < H) {
+                T2 v[2] = {mk2<T>(0, 0), mk2<T>(0, 0)};
+                if (interior) {
+                    const Pair<T2> pv = xp[q];
+                    v[0] = pv.a;
+                    v[1] = pv.b;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        v[e] = gs_apply(cf[h][e], v[e]);
+                        if (a.conj && 2 * q + e != 0) v[e] = conj2(v[e]);
+                    }
                 }
-                if (a.conj && k != 0) v = conj2(v);
+                buf0[2 * q] = v[0];
+                buf0[2 * q + 1] = v[1];
             }
-            buf0[k] = v;
         }
         __syncthreads();
-        for (int k = lt; k < S; k += TS) {
-            T2 Z;
-            if (k == 0) {
-                T2 p0 = buf0[0];
-                Z = mk2<T>((T)0.5 * (p0.x + p0.y), (T)0.5 * (p0.x - p0.y));
-            } else {
-                T2 xk = buf0[k], xs = conj2(buf0[S - k]);
-                T2 E = scale2((T)0.5, add2(xk, xs));
-                T2 O = cmul(scale2((T)0.5, sub2(xk, xs)), conj2(tw[k]));
-                Z = mk2<T>(E.x - O.y, E.y + O.x);  // E + i O
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = lt + h * TS;
+            if (q < H) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int k = 2 * q + e;
+                    T2 Z;
+                    if (k == 0) {
+                        T2 p0 = buf0[0];
+                        Z = mk2<T>((T)0.5 * (p0.x + p0.y), (T)0.5 * (p0.x - p0.y));
+                    } else {
+                        T2 xk = buf0[k], xs = conj2(buf0[S - k]);
+                        T2 E = scale2((T)0.5, add2(xk, xs));
+                        T2 O = cmul(scale2((T)0.5, sub2(xk, xs)), pw[h][e]);
+                        Z = mk2<T>(E.x - O.y, E.y + O.x);  // E + i O
+                    }
+                    buf1[k] = conj2(Z);
+                }
             }
-            buf1[k] = conj2(Z);
         }
         __syncthreads();
-        T2* res = fft_team<T2>(buf1, buf0, S, lt, TS, tw);
+        T2* res = fft_lane<T2>(buf1, buf0, S, lt, TS, LF);
         if (interior) {
             double2* u2 = (double2*)a.U + chunk;
             for (int m = lt; m < S; m += TS) {
