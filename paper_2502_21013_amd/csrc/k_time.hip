@@ -16,6 +16,8 @@
 // Geometry on the uniform grid (h = 1/n, |T| = h^2/2): with G = h grad u_T (node
 // differences) and g~ = h grad phi (integer vectors), |T| nu grad u . grad phi = nu G.g~ / 2,
 // and |grad u|^2 = n^2 |G|^2.
+#include <type_traits>
+
 #include "pt_device.h"
 
 namespace pt {
@@ -253,7 +255,8 @@ __device__ __forceinline__ double upper_four(const FwdArgs& a, const Win& v, con
 constexpr int kRowBatch = 4;
 
 template <typename T, bool UNI, int KP>
-__global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
+__global__ void __launch_bounds__(kBlock)
+k_residual(FwdArgs a, void* rt_) {
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int RB = kRowBatch;
@@ -286,7 +289,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
         ai.bload = a.bload + (size_t)bi * a.nodes;
         ai.wave = a.wave + (size_t)bi * a.N;
     }
-    Win v[KP][2];
     // uniform row base + per-lane byte offset of (column i-1+d, instance bi, pair lt + TS k)
     const int lgST = a.lgST;  // 2^lgST time pairs per node over all instances (= slots per node)
     const long STp = a.ST;
@@ -301,9 +303,18 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
         if (cj < 0 || cj > n) return make_double2(0.0, 0.0);
         return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(rowU(cj)) + ofs[d][k]);
     };
-    auto ld = [&](int ci, int cj, int k) -> double2 { return ldd(ci - i + 1, cj, k); };
-    // window at the first interior row of the chunk
+    // Window of u (both time levels of the lane's pair) on the columns i-1 (Wv), i (Cv) and
+    // i+1 (Ev) in row slots modulo 4: row j lives in slot (j - jin + 1) & 3. The row loop
+    // below is unrolled by 4, so the slots are compile-time constants and the window is
+    // never moved between registers.
     const int jin = sr.row0 > 1 ? sr.row0 : 1;
+    double2 Wv[KP][4], Cv[KP][4], Ev[KP][4];
+    double carry[KP][2];
+    auto win = [&](int k, int h, int s0, int s1, int s2, double cy) -> Win {
+        auto g = [h](const double2& x) { return h ? x.y : x.x; };
+        return Win{g(Wv[k][s0]), g(Cv[k][s0]), g(Wv[k][s1]), g(Cv[k][s1]), g(Ev[k][s1]),
+                   g(Wv[k][s2]), g(Cv[k][s2]), g(Ev[k][s2]), cy};
+    };
     if (a.mode == TM_RESIDUAL && colint && jin < sr.row1 && jin < n) {
         bool ir_s[2], ir_sw[2];
         double th_s[2], th_sw[2];
@@ -311,19 +322,32 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
         cell_mat(ai, i - 1, jin - 1, ir_sw, th_sw);
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-            double2 sw = ld(i - 1, jin - 1, k), s_ = ld(i, jin - 1, k), w = ld(i - 1, jin, k), c = ld(i, jin, k),
-                    e = ld(i + 1, jin, k), nw = ld(i - 1, jin + 1, k), nn = ld(i, jin + 1, k),
-                    ne = ld(i + 1, jin + 1, k);
-            v[k][0] = Win{sw.x, s_.x, w.x, c.x, e.x, nw.x, nn.x, ne.x, 0.0};
-            v[k][1] = Win{sw.y, s_.y, w.y, c.y, e.y, nw.y, nn.y, ne.y, 0.0};
-            v[k][0].carry = lower_three(ai, v[k][0], ir_s, th_s, ir_sw, th_sw);
-            v[k][1].carry = lower_three(ai, v[k][1], ir_s, th_s, ir_sw, th_sw);
+            Wv[k][0] = ldd(0, jin - 1, k);
+            Cv[k][0] = ldd(1, jin - 1, k);
+            Wv[k][1] = ldd(0, jin, k);
+            Cv[k][1] = ldd(1, jin, k);
+            Ev[k][1] = ldd(2, jin, k);
+            Wv[k][2] = ldd(0, jin + 1, k);
+            Cv[k][2] = ldd(1, jin + 1, k);
+            Ev[k][2] = ldd(2, jin + 1, k);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) carry[k][h] = lower_three(ai, win(k, h, 0, 1, 2, 0.0), ir_s, th_s, ir_sw, th_sw);
         }
     }
-    for (int jb = sr.row0; jb < sr.row1; jb += RB) {
+    // a first row 0 of the chunk is boundary: zero output
+    if (sr.row0 == 0 && colvalid) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int m = lt + TS * k;
+            if (a.rout) ((double2*)a.rout)[(long)i * STp + bi * S + m] = make_double2(0.0, 0.0);
+            if (rt) rt[(long)i * STp + bi * S + m] = mk2<T>((T)0, (T)0);
+        }
+    }
+    for (int jb = jin; jb < sr.row1; jb += RB) {
         unsigned mass_bits = 0;
-#pragma unroll 1
-        for (int q = 0; q < RB; ++q) {
+        auto row = [&](auto q_) {
+            constexpr int q = decltype(q_)::value;  // also the slot of row j - 1
+            constexpr int s0 = q, s1 = (q + 1) & 3, s2 = (q + 2) & 3, s3 = (q + 3) & 3;
             const int j = jb + q;
             const bool interior = colint && j < sr.row1 && j > 0 && j < n;
             const int node = colvalid ? j * side + i : 0;
@@ -335,15 +359,14 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                 mue[k] = muo[k] = 0.0;
             }
             if (interior && a.mode == TM_RESIDUAL) {
-                // the next row's three new neighbour series, loaded before this row is computed
+                // the three new neighbour series of row j+2, loaded before this row is computed
                 const bool adv = j + 1 < sr.row1 && j + 1 < n;
-                double2 pnw[KP], pnn[KP], pne[KP];
                 if (adv) {
 #pragma unroll
                     for (int k = 0; k < KP; ++k) {
-                        pnw[k] = ld(i - 1, j + 2, k);
-                        pnn[k] = ld(i, j + 2, k);
-                        pne[k] = ld(i + 1, j + 2, k);
+                        Wv[k][s3] = ldd(0, j + 2, k);
+                        Cv[k][s3] = ldd(1, j + 2, k);
+                        Ev[k][s3] = ldd(2, j + 2, k);
                     }
                 }
                 bool ir_c[2], ir_w[2];
@@ -361,39 +384,23 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                 const double bl = ai.bload[node];
                 const double2* w2 = (const double2*)ai.wave;
                 const double2* F2 = (const double2*)a.F;
-                double cu[KP][2];
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     const int m = lt + TS * k;
-                    double K0 = upper_four(ai, v[k][0], ir_c, th_c, ir_w, th_w, cu[k][0]);
-                    double K1 = upper_four(ai, v[k][1], ir_c, th_c, ir_w, th_w, cu[k][1]);
+                    const Win p0 = win(k, 0, s0, s1, s2, carry[k][0]), p1 = win(k, 1, s0, s1, s2, carry[k][1]);
+                    double cu0, cu1;
+                    double K0 = upper_four(ai, p0, ir_c, th_c, ir_w, th_w, cu0);
+                    double K1 = upper_four(ai, p1, ir_c, th_c, ir_w, th_w, cu1);
                     double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * w2[m].x, bl * w2[m].y);
                     ff += f.x * f.x + f.y * f.y;
                     r[k] = make_double2(f.x - K0, f.y - K1);
                     if (mass) {
-                        const Win& p = v[k][0];
-                        const Win& o = v[k][1];
-                        mue[k] = mc * p.c + mE * p.e + mW * p.w + mN * p.n + mS * p.s + mNE * p.ne + mSW * p.sw;
-                        muo[k] = mc * o.c + mE * o.e + mW * o.w + mN * o.n + mS * o.s + mNE * o.ne + mSW * o.sw;
+                        mue[k] = mc * p0.c + mE * p0.e + mW * p0.w + mN * p0.n + mS * p0.s + mNE * p0.ne + mSW * p0.sw;
+                        muo[k] = mc * p1.c + mE * p1.e + mW * p1.w + mN * p1.n + mS * p1.s + mNE * p1.ne + mSW * p1.sw;
                     }
-                }
-                if (adv) {  // advance the window to row j+1
-#pragma unroll
-                    for (int k = 0; k < KP; ++k) {
-                        const double2 nw = pnw[k], nn = pnn[k], ne = pne[k];
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            Win& p = v[k][h];
-                            p.sw = p.w;
-                            p.s = p.c;
-                            p.w = p.nw;
-                            p.c = p.n;
-                            p.e = p.ne;
-                            p.nw = h ? nw.y : nw.x;
-                            p.n = h ? nn.y : nn.x;
-                            p.ne = h ? ne.y : ne.x;
-                            p.carry = cu[k][h];
-                        }
+                    if (adv) {
+                        carry[k][0] = cu0;
+                        carry[k][1] = cu1;
                     }
                 }
             } else if (interior) {  // TM_SIGNAL: the field itself
@@ -407,7 +414,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(FwdArgs a, void* rt_) {
                 me[q * S + m] = mue[k];
                 xo[q * S + m] = muo[k];
             }
-        }
+        };
+        static_assert(kRowBatch == 4, "the row window is kept in slots modulo 4");
+        row(std::integral_constant<int, 0>());
+        row(std::integral_constant<int, 1>());
+        row(std::integral_constant<int, 2>());
+        row(std::integral_constant<int, 3>());
         __syncthreads();
         // M (u^n - u^{n-1}) = M u^n - M u^{n-1}: the odd-time product of pair m-1 (cyclic)
 #pragma unroll 1
