@@ -211,6 +211,76 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None):
             "outer_iters": outer, "rel_residual": st.rel_residual}
 
 
+# ---------------------------------------------------------------- HBM traffic from rocprofv3 counters
+
+KERNEL_CLASSES = [("k_residual", "residual_sweep"), ("k_rfft", "rfft"), ("k_vc_down", "vcycle_down_fine"),
+                  ("k_vc_up", "vcycle_up_fine"), ("k_matvec", "matvec_dot"), ("k_inverse", "inverse_rfft_update")]
+
+
+def _pmc_rows(db_path):
+    """(kernel name, counter, value, duration) of every dispatch in a rocprofv3 --pmc database."""
+    import re
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    cols = [d[1] for d in db.execute("pragma table_info(counters_collection)")]
+    ni, vi, ci, di = (cols.index(c) for c in ("kernel_name", "value", "counter_name", "duration"))
+    out = []
+    for r in db.execute("select * from counters_collection"):
+        out.append((re.sub(r"\(.*", "", r[ni]).replace("void ", ""), r[ci], float(r[vi]), float(r[di])))
+    return out
+
+
+def _per_class(rows, counter):
+    """Average counter value (KiB) per dispatch of the finest-level launches of each kernel class:
+    the dispatches lasting at least half as long as the longest one of that kernel."""
+    res = {}
+    for key, cls in KERNEL_CLASSES:
+        ds = [(v, d) for (k, c, v, d) in rows if c == counter and key in k]
+        if not ds:
+            continue
+        dmax = max(d for _, d in ds)
+        vals = [v for v, d in ds if d >= 0.5 * dmax]
+        res[cls] = sum(vals) / len(vals)
+    return res
+
+
+def copy_calibration(gib=1.0, reps=3):
+    """A plain device copy of a known size, for scaling FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    n = int(gib * 2 ** 30)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "reps": reps}), flush=True)
+
+
+def pmc_summary(fetch_db, write_db, cal_fetch_db, cal_write_db, workload, mode, out, commands):
+    """HBM bytes per launch of each kernel class: FETCH_SIZE and WRITE_SIZE (separate runs),
+    each scaled by what the same counter reads for the 1 GiB calibration copy."""
+    def copy_val(db, counter):
+        vals = [v for (k, c, v, d) in _pmc_rows(db) if c == counter and ("copy" in k.lower() or "elementwise" in k)]
+        return max(vals)
+    n = 2 ** 30
+    ff = n / (copy_val(cal_fetch_db, "FETCH_SIZE") * 1024.0)
+    wf = n / (copy_val(cal_write_db, "WRITE_SIZE") * 1024.0)
+    fe = _per_class(_pmc_rows(fetch_db), "FETCH_SIZE")
+    wr = _per_class(_pmc_rows(write_db), "WRITE_SIZE")
+    kern = {}
+    for cls in fe:
+        if cls in wr:
+            fb, wb = fe[cls] * 1024.0 * ff, wr[cls] * 1024.0 * wf
+            kern[cls] = {"fetch_kib": fe[cls], "write_kib": wr[cls], "read_bytes": fb, "write_bytes": wb,
+                         "hbm_bytes_per_launch": fb + wb}
+    data = {"source_hash": kernel_source_hash(), "workload": workload,
+            "calibration": {"copy_bytes": n, "fetch_factor": ff, "write_factor": wf},
+            "kernels": {mode: kern}, "commands": commands}
+    with open(out, "w") as fh:
+        json.dump(data, fh, indent=1)
+    print(json.dumps(data), flush=True)
+
+
 def cpu_baseline(seed, n=32, N=64, tol=1e-8):
     """FP64 oracle (space-time sparse LU inside the same fixed-point loop) on a bounded sample:
     the same materials and source at n x n cells and N steps, one thread."""
@@ -247,7 +317,17 @@ def main():
     ap.add_argument("--max-outer", type=int, default=2000,
                     help="cap on outer steps per solve; below the count needed for 1e-8 the run is a "
                          "profiling run (marked in the output), not a metric measurement")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write the HBM traffic table (--pmc-out) from four rocprofv3 --pmc databases")
+    ap.add_argument("--pmc-out", default=os.path.join(ROOT, "profiles", "pmc_counters.json"))
+    ap.add_argument("--pmc-commands", default="", help="the profiling commands, recorded in the table")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, workload=args.workload, mode=args.modes.split(",")[0], out=args.pmc_out,
+                    commands=args.pmc_commands)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU sharding of this "
               "solver is a design note, not an implementation", file=sys.stderr)
@@ -257,6 +337,9 @@ def main():
     import paper_2502_21013_amd as P
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        copy_calibration()
+        return
     P.library()
     if args.workload == "c4":
         main_many(args, P)

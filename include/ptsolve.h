@@ -120,6 +120,12 @@ typedef struct {
     int32_t adjoint;       /* 1: reserve the workspace of pt_adjoint_solve / pt_loss_gradients
                               (two more time fields and a per-triangle table); single-problem
                               plans only */
+    int32_t init_static;   /* 1: start from the static solution (Sec. 4, "Initialization"): the
+                              decoupled problems K(u^n) = f^n of sigma = 0, solved by the same
+                              iteration to init_tol; cannot be combined with use_initial_guess */
+    double init_tol;       /* relative residual of the static start (default 1e-8) */
+    int32_t stop_relative_initial; /* 1: stop when ||F - A(U^k)|| <= tol ||F - A(U^0)|| (the paper's
+                              rule); 0: tol ||F|| (the same for U^0 = 0) */
     int32_t graph;         /* 1: capture the kernels of check_every outer steps into a HIP
                               graph on the first call (per plan and workspace address) and
                               replay it; same iterates as 0. Cannot be combined with timing. */
@@ -137,6 +143,8 @@ typedef struct {
                                    device time per kernel class (options.timing = 1) */
     int64_t* kernel_launches;   /* caller-owned host array [PT_KERNEL_CLASSES] or NULL */
     int32_t converged_at;       /* outer step at whose check rel <= tol first held, -1 if never */
+    int32_t init_iters;         /* steps of the static start (options.init_static) */
+    double rel_initial;         /* ||F - A(U^0)|| / ||F|| of the iteration's starting iterate */
 } pt_stats;
 
 /* Kernel classes reported by the per-kernel timer; pt_kernel_class_name() names them. */
@@ -146,7 +154,8 @@ typedef struct pt_plan pt_plan;
 
 /* Fill *o with the defaults (tol 1e-8, max_outer 1000, check_every 1, FP64,
  * PT_INNER_GALERKIN1, inner_iters 1, vc_sweeps 1, vc_omega 0.8, no initial guess,
- * diverge_factor 1e3, xcd_remap 1, timing 0, default grid targets, adjoint 0, graph 0). */
+ * diverge_factor 1e3, xcd_remap 1, timing 0, default grid targets, adjoint 0, no static start
+ * (init_tol 1e-8), stop relative to ||F||, graph 0). */
 void pt_options_default(pt_options* o);
 
 /* Validate the problem and options (host only, no device work) and create a plan. */

@@ -73,10 +73,13 @@ class SolveStats:
     kernel_ms: Dict[str, float] = field(default_factory=dict)
     kernel_launches: Dict[str, int] = field(default_factory=dict)
     converged_at: int = -1
+    init_iters: int = 0
+    rel_initial: float = float("nan")
 
 
 def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega, use_initial_guess,
-             diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0, adjoint=False) -> L.Options:
+             diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0, adjoint=False,
+             init_static=False, init_tol=1e-8, stop_relative_initial=False) -> L.Options:
     o = L.Options()
     lib.pt_options_default(C.byref(o))
     o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
@@ -89,6 +92,9 @@ def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc
     o.graph = 1 if graph else 0
     o.grid_slot, o.grid_team = int(grid_slot), int(grid_team)
     o.adjoint = 1 if adjoint else 0
+    o.init_static = 1 if init_static else 0
+    o.init_tol = float(init_tol)
+    o.stop_relative_initial = 1 if stop_relative_initial else 0
     return o
 
 
@@ -114,7 +120,7 @@ class _StatsBuf:
                           time_ms=s.time_ms, history=list(self.hist[: s.history_len]),
                           kernel_ms={names[i]: self.kms[i] for i in range(n) if self.kcnt[i]},
                           kernel_launches={names[i]: int(self.kcnt[i]) for i in range(n) if self.kcnt[i]},
-                          converged_at=s.converged_at)
+                          converged_at=s.converged_at, init_iters=s.init_iters, rel_initial=s.rel_initial)
 
 
 class Plan:
@@ -123,7 +129,8 @@ class Plan:
     def __init__(self, problem, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
-                 adjoint=False, theta=None, sigma=None, load=None, device=None):
+                 adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, theta=None,
+                 sigma=None, load=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -134,7 +141,8 @@ class Plan:
         self._keep = (theta, sigma, load)  # device tables must outlive the plan's calls
         self._ps = problem_struct(problem, theta, sigma, load)
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
-                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint)
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
+                     init_static, init_tol, stop_relative_initial)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -309,7 +317,7 @@ class BatchPlan(Plan):
     def __init__(self, problems, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
-                 adjoint=False, device=None):
+                 adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, device=None):
         import torch
         problems = list(problems)
         self.lib = L.load()
@@ -323,7 +331,8 @@ class BatchPlan(Plan):
         self._keep = ()
         self._pa = (L.Problem * self.count)(*[problem_struct(p) for p in problems])
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
-                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint)
+                     use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
+                     init_static, init_tol, stop_relative_initial)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create_batch(self._pa, self.count, C.byref(o), C.byref(h))

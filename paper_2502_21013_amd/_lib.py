@@ -45,7 +45,9 @@ class Options(C.Structure):
         ("precision", C.c_int32), ("inner", C.c_int32), ("inner_iters", C.c_int32),
         ("vc_sweeps", C.c_int32), ("vc_omega", C.c_double), ("use_initial_guess", C.c_int32),
         ("diverge_factor", C.c_double), ("xcd_remap", C.c_int32), ("timing", C.c_int32),
-        ("grid_slot", C.c_int32), ("grid_team", C.c_int32), ("adjoint", C.c_int32), ("graph", C.c_int32),
+        ("grid_slot", C.c_int32), ("grid_team", C.c_int32), ("adjoint", C.c_int32),
+        ("init_static", C.c_int32), ("init_tol", C.c_double), ("stop_relative_initial", C.c_int32),
+        ("graph", C.c_int32),
     ]
 
 
@@ -55,7 +57,7 @@ class Stats(C.Structure):
         ("time_ms", C.c_double), ("residual_history", C.POINTER(C.c_double)),
         ("history_cap", C.c_int32), ("history_len", C.c_int32),
         ("kernel_ms", C.POINTER(C.c_double)), ("kernel_launches", C.POINTER(C.c_int64)),
-        ("converged_at", C.c_int32),
+        ("converged_at", C.c_int32), ("init_iters", C.c_int32), ("rel_initial", C.c_double),
     ]
 
 

@@ -149,6 +149,11 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused V(1,1) cycle)");
     if (!(o->vc_omega > 0 && o->vc_omega < 1)) return fail(PT_ERR_INVALID, "vc_omega must be in (0, 1)");
     if (o->adjoint != 0 && o->adjoint != 1) return fail(PT_ERR_INVALID, "adjoint must be 0 or 1");
+    if (o->init_static != 0 && o->init_static != 1) return fail(PT_ERR_INVALID, "init_static must be 0 or 1");
+    if (o->init_static && (!(o->init_tol > 0) || !std::isfinite(o->init_tol)))
+        return fail(PT_ERR_INVALID, "init_tol must be positive");
+    if (o->init_static && o->use_initial_guess)
+        return fail(PT_ERR_INVALID, "init_static and use_initial_guess cannot be combined");
     if (o->grid_slot < 0 || (o->grid_slot > 0 && o->grid_slot < 8) || o->grid_slot > (1 << 22) || o->grid_team < 0 ||
         (o->grid_team > 0 && o->grid_team < 8) || o->grid_team > (1 << 22))
         return fail(PT_ERR_INVALID, "grid_slot and grid_team must be 0 or in [8, 4194304]");
@@ -506,76 +511,106 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
     double* scal = (double*)(ws + p.off_scal);
     int* flag = (int*)(ws + p.off_flag);
     TM(KID_MEMSET, launch_zero16(flag, 16, st));
-    residual_step(p, ws, adjoint, st);
-    std::vector<double> h(2 * (size_t)B), rel(B, INFINITY), fnorm(B, 0.0), best(B, INFINITY);
+    std::vector<double> h(2 * (size_t)B), rel(B, INFINITY), fnorm(B, 0.0), best(B, INFINITY), d0(B, 0.0);
     std::vector<int> conv(B, -1);
-    pt_status result = PT_ERR_NOT_CONVERGED;
     const int ce = p.opt.check_every;
-    int k = 0, hist = 0;
-    for (;;) {
-        bool last = (k >= p.opt.max_outer);
-        if (last || k % ce == 0) {
-            int hflag = 0;
-            PT_HIP(hipMemcpyAsync(h.data(), scal, 2 * (size_t)B * sizeof(double), hipMemcpyDeviceToHost, st));
-            PT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-            PT_HIP(hipStreamSynchronize(st));
-            PT_HIP(hipGetLastError());
-            tm_flush(p);
-            bool all = true;
-            int bad = -1;
-            for (int b = 0; b < B; ++b) {
-                const double r2 = h[2 * b], f2 = h[2 * b + 1];
-                fnorm[b] = std::sqrt(f2);
-                rel[b] = (f2 > 0) ? std::sqrt(r2 / f2) : std::sqrt(r2);
-                if (stats && stats[b].residual_history && hist < stats[b].history_cap)
-                    stats[b].residual_history[hist] = rel[b];
-                if (!std::isfinite(rel[b]) && bad < 0) bad = b;
-                if (rel[b] <= p.opt.tol) {
-                    if (conv[b] < 0) conv[b] = k;
-                } else {
-                    all = false;
+    int hist = 0;
+    // One run of the iteration from the current iterate (whose residual step has been
+    // launched) until every instance meets tol, a failure, or max_steps updates. relative0:
+    // divide by the residual of the starting iterate instead of ||F||.
+    auto run = [&](double tol, int max_steps, bool record, bool relative0, int& k, pt_status& result) -> pt_status {
+        std::fill(best.begin(), best.end(), INFINITY);
+        std::fill(conv.begin(), conv.end(), -1);
+        result = PT_ERR_NOT_CONVERGED;
+        k = 0;
+        for (;;) {
+            bool last = (k >= max_steps);
+            if (last || k % ce == 0) {
+                int hflag = 0;
+                PT_HIP(hipMemcpyAsync(h.data(), scal, 2 * (size_t)B * sizeof(double), hipMemcpyDeviceToHost, st));
+                PT_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+                PT_HIP(hipStreamSynchronize(st));
+                PT_HIP(hipGetLastError());
+                tm_flush(p);
+                bool all = true;
+                int bad = -1;
+                for (int b = 0; b < B; ++b) {
+                    const double r2 = h[2 * b], f2 = h[2 * b + 1];
+                    fnorm[b] = std::sqrt(f2);
+                    if (k == 0) d0[b] = std::sqrt(r2);
+                    if (relative0)
+                        rel[b] = d0[b] > 0 ? std::sqrt(r2) / d0[b] : 0.0;
+                    else
+                        rel[b] = (f2 > 0) ? std::sqrt(r2 / f2) : std::sqrt(r2);
+                    if (record && stats && stats[b].residual_history && hist < stats[b].history_cap)
+                        stats[b].residual_history[hist] = rel[b];
+                    if (!std::isfinite(rel[b]) && bad < 0) bad = b;
+                    if (rel[b] <= tol) {
+                        if (conv[b] < 0) conv[b] = k;
+                    } else {
+                        all = false;
+                    }
+                }
+                if (record) ++hist;
+                auto inst = [&](int b) { return B > 1 ? " (instance " + std::to_string(b) + ")" : std::string(); };
+                if (bad >= 0) {
+                    result = fail(PT_ERR_NONFINITE,
+                                  "residual norm is not finite at outer step " + std::to_string(k) + inst(bad));
+                    return PT_OK;
+                }
+                if (hflag) {
+                    result = fail(PT_ERR_BREAKDOWN, "COCG breakdown before outer step " + std::to_string(k));
+                    return PT_OK;
+                }
+                if (all) {
+                    result = PT_OK;
+                    return PT_OK;
+                }
+                int grew = -1;
+                for (int b = 0; b < B; ++b) {
+                    if (rel[b] < best[b]) best[b] = rel[b];
+                    if (grew < 0 && p.opt.diverge_factor > 0 && rel[b] > p.opt.diverge_factor * best[b]) grew = b;
+                }
+                if (grew >= 0) {
+                    result = fail(PT_ERR_DIVERGED, "residual grew by more than diverge_factor at outer step " +
+                                                       std::to_string(k) + inst(grew));
+                    return PT_OK;
                 }
             }
-            ++hist;
-            auto inst = [&](int b) { return B > 1 ? " (instance " + std::to_string(b) + ")" : std::string(); };
-            if (bad >= 0) {
-                result = fail(PT_ERR_NONFINITE, "residual norm is not finite at outer step " + std::to_string(k) + inst(bad));
-                break;
+            if (last) {
+                result = fail(PT_ERR_NOT_CONVERGED, "max_outer reached");
+                return PT_OK;
             }
-            if (hflag) {
-                result = fail(PT_ERR_BREAKDOWN, "COCG breakdown before outer step " + std::to_string(k));
-                break;
-            }
-            if (all) {
-                result = PT_OK;
-                break;
-            }
-            int grew = -1;
-            for (int b = 0; b < B; ++b) {
-                if (rel[b] < best[b]) best[b] = rel[b];
-                if (grew < 0 && p.opt.diverge_factor > 0 && rel[b] > p.opt.diverge_factor * best[b]) grew = b;
-            }
-            if (grew >= 0) {
-                result = fail(PT_ERR_DIVERGED, "residual grew by more than diverge_factor at outer step " +
-                                                   std::to_string(k) + inst(grew));
-                break;
+            if (p.opt.graph && k % ce == 0 && k + ce <= max_steps) {
+                hipGraphExec_t exec = nullptr;
+                pt_status g = graph_get(p, ws, ce, adjoint, &exec);
+                if (g != PT_OK) return g;
+                PT_HIP(hipGraphLaunch(exec, st));
+                k += ce;
+            } else {
+                pt_status g = outer_segment(p, ws, adjoint, st);
+                if (g != PT_OK) return g;
+                ++k;
             }
         }
-        if (last) {
-            result = fail(PT_ERR_NOT_CONVERGED, "max_outer reached");
-            break;
-        }
-        if (p.opt.graph && k % ce == 0 && k + ce <= p.opt.max_outer) {
-            hipGraphExec_t exec = nullptr;
-            s = graph_get(p, ws, ce, adjoint, &exec);
-            if (s != PT_OK) return s;
-            PT_HIP(hipGraphLaunch(exec, st));
-            k += ce;
-        } else {
-            s = outer_segment(p, ws, adjoint, st);
-            if (s != PT_OK) return s;
-            ++k;
-        }
+    };
+    pt_status result = PT_OK;
+    int k = 0, init_iters = 0;
+    if (p.opt.init_static && !adjoint) {
+        // Static start (Sec. 4, "Initialization"): the decoupled problems K(u^n) = f^n of sigma = 0,
+        // i.e. the same iteration with every mass table zeroed; then the tables are rebuilt.
+        for (int l = 0; l < p.nlev; ++l) TM(KID_MEMSET, launch_zero16(ws + p.lev[l].off_mt, 4 * p.lev[l].nodes * sizeof(double), st));
+        residual_step(p, ws, false, st);
+        s = run(p.opt.init_tol, p.opt.max_outer, false, false, init_iters, result);
+        if (s != PT_OK) return s;
+        if (result == PT_ERR_NOT_CONVERGED) result = PT_OK;  // the start need not be exact
+        TM(KID_SETUP, launch_setup_fine(p, ws, st));
+        for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin(p, ws, l, st));
+    }
+    if (result == PT_OK) {
+        residual_step(p, ws, adjoint, st);
+        s = run(p.opt.tol, p.opt.max_outer, true, p.opt.stop_relative_initial != 0, k, result);
+        if (s != PT_OK) return s;
     }
     TM(KID_TRANSPOSE, launch_transpose_out(p, X0, d_x, st));
     PT_HIP(hipEventRecord(ev.e1, st));
@@ -593,6 +628,8 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
             o.time_ms = ms;
             o.history_len = hist < o.history_cap ? hist : o.history_cap;
             o.converged_at = conv[b];
+            o.init_iters = init_iters;
+            o.rel_initial = fnorm[b] > 0 ? d0[b] / fnorm[b] : d0[b];
             for (int c = 0; c < KID_COUNT; ++c) {
                 if (o.kernel_ms) o.kernel_ms[c] = p.tm ? p.tm->ms[c] : 0.0;
                 if (o.kernel_launches) o.kernel_launches[c] = p.tm ? p.tm->cnt[c] : 0;
@@ -654,6 +691,7 @@ void pt_options_default(pt_options* o) {
     o->use_initial_guess = 0;
     o->diverge_factor = 1e3;
     o->xcd_remap = 1;
+    o->init_tol = 1e-8;
 }
 
 static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_options* opts, pt_plan** out) {

@@ -184,3 +184,9 @@ def test_adjoint_entry_points_need_an_adjoint_plan(P):
                                  None) == L.PT_ERR_INVALID
     with pytest.raises(P.PTError):
         P.BatchPlan([W.with_size(p, 8, 8) for p in W.config4(0, 2)], adjoint=True)
+
+
+@pytest.mark.parametrize("kw", [dict(init_static=True, init_tol=0.0), dict(init_static=True, use_initial_guess=True)])
+def test_static_start_options_are_validated(P, kw):
+    with pytest.raises(P.PTError):
+        P.Plan(W.config1(), **kw)

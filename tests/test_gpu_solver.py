@@ -158,3 +158,48 @@ def test_config3_full_size_sampled_slices(gpu, P, precision):
     del U
     plan.close()
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- the paper's initialisation
+
+def test_static_start_reaches_the_same_solution(gpu, P):
+    # the static start (sigma = 0 problems) then the periodic iteration converge to the
+    # oracle's periodic solution; the start itself is the oracle's sigma = 0 solution
+    import dataclasses
+    say("static start")
+    p = W.with_size(W.config2(7), 16, 16)
+    d = fem.discretise(p)
+    ref = pp.fixed_point(d, tol=1e-12, max_iter=3000)
+    plan = P.Plan(p, tol=1e-12, max_outer=3000, init_static=True, init_tol=1e-12)
+    U, st = plan.solve()
+    assert st.init_iters > 10 and st.rel_residual <= 1e-12
+    assert 0 < st.rel_initial < 1
+    assert np.linalg.norm(U.cpu().numpy() - pp.to_full(d, ref.U)) <= 1e-8 * np.linalg.norm(pp.to_full(d, ref.U))
+    # the start: static solution = periodic solution of the sigma = 0 problem
+    p0 = dataclasses.replace(p, sigma_in=0.0)
+    d0 = fem.discretise(p0)
+    U0 = pp.fixed_point(d0, tol=1e-13, max_iter=3000).U
+    Fs = pp.load_series(d)
+    R0 = pp.residual(d, U0, Fs)
+    assert abs(np.linalg.norm(R0) / np.linalg.norm(Fs) - st.rel_initial) <= 1e-6 * st.rel_initial
+
+
+def test_static_start_is_exact_without_conductivity(gpu, P):
+    import dataclasses
+    say("static start sigma 0")
+    p = dataclasses.replace(W.with_size(W.config2(8), 16, 16), sigma_in=0.0)
+    U, st = P.Plan(p, tol=1e-10, init_static=True, init_tol=1e-11).solve()
+    assert st.outer_iters == 0 and st.init_iters > 10 and st.rel_residual <= 1e-10
+
+
+def test_relative_to_initial_residual_matches_from_zero(gpu, P):
+    # from U^0 = 0 the paper's denominator ||F - A(U^0)|| is ||F||
+    say("stop relative to the initial residual")
+    p = W.with_size(W.config2(9), 16, 16)
+    U1, s1 = P.Plan(p, tol=1e-9).solve()
+    U2, s2 = P.Plan(p, tol=1e-9, stop_relative_initial=True).solve()
+    assert s1.outer_iters == s2.outer_iters and torch.equal(U1, U2)
+    assert s2.rel_initial == pytest.approx(1.0)
+    # after a static start the rule divides by the start's residual: more steps to the same tol
+    U3, s3 = P.Plan(p, tol=1e-9, init_static=True, stop_relative_initial=True).solve()
+    assert s3.rel_residual <= 1e-9 and s3.rel_residual * s3.rel_initial <= 1e-9
