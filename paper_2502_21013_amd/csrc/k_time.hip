@@ -343,6 +343,10 @@ k_residual(FwdArgs a, void* rt_) {
             if (rt) rt[(long)i * STp + bi * S + m] = mk2<T>((T)0, (T)0);
         }
     }
+    // the source waveform at the lane's time pairs is the same on every row
+    double2 wv[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) wv[k] = ((const double2*)ai.wave)[lt + TS * k];
     for (int jb = jin; jb < sr.row1; jb += RB) {
         unsigned mass_bits = 0;
         auto row = [&](auto q_) {
@@ -382,7 +386,6 @@ k_residual(FwdArgs a, void* rt_) {
                                   (mNE != 0.0) || (mSW != 0.0);
                 if (mass) mass_bits |= 1u << q;
                 const double bl = ai.bload[node];
-                const double2* w2 = (const double2*)ai.wave;
                 const double2* F2 = (const double2*)a.F;
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
@@ -391,7 +394,7 @@ k_residual(FwdArgs a, void* rt_) {
                     double cu0, cu1;
                     double K0 = upper_four(ai, p0, ir_c, th_c, ir_w, th_w, cu0);
                     double K1 = upper_four(ai, p1, ir_c, th_c, ir_w, th_w, cu1);
-                    double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * w2[m].x, bl * w2[m].y);
+                    double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * wv[k].x, bl * wv[k].y);
                     ff += f.x * f.x + f.y * f.y;
                     r[k] = make_double2(f.x - K0, f.y - K1);
                     if (mass) {
