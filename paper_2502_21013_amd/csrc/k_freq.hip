@@ -450,32 +450,142 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
             rc = q3.r;
             rn = q5.r;
         }
-        for (int aj = j0; aj < sr.row1; ++aj) {
-            const bool more = aj + 1 < sr.row1;
-            UpIn<W> p0, p1, p2;
-            if (more) {
-                p0 = load(0, aj + 1);
-                p1 = load(1, aj + 2);
-                p2 = load(2, aj + 2);
+        // Coarse window: x_c on the coarse columns kc0 + d (d < 3; two suffice when ai is odd)
+        // and the coarse rows R0, R0 + 1 with R0 = (aj + 1) >> 1, which hold every coarse value
+        // that the P1 interpolation needs at the step's new points (ai-1, aj+1), (ai, aj+2),
+        // (ai+1, aj+2). The window moves by one coarse row every second fine row, so each
+        // coarse value is loaded once per column walk instead of at every fine point (FP64
+        // mode). The parities of ai and aj (uniform) are compile-time in the code below.
+        const int kc0 = (ai - 1) >> 1;
+        const int nc = C.n;
+        unsigned occ[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) occ[d] = (((unsigned)(kc0 + d) << lgST) + L.s0) * E;
+        auto rload = [&](int d, int bj) -> W {
+            return (bj >= 0 && bj <= nF) ? *cboff(row_of(rin, bj, sf, lgR), ofn[d]) : sv_zero<T>();
+        };
+        auto mload = [&](int d, int bj) -> double { return (bj >= 0 && bj <= nF) ? F.mt[(long)bj * sf + ai - 1 + d] : 0.0; };
+        auto walk = [&](auto aodd_) {
+            constexpr bool AODD = decltype(aodd_)::value;
+            constexpr int NCOL = AODD ? 2 : 3;
+            W cw[3][2];
+            auto load_crow = [&](int cr, auto e_) {
+                constexpr int e = decltype(e_)::value;
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    cw[d][e] = (d < NCOL && cr >= 0 && cr <= nc) ? *cboff(row_of(xc, cr, sc, lgR), occ[d]) : sv_zero<T>();
+            };
+            int R0 = (j0 + 1) >> 1;
+            load_crow(R0, std::integral_constant<int, 0>());
+            load_crow(R0 + 1, std::integral_constant<int, 1>());
+            // P x_c at fine column ai-1+c on a row of parity ROWODD whose coarse row is R0 + e:
+            // coarse column offset d and column parity of the fine column follow from AODD
+            auto px = [&](auto c_, auto rowodd_, auto e_) -> W {
+                constexpr int c = decltype(c_)::value;
+                constexpr bool ROWODD = decltype(rowodd_)::value;
+                constexpr int e = decltype(e_)::value;
+                constexpr int d = c == 0 ? 0 : (c == 2 ? 1 : (AODD ? 0 : 1));
+                constexpr bool CODD = AODD ? (c == 1) : (c != 1);
+                const W a0 = cw[d][e];
+                if (!CODD && !ROWODD) return a0;
+                constexpr int d1 = CODD ? d + 1 : d;
+                constexpr int e1 = ROWODD ? e + 1 : e;
+                return sv_scale((T)0.5, sv_add(a0, cw[d1][e1]));
+            };
+            auto x2_at = [&](int bj, const W& r, double mc, const W& pxv) -> W {
+                if (bj < 0 || bj > nF) return sv_zero<T>();
+                return sv_add(jacobi<T>(dl, idl, om, mc, L.z, r), pxv);
+            };
+            auto step = [&](int aj, auto ajodd_) {
+                constexpr bool AJODD = decltype(ajodd_)::value;
+                const bool more = aj + 1 < sr.row1;
+                W r0, r1, r2;
+                double m0 = 0, m1 = 0, m2 = 0;
+                if (more) {
+                    if (AJODD) {  // R0 = (aj + 1) / 2 moved up by one: shift the coarse window
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) cw[d][0] = cw[d][1];
+                        R0 += 1;
+                        load_crow(R0 + 1, std::integral_constant<int, 1>());
+                    }
+                    r0 = rload(0, aj + 1);
+                    r1 = rload(1, aj + 2);
+                    r2 = rload(2, aj + 2);
+                    m0 = mload(0, aj + 1);
+                    m1 = mload(1, aj + 2);
+                    m2 = mload(2, aj + 2);
+                }
+                W out = sv_zero<T>();
+                if (aj > 0 && aj < nF) {
+                    const long a = (long)aj * sf + ai;
+                    W Ax = apply_A<T>(mrow(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
+                    out = sv_add(xcn, jacobi<T>(dl, idl, om, F.mt[a], L.z, sv_sub(rc, Ax)));
+                    if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
+                }
+                *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
+                if (more) {
+                    // aj even: row aj + 1 (column ai-1) is odd on coarse row R0, row aj + 2 even on
+                    // R0 + 1; aj odd: aj + 1 even on R0, aj + 2 odd on R0
+                    using RW = std::integral_constant<bool, !AJODD>;
+                    using RCE = std::integral_constant<bool, AJODD>;
+                    using EW = std::integral_constant<int, 0>;
+                    using ECE = std::integral_constant<int, AJODD ? 0 : 1>;
+                    xsw = xw;
+                    xs = xcn;
+                    xw = x2_at(aj + 1, r0, m0, px(std::integral_constant<int, 0>(), RW(), EW()));
+                    xcn = xn;
+                    rc = rn;
+                    xe = xne;
+                    xn = x2_at(aj + 2, r1, m1, px(std::integral_constant<int, 1>(), RCE(), ECE()));
+                    rn = r1;
+                    xne = x2_at(aj + 2, r2, m2, px(std::integral_constant<int, 2>(), RCE(), ECE()));
+                }
+            };
+            int aj = j0;
+            if ((aj & 1) && aj < sr.row1) {
+                step(aj, std::true_type());
+                ++aj;
             }
-            W out = sv_zero<T>();
-            if (aj > 0 && aj < nF) {
-                const long a = (long)aj * sf + ai;
-                W Ax = apply_A<T>(mrow(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
-                out = sv_add(xcn, jacobi<T>(dl, idl, om, F.mt[a], L.z, sv_sub(rc, Ax)));
-                if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
+            for (; aj < sr.row1; aj += 2) {
+                step(aj, std::false_type());
+                if (aj + 1 < sr.row1) step(aj + 1, std::true_type());
             }
-            *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
-            if (more) {
-                xsw = xw;
-                xs = xcn;
-                xw = up_eval(p0, dl, idl, om, L.z);
-                xcn = xn;
-                rc = rn;
-                xe = xne;
-                xn = up_eval(p1, dl, idl, om, L.z);
-                rn = p1.r;
-                xne = up_eval(p2, dl, idl, om, L.z);
+        };
+        if constexpr (V == 1) {
+            if (ai & 1)
+                walk(std::true_type());
+            else
+                walk(std::false_type());
+        } else {
+            // FP32 (two slots per lane): the coarse window would cost a wave of occupancy, so
+            // the interpolation inputs are loaded per point
+            for (int aj = j0; aj < sr.row1; ++aj) {
+                const bool more = aj + 1 < sr.row1;
+                UpIn<W> p0, p1, p2;
+                if (more) {
+                    p0 = load(0, aj + 1);
+                    p1 = load(1, aj + 2);
+                    p2 = load(2, aj + 2);
+                }
+                W out = sv_zero<T>();
+                if (aj > 0 && aj < nF) {
+                    const long a = (long)aj * sf + ai;
+                    W Ax = apply_A<T>(mrow(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
+                    out = sv_add(xcn, jacobi<T>(dl, idl, om, F.mt[a], L.z, sv_sub(rc, Ax)));
+                    if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
+                }
+                *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
+                if (more) {
+                    xsw = xw;
+                    xs = xcn;
+                    xw = up_eval(p0, dl, idl, om, L.z);
+                    xcn = xn;
+                    rc = rn;
+                    xe = xne;
+                    xn = up_eval(p1, dl, idl, om, L.z);
+                    rn = p1.r;
+                    xne = up_eval(p2, dl, idl, om, L.z);
+                }
             }
         }
     } else if (ai < sf) {
