@@ -126,6 +126,10 @@ typedef struct {
     double init_tol;       /* relative residual of the static start (default 1e-8) */
     int32_t stop_relative_initial; /* 1: stop when ||F - A(U^k)|| <= tol ||F - A(U^0)|| (the paper's
                               rule); 0: tol ||F|| (the same for U^0 = 0) */
+    int32_t krylov_dim;    /* > 0: reserve the workspace of pt_newton_solve with flexible GMRES of
+                              this restart length (1..64); single-problem plans only */
+    double forcing;        /* Newton: relative tolerance of each linear solve (default 1e-2) */
+    int32_t max_krylov;    /* Newton: Krylov steps per Newton step at most (default 100) */
     int32_t graph;         /* 1: capture the kernels of check_every outer steps into a HIP
                               graph on the first call (per plan and workspace address) and
                               replay it; same iterates as 0. Cannot be combined with timing. */
@@ -145,6 +149,7 @@ typedef struct {
     int32_t converged_at;       /* outer step at whose check rel <= tol first held, -1 if never */
     int32_t init_iters;         /* steps of the static start (options.init_static) */
     double rel_initial;         /* ||F - A(U^0)|| / ||F|| of the iteration's starting iterate */
+    int32_t krylov_iters;       /* pt_newton_solve: Krylov steps over all Newton steps */
 } pt_stats;
 
 /* Kernel classes reported by the per-kernel timer; pt_kernel_class_name() names them. */
@@ -273,6 +278,24 @@ pt_status pt_adjoint_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, const dou
 pt_status pt_loss_gradients(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
                             const double* d_lambda, double* d_gtheta, double* d_gsigma,
                             int32_t per_cell, double* loss_out, void* stream);
+
+/* Newton's method on A(U) = F (the outer loop of method (M2), Sec. 4): each step solves
+ * J(U^k) D = F - A(U^k), J the linearised operator of eqs. (disc1)-(disc2), by flexible
+ * GMRES(krylov_dim) right-preconditioned with the periodic solve of the fixed-point
+ * iteration (I (x) (M/tau + Khat) - C_N (x) (M/tau), applied by the time DFT and the
+ * inner method), to relative accuracy options.forcing, then backtracks U^k + lambda D
+ * (lambda = 1, 1/2, ...) until ||F - A|| <= (1 - 1e-4 lambda) ||F - A(U^k)|| (Armijo).
+ * The plan needs options.krylov_dim > 0. Stops as pt_solve (options.tol, max_outer Newton
+ * steps); stats.outer_iters counts Newton steps, stats.krylov_iters the Krylov steps.
+ * d_u, statuses and blocking as pt_solve; a failed line search gives PT_ERR_NOT_CONVERGED. */
+pt_status pt_newton_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream,
+                          pt_stats* stats);
+
+/* d_out = J(U) d_v (transpose = 0) or J(U)^T d_v (transpose = 1) at the state d_u, all time
+ * fields [N][n+1][n+1] (boundary entries of d_out are 0). The plan needs options.adjoint or
+ * options.krylov_dim. Blocks until the stream has finished. */
+pt_status pt_jacobian_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
+                            const double* d_v, double* d_out, int32_t transpose, void* stream);
 
 /* Name of kernel class id (0 <= id < PT_KERNEL_CLASSES), or NULL. */
 const char* pt_kernel_class_name(int32_t id);

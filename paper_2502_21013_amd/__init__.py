@@ -75,11 +75,13 @@ class SolveStats:
     converged_at: int = -1
     init_iters: int = 0
     rel_initial: float = float("nan")
+    krylov_iters: int = 0
 
 
 def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega, use_initial_guess,
              diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0, adjoint=False,
-             init_static=False, init_tol=1e-8, stop_relative_initial=False) -> L.Options:
+             init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0, forcing=1e-2,
+             max_krylov=100) -> L.Options:
     o = L.Options()
     lib.pt_options_default(C.byref(o))
     o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
@@ -95,6 +97,7 @@ def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc
     o.init_static = 1 if init_static else 0
     o.init_tol = float(init_tol)
     o.stop_relative_initial = 1 if stop_relative_initial else 0
+    o.krylov_dim, o.forcing, o.max_krylov = int(krylov_dim), float(forcing), int(max_krylov)
     return o
 
 
@@ -120,7 +123,8 @@ class _StatsBuf:
                           time_ms=s.time_ms, history=list(self.hist[: s.history_len]),
                           kernel_ms={names[i]: self.kms[i] for i in range(n) if self.kcnt[i]},
                           kernel_launches={names[i]: int(self.kcnt[i]) for i in range(n) if self.kcnt[i]},
-                          converged_at=s.converged_at, init_iters=s.init_iters, rel_initial=s.rel_initial)
+                          converged_at=s.converged_at, init_iters=s.init_iters, rel_initial=s.rel_initial,
+                          krylov_iters=s.krylov_iters)
 
 
 class Plan:
@@ -129,8 +133,8 @@ class Plan:
     def __init__(self, problem, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
-                 adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, theta=None,
-                 sigma=None, load=None, device=None):
+                 adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0,
+                 forcing=1e-2, max_krylov=100, theta=None, sigma=None, load=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -142,7 +146,7 @@ class Plan:
         self._ps = problem_struct(problem, theta, sigma, load)
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
                      use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
-                     init_static, init_tol, stop_relative_initial)
+                     init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -229,6 +233,29 @@ class Plan:
         if raise_on_error and st != L.PT_OK:
             raise PTError(st, "pt_adjoint_solve")
         return Lam, stats
+
+    def newton_solve(self, U=None, history_cap: int = 512, raise_on_error: bool = True):
+        """Newton's method with flexible GMRES steps and Armijo backtracking (pt_newton_solve)."""
+        if U is None:
+            U = self.new_time_field()
+        ws, nb = self.workspace()
+        buf = _StatsBuf(history_cap)
+        s = L.Stats()
+        buf.fill(s)
+        st = self.lib.pt_newton_solve(self._h, ws, nb, self._time_field(U, "U"), self._stream(), C.byref(s))
+        stats = buf.result(self.lib, st, s)
+        if raise_on_error and st != L.PT_OK:
+            raise PTError(st, "pt_newton_solve")
+        return U, stats
+
+    def jacobian_apply(self, U, V, transpose: bool = False):
+        """J(U) V or J(U)^T V (pt_jacobian_apply)."""
+        out = self.new_time_field()
+        ws, nb = self.workspace()
+        self._check(self.lib.pt_jacobian_apply(self._h, ws, nb, self._time_field(U, "U"), self._time_field(V, "V"),
+                                               C.c_void_p(out.data_ptr()), 1 if transpose else 0, self._stream()),
+                    "pt_jacobian_apply")
+        return out
 
     def loss_gradients(self, U, Lam=None, per_cell: bool = False):
         """(loss, dl/dtheta, dl/dsigma) at the state U with adjoint state Lam (pt_loss_gradients);
@@ -317,7 +344,8 @@ class BatchPlan(Plan):
     def __init__(self, problems, *, tol=1e-8, max_outer=1000, check_every=1, precision="fp64",
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
-                 adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, device=None):
+                 adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0,
+                 forcing=1e-2, max_krylov=100, device=None):
         import torch
         problems = list(problems)
         self.lib = L.load()
@@ -332,7 +360,7 @@ class BatchPlan(Plan):
         self._pa = (L.Problem * self.count)(*[problem_struct(p) for p in problems])
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
                      use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
-                     init_static, init_tol, stop_relative_initial)
+                     init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create_batch(self._pa, self.count, C.byref(o), C.byref(h))
@@ -378,4 +406,4 @@ class BatchPlan(Plan):
         raise TypeError("component entry points take a single-problem plan")
 
     residual = apply_K = rfft = irfft = shifted_apply = precond_apply = periodic_solve = _single
-    adjoint_solve = loss_gradients = _single
+    adjoint_solve = loss_gradients = newton_solve = jacobian_apply = _single

@@ -47,6 +47,7 @@ class Options(C.Structure):
         ("diverge_factor", C.c_double), ("xcd_remap", C.c_int32), ("timing", C.c_int32),
         ("grid_slot", C.c_int32), ("grid_team", C.c_int32), ("adjoint", C.c_int32),
         ("init_static", C.c_int32), ("init_tol", C.c_double), ("stop_relative_initial", C.c_int32),
+        ("krylov_dim", C.c_int32), ("forcing", C.c_double), ("max_krylov", C.c_int32),
         ("graph", C.c_int32),
     ]
 
@@ -58,6 +59,7 @@ class Stats(C.Structure):
         ("history_cap", C.c_int32), ("history_len", C.c_int32),
         ("kernel_ms", C.POINTER(C.c_double)), ("kernel_launches", C.POINTER(C.c_int64)),
         ("converged_at", C.c_int32), ("init_iters", C.c_int32), ("rel_initial", C.c_double),
+        ("krylov_iters", C.c_int32),
     ]
 
 
@@ -98,6 +100,8 @@ def load():
         "pt_periodic_solve": (i32, [vp, vp, sz, vp, vp, i32, vp]),
         "pt_adjoint_solve": (i32, [vp, vp, sz, vp, vp, vp, C.POINTER(Stats)]),
         "pt_loss_gradients": (i32, [vp, vp, sz, vp, vp, vp, vp, i32, dp, vp]),
+        "pt_newton_solve": (i32, [vp, vp, sz, vp, vp, C.POINTER(Stats)]),
+        "pt_jacobian_apply": (i32, [vp, vp, sz, vp, vp, vp, i32, vp]),
         "pt_status_string": (C.c_char_p, [i32]),
         "pt_last_error": (C.c_char_p, []),
         "pt_version": (i32, []),

@@ -150,6 +150,9 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (!(o->vc_omega > 0 && o->vc_omega < 1)) return fail(PT_ERR_INVALID, "vc_omega must be in (0, 1)");
     if (o->adjoint != 0 && o->adjoint != 1) return fail(PT_ERR_INVALID, "adjoint must be 0 or 1");
     if (o->init_static != 0 && o->init_static != 1) return fail(PT_ERR_INVALID, "init_static must be 0 or 1");
+    if (o->krylov_dim < 0 || o->krylov_dim > 64) return fail(PT_ERR_INVALID, "krylov_dim must be in [0, 64]");
+    if (o->krylov_dim > 0 && (!(o->forcing > 0 && o->forcing < 1) || o->max_krylov < 1))
+        return fail(PT_ERR_INVALID, "forcing must be in (0, 1) and max_krylov >= 1");
     if (o->init_static && (!(o->init_tol > 0) || !std::isfinite(o->init_tol)))
         return fail(PT_ERR_INVALID, "init_tol must be positive");
     if (o->init_static && o->use_initial_guess)
@@ -185,6 +188,7 @@ static pt_status validate_batch(const pt_problem* pr, int count, const pt_option
             return fail(PT_ERR_INVALID, "batch instances must share sigma_in, sigma_rect and nu_max");
     }
     if (o->adjoint) return fail(PT_ERR_INVALID, "adjoint plans take a single problem");
+    if (o->krylov_dim) return fail(PT_ERR_INVALID, "Newton plans take a single problem");
     for (int b = 0; b < count; ++b)
         if (pr[b].d_theta || pr[b].d_sigma || pr[b].d_load)
             return fail(PT_ERR_INVALID, "d_theta, d_sigma and d_load must be NULL in a batch of more than one");
@@ -230,6 +234,7 @@ static void layout(Plan& p) {
     size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows) * S * 3;
     size_t part_team = (size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2;
     size_t part_adj = p.opt.adjoint ? std::max<size_t>((size_t)kAdjBlocks * 2, (size_t)p.n * p.n * 2) : 0;
+    if (p.opt.krylov_dim > 0) part_adj = std::max<size_t>(part_adj, (size_t)kAdjBlocks * 2);
     p.part_bytes = std::max(std::max(part_slot, part_team), part_adj) * sizeof(double);
     p.off_part = take(p.part_bytes);
     p.off_scal = take(2 * B * sizeof(double));
@@ -240,6 +245,19 @@ static void layout(Plan& p) {
         p.off_sig = take(2 * (size_t)p.n * p.n * sizeof(double));
     } else {
         p.off_L = p.off_G = p.off_sig = 0;
+    }
+    if (p.opt.krylov_dim > 0) {
+        const size_t tf = p.nodes * p.N * sizeof(double);
+        const size_t m = p.opt.krylov_dim;
+        p.off_R = take(tf);
+        p.off_Ut = take(tf);
+        p.off_D = take(tf);
+        p.tf_stride = align256(tf);  // byte distance of consecutive basis fields
+        p.off_V = take((m + 1) * p.tf_stride);
+        p.off_Z = take(m * p.tf_stride);
+    } else {
+        p.off_R = p.off_Ut = p.off_D = p.off_V = p.off_Z = 0;
+        p.tf_stride = 0;
     }
     p.off_coef = take(8 * S * 2 * sizeof(double));  // eight double2 per-slot arrays
     p.off_coef2 = p.off_coef + 4 * S * 2 * sizeof(double);
@@ -640,6 +658,207 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
     return result;
 }
 
+// ---------------------------------------------------------------- Newton outer loop
+
+// Newton's method on A(U) = F with flexible GMRES for the steps and Armijo backtracking
+// (method (M2) of Sec. 4 with the periodic solve of the fixed-point iteration in place of
+// multigrid in time as the preconditioner).
+static pt_status newton_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, hipStream_t st, pt_stats* stats) {
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    char* ws = (char*)d_ws;
+    EventPair ev;
+    PT_HIP(hipEventCreate(&ev.e0));
+    PT_HIP(hipEventCreate(&ev.e1));
+    s = timer_start(p);
+    if (s != PT_OK) return s;
+    PT_HIP(hipEventRecord(ev.e0, st));
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    const int m = p.opt.krylov_dim;
+    double* U = (double*)(ws + p.off_U);
+    double* R = (double*)(ws + p.off_R);
+    double* Ut = (double*)(ws + p.off_Ut);
+    double* D = (double*)(ws + p.off_D);
+    auto Vf = [&](int i) { return (double*)(ws + p.off_V + (size_t)i * p.tf_stride); };
+    auto Zf = [&](int i) { return (double*)(ws + p.off_Z + (size_t)i * p.tf_stride); };
+    double* part = (double*)(ws + p.off_part);
+    double* scal = (double*)(ws + p.off_scal);
+    if (p.prob.d_load) launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st);
+    if (p.opt.use_initial_guess)
+        launch_transpose_in(p, d_u, U, st);
+    else
+        launch_zero16(U, p.nodes * p.N * sizeof(double), st);
+    double h2[2];
+    auto fetch2 = [&]() -> pt_status {
+        PT_HIP(hipMemcpyAsync(h2, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        PT_HIP(hipStreamSynchronize(st));
+        PT_HIP(hipGetLastError());
+        return PT_OK;
+    };
+    // ||F - A(X)|| and ||F|| with the residual (FP64, node-major) into Rout
+    auto residual = [&](const double* X, double* Rout, double& r, double& f) -> pt_status {
+        launch_forward(p, ws, TM_RESIDUAL, X, nullptr, Rout, part, st);
+        launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st);
+        pt_status q = fetch2();
+        r = std::sqrt(h2[0]);
+        f = std::sqrt(h2[1]);
+        return q;
+    };
+    auto dot = [&](const double* a, const double* b, double& out) -> pt_status {
+        const int np = launch_tdot(p, a, b, part, st);
+        launch_reduce_pairs(p, part, np, scal, st);
+        pt_status q = fetch2();
+        out = h2[0];
+        return q;
+    };
+    // z = P^{-1} v: time DFT, the inner method per frequency, inverse DFT
+    auto precond = [&](const double* v, double* z) -> pt_status {
+        launch_forward(p, ws, TM_SIGNAL, v, ws + p.lev[0].off_r, nullptr, part, st);
+        const void* X = nullptr;
+        const double* coef = nullptr;
+        pt_status q = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
+        if (q != PT_OK) return q;
+        launch_inverse(p, ws, X, coef, z, 0, st);
+        return PT_OK;
+    };
+    double r = 0, f = 0, d0 = 0, rel = INFINITY;
+    s = residual(U, R, r, f);
+    if (s != PT_OK) return s;
+    d0 = r;
+    pt_status result = PT_ERR_NOT_CONVERGED;
+    int k = 0, hist = 0, kry = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hc = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+    for (;;) {
+        const double den = p.opt.stop_relative_initial ? d0 : f;
+        rel = den > 0 ? r / den : r;
+        if (stats && stats->residual_history && hist < stats->history_cap) stats->residual_history[hist] = rel;
+        ++hist;
+        if (!std::isfinite(rel)) {
+            result = fail(PT_ERR_NONFINITE, "residual norm is not finite at Newton step " + std::to_string(k));
+            break;
+        }
+        if (rel <= p.opt.tol) {
+            result = PT_OK;
+            break;
+        }
+        if (k >= p.opt.max_outer) {
+            result = fail(PT_ERR_NOT_CONVERGED, "max_outer reached");
+            break;
+        }
+        // flexible GMRES for J D = R from D = 0
+        launch_zero16(D, p.nodes * p.N * sizeof(double), st);
+        double beta = r;
+        launch_taxpby(p, 1.0 / beta, R, 0.0, Vf(0), st);
+        int steps_here = 0;
+        for (;;) {
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int jd = 0;
+            double est = beta;
+            for (int j = 0; j < m; ++j) {
+                s = precond(Vf(j), Zf(j));
+                if (s != PT_OK) return s;
+                launch_jac_apply(p, ws, Zf(j), nullptr, Vf(j + 1), +1, st);
+                for (int i = 0; i <= j; ++i) {  // modified Gram-Schmidt
+                    double hij = 0;
+                    s = dot(Vf(j + 1), Vf(i), hij);
+                    if (s != PT_OK) return s;
+                    Hc(i, j) = hij;
+                    launch_taxpby(p, -hij, Vf(i), 1.0, Vf(j + 1), st);
+                }
+                double nn = 0;
+                s = dot(Vf(j + 1), Vf(j + 1), nn);
+                if (s != PT_OK) return s;
+                const double hn = std::sqrt(nn);
+                Hc(j + 1, j) = hn;
+                if (hn > 0) launch_taxpby(p, 1.0 / hn, Vf(j + 1), 0.0, Vf(j + 1), st);
+                for (int i = 0; i < j; ++i) {  // previous Givens rotations on column j
+                    const double a0 = Hc(i, j), a1 = Hc(i + 1, j);
+                    Hc(i, j) = cs[i] * a0 + sn[i] * a1;
+                    Hc(i + 1, j) = -sn[i] * a0 + cs[i] * a1;
+                }
+                const double a0 = Hc(j, j), a1 = Hc(j + 1, j), rr = std::hypot(a0, a1);
+                cs[j] = rr > 0 ? a0 / rr : 1.0;
+                sn[j] = rr > 0 ? a1 / rr : 0.0;
+                Hc(j, j) = rr;
+                Hc(j + 1, j) = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                est = std::fabs(g[j + 1]);
+                jd = j + 1;
+                ++steps_here;
+                ++kry;
+                if (est <= p.opt.forcing * r || hn == 0.0 || steps_here >= p.opt.max_krylov) break;
+            }
+            for (int i = jd - 1; i >= 0; --i) {  // H y = g, upper triangular
+                double sacc = g[i];
+                for (int l = i + 1; l < jd; ++l) sacc -= Hc(i, l) * y[l];
+                y[i] = Hc(i, i) != 0.0 ? sacc / Hc(i, i) : 0.0;
+            }
+            for (int i = 0; i < jd; ++i) launch_taxpby(p, y[i], Zf(i), 1.0, D, st);
+            if (est <= p.opt.forcing * r || steps_here >= p.opt.max_krylov) break;
+            // restart from the true residual R - J D
+            launch_jac_apply(p, ws, D, R, Vf(0), +1, st);
+            double bb = 0;
+            s = dot(Vf(0), Vf(0), bb);
+            if (s != PT_OK) return s;
+            beta = std::sqrt(bb);
+            if (!(beta > 0)) break;
+            launch_taxpby(p, 1.0 / beta, Vf(0), 0.0, Vf(0), st);
+        }
+        // Armijo backtracking on ||F - A(U + lambda D)||
+        double lam = 1.0;
+        bool accepted = false;
+        double* Rt = Vf(0);
+        for (int ls = 0; ls < 30; ++ls) {
+            launch_taxpby(p, 1.0, U, 0.0, Ut, st);
+            launch_taxpby(p, lam, D, 1.0, Ut, st);
+            double rt = 0, ft = 0;
+            s = residual(Ut, Rt, rt, ft);
+            if (s != PT_OK) return s;
+            if (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * r) {
+                launch_taxpby(p, 1.0, Ut, 0.0, U, st);
+                launch_taxpby(p, 1.0, Rt, 0.0, R, st);
+                r = rt;
+                accepted = true;
+                break;
+            }
+            lam *= 0.5;
+        }
+        if (!accepted) {
+            result = fail(PT_ERR_NOT_CONVERGED, "line search failed at Newton step " + std::to_string(k));
+            break;
+        }
+        ++k;
+    }
+    launch_transpose_out(p, U, d_u, st);
+    PT_HIP(hipEventRecord(ev.e1, st));
+    PT_HIP(hipEventSynchronize(ev.e1));
+    PT_HIP(hipGetLastError());
+    tm_flush(p);
+    float ms = 0.f;
+    PT_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    if (stats) {
+        stats->outer_iters = k;
+        stats->rel_residual = rel;
+        stats->f_norm = f;
+        stats->time_ms = ms;
+        stats->history_len = hist < stats->history_cap ? hist : stats->history_cap;
+        stats->converged_at = result == PT_OK ? k : -1;
+        stats->init_iters = 0;
+        stats->rel_initial = f > 0 ? d0 / f : d0;
+        stats->krylov_iters = kry;
+        for (int c = 0; c < KID_COUNT; ++c) {
+            if (stats->kernel_ms) stats->kernel_ms[c] = p.tm ? p.tm->ms[c] : 0.0;
+            if (stats->kernel_launches) stats->kernel_launches[c] = p.tm ? p.tm->cnt[c] : 0;
+        }
+    }
+    if (p.tm) p.tm->on = false;
+    return result;
+}
+
 }  // namespace pt
 
 using namespace pt;
@@ -692,6 +911,8 @@ void pt_options_default(pt_options* o) {
     o->diverge_factor = 1e3;
     o->xcd_remap = 1;
     o->init_tol = 1e-8;
+    o->forcing = 1e-2;
+    o->max_krylov = 100;
 }
 
 static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_options* opts, pt_plan** out) {
@@ -997,6 +1218,39 @@ pt_status pt_loss_gradients(pt_plan* plan, void* d_ws, size_t ws_bytes, const do
     PT_HIP(hipStreamSynchronize(st));
     PT_HIP(hipGetLastError());
     if (loss_out) *loss_out = h[0];
+    return PT_OK;
+}
+
+pt_status pt_newton_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream, pt_stats* stats) {
+    if (!plan || !d_u) return fail(PT_ERR_INVALID, "plan and d_u must not be NULL");
+    Plan& p = plan->p;
+    if (p.B != 1 || p.opt.krylov_dim < 1) return fail(PT_ERR_INVALID, "the plan was not created with options.krylov_dim > 0");
+    return newton_impl(p, d_ws, ws_bytes, d_u, (hipStream_t)stream, stats);
+}
+
+pt_status pt_jacobian_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, const double* d_v,
+                            double* d_out, int32_t transpose, void* stream) {
+    if (!plan || !d_u || !d_v || !d_out) return fail(PT_ERR_INVALID, "plan, d_u, d_v and d_out must not be NULL");
+    Plan& p = plan->p;
+    if (p.B != 1 || !(p.opt.adjoint || p.opt.krylov_dim > 0))
+        return fail(PT_ERR_INVALID, "the plan needs options.adjoint or options.krylov_dim");
+    if (transpose != 0 && transpose != 1) return fail(PT_ERR_INVALID, "transpose must be 0 or 1");
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    // the state goes to the iterate buffer, v to a scratch field, J v through the second one
+    double* U = (double*)(ws + p.off_U);
+    double* V = (double*)(ws + (p.opt.krylov_dim > 0 ? p.off_D : p.off_L));
+    double* O = (double*)(ws + (p.opt.krylov_dim > 0 ? p.off_Ut : p.off_G));
+    launch_transpose_in(p, d_u, U, st);
+    launch_transpose_in(p, d_v, V, st);
+    launch_jac_apply(p, ws, V, nullptr, O, transpose ? -1 : +1, st);
+    launch_transpose_out(p, O, d_out, st);
+    PT_HIP(hipStreamSynchronize(st));
+    PT_HIP(hipGetLastError());
     return PT_OK;
 }
 

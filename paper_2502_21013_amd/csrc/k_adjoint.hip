@@ -190,6 +190,49 @@ __global__ void __launch_bounds__(kBlock) k_adj_residual(AdjArgs a, T* rt) {
     block_pair_sum(rr, gg, a.part + 2 * (size_t)blockIdx.x);
 }
 
+// The linearised operator at the state U: (J v)^n = (M/tau)(v^n - v^{n-dir}) + K'(u^n) v^n with
+// dir = +1 (J, eqs. (disc1)-(disc2) linearised) or -1 (J^T: the time coupling runs the other
+// way, K' being symmetric). Writes out = J v when b is null and out = b - J v otherwise;
+// boundary entries are 0. FP64 throughout.
+__global__ void __launch_bounds__(kBlock) k_jac_apply(AdjArgs a, const double* v, const double* b, double* out,
+                                                      int dir) {
+    const size_t total = a.nodes * (size_t)a.N;
+    const size_t sd = a.side;
+    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
+        const size_t node = id >> a.lgN;
+        const int t = (int)(id & (size_t)(a.N - 1));
+        const int i = (int)(node % sd), j = (int)(node / sd);
+        double Jv = 0.0;
+        const bool interior = i > 0 && j > 0 && i < a.n && j < a.n;
+        if (interior) {
+            const Stencil u = load_stencil(a.U, node, sd, a.N, t);
+            const Stencil l = load_stencil(v, node, sd, a.N, t);
+            const size_t c_ij = (size_t)j * a.n + i, c_w = c_ij - 1, c_s = c_ij - a.n, c_sw = c_ij - a.n - 1;
+            const size_t tri[6] = {2 * c_ij, 2 * c_ij + 1, 2 * c_w, 2 * c_s + 1, 2 * c_sw, 2 * c_sw + 1};
+            const double gux[6] = {u.e - u.c, u.ne - u.nn, u.c - u.w, u.e - u.c, u.s - u.sw, u.c - u.w};
+            const double guy[6] = {u.ne - u.e, u.nn - u.c, u.nn - u.c, u.c - u.s, u.c - u.s, u.w - u.sw};
+            const double glx[6] = {l.e - l.c, l.ne - l.nn, l.c - l.w, l.e - l.c, l.s - l.sw, l.c - l.w};
+            const double gly[6] = {l.ne - l.e, l.nn - l.c, l.nn - l.c, l.c - l.s, l.c - l.s, l.w - l.sw};
+            const int px[6] = {-1, 0, 1, -1, 0, 1};
+            const int py[6] = {0, -1, -1, 1, 1, 0};
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const bool iron = a.flags[tri[k]] & 1;
+                const double th = a.theta ? a.theta[tri[k]] : 1.0;
+                const Law L = tri_law(a, iron, th, gux[k], guy[k]);
+                Jv += tri_lin(L, gux[k], guy[k], glx[k], gly[k], px[k], py[k]);
+            }
+            const MassRow m = mass_row(a, node);
+            if (m.any) {
+                const int to = dir > 0 ? (t == 0 ? a.N - 1 : t - 1) : (t + 1 == a.N ? 0 : t + 1);
+                const Stencil lo = load_stencil(v, node, sd, a.N, to);
+                Jv += a.inv_tau * (mass_apply(m, l) - mass_apply(m, lo));
+            }
+        }
+        out[id] = interior ? (b ? b[id] - Jv : Jv) : 0.0;
+    }
+}
+
 // One workgroup per cell (ci, cj), threads over time. Per triangle T of the cell:
 //   gtheta_T = - sum_n |T| nuhat_T(|grad u^n|^2) grad u^n . grad lambda^n
 //   gsigma_T = tau sum_n du^T M_T du - sum_n lambda^T M_T du,  du = (u^n - u^{n-1})/tau
@@ -317,6 +360,12 @@ void launch_adj_grad(const Plan& p, char* ws, bool with_lambda, double* gth, dou
     AdjArgs a = mk_adj(p, ws);
     if (!with_lambda) a.L = nullptr;
     hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)p.n * (unsigned)p.n), dim3(kBlock), 0, st, a, gth, gsg, per_cell);
+}
+
+void launch_jac_apply(const Plan& p, char* ws, const double* v, const double* b, double* out, int dir,
+                      hipStream_t st) {
+    AdjArgs a = mk_adj(p, ws);
+    hipLaunchKernelGGL(k_jac_apply, dim3(adj_grid(p.nodes * p.N)), dim3(kBlock), 0, st, a, v, b, out, dir);
 }
 
 }  // namespace pt

@@ -107,6 +107,8 @@ struct Plan {
     size_t off_flags, off_b, off_tw64, off_tw32, off_zs, off_wave;
     size_t off_part, part_bytes, off_scal, off_flag, off_coef, off_coef2, off_hist, off_inst;
     size_t off_L, off_G, off_sig;   // adjoint plans: adjoint iterate, dl/dU, per-triangle sigma
+    size_t off_R, off_Ut, off_D, off_V, off_Z;  // Newton plans: residual, trial, step, Krylov bases
+    size_t tf_stride;                           // bytes between consecutive Krylov basis fields
     size_t ws_bytes;
     bool has_cocg_vectors;
     // host copies of the small tables uploaded at every call
@@ -160,6 +162,13 @@ void launch_adj_source(const Plan& p, char* ws, hipStream_t st);
 int launch_adj_residual(const Plan& p, char* ws, void* rt, hipStream_t st);  // returns the partial count
 void launch_adj_grad(const Plan& p, char* ws, bool with_lambda, double* gth, double* gsg, int per_cell,
                      hipStream_t st);
+// out = J v (b null) or b - J v, J the linearised operator at the state in the iterate buffer;
+// dir = +1: J, dir = -1: J^T
+void launch_jac_apply(const Plan& p, char* ws, const double* v, const double* b, double* out, int dir,
+                      hipStream_t st);
+// time-field vector operations (k_krylov.hip); launch_tdot returns the partial count
+int launch_tdot(const Plan& p, const double* a, const double* b, double* part, hipStream_t st);
+void launch_taxpby(const Plan& p, double alpha, const double* x, double beta, double* y, hipStream_t st);
 void launch_apply_K(const Plan& p, char* ws, const double* u, double* ku, int nslices,
                     hipStream_t st);
 // frequency (k_freq.hip)

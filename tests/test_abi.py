@@ -190,3 +190,23 @@ def test_adjoint_entry_points_need_an_adjoint_plan(P):
 def test_static_start_options_are_validated(P, kw):
     with pytest.raises(P.PTError):
         P.Plan(W.config1(), **kw)
+
+
+@pytest.mark.parametrize("kw", [dict(krylov_dim=65), dict(krylov_dim=-1), dict(krylov_dim=4, forcing=1.0),
+                                dict(krylov_dim=4, max_krylov=0)])
+def test_newton_options_are_validated(P, kw):
+    with pytest.raises(P.PTError):
+        P.Plan(W.config1(), **kw)
+
+
+def test_newton_entry_points_need_a_newton_plan(P):
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    plan = P.Plan(W.with_size(W.config1(), 8, 8))
+    dummy = C.c_void_p(0x1000)
+    assert lib.pt_newton_solve(plan._h, dummy, plan.workspace_bytes, dummy, None, None) == L.PT_ERR_INVALID
+    assert lib.pt_jacobian_apply(plan._h, dummy, plan.workspace_bytes, dummy, dummy, dummy, 0, None) == L.PT_ERR_INVALID
+    nplan = P.Plan(W.with_size(W.config1(), 8, 8), krylov_dim=6)
+    assert nplan.workspace_bytes > plan.workspace_bytes + 14 * 81 * 8 * 8
+    with pytest.raises(P.PTError):
+        P.BatchPlan([W.with_size(p, 8, 8) for p in W.config4(0, 2)], krylov_dim=4)
