@@ -475,7 +475,8 @@ __global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs 
                 for (int d = 0; d < 3; ++d)
                     cw[d][e] = (d < NCOL && cr >= 0 && cr <= nc) ? *cboff(row_of(xc, cr, sc, lgR), occ[d]) : sv_zero<T>();
             };
-            int R0 = (j0 + 1) >> 1;
+            // the window of the step before the first one: the first step moves it up when j0 is odd
+            int R0 = j0 >> 1;
             load_crow(R0, std::integral_constant<int, 0>());
             load_crow(R0 + 1, std::integral_constant<int, 1>());
             // P x_c at fine column ai-1+c on a row of parity ROWODD whose coarse row is R0 + e:
