@@ -384,8 +384,9 @@ __device__ __forceinline__ SV<T> up_eval(const UpIn<SV<T>>& u, T dl, T idl, T om
 // stencil of row j are kept in registers and only the three new ones of row j+1,
 // (i-1, j+1), (i, j+2) and (i+1, j+2), are evaluated per step; their inputs are loaded
 // before the current row is computed so that the loads overlap the arithmetic.
+// three waves per SIMD (at most 168 VGPRs): the FP64 coarse window would otherwise drop to two
 template <typename T, bool UNI>
-__global__ void __launch_bounds__(kBlock) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
     using W = SV<T>;
     constexpr int V = W::V;
