@@ -260,3 +260,23 @@ def test_half_wave_symmetry_and_energy_balance(gpu, P):
     lhs = p.tau * np.sum(dU * (d.M @ dU.T).T)
     rhs = 2 * np.sum((F - pp.K_free(d, Uf)) * Uf)
     assert abs(lhs - rhs) <= 1e-8 * abs(lhs)
+
+
+# ---------------------------------------------------------------- extreme sizes
+
+_extreme_ref = {}
+
+@pytest.mark.parametrize("n,N", [(4, 4), (8, 1024), (16, 64), (64, 8)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solution_at_extreme_sizes_matches_oracle(gpu, P, n, N, precision):
+    # smallest grid and period, the longest period (two time pairs per lane in the residual
+    # sweep), a period with fewer slots than a wavefront, and a short period on a larger grid
+    say(f"extreme n={n} N={N} {precision}")
+    p = W.with_size(W.config2(11), n, N)
+    if (n, N) not in _extreme_ref:
+        d = fem.discretise(p)
+        _extreme_ref[(n, N)] = (d, pp.fixed_point(d, tol=1e-13, max_iter=3000))
+    d, ref = _extreme_ref[(n, N)]
+    U, st = P.Plan(p, tol=1e-12, max_outer=3000, precision=precision).solve()
+    assert st.rel_residual <= 1e-12
+    assert rel_err(U.cpu().numpy(), pp.to_full(d, ref.U)) <= 1e-8
