@@ -200,13 +200,34 @@ __device__ __forceinline__ NodeMat node_materials(const FwdArgs& a, int i, int j
     return m;
 }
 
+// Read-only table entry at an index that is the same on every lane of the wavefront (UNI):
+// read through the scalar unit (constant address space), so that the wait for it does not
+// also wait for the vector loads in flight. The tables (materials, mass, load) are never
+// written while a kernel reads them, so the scalar data cache needs no coherence here.
+template <typename X> using ConstPtr = const __attribute__((address_space(4))) X*;
+
+template <bool UNI, typename X>
+__device__ __forceinline__ X uload(const X* p, size_t idx) {
+    if constexpr (UNI) return ((ConstPtr<X>)p)[idx];
+    else return p[idx];
+}
+
 // Material flags and scales of the two triangles T_a (t = 0) and T_b (t = 1) of cell (ci, cj).
+// The two flag bytes of a cell share one aligned dword (the flag table of an instance starts
+// at a multiple of 2 n^2 bytes, n >= 4).
+template <bool UNI = false>
 __device__ __forceinline__ void cell_mat(const FwdArgs& a, int ci, int cj, bool ir[2], double th[2]) {
     size_t c = (size_t)cj * a.n + ci;
-    ir[0] = a.flags[2 * c] & 1;
-    ir[1] = a.flags[2 * c + 1] & 1;
-    th[0] = a.theta ? a.theta[2 * c] : 1.0;
-    th[1] = a.theta ? a.theta[2 * c + 1] : 1.0;
+    if constexpr (UNI) {
+        const uint32_t w = ((ConstPtr<uint32_t>)a.flags)[c >> 1] >> (16 * (c & 1));
+        ir[0] = w & 1u;
+        ir[1] = (w >> 8) & 1u;
+    } else {
+        ir[0] = a.flags[2 * c] & 1;
+        ir[1] = a.flags[2 * c + 1] & 1;
+    }
+    th[0] = a.theta ? uload<UNI>(a.theta, 2 * c) : 1.0;
+    th[1] = a.theta ? uload<UNI>(a.theta, 2 * c + 1) : 1.0;
 }
 
 // Per-lane state of the column walk for one time value: u on the rows j-1 (s, sw), j
@@ -251,12 +272,19 @@ __device__ __forceinline__ double upper_four(const FwdArgs& a, const Win& v, con
 // carrying the lower triangles' part of K. Rows are processed in batches of kRowBatch so
 // that one LDS exchange per batch forms M u^{n-1} from the neighbouring lane's M u^n.
 // Writes R in the solver precision (node-major, [node][N]) for the DFT, and/or in double
-// (rout), plus the FP64 norm partials. UNI: one column per wavefront.
+// (rout), plus the FP64 norm partials. UNI: one column per wavefront. RK: the source is the
+// separable b w(t) (RK_WAVE) or an explicit series F (RK_LOAD), or the sweep copies the field
+// itself (RK_SIGNAL: no operator, no mass term).
+// Every row issues the same vector loads on every path (indexes clamped to the grid where a
+// row or column lies outside it; such values are never used), so that the wait for the data
+// of a row never also waits for the loads of the rows after it.
 constexpr int kRowBatch = 4;
+enum ResKind { RK_WAVE = 0, RK_LOAD = 1, RK_SIGNAL = 2 };
 
-template <typename T, bool UNI, int KP>
+template <typename T, bool UNI, int KP, int RK>
 __global__ void __launch_bounds__(kBlock)
 k_residual(FwdArgs a, void* rt_) {
+    constexpr bool SIG = RK == RK_SIGNAL;
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int RB = kRowBatch;
@@ -292,15 +320,18 @@ k_residual(FwdArgs a, void* rt_) {
     // uniform row base + per-lane byte offset of (column i-1+d, instance bi, pair lt + TS k)
     const int lgST = a.lgST;  // 2^lgST time pairs per node over all instances (= slots per node)
     const long STp = a.ST;
+    const int bl_ = bi < a.B ? bi : a.B - 1;   // clamped instance and columns for the loads
     unsigned ofs[3][KP];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
+        const int c = i - 1 + d < 0 ? 0 : (i - 1 + d > n ? n : i - 1 + d);
 #pragma unroll
         for (int k = 0; k < KP; ++k)
-            ofs[d][k] = ((((unsigned)(i - 1 + d)) << lgST) + (unsigned)(bi * S + lt + TS * k)) * (unsigned)sizeof(double2);
+            ofs[d][k] = ((((unsigned)c) << lgST) + (unsigned)(bl_ * S + lt + TS * k)) * (unsigned)sizeof(double2);
+    }
     auto rowU = [&](int cj) { return U2 + ((size_t)(cj * side) << lgST); };
+    // u of row cj (0 <= cj <= n) on column i-1+d
     auto ldd = [&](int d, int cj, int k) -> double2 {
-        if (cj < 0 || cj > n) return make_double2(0.0, 0.0);
         return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(rowU(cj)) + ofs[d][k]);
     };
     // Window of u (both time levels of the lane's pair) on the columns i-1 (Wv), i (Cv) and
@@ -315,11 +346,11 @@ k_residual(FwdArgs a, void* rt_) {
         return Win{g(Wv[k][s0]), g(Cv[k][s0]), g(Wv[k][s1]), g(Cv[k][s1]), g(Ev[k][s1]),
                    g(Wv[k][s2]), g(Cv[k][s2]), g(Ev[k][s2]), cy};
     };
-    if (a.mode == TM_RESIDUAL && colint && jin < sr.row1 && jin < n) {
+    if (!SIG && colint && jin < sr.row1 && jin < n) {
         bool ir_s[2], ir_sw[2];
         double th_s[2], th_sw[2];
-        cell_mat(ai, i, jin - 1, ir_s, th_s);
-        cell_mat(ai, i - 1, jin - 1, ir_sw, th_sw);
+        cell_mat<UNI>(ai, i, jin - 1, ir_s, th_s);
+        cell_mat<UNI>(ai, i - 1, jin - 1, ir_sw, th_sw);
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             Wv[k][0] = ldd(0, jin - 1, k);
@@ -362,53 +393,77 @@ k_residual(FwdArgs a, void* rt_) {
                 r[k] = make_double2(0.0, 0.0);
                 mue[k] = muo[k] = 0.0;
             }
-            if (interior && a.mode == TM_RESIDUAL) {
-                // the three new neighbour series of row j+2, loaded before this row is computed
-                const bool adv = j + 1 < sr.row1 && j + 1 < n;
-                if (adv) {
+            if constexpr (SIG) {
+                // the field itself (loaded on every path, row clamped to the grid)
+                const int jl = j < n ? j : n;
+                double2 uv[KP];
 #pragma unroll
-                    for (int k = 0; k < KP; ++k) {
-                        Wv[k][s3] = ldd(0, j + 2, k);
-                        Cv[k][s3] = ldd(1, j + 2, k);
-                        Ev[k][s3] = ldd(2, j + 2, k);
-                    }
+                for (int k = 0; k < KP; ++k) uv[k] = ldd(1, jl, k);
+                if (interior) {
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) r[k] = uv[k];
                 }
-                bool ir_c[2], ir_w[2];
-                double th_c[2], th_w[2];
-                cell_mat(ai, i, j, ir_c, th_c);
-                cell_mat(ai, i - 1, j, ir_w, th_w);
-                const size_t nodes = a.nodes;
-                const long sd = side;
-                const double mc = a.mt[node], mE = a.mt[nodes + node], mW = a.mt[nodes + node - 1],
-                             mN = a.mt[2 * nodes + node], mS = a.mt[2 * nodes + node - sd],
-                             mNE = a.mt[3 * nodes + node], mSW = a.mt[3 * nodes + node - sd - 1];
-                const bool mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) ||
-                                  (mNE != 0.0) || (mSW != 0.0);
-                if (mass) mass_bits |= 1u << q;
-                const double bl = ai.bload[node];
-                const double2* F2 = (const double2*)a.F;
+            } else {
+                double2 fx[KP];
+                if constexpr (RK == RK_LOAD) {
+                    // the explicit source series first: waiting for it leaves the neighbour
+                    // series of row j+2 in flight
+                    const long nl = (long)(j < n ? j : n) * side + i;
+                    const double2* F2 = (const double2*)a.F;
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) fx[k] = F2[nl * S_ + lt + TS * k];
+                }
+                // the three new neighbour series of row j+2 (clamped to row n at the end of the
+                // grid), loaded before this row is computed
+                const bool adv = j + 1 < sr.row1 && j + 1 < n;
+                const int jn = j + 2 < n ? j + 2 : n;
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
-                    const int m = lt + TS * k;
-                    const Win p0 = win(k, 0, s0, s1, s2, carry[k][0]), p1 = win(k, 1, s0, s1, s2, carry[k][1]);
-                    double cu0, cu1;
-                    double K0 = upper_four(ai, p0, ir_c, th_c, ir_w, th_w, cu0);
-                    double K1 = upper_four(ai, p1, ir_c, th_c, ir_w, th_w, cu1);
-                    double2 f = F2 ? F2[(long)node * S_ + m] : make_double2(bl * wv[k].x, bl * wv[k].y);
-                    ff += f.x * f.x + f.y * f.y;
-                    r[k] = make_double2(f.x - K0, f.y - K1);
-                    if (mass) {
-                        mue[k] = mc * p0.c + mE * p0.e + mW * p0.w + mN * p0.n + mS * p0.s + mNE * p0.ne + mSW * p0.sw;
-                        muo[k] = mc * p1.c + mE * p1.e + mW * p1.w + mN * p1.n + mS * p1.s + mNE * p1.ne + mSW * p1.sw;
-                    }
-                    if (adv) {
-                        carry[k][0] = cu0;
-                        carry[k][1] = cu1;
+                    Wv[k][s3] = ldd(0, jn, k);
+                    Cv[k][s3] = ldd(1, jn, k);
+                    Ev[k][s3] = ldd(2, jn, k);
+                }
+                if (interior) {
+                    // mass row, load and materials of the row (all requested before any is used)
+                    const size_t nodes = a.nodes;
+                    const long sd = side;
+                    const double mc = uload<UNI>(a.mt, node), mE = uload<UNI>(a.mt, nodes + node),
+                                 mW = uload<UNI>(a.mt, nodes + node - 1), mN = uload<UNI>(a.mt, 2 * nodes + node),
+                                 mS = uload<UNI>(a.mt, 2 * nodes + node - sd),
+                                 mNE = uload<UNI>(a.mt, 3 * nodes + node),
+                                 mSW = uload<UNI>(a.mt, 3 * nodes + node - sd - 1);
+                    double bl = 0.0;
+                    if constexpr (RK == RK_WAVE) bl = uload<UNI>(ai.bload, node);
+                    bool ir_c[2], ir_w[2];
+                    double th_c[2], th_w[2];
+                    cell_mat<UNI>(ai, i, j, ir_c, th_c);
+                    cell_mat<UNI>(ai, i - 1, j, ir_w, th_w);
+                    const bool mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) ||
+                                      (mNE != 0.0) || (mSW != 0.0);
+                    if (mass) mass_bits |= 1u << q;
+#pragma unroll
+                    for (int k = 0; k < KP; ++k) {
+                        const Win p0 = win(k, 0, s0, s1, s2, carry[k][0]), p1 = win(k, 1, s0, s1, s2, carry[k][1]);
+                        double cu0, cu1;
+                        double K0 = upper_four(ai, p0, ir_c, th_c, ir_w, th_w, cu0);
+                        double K1 = upper_four(ai, p1, ir_c, th_c, ir_w, th_w, cu1);
+                        double2 f;
+                        if constexpr (RK == RK_LOAD) f = fx[k];
+                        else f = make_double2(bl * wv[k].x, bl * wv[k].y);
+                        ff += f.x * f.x + f.y * f.y;
+                        r[k] = make_double2(f.x - K0, f.y - K1);
+                        if (mass) {
+                            mue[k] = mc * p0.c + mE * p0.e + mW * p0.w + mN * p0.n + mS * p0.s + mNE * p0.ne +
+                                     mSW * p0.sw;
+                            muo[k] = mc * p1.c + mE * p1.e + mW * p1.w + mN * p1.n + mS * p1.s + mNE * p1.ne +
+                                     mSW * p1.sw;
+                        }
+                        if (adv) {
+                            carry[k][0] = cu0;
+                            carry[k][1] = cu1;
+                        }
                     }
                 }
-            } else if (interior) {  // TM_SIGNAL: the field itself
-#pragma unroll
-                for (int k = 0; k < KP; ++k) r[k] = U2[(long)node * STp + bi * S + lt + TS * k];
             }
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
@@ -602,16 +657,27 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     bool uni = TS >= 64;
     void* rt = out ? (void*)(ws + p.off_P) : nullptr;  // R in solver precision, node-major
     tm_begin(p, KID_RESIDUAL, st);
-#define PT_RES(TT, U, K) hipLaunchKernelGGL((k_residual<TT, U, K>), dim3(gf.blocks), blk, shm, st, a, rt)
+    const int rk = mode == TM_SIGNAL ? RK_SIGNAL : (a.F ? RK_LOAD : RK_WAVE);
+#define PT_RES(TT, U, K, G) hipLaunchKernelGGL((k_residual<TT, U, K, G>), dim3(gf.blocks), blk, shm, st, a, rt)
+#define PT_RES_MODE(TT, U, K)               \
+    do {                                    \
+        if (rk == RK_SIGNAL)                \
+            PT_RES(TT, U, K, RK_SIGNAL);    \
+        else if (rk == RK_LOAD)             \
+            PT_RES(TT, U, K, RK_LOAD);      \
+        else                                \
+            PT_RES(TT, U, K, RK_WAVE);      \
+    } while (0)
     if (p.fp32) {
-        if (KP == 2) PT_RES(float, true, 2);
-        else if (uni) PT_RES(float, true, 1);
-        else PT_RES(float, false, 1);
+        if (KP == 2) PT_RES_MODE(float, true, 2);
+        else if (uni) PT_RES_MODE(float, true, 1);
+        else PT_RES_MODE(float, false, 1);
     } else {
-        if (KP == 2) PT_RES(double, true, 2);
-        else if (uni) PT_RES(double, true, 1);
-        else PT_RES(double, false, 1);
+        if (KP == 2) PT_RES_MODE(double, true, 2);
+        else if (uni) PT_RES_MODE(double, true, 1);
+        else PT_RES_MODE(double, false, 1);
     }
+#undef PT_RES_MODE
 #undef PT_RES
     tm_end(p, KID_RESIDUAL, st);
     if (!out) return;
