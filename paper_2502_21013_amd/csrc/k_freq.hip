@@ -61,16 +61,17 @@ struct MRow {
     }
 };
 
+template <bool UNI>
 __device__ __forceinline__ MRow mrow(const LvArgs& L, long a) {
     const long nd = (long)L.nodes, sd = L.side;
     MRow m;
-    m.c = L.mt[a];
-    m.e = L.mt[nd + a];
-    m.w = L.mt[nd + a - 1];
-    m.n = L.mt[2 * nd + a];
-    m.s = L.mt[2 * nd + a - sd];
-    m.ne = L.mt[3 * nd + a];
-    m.sw = L.mt[3 * nd + a - sd - 1];
+    m.c = uload<UNI>(L.mt, a);
+    m.e = uload<UNI>(L.mt, nd + a);
+    m.w = uload<UNI>(L.mt, nd + a - 1);
+    m.n = uload<UNI>(L.mt, 2 * nd + a);
+    m.s = uload<UNI>(L.mt, 2 * nd + a - sd);
+    m.ne = uload<UNI>(L.mt, 3 * nd + a);
+    m.sw = uload<UNI>(L.mt, 3 * nd + a - sd - 1);
     return m;
 }
 
@@ -220,7 +221,9 @@ __device__ __forceinline__ void store_dot_partials(const double (*acc)[3], doubl
 // it into the coarse rows it belongs to with the P^T weights: row 2cj-1 contributes
 // (c-1, c) x 1/2, row 2cj contributes (c-1, c, c+1) x (1/2, 1, 1/2), row 2cj+1
 // contributes (c, c+1) x 1/2 (P1 interpolation on the SW-NE split grid). The inputs of
-// row R+2 are loaded before row R is computed.
+// row R+2 are loaded before row R is computed, on every path (the row clamped to the grid
+// after the last one), and the mass rows of a uniform column come through the scalar unit,
+// so that the wait for a row's inputs never waits for the loads of the row after it.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_, void* rout_) {
     using W = SV<T>;
@@ -254,21 +257,14 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     for (int d = 0; d < 5; ++d) of[d] = (((unsigned)(c - 2 + d) << lgST) + L.s0) * E;
     // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
     W xa[5], xb[5], xq[5], rb[3], rq[3];
+    // rows 2 cj0 - 2 .. 2 cj1 (all inside the grid, 0 <= R <= nF) are fetched
     auto fetch_row = [&](int R, W* rv, double* mv) {
-        if (R >= 0 && R <= nF) {
-            const W* fr = row_of(rin, R, sf, lgR);
-            const double* mr = F.mt + (long)R * sf + (c - 2);
+        const W* fr = row_of(rin, R, sf, lgR);
+        const long mr = (long)R * sf + (c - 2);
 #pragma unroll
-            for (int d = 0; d < 5; ++d) {
-                rv[d] = *cboff(fr, of[d]);
-                mv[d] = mr[d];
-            }
-        } else {
-#pragma unroll
-            for (int d = 0; d < 5; ++d) {
-                rv[d] = zero;
-                mv[d] = 0.0;
-            }
+        for (int d = 0; d < 5; ++d) {
+            rv[d] = *cboff(fr, of[d]);
+            mv[d] = uload<UNI>(F.mt, mr + d);
         }
     };
     auto eval_row = [&](const W* rv, const double* mv, W* xr, W* rr) {
@@ -293,21 +289,15 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     for (int R = Rs; R <= Re; ++R) {
         W nr[5];
         double nm[5];
-        if (R < Re) fetch_row(R + 2, nr, nm);  // next row's inputs, loaded before this row is computed
+        // next row's inputs, loaded before this row is computed (unused after the last row)
+        fetch_row(R + 2 < nF ? R + 2 : nF, nr, nm);
+        issue_fence();
         // s = r - A x1 at (c-1+k, R), k = 0..2; window rows: xa = R-1, xb = R, xq = R+1
-        const double* m0 = F.mt + (long)R * sf + (c - 1);
+        const long m0 = (long)R * sf + (c - 1);
         W sv[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double* mp = m0 + k;
-            MRow m;
-            m.c = mp[0];
-            m.e = mp[nd];
-            m.w = mp[nd - 1];
-            m.n = mp[2 * nd];
-            m.s = mp[2 * nd - sf];
-            m.ne = mp[3 * nd];
-            m.sw = mp[3 * nd - sf - 1];
+            const MRow m = mrow<UNI>(F, m0 + k);
             W Ax = apply_A<T>(m, nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1], xa[k + 1], xq[k + 2], xa[k]);
             sv[k] = sv_sub(rb[k], Ax);
         }
@@ -415,25 +405,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
             och[d] = (((unsigned)hi << lgST) + L.s0) * E;
             ocq[d] = (((unsigned)(hi + (bi & 1)) << lgST) + L.s0) * E;
         }
+        // inputs of fine point (ai-1+d, bj); every load is issued on every path (row clamped to
+        // the grid; c1 is the node of c0 again where the point coincides with a coarse node)
         auto load = [&](int d, int bj) -> UpIn<W> {
             UpIn<W> u;
-            if (bj < 0 || bj > nF) {
-                u.kind = 0;
-                u.r = u.c0 = u.c1 = sv_zero<T>();
-                u.mc = 0.0;
-                return u;
-            }
-            u.r = *cboff(row_of(rin, bj, sf, lgR), ofn[d]);
-            u.mc = F.mt[(long)bj * sf + ai - 1 + d];
-            const int hj = bj >> 1, oj = bj & 1;
+            const int bc = clampi(bj, 0, nF);
+            u.r = *cboff(row_of(rin, bc, sf, lgR), ofn[d]);
+            u.mc = uload<UNI>(F.mt, (long)bc * sf + ai - 1 + d);
+            const int hj = bc >> 1, oj = bc & 1;
             u.c0 = *cboff(row_of(xc, hj, sc, lgR), och[d]);
-            if (!odd[d] && !oj) {
-                u.kind = 1;
-                u.c1 = sv_zero<T>();
-            } else {
-                u.kind = 2;
-                u.c1 = *cboff(row_of(xc, hj + oj, sc, lgR), ocq[d]);
-            }
+            u.c1 = *cboff(row_of(xc, hj + oj, sc, lgR), ocq[d]);
+            u.kind = (bj < 0 || bj > nF) ? 0 : ((!odd[d] && !oj) ? 1 : 2);
             return u;
         };
         const int j0 = sr.row0;
@@ -462,19 +444,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         unsigned occ[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) occ[d] = (((unsigned)(kc0 + d) << lgST) + L.s0) * E;
-        auto rload = [&](int d, int bj) -> W {
-            return (bj >= 0 && bj <= nF) ? *cboff(row_of(rin, bj, sf, lgR), ofn[d]) : sv_zero<T>();
+        // rows outside the grid are clamped onto it: their values are never used (x2_at)
+        auto rload = [&](int d, int bj) -> W { return *cboff(row_of(rin, clampi(bj, 0, nF), sf, lgR), ofn[d]); };
+        auto mload = [&](int d, int bj) -> double {
+            return uload<UNI>(F.mt, (long)clampi(bj, 0, nF) * sf + ai - 1 + d);
         };
-        auto mload = [&](int d, int bj) -> double { return (bj >= 0 && bj <= nF) ? F.mt[(long)bj * sf + ai - 1 + d] : 0.0; };
         auto walk = [&](auto aodd_) {
             constexpr bool AODD = decltype(aodd_)::value;
             constexpr int NCOL = AODD ? 2 : 3;
             W cw[3][2];
             auto load_crow = [&](int cr, auto e_) {
                 constexpr int e = decltype(e_)::value;
+                const int cc = clampi(cr, 0, nc);   // rows past the grid feed only discarded points
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    cw[d][e] = (d < NCOL && cr >= 0 && cr <= nc) ? *cboff(row_of(xc, cr, sc, lgR), occ[d]) : sv_zero<T>();
+                    cw[d][e] = d < NCOL ? *cboff(row_of(xc, cc, sc, lgR), occ[d]) : sv_zero<T>();
             };
             // the window of the step before the first one: the first step moves it up when j0 is odd
             int R0 = j0 >> 1;
@@ -498,33 +482,27 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 if (bj < 0 || bj > nF) return sv_zero<T>();
                 return sv_add(jacobi<T>(dl, idl, om, mc, L.z, r), pxv);
             };
+            // one fine row aj < row1 (inside the chunk: computed and stored; past it: loads only)
             auto step = [&](int aj, auto ajodd_) {
                 constexpr bool AJODD = decltype(ajodd_)::value;
-                const bool more = aj + 1 < sr.row1;
-                W r0, r1, r2;
-                double m0 = 0, m1 = 0, m2 = 0;
-                if (more) {
-                    if (AJODD) {  // R0 = (aj + 1) / 2 moved up by one: shift the coarse window
+                const bool here = aj < sr.row1, more = aj + 1 < sr.row1;
+                if (AJODD) {  // R0 = (aj + 1) / 2 moved up by one: shift the coarse window
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) cw[d][0] = cw[d][1];
-                        R0 += 1;
-                        load_crow(R0 + 1, std::integral_constant<int, 1>());
-                    }
-                    r0 = rload(0, aj + 1);
-                    r1 = rload(1, aj + 2);
-                    r2 = rload(2, aj + 2);
-                    m0 = mload(0, aj + 1);
-                    m1 = mload(1, aj + 2);
-                    m2 = mload(2, aj + 2);
+                    for (int d = 0; d < 3; ++d) cw[d][0] = cw[d][1];
+                    R0 += 1;
+                    load_crow(R0 + 1, std::integral_constant<int, 1>());
                 }
+                const W r0 = rload(0, aj + 1), r1 = rload(1, aj + 2), r2 = rload(2, aj + 2);
+                const double m0 = mload(0, aj + 1), m1 = mload(1, aj + 2), m2 = mload(2, aj + 2);
+                issue_fence();
                 W out = sv_zero<T>();
-                if (aj > 0 && aj < nF) {
+                if (here && aj > 0 && aj < nF) {
                     const long a = (long)aj * sf + ai;
-                    W Ax = apply_A<T>(mrow(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
-                    out = sv_add(xcn, jacobi<T>(dl, idl, om, F.mt[a], L.z, sv_sub(rc, Ax)));
+                    W Ax = apply_A<T>(mrow<UNI>(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
+                    out = sv_add(xcn, jacobi<T>(dl, idl, om, uload<UNI>(F.mt, a), L.z, sv_sub(rc, Ax)));
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
                 }
-                *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
+                if (here) *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
                 if (more) {
                     // aj even: row aj + 1 (column ai-1) is odd on coarse row R0, row aj + 2 even on
                     // R0 + 1; aj odd: aj + 1 even on R0, aj + 2 odd on R0
@@ -544,13 +522,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 }
             };
             int aj = j0;
-            if ((aj & 1) && aj < sr.row1) {
+            if (aj & 1) {  // j0 < row1 here
                 step(aj, std::true_type());
                 ++aj;
             }
             for (; aj < sr.row1; aj += 2) {
                 step(aj, std::false_type());
-                if (aj + 1 < sr.row1) step(aj + 1, std::true_type());
+                step(aj + 1, std::true_type());
             }
         };
         if constexpr (V == 1) {
@@ -563,17 +541,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
             // the interpolation inputs are loaded per point
             for (int aj = j0; aj < sr.row1; ++aj) {
                 const bool more = aj + 1 < sr.row1;
-                UpIn<W> p0, p1, p2;
-                if (more) {
-                    p0 = load(0, aj + 1);
-                    p1 = load(1, aj + 2);
-                    p2 = load(2, aj + 2);
-                }
+                const UpIn<W> p0 = load(0, aj + 1), p1 = load(1, aj + 2), p2 = load(2, aj + 2);
+                issue_fence();
                 W out = sv_zero<T>();
                 if (aj > 0 && aj < nF) {
                     const long a = (long)aj * sf + ai;
-                    W Ax = apply_A<T>(mrow(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
-                    out = sv_add(xcn, jacobi<T>(dl, idl, om, F.mt[a], L.z, sv_sub(rc, Ax)));
+                    W Ax = apply_A<T>(mrow<UNI>(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
+                    out = sv_add(xcn, jacobi<T>(dl, idl, om, uload<UNI>(F.mt, a), L.z, sv_sub(rc, Ax)));
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
                 }
                 *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
@@ -622,10 +596,8 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
         const unsigned ow = (((unsigned)(ai - 1) << lgST) + L.s0) * E, oc = ow + (unsigned)ST * E,
                        oe = oc + (unsigned)ST * E;
-        auto ld = [&](unsigned o, int bj) -> W {
-            if (bj < 0 || bj > nF) return sv_zero<T>();
-            return *cboff(row_of(x, bj, sf, lgR), o);
-        };
+        // rows outside the grid are clamped onto it (loaded on every path, never used)
+        auto ld = [&](unsigned o, int bj) -> W { return *cboff(row_of(x, clampi(bj, 0, nF), sf, lgR), o); };
         const int j0 = sr.row0;
         W Wc[4], Cc[4], Ec[4];
         Wc[0] = ld(ow, j0 - 1);
@@ -638,24 +610,25 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
         auto row = [&](int aj, auto r_) {
             constexpr int r = decltype(r_)::value;  // slot of row aj - 1
             constexpr int s0 = r, s1 = (r + 1) & 3, s2 = (r + 2) & 3, s3 = (r + 3) & 3;
-            if (aj + 1 < sr.row1) {  // next row's new points, loaded before this row is computed
-                Wc[s2] = ld(ow, aj + 1);
-                Cc[s3] = ld(oc, aj + 2);
-                Ec[s3] = ld(oe, aj + 2);
-            }
+            // next row's new points, loaded before this row is computed (on every path)
+            Wc[s2] = ld(ow, aj + 1);
+            Cc[s3] = ld(oc, aj + 2);
+            Ec[s3] = ld(oe, aj + 2);
+            issue_fence();
+            if (aj >= sr.row1) return;
             W out = sv_zero<T>();
             if (aj > 0 && aj < nF) {
-                out = apply_A<T>(mrow(F, (long)aj * sf + ai), nu, L.z, Cc[s1], Ec[s1], Wc[s1], Cc[s2], Cc[s0], Ec[s2],
-                                 Wc[s0]);
+                out = apply_A<T>(mrow<UNI>(F, (long)aj * sf + ai), nu, L.z, Cc[s1], Ec[s1], Wc[s1], Cc[s2], Cc[s0],
+                                 Ec[s2], Wc[s0]);
                 if (dotmode != DOT_NONE) sv_dot_acc(acc, Cc[s1], out, dotmode == DOT_HERM);
             }
             if (y) *boff(row_of(y, aj, sf, lgR), oc) = out;
         };
         for (int aj = j0; aj < sr.row1; aj += 4) {
             row(aj, std::integral_constant<int, 0>());
-            if (aj + 1 < sr.row1) row(aj + 1, std::integral_constant<int, 1>());
-            if (aj + 2 < sr.row1) row(aj + 2, std::integral_constant<int, 2>());
-            if (aj + 3 < sr.row1) row(aj + 3, std::integral_constant<int, 3>());
+            row(aj + 1, std::integral_constant<int, 1>());
+            row(aj + 2, std::integral_constant<int, 2>());
+            row(aj + 3, std::integral_constant<int, 3>());
         }
     } else if (ai < sf && y) {
         const unsigned oc = (((unsigned)ai << lgST) + L.s0) * E;

@@ -200,18 +200,6 @@ __device__ __forceinline__ NodeMat node_materials(const FwdArgs& a, int i, int j
     return m;
 }
 
-// Read-only table entry at an index that is the same on every lane of the wavefront (UNI):
-// read through the scalar unit (constant address space), so that the wait for it does not
-// also wait for the vector loads in flight. The tables (materials, mass, load) are never
-// written while a kernel reads them, so the scalar data cache needs no coherence here.
-template <typename X> using ConstPtr = const __attribute__((address_space(4))) X*;
-
-template <bool UNI, typename X>
-__device__ __forceinline__ X uload(const X* p, size_t idx) {
-    if constexpr (UNI) return ((ConstPtr<X>)p)[idx];
-    else return p[idx];
-}
-
 // Material flags and scales of the two triangles T_a (t = 0) and T_b (t = 1) of cell (ci, cj).
 // The two flag bytes of a cell share one aligned dword (the flag table of an instance starts
 // at a multiple of 2 n^2 bytes, n >= 4).

@@ -144,4 +144,24 @@ __device__ __forceinline__ SweepRange sweep_range(int vb, int col_groups, int pe
     return r;
 }
 
+// Read-only table entry at an index that is the same on every lane of the wavefront (UNI):
+// read through the scalar unit (constant address space), so that the wait for it does not
+// also wait for the vector loads in flight. The tables (materials, mass, load) are never
+// written while a kernel reads them, and the scalar data cache is invalidated at every
+// kernel launch, so it needs no coherence with the vector stores.
+template <typename X> using ConstPtr = const __attribute__((address_space(4))) X*;
+
+template <bool UNI, typename X>
+__device__ __forceinline__ X uload(const X* p, size_t idx) {
+    if constexpr (UNI) return ((ConstPtr<X>)p)[idx];
+    else return p[idx];
+}
+
+// Compiler-only ordering point: memory operations are not moved across it (no instruction
+// is emitted). Placed after a prefetch so that the loads are issued before the arithmetic
+// that precedes their first use instead of being sunk next to it.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 }  // namespace pt
