@@ -226,6 +226,7 @@ static void layout(Plan& p) {
     }
     p.off_flags = take(B * 2 * (size_t)p.n * p.n);
     p.off_b = take(B * p.nodes * sizeof(double));
+    p.off_rec = take(B * p.nodes * kRecDoubles * sizeof(double));
     p.off_tw64 = take((size_t)p.N * 2 * sizeof(double));
     p.off_tw32 = take((size_t)p.N * 2 * sizeof(float));
     p.off_zs = take(S * 3 * sizeof(double));
@@ -341,6 +342,7 @@ static pt_status setup(Plan& p, char* ws, hipStream_t st) {
     PT_HIP(hipMemcpyAsync(ws + p.off_inst, p.h_inst, (size_t)p.B * 4 * sizeof(double), hipMemcpyHostToDevice, st));
     TM(KID_SETUP, launch_setup_fine(p, ws, st));
     for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin(p, ws, l, st));
+    TM(KID_SETUP, launch_row_records(p, ws, st));
     PT_HIP(hipGetLastError());
     return PT_OK;
 }
@@ -618,12 +620,14 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
         // Static start (Sec. 4, "Initialization"): the decoupled problems K(u^n) = f^n of sigma = 0,
         // i.e. the same iteration with every mass table zeroed; then the tables are rebuilt.
         for (int l = 0; l < p.nlev; ++l) TM(KID_MEMSET, launch_zero16(ws + p.lev[l].off_mt, 4 * p.lev[l].nodes * sizeof(double), st));
+        TM(KID_SETUP, launch_row_records(p, ws, st));
         residual_step(p, ws, false, st);
         s = run(p.opt.init_tol, p.opt.max_outer, false, false, init_iters, result);
         if (s != PT_OK) return s;
         if (result == PT_ERR_NOT_CONVERGED) result = PT_OK;  // the start need not be exact
         TM(KID_SETUP, launch_setup_fine(p, ws, st));
         for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin(p, ws, l, st));
+        TM(KID_SETUP, launch_row_records(p, ws, st));
     }
     if (result == PT_OK) {
         residual_step(p, ws, adjoint, st);

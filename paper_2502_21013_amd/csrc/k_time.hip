@@ -130,6 +130,7 @@ struct FwdArgs {
     const double* mt;      // [4][nodes]
     const uint8_t* flags;  // [2 n^2]
     const double* theta;   // [2 n^2] or null
+    const double* rec;     // [B][nodes][kRecDoubles] residual-sweep records
     const void* tw;        // T2 [N]
     void* out;             // T2 [nodes][S] or null
     double* rout;          // [nodes][N] or null
@@ -254,6 +255,141 @@ __device__ __forceinline__ double upper_four(const FwdArgs& a, const Win& v, con
     return 0.5 * (nu1 * (-g1x) + nu2 * (-g2y) + nu3 * (g3x - g3y)) + v.carry;
 }
 
+// ---------------------------------------------------------------- residual-sweep records
+
+// Everything the residual sweep needs at node (i, j) besides u, in one record read through the
+// scalar unit: the seven mass-stencil coefficients (centre, E, W, N, S, NE, SW), the load
+// amplitude b, and for the triangles T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i-1,j) the pair (A, B)
+// of the reluctivity law nu = A - B / (1 + s^2): A = theta (nu_a + nu_b), B = theta nu_b in
+// iron, A = theta nu_out and B = 0 elsewhere (Sec. 4, "Test problem": the same law as nu_tri).
+struct NodeRec {
+    double m[7];
+    double bl;
+    double law[4][2];
+};
+static_assert(sizeof(NodeRec) == kRecDoubles * sizeof(double), "record size");
+
+// Record idx of a table (through the scalar unit when UNI: adjacent words, merged into wide
+// scalar loads).
+template <bool UNI>
+__device__ __forceinline__ NodeRec load_rec(const NodeRec* base, size_t idx) {
+    const double* p = reinterpret_cast<const double*>(base + idx);
+    NodeRec r;
+    double* o = &r.m[0];
+#pragma unroll
+    for (int k = 0; k < kRecDoubles; ++k) o[k] = uload<UNI>(p, (size_t)k);
+    return r;
+}
+
+struct RecArgs {
+    int n, side, B;
+    size_t nodes;
+    const double* mt;      // [4][nodes] fine mass stencil (shared by the instances)
+    const double* bload;   // [B][nodes]
+    const uint8_t* flags;  // [B][2 n^2]
+    const double* theta;   // [2 n^2] or null (one instance)
+    const double* inst;    // [B][4] nu_a, nu_b, nu_out
+    NodeRec* rec;          // [B][nodes]
+};
+
+__global__ void __launch_bounds__(kBlock) k_row_records(RecArgs a) {
+    const size_t total = (size_t)a.B * a.nodes, nt = 2 * (size_t)a.n * a.n;
+    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
+        const int b = (int)(id / a.nodes);
+        const size_t node = id - (size_t)b * a.nodes;
+        const int i = (int)(node % a.side), j = (int)(node / a.side);
+        NodeRec r;
+        const bool interior = i > 0 && j > 0 && i < a.n && j < a.n;
+        const size_t nd = a.nodes, sd = a.side;
+        if (interior) {
+            r.m[0] = a.mt[node];
+            r.m[1] = a.mt[nd + node];
+            r.m[2] = a.mt[nd + node - 1];
+            r.m[3] = a.mt[2 * nd + node];
+            r.m[4] = a.mt[2 * nd + node - sd];
+            r.m[5] = a.mt[3 * nd + node];
+            r.m[6] = a.mt[3 * nd + node - sd - 1];
+        } else {
+            for (int k = 0; k < 7; ++k) r.m[k] = 0.0;
+        }
+        r.bl = a.bload[id];
+        const double nu_a = a.inst[4 * b], nu_b = a.inst[4 * b + 1], nu_out = a.inst[4 * b + 2];
+        for (int t = 0; t < 4; ++t) {
+            const int ci = i - (t >> 1), typ = t & 1;   // cells (i, j), (i, j), (i-1, j), (i-1, j)
+            double A = 0.0, Bv = 0.0;
+            if (ci >= 0 && ci < a.n && j < a.n) {
+                const size_t tri = 2 * ((size_t)j * a.n + ci) + typ;
+                const double th = a.theta ? a.theta[tri] : 1.0;
+                if (a.flags[(size_t)b * nt + tri] & 1) {
+                    A = th * (nu_a + nu_b);
+                    Bv = th * nu_b;
+                } else {
+                    A = th * nu_out;
+                }
+            }
+            r.law[t][0] = A;
+            r.law[t][1] = Bv;
+        }
+        a.rec[id] = r;
+    }
+}
+
+void launch_row_records(const Plan& p, char* ws, hipStream_t st) {
+    RecArgs a;
+    a.n = p.n;
+    a.side = p.side;
+    a.B = p.B;
+    a.nodes = p.nodes;
+    a.mt = (const double*)(ws + p.lev[0].off_mt);
+    a.bload = (const double*)(ws + p.off_b);
+    a.flags = (const uint8_t*)(ws + p.off_flags);
+    a.theta = p.prob.d_theta;
+    a.inst = (const double*)(ws + p.off_inst);
+    a.rec = (NodeRec*)(ws + p.off_rec);
+    size_t g = ((size_t)p.B * p.nodes + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_row_records, dim3((unsigned)g), dim3(kBlock), 0, st, a);
+}
+
+// Reluctivity from a record pair (A, B): nu = A - B / (1 + s^2), s^2 = n^2 |G|^2. NL: the
+// law is evaluated without a branch (exactly A where B = 0, since 1 / (1 + s^2) is finite), so
+// that the laws of all triangles of a row form independent chains; otherwise every B is 0.
+template <bool NL>
+__device__ __forceinline__ double nu_law(double gx, double gy, double n2, const double law[2]) {
+    if constexpr (!NL) return law[0];
+    return law[0] - law[1] * rcp_ge1(1.0 + n2 * (gx * gx + gy * gy));
+}
+
+// lower_three / upper_four with the reluctivity laws of a record: the record of node
+// (i, j-1) holds T_b(i,j-1), T_a(i-1,j-1), T_b(i-1,j-1) as its laws 1, 2, 3; the record of
+// node (i, j) holds T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i-1,j) as laws 0..3.
+__device__ __forceinline__ double lower_three_rec(const Win& v, double n2, const NodeRec& rs) {
+    double g4x = v.e - v.c, g4y = v.c - v.s;
+    double g5x = v.s - v.sw, g5y = v.c - v.s;
+    double g6x = v.c - v.w, g6y = v.w - v.sw;
+    return 0.5 * (nu_law<true>(g4x, g4y, n2, rs.law[1]) * (g4y - g4x) + nu_law<true>(g5x, g5y, n2, rs.law[2]) * g5y +
+                  nu_law<true>(g6x, g6y, n2, rs.law[3]) * g6x);
+}
+
+// whether any of the four laws of a record is nonlinear (uniform per row in a column walk)
+__device__ __forceinline__ bool rec_nonlinear(const NodeRec& r) {
+    return (r.law[0][1] != 0.0) || (r.law[1][1] != 0.0) || (r.law[2][1] != 0.0) || (r.law[3][1] != 0.0);
+}
+
+template <bool NL>
+__device__ __forceinline__ double upper_four_rec(const Win& v, double n2, const NodeRec& rc, double& carry_up) {
+    double g1x = v.e - v.c, g1y = v.ne - v.e;    // T_a(i,j)
+    double g2x = v.ne - v.n, g2y = v.n - v.c;    // T_b(i,j)
+    double g3x = v.c - v.w, g3y = v.n - v.c;     // T_a(i-1,j)
+    double g4x = v.n - v.nw, g4y = v.nw - v.w;   // T_b(i-1,j)
+    double nu1 = nu_law<NL>(g1x, g1y, n2, rc.law[0]);
+    double nu2 = nu_law<NL>(g2x, g2y, n2, rc.law[1]);
+    double nu3 = nu_law<NL>(g3x, g3y, n2, rc.law[2]);
+    double nu4 = nu_law<NL>(g4x, g4y, n2, rc.law[3]);
+    carry_up = 0.5 * (nu2 * (g2y - g2x) + nu3 * g3y + nu4 * g4x);
+    return 0.5 * (nu1 * (-g1x) + nu2 * (-g2y) + nu3 * (g3x - g3y)) + v.carry;
+}
+
 // Residual sweep: team of TS = S / KP threads per grid column (KP = 1 or 2 time pairs per
 // lane); lane lt owns the time pairs (2m, 2m+1), m = lt + TS k. The team walks down its
 // column keeping u on rows j-1..j+1 in registers (three new neighbour series per row) and
@@ -296,15 +432,8 @@ k_residual(FwdArgs a, void* rt_) {
     const int bi = vcol / side;
     const int i = vcol - bi * side;
     const bool colvalid = vcol < side * a.B, colint = colvalid && i > 0 && i < n;
-    FwdArgs ai = a;   // this instance's material parameters
-    if (a.inst && colvalid) {
-        ai.nu_a = a.inst[4 * bi];
-        ai.nu_b = a.inst[4 * bi + 1];
-        ai.nu_out = a.inst[4 * bi + 2];
-        ai.flags = a.flags + (size_t)bi * 2 * a.n * a.n;
-        ai.bload = a.bload + (size_t)bi * a.nodes;
-        ai.wave = a.wave + (size_t)bi * a.N;
-    }
+    // this instance's source waveform (its materials and load are in the records)
+    const double* wave = a.wave + (colvalid ? (size_t)bi * a.N : 0);
     // uniform row base + per-lane byte offset of (column i-1+d, instance bi, pair lt + TS k)
     const int lgST = a.lgST;  // 2^lgST time pairs per node over all instances (= slots per node)
     const long STp = a.ST;
@@ -334,11 +463,9 @@ k_residual(FwdArgs a, void* rt_) {
         return Win{g(Wv[k][s0]), g(Cv[k][s0]), g(Wv[k][s1]), g(Cv[k][s1]), g(Ev[k][s1]),
                    g(Wv[k][s2]), g(Cv[k][s2]), g(Ev[k][s2]), cy};
     };
+    const NodeRec* recb = (const NodeRec*)a.rec + (colvalid ? (size_t)bi * a.nodes : 0);
     if (!SIG && colint && jin < sr.row1 && jin < n) {
-        bool ir_s[2], ir_sw[2];
-        double th_s[2], th_sw[2];
-        cell_mat<UNI>(ai, i, jin - 1, ir_s, th_s);
-        cell_mat<UNI>(ai, i - 1, jin - 1, ir_sw, th_sw);
+        const NodeRec rs = load_rec<UNI>(recb, (size_t)(jin - 1) * side + i);
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             Wv[k][0] = ldd(0, jin - 1, k);
@@ -350,7 +477,7 @@ k_residual(FwdArgs a, void* rt_) {
             Cv[k][2] = ldd(1, jin + 1, k);
             Ev[k][2] = ldd(2, jin + 1, k);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) carry[k][h] = lower_three(ai, win(k, h, 0, 1, 2, 0.0), ir_s, th_s, ir_sw, th_sw);
+            for (int h = 0; h < 2; ++h) carry[k][h] = lower_three_rec(win(k, h, 0, 1, 2, 0.0), a.n2, rs);
         }
     }
     // a first row 0 of the chunk is boundary: zero output
@@ -365,7 +492,7 @@ k_residual(FwdArgs a, void* rt_) {
     // the source waveform at the lane's time pairs is the same on every row
     double2 wv[KP];
 #pragma unroll
-    for (int k = 0; k < KP; ++k) wv[k] = ((const double2*)ai.wave)[lt + TS * k];
+    for (int k = 0; k < KP; ++k) wv[k] = ((const double2*)wave)[lt + TS * k];
     for (int jb = jin; jb < sr.row1; jb += RB) {
         unsigned mass_bits = 0;
         auto row = [&](auto q_) {
@@ -412,40 +539,39 @@ k_residual(FwdArgs a, void* rt_) {
                     Ev[k][s3] = ldd(2, jn, k);
                 }
                 if (interior) {
-                    // mass row, load and materials of the row (all requested before any is used)
-                    const size_t nodes = a.nodes;
-                    const long sd = side;
-                    const double mc = uload<UNI>(a.mt, node), mE = uload<UNI>(a.mt, nodes + node),
-                                 mW = uload<UNI>(a.mt, nodes + node - 1), mN = uload<UNI>(a.mt, 2 * nodes + node),
-                                 mS = uload<UNI>(a.mt, 2 * nodes + node - sd),
-                                 mNE = uload<UNI>(a.mt, 3 * nodes + node),
-                                 mSW = uload<UNI>(a.mt, 3 * nodes + node - sd - 1);
-                    double bl = 0.0;
-                    if constexpr (RK == RK_WAVE) bl = uload<UNI>(ai.bload, node);
-                    bool ir_c[2], ir_w[2];
-                    double th_c[2], th_w[2];
-                    cell_mat<UNI>(ai, i, j, ir_c, th_c);
-                    cell_mat<UNI>(ai, i - 1, j, ir_w, th_w);
+                    // mass row, load and reluctivity laws of the row: one record
+                    const NodeRec rc = load_rec<UNI>(recb, (size_t)node);
+                    issue_fence();   // both halves of the record requested before either is used
+                    const double mc = rc.m[0], mE = rc.m[1], mW = rc.m[2], mN = rc.m[3], mS = rc.m[4],
+                                 mNE = rc.m[5], mSW = rc.m[6];
+                    const double bl = rc.bl;
+                    const bool nl = rec_nonlinear(rc);
                     const bool mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) ||
                                       (mNE != 0.0) || (mSW != 0.0);
                     if (mass) mass_bits |= 1u << q;
 #pragma unroll
                     for (int k = 0; k < KP; ++k) {
                         const Win p0 = win(k, 0, s0, s1, s2, carry[k][0]), p1 = win(k, 1, s0, s1, s2, carry[k][1]);
-                        double cu0, cu1;
-                        double K0 = upper_four(ai, p0, ir_c, th_c, ir_w, th_w, cu0);
-                        double K1 = upper_four(ai, p1, ir_c, th_c, ir_w, th_w, cu1);
-                        double2 f;
-                        if constexpr (RK == RK_LOAD) f = fx[k];
-                        else f = make_double2(bl * wv[k].x, bl * wv[k].y);
-                        ff += f.x * f.x + f.y * f.y;
-                        r[k] = make_double2(f.x - K0, f.y - K1);
+                        // mass products first: the whole record is then needed at the top of the row
                         if (mass) {
                             mue[k] = mc * p0.c + mE * p0.e + mW * p0.w + mN * p0.n + mS * p0.s + mNE * p0.ne +
                                      mSW * p0.sw;
                             muo[k] = mc * p1.c + mE * p1.e + mW * p1.w + mN * p1.n + mS * p1.s + mNE * p1.ne +
                                      mSW * p1.sw;
                         }
+                        double2 f;
+                        if constexpr (RK == RK_LOAD) f = fx[k];
+                        else f = make_double2(bl * wv[k].x, bl * wv[k].y);
+                        ff += f.x * f.x + f.y * f.y;
+                        double cu0, cu1, K0, K1;
+                        if (nl) {
+                            K0 = upper_four_rec<true>(p0, a.n2, rc, cu0);
+                            K1 = upper_four_rec<true>(p1, a.n2, rc, cu1);
+                        } else {
+                            K0 = upper_four_rec<false>(p0, a.n2, rc, cu0);
+                            K1 = upper_four_rec<false>(p1, a.n2, rc, cu1);
+                        }
+                        r[k] = make_double2(f.x - K0, f.y - K1);
                         if (adv) {
                             carry[k][0] = cu0;
                             carry[k][1] = cu1;
@@ -627,6 +753,7 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.mt = (const double*)(ws + p.lev[0].off_mt);
     a.flags = (const uint8_t*)(ws + p.off_flags);
     a.theta = p.prob.d_theta;
+    a.rec = (const double*)(ws + p.off_rec);
     a.tw = ws + (p.fp32 ? p.off_tw32 : p.off_tw64);
     a.out = nullptr;
     a.rout = rout;
@@ -754,7 +881,13 @@ struct InvArgs {
     double* U;            // [nodes][N]
 };
 
-template <typename T>
+// Inverse packed real DFT of one node per team and row (the inverse of k_rfft), scaled by
+// the per-slot coefficients, added to (ACC) or stored as the time series. The rows of a
+// chunk are software-pipelined: the spectrum of row j+1 and the field of row j are loaded
+// at the start of row j (on every path: indexes clamped to valid memory), so both overlap
+// the transform of row j; the results of row j are stored after the loads of row j+1 are
+// issued, so that no register reuse behind a store in flight stalls the next row.
+template <typename T, bool ACC>
 __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -770,7 +903,7 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
     const SweepRange sr = sweep_range(vb, a.col_groups, a.nb, a.rows_per_chunk, a.side);
     const int vcol = sr.col0 + team;  // b (n+1) + i
     const bool valid = vcol < a.side * a.B;
-    const int bi = valid ? vcol / a.side : 0, i = vcol - bi * a.side;
+    const int bi = valid ? vcol / a.side : 0, i = valid ? vcol - bi * a.side : 0;
     // per-lane constants of the slot pairs q = lt + h TS: twiddles and coefficients of slots 2q, 2q+1
     T2 pw[2][2];
     GS<T> cf[2][2];
@@ -790,20 +923,62 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
             }
         }
     }
+    // slot / time-pair offset of (row j, column i, instance bi); rows past the chunk map onto
+    // its last row (loaded, never used)
+    auto chunk_of = [&](int j) -> size_t {
+        const int jj = j < sr.row1 ? j : sr.row1 - 1;
+        return ((size_t)jj * a.side + i) * a.ST + (size_t)bi * S;
+    };
+    constexpr int kMaxPer = 4;  // S / TS time pairs per lane (TS = S / 4, or 1 when S = 2)
+    auto load_x = [&](int j, Pair<T2>* pv) {
+        const Pair<T2>* xp = (const Pair<T2>*)a.xhat + chunk_of(j) / 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = lt + h * TS;
+            pv[h] = xp[q < H ? q : H - 1];
+        }
+    };
+    Pair<T2> pn[2];
+    if (sr.row0 < sr.row1) load_x(sr.row0, pn);
+    double2 op[kMaxPer];   // results of the previous row, stored one row late
+    double2* up = nullptr;
+    auto store_prev = [&]() {
+        if (!up) return;
+#pragma unroll
+        for (int r = 0; r < kMaxPer; ++r) {
+            const int m = lt + r * TS;
+            if (m < S) up[m] = op[r];
+        }
+    };
     for (int j = sr.row0; j < sr.row1; ++j) {
-        size_t node = valid ? (size_t)j * a.side + i : 0;
-        bool interior = valid && i > 0 && j > 0 && i < a.n && j < a.n;
-        const size_t chunk = node * a.ST + (size_t)bi * S;  // slot / time-pair offset of (node, instance), even
-        const Pair<T2>* xp = (const Pair<T2>*)a.xhat + chunk / 2;
+        const bool interior = valid && i > 0 && j > 0 && i < a.n && j < a.n;
+        const size_t chunk = chunk_of(j);
+        Pair<T2> pv[2] = {pn[0], pn[1]};
+        load_x(j + 1, pn);
+        double2 uo[kMaxPer];
+        double2* u2 = (double2*)a.U + chunk;
+        if constexpr (ACC) {
+#pragma unroll
+            for (int r = 0; r < kMaxPer; ++r) {
+                const int m = lt + r * TS;
+                uo[r] = u2[m < S ? m : S - 1];
+            }
+        }
+        issue_fence();
+        store_prev();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            consume(pv[h].a);
+            consume(pv[h].b);
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int q = lt + h * TS;
             if (q < H) {
                 T2 v[2] = {mk2<T>(0, 0), mk2<T>(0, 0)};
                 if (interior) {
-                    const Pair<T2> pv = xp[q];
-                    v[0] = pv.a;
-                    v[1] = pv.b;
+                    v[0] = pv[h].a;
+                    v[1] = pv[h].b;
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         v[e] = gs_apply(cf[h][e], v[e]);
@@ -838,28 +1013,26 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
         }
         __syncthreads();
         T2* res = fft_lane<T2>(buf1, buf0, S, lt, TS, LF);
-        if (interior) {
-            double2* u2 = (double2*)a.U + chunk;
-            for (int m = lt; m < S; m += TS) {
-                T2 z = res[m];
-                double x0 = (double)(z.x * invS), x1 = (double)(-z.y * invS);
-                double2 o;
-                if (a.accumulate) {
-                    o = u2[m];
-                    o.x += x0;
-                    o.y += x1;
-                } else {
-                    o.x = x0;
-                    o.y = x1;
+        up = (interior || (valid && !ACC)) ? u2 : nullptr;
+#pragma unroll
+        for (int r = 0; r < kMaxPer; ++r) {
+            const int m = lt + r * TS;
+            double2 o = make_double2(0.0, 0.0);
+            if (interior && m < S) {
+                const T2 z = res[m];
+                o.x = (double)(z.x * invS);
+                o.y = (double)(-z.y * invS);
+                if constexpr (ACC) {
+                    o.x += uo[r].x;
+                    o.y += uo[r].y;
                 }
-                u2[m] = o;
             }
-        } else if (valid && !a.accumulate) {
-            double2* u2 = (double2*)a.U + chunk;
-            for (int m = lt; m < S; m += TS) u2[m] = make_double2(0.0, 0.0);
+            op[r] = o;
+            if constexpr (ACC) consume(uo[r]);
         }
         __syncthreads();
     }
+    store_prev();
 }
 
 void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coef, double* Uw, int accumulate,
@@ -886,10 +1059,17 @@ void launch_inverse(const Plan& p, char* ws, const void* xhat, const double* coe
     a.U = Uw;
     size_t shm = (size_t)g.per_step * 2 * p.S * p.elem;
     dim3 blk(g.per_step * g.slot_chunk);
-    if (p.fp32)
-        hipLaunchKernelGGL(k_inverse<float>, dim3(g.blocks), blk, shm, st, a);
-    else
-        hipLaunchKernelGGL(k_inverse<double>, dim3(g.blocks), blk, shm, st, a);
+    if (p.fp32) {
+        if (accumulate)
+            hipLaunchKernelGGL((k_inverse<float, true>), dim3(g.blocks), blk, shm, st, a);
+        else
+            hipLaunchKernelGGL((k_inverse<float, false>), dim3(g.blocks), blk, shm, st, a);
+    } else {
+        if (accumulate)
+            hipLaunchKernelGGL((k_inverse<double, true>), dim3(g.blocks), blk, shm, st, a);
+        else
+            hipLaunchKernelGGL((k_inverse<double, false>), dim3(g.blocks), blk, shm, st, a);
+    }
 }
 
 // ---------------------------------------------------------------- transposes

@@ -162,6 +162,20 @@ __device__ __forceinline__ X uload(const X* p, size_t idx) {
 // that precedes their first use instead of being sunk next to it.
 __device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
 
+// Marks a loaded value as used here on every path (no instruction is emitted): the wait for
+// the load then sits at this point on all paths, instead of a conservative wait for all
+// loads at a later register reuse on paths where the value is never read.
+__device__ __forceinline__ void consume(double x) { asm volatile("" ::"v"(x)); }
+__device__ __forceinline__ void consume(float x) { asm volatile("" ::"v"(x)); }
+__device__ __forceinline__ void consume(double2 x) {
+    consume(x.x);
+    consume(x.y);
+}
+__device__ __forceinline__ void consume(float2 x) {
+    consume(x.x);
+    consume(x.y);
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 }  // namespace pt

@@ -25,6 +25,7 @@ constexpr int kMaxLevels = 16;
 constexpr int kNumXcd = 8;
 constexpr int kReduceRows = 64;      // first-stage row groups of the dot-product reduction
 constexpr int kAdjBlocks = 8192;     // workgroups of the grid-stride adjoint kernels
+constexpr int kRecDoubles = 16;      // residual-sweep record per node: mass row, load, reluctivity laws
 
 // Per-slot scalar in "generic" form: for slot s >= 1 a complex number (x + i y);
 // for slot 0 two reals, x acting on the real part (k = 0) and y on the imaginary
@@ -105,6 +106,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t off_U, off_F, off_P, off_cx, off_cr, off_cq, off_cp;
     size_t off_flags, off_b, off_tw64, off_tw32, off_zs, off_wave;
+    size_t off_rec;     // per-instance, per-node records of the residual sweep (kRecDoubles doubles)
     size_t off_part, part_bytes, off_scal, off_flag, off_coef, off_coef2, off_hist, off_inst;
     size_t off_L, off_G, off_sig;   // adjoint plans: adjoint iterate, dl/dU, per-triangle sigma
     size_t off_R, off_Ut, off_D, off_V, off_Z;  // Newton plans: residual, trial, step, Krylov bases
@@ -138,6 +140,7 @@ Geom fwd_geom(int side, int S, int B, int target);
 // setup (k_setup.hip)
 void launch_setup_fine(const Plan& p, char* ws, hipStream_t st);
 void launch_galerkin(const Plan& p, char* ws, int l, hipStream_t st);
+void launch_row_records(const Plan& p, char* ws, hipStream_t st);
 // time axis (k_time.hip)
 void launch_transpose_in(const Plan& p, const double* src, double* dst, hipStream_t st);
 void launch_transpose_out(const Plan& p, const double* src, double* dst, hipStream_t st);
