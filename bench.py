@@ -135,8 +135,10 @@ def main_many(args, P):
 def algorithmic_bytes(p, elem):
     """Bytes each dominant kernel must move per launch (all (n+1)^2 grid nodes).
 
-    residual_sweep:           read U (8 B per node-time), write R (elem/2 per node-time)
-    rfft (packed DFT):        read R, write R^ (elem per node-slot each)
+    residual_sweep:           read U (8 B per node-time), write the residual spectrum R^ (its
+                              packed DFT, fused into the sweep: elem per node-slot)
+    rfft (packed DFT):        read R, write R^ (elem per node-slot each); outside the
+                              fixed-point step (preconditioner applications of other solvers)
     vcycle_down_fine:         read r (fine), write r_c (coarse)
     vcycle_up_fine:           read r (fine), read x_c (coarse), write x (fine)
     matvec_dot:               read p (fine)

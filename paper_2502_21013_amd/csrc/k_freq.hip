@@ -120,18 +120,19 @@ template <typename T> __device__ __forceinline__ SV<T> sv_fma(T s, const SV<T>& 
 }
 
 // (A x)_a for interior node a with mass row m, given the 7 neighbour values of x; z[k] is
-// the shift of the lane's slot k.
-template <typename T>
-__device__ __forceinline__ SV<T> apply_A(const MRow& m, T nu, const GS<T>* z, const SV<T>& xc, const SV<T>& xe,
-                                         const SV<T>& xw, const SV<T>& xn, const SV<T>& xs, const SV<T>& xne,
-                                         const SV<T>& xsw) {
+// the shift of the lane's slot k. MASS = false: the mass row is zero (stiffness part only);
+// MASS = true: the mass part is added without a branch (no change where the row is zero).
+template <typename T, bool MASS>
+__device__ __forceinline__ SV<T> apply_A_t(const MRow& m, T nu, const GS<T>* z, const SV<T>& xc, const SV<T>& xe,
+                                           const SV<T>& xw, const SV<T>& xn, const SV<T>& xs, const SV<T>& xne,
+                                           const SV<T>& xsw) {
     SV<T> out;
 #pragma unroll
     for (int k = 0; k < SV<T>::V; ++k) {
         out.v[k].x = nu * ((T)4 * xc.v[k].x - xe.v[k].x - xw.v[k].x - xn.v[k].x - xs.v[k].x);
         out.v[k].y = nu * ((T)4 * xc.v[k].y - xe.v[k].y - xw.v[k].y - xn.v[k].y - xs.v[k].y);
     }
-    if (!m.any()) return out;
+    if constexpr (!MASS) return out;
     const T mc = (T)m.c, me = (T)m.e, mw = (T)m.w, mn = (T)m.n, ms = (T)m.s, mne = (T)m.ne, msw = (T)m.sw;
 #pragma unroll
     for (int k = 0; k < SV<T>::V; ++k) {
@@ -147,7 +148,34 @@ __device__ __forceinline__ SV<T> apply_A(const MRow& m, T nu, const GS<T>* z, co
     return out;
 }
 
-// omega D^{-1} r with D = dl + z diag(M) (dm the node's diagonal mass entry)
+template <typename T>
+__device__ __forceinline__ SV<T> apply_A(const MRow& m, T nu, const GS<T>* z, const SV<T>& xc, const SV<T>& xe,
+                                         const SV<T>& xw, const SV<T>& xn, const SV<T>& xs, const SV<T>& xne,
+                                         const SV<T>& xsw) {
+    if (m.any()) return apply_A_t<T, true>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw);
+    return apply_A_t<T, false>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw);
+}
+
+// omega D^{-1} r with D = dl + z diag(M) (dm the node's diagonal mass entry). MASS = false:
+// dm = 0; MASS = true: any dm, the inverse chosen without a branch (same values as gs_inv_diag).
+template <typename T, bool MASS>
+__device__ __forceinline__ SV<T> jacobi_t(T dl, T idl, T om, double dm, const GS<T>* z, const SV<T>& r) {
+    SV<T> out;
+#pragma unroll
+    for (int k = 0; k < SV<T>::V; ++k) {
+        GS<T> di;
+        if constexpr (MASS) {
+            di = gs_inv_diag_sel<T>(dl, idl, (T)dm, z[k]);
+        } else {
+            di.a = idl;
+            di.b = (T)0;
+            di.c = idl;
+        }
+        out.v[k] = scale2(om, gs_apply(di, r.v[k]));
+    }
+    return out;
+}
+
 template <typename T>
 __device__ __forceinline__ SV<T> jacobi(T dl, T idl, T om, double dm, const GS<T>* z, const SV<T>& r) {
     SV<T> out;
@@ -267,12 +295,19 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             mv[d] = uload<UNI>(F.mt, mr + d);
         }
     };
+    // x1 on a row: one branch per row (uniform) on whether any of its five diagonal mass
+    // entries is nonzero, then five independent Jacobi steps
     auto eval_row = [&](const W* rv, const double* mv, W* xr, W* rr) {
+        const bool anym = mv[0] != 0.0 || mv[1] != 0.0 || mv[2] != 0.0 || mv[3] != 0.0 || mv[4] != 0.0;
+        if (anym) {
 #pragma unroll
-        for (int d = 0; d < 5; ++d) {
-            xr[d] = jacobi<T>(dl, idl, om, mv[d], L.z, rv[d]);
-            if (d >= 1 && d <= 3) rr[d - 1] = rv[d];
+            for (int d = 0; d < 5; ++d) xr[d] = jacobi_t<T, true>(dl, idl, om, mv[d], L.z, rv[d]);
+        } else {
+#pragma unroll
+            for (int d = 0; d < 5; ++d) xr[d] = jacobi_t<T, false>(dl, idl, om, mv[d], L.z, rv[d]);
         }
+#pragma unroll
+        for (int d = 1; d <= 3; ++d) rr[d - 1] = rv[d];
     };
     const int Rs = 2 * cj0 - 1, Re = 2 * cj1 - 1;
     {
@@ -295,11 +330,20 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
         // s = r - A x1 at (c-1+k, R), k = 0..2; window rows: xa = R-1, xb = R, xq = R+1
         const long m0 = (long)R * sf + (c - 1);
         W sv[3];
+        MRow mr3[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const MRow m = mrow<UNI>(F, m0 + k);
-            W Ax = apply_A<T>(m, nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1], xa[k + 1], xq[k + 2], xa[k]);
-            sv[k] = sv_sub(rb[k], Ax);
+        for (int k = 0; k < 3; ++k) mr3[k] = mrow<UNI>(F, m0 + k);
+        // one branch per row on whether any of the three mass rows is nonzero
+        if (mr3[0].any() || mr3[1].any() || mr3[2].any()) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                sv[k] = sv_sub(rb[k], apply_A_t<T, true>(mr3[k], nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1],
+                                                         xa[k + 1], xq[k + 2], xa[k]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                sv[k] = sv_sub(rb[k], apply_A_t<T, false>(mr3[k], nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1],
+                                                          xa[k + 1], xq[k + 2], xa[k]));
         }
         if (R & 1) {
             if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
@@ -360,12 +404,22 @@ template <typename W> struct UpIn {
     int kind;  // 0: outside the grid rows, 1: coincides with a coarse node, 2: edge midpoint
 };
 
-template <typename T>
-__device__ __forceinline__ SV<T> up_eval(const UpIn<SV<T>>& u, T dl, T idl, T om, const GS<T>* z) {
+// x2 at one fine point (the kind is uniform in a column walk); MASS as in jacobi_t
+template <typename T, bool MASS>
+__device__ __forceinline__ SV<T> up_eval_t(const UpIn<SV<T>>& u, T dl, T idl, T om, const GS<T>* z) {
     if (u.kind == 0) return sv_zero<T>();
-    SV<T> v = jacobi<T>(dl, idl, om, u.mc, z, u.r);
+    const SV<T> v = jacobi_t<T, MASS>(dl, idl, om, u.mc, z, u.r);
     if (u.kind == 1) return sv_add(v, u.c0);
     return sv_fma((T)0.5, sv_add(u.c0, u.c1), v);
+}
+
+// x3 = x2 + omega D^{-1} (r - A x2) at an interior node with mass row m (m.c its diagonal)
+template <typename T, bool MASS>
+__device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl, T om, const GS<T>* z, const SV<T>& r,
+                                               const SV<T>& xc, const SV<T>& xe, const SV<T>& xw, const SV<T>& xn,
+                                               const SV<T>& xs, const SV<T>& xne, const SV<T>& xsw) {
+    const SV<T> Ax = apply_A_t<T, MASS>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw);
+    return sv_add(xc, jacobi_t<T, MASS>(dl, idl, om, m.c, z, sv_sub(r, Ax)));
 }
 
 // x2 = omega D^{-1} r + P x_c (pre-smoothed iterate plus coarse correction), then one
@@ -423,13 +477,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         {
             const UpIn<W> q0 = load(0, j0 - 1), q1 = load(1, j0 - 1), q2 = load(0, j0), q3 = load(1, j0),
                           q4 = load(2, j0), q5 = load(1, j0 + 1), q6 = load(2, j0 + 1);
-            xsw = up_eval(q0, dl, idl, om, L.z);
-            xs = up_eval(q1, dl, idl, om, L.z);
-            xw = up_eval(q2, dl, idl, om, L.z);
-            xcn = up_eval(q3, dl, idl, om, L.z);
-            xe = up_eval(q4, dl, idl, om, L.z);
-            xn = up_eval(q5, dl, idl, om, L.z);
-            xne = up_eval(q6, dl, idl, om, L.z);
+            xsw = up_eval_t<T, true>(q0, dl, idl, om, L.z);
+            xs = up_eval_t<T, true>(q1, dl, idl, om, L.z);
+            xw = up_eval_t<T, true>(q2, dl, idl, om, L.z);
+            xcn = up_eval_t<T, true>(q3, dl, idl, om, L.z);
+            xe = up_eval_t<T, true>(q4, dl, idl, om, L.z);
+            xn = up_eval_t<T, true>(q5, dl, idl, om, L.z);
+            xne = up_eval_t<T, true>(q6, dl, idl, om, L.z);
             rc = q3.r;
             rn = q5.r;
         }
@@ -478,9 +532,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 constexpr int e1 = ROWODD ? e + 1 : e;
                 return sv_scale((T)0.5, sv_add(a0, cw[d1][e1]));
             };
-            auto x2_at = [&](int bj, const W& r, double mc, const W& pxv) -> W {
+            auto x2_at = [&](int bj, const W& r, double mc, const W& pxv, auto mass_) -> W {
+                constexpr bool MASS = decltype(mass_)::value;
                 if (bj < 0 || bj > nF) return sv_zero<T>();
-                return sv_add(jacobi<T>(dl, idl, om, mc, L.z, r), pxv);
+                return sv_add(jacobi_t<T, MASS>(dl, idl, om, mc, L.z, r), pxv);
             };
             // one fine row aj < row1 (inside the chunk: computed and stored; past it: loads only)
             auto step = [&](int aj, auto ajodd_) {
@@ -497,9 +552,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 issue_fence();
                 W out = sv_zero<T>();
                 if (here && aj > 0 && aj < nF) {
-                    const long a = (long)aj * sf + ai;
-                    W Ax = apply_A<T>(mrow<UNI>(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
-                    out = sv_add(xcn, jacobi<T>(dl, idl, om, uload<UNI>(F.mt, a), L.z, sv_sub(rc, Ax)));
+                    const MRow m = mrow<UNI>(F, (long)aj * sf + ai);
+                    if (m.any())
+                        out = post_smooth_t<T, true>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
+                    else
+                        out = post_smooth_t<T, false>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
                 }
                 if (here) *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
@@ -512,13 +569,22 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                     using ECE = std::integral_constant<int, AJODD ? 0 : 1>;
                     xsw = xw;
                     xs = xcn;
-                    xw = x2_at(aj + 1, r0, m0, px(std::integral_constant<int, 0>(), RW(), EW()));
                     xcn = xn;
                     rc = rn;
                     xe = xne;
-                    xn = x2_at(aj + 2, r1, m1, px(std::integral_constant<int, 1>(), RCE(), ECE()));
                     rn = r1;
-                    xne = x2_at(aj + 2, r2, m2, px(std::integral_constant<int, 2>(), RCE(), ECE()));
+                    const W p0 = px(std::integral_constant<int, 0>(), RW(), EW());
+                    const W p1 = px(std::integral_constant<int, 1>(), RCE(), ECE());
+                    const W p2 = px(std::integral_constant<int, 2>(), RCE(), ECE());
+                    if (m0 != 0.0 || m1 != 0.0 || m2 != 0.0) {  // one branch per row
+                        xw = x2_at(aj + 1, r0, m0, p0, std::true_type());
+                        xn = x2_at(aj + 2, r1, m1, p1, std::true_type());
+                        xne = x2_at(aj + 2, r2, m2, p2, std::true_type());
+                    } else {
+                        xw = x2_at(aj + 1, r0, m0, p0, std::false_type());
+                        xn = x2_at(aj + 2, r1, m1, p1, std::false_type());
+                        xne = x2_at(aj + 2, r2, m2, p2, std::false_type());
+                    }
                 }
             };
             int aj = j0;
@@ -538,29 +604,57 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 walk(std::false_type());
         } else {
             // FP32 (two slots per lane): the coarse window would cost a wave of occupancy, so
-            // the interpolation inputs are loaded per point
+            // the interpolation inputs are loaded per point, one row ahead of their use (two rows
+            // ahead measured no faster at 165 VGPRs)
+            constexpr int AHEAD = 1;
+            UpIn<W> n0, n1, n2;
+            if constexpr (AHEAD == 2) {
+                n0 = load(0, j0 + 1);
+                n1 = load(1, j0 + 2);
+                n2 = load(2, j0 + 2);
+            }
             for (int aj = j0; aj < sr.row1; ++aj) {
                 const bool more = aj + 1 < sr.row1;
-                const UpIn<W> p0 = load(0, aj + 1), p1 = load(1, aj + 2), p2 = load(2, aj + 2);
+                UpIn<W> p0, p1, p2;
+                if constexpr (AHEAD == 2) {
+                    p0 = n0;
+                    p1 = n1;
+                    p2 = n2;
+                    n0 = load(0, aj + 2);
+                    n1 = load(1, aj + 3);
+                    n2 = load(2, aj + 3);
+                } else {
+                    p0 = load(0, aj + 1);
+                    p1 = load(1, aj + 2);
+                    p2 = load(2, aj + 2);
+                }
                 issue_fence();
                 W out = sv_zero<T>();
                 if (aj > 0 && aj < nF) {
-                    const long a = (long)aj * sf + ai;
-                    W Ax = apply_A<T>(mrow<UNI>(F, a), nu, L.z, xcn, xe, xw, xn, xs, xne, xsw);
-                    out = sv_add(xcn, jacobi<T>(dl, idl, om, uload<UNI>(F.mt, a), L.z, sv_sub(rc, Ax)));
+                    const MRow m = mrow<UNI>(F, (long)aj * sf + ai);
+                    if (m.any())
+                        out = post_smooth_t<T, true>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
+                    else
+                        out = post_smooth_t<T, false>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
                 }
                 *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
                 if (more) {
                     xsw = xw;
                     xs = xcn;
-                    xw = up_eval(p0, dl, idl, om, L.z);
                     xcn = xn;
                     rc = rn;
                     xe = xne;
-                    xn = up_eval(p1, dl, idl, om, L.z);
                     rn = p1.r;
-                    xne = up_eval(p2, dl, idl, om, L.z);
+                    if (p0.mc != 0.0 || p1.mc != 0.0 || p2.mc != 0.0) {  // one branch per row
+                        xw = up_eval_t<T, true>(p0, dl, idl, om, L.z);
+                        xn = up_eval_t<T, true>(p1, dl, idl, om, L.z);
+                        xne = up_eval_t<T, true>(p2, dl, idl, om, L.z);
+                    } else {
+                        xw = up_eval_t<T, false>(p0, dl, idl, om, L.z);
+                        xn = up_eval_t<T, false>(p1, dl, idl, om, L.z);
+                        xne = up_eval_t<T, false>(p2, dl, idl, om, L.z);
+                    }
                 }
             }
         }

@@ -109,6 +109,78 @@ __device__ __forceinline__ T2* fft_lane(T2* a, T2* b, int S, int lt, int TS, con
     return a;
 }
 
+// fft_lane with the twiddles read from the table at each stage (the same entries as
+// lane_fft_twiddles), for kernels that cannot keep them in registers.
+template <typename T2>
+__device__ __forceinline__ T2* fft_lane_tab(T2* a, T2* b, int S, int lt, int TS, const T2* tw) {
+    int Ns = 1;
+    const int Q = S >> 2;
+#pragma unroll
+    for (int st = 0; st < kFftMaxR4; ++st) {
+        if (Ns * 4 > S) break;
+        if (lt < Q) {
+            const int j = lt, k = j & (Ns - 1), stp = S / (2 * Ns);
+            T2 v0 = a[j], v1 = a[j + Q], v2 = a[j + 2 * Q], v3 = a[j + 3 * Q];
+            if (st > 0) {
+                v1 = cmul(v1, tw[k * stp]);
+                v2 = cmul(v2, tw[2 * k * stp]);
+                v3 = cmul(v3, tw[3 * k * stp]);
+            }
+            T2 t0 = add2(v0, v2), t1 = sub2(v0, v2), t2 = add2(v1, v3), t3 = mul_mi(sub2(v1, v3));
+            const int idx = (j / Ns) * Ns * 4 + k;
+            b[idx] = add2(t0, t2);
+            b[idx + Ns] = add2(t1, t3);
+            b[idx + 2 * Ns] = sub2(t0, t2);
+            b[idx + 3 * Ns] = sub2(t1, t3);
+        }
+        __syncthreads();
+        T2* t = a;
+        a = b;
+        b = t;
+        Ns *= 4;
+    }
+    if (Ns < S) {
+        const int H = S >> 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lt + h * TS;
+            if (j < H) {
+                const int k = j & (Ns - 1);
+                T2 v0 = a[j];
+                T2 v1 = cmul(a[j + H], tw[(k * (S / Ns)) & (2 * S - 1)]);
+                const int idx = (j / Ns) * Ns * 2 + k;
+                b[idx] = add2(v0, v1);
+                b[idx + Ns] = sub2(v0, v1);
+            }
+        }
+        __syncthreads();
+        T2* t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Packed real DFT split: X_k of the real series whose half-length transform is z (k = 2q+e
+// for the lane's slot pair q), with pw the twiddles exp(-2 pi i k / N) of its two slots.
+template <typename T, typename T2>
+__device__ __forceinline__ void rfft_split(const T2* z, int S, int q, const T2 pw[2], int conj, T2 X[2]) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int k = 2 * q + e;
+        if (k == 0) {
+            T2 z0 = z[0];
+            X[e] = mk2<T>(z0.x + z0.y, z0.x - z0.y);
+        } else {
+            T2 zk = z[k], zc = conj2(z[S - k]);
+            T2 E = scale2((T)0.5, add2(zk, zc));
+            T2 O = scale2((T)0.5, mul_mi(sub2(zk, zc)));
+            X[e] = add2(E, cmul(pw[e], O));
+            if (conj) X[e] = conj2(X[e]);
+        }
+    }
+}
+
 // Two consecutive slot values (one 16-byte access in FP32).
 template <typename T2> struct alignas(16) Pair {
     T2 a, b;
@@ -402,24 +474,35 @@ __device__ __forceinline__ double upper_four_rec(const Win& v, double n2, const 
 // Every row issues the same vector loads on every path (indexes clamped to the grid where a
 // row or column lies outside it; such values are never used), so that the wait for the data
 // of a row never also waits for the loads of the rows after it.
+// FUSE (KP = 1, 4 <= S <= 256): instead of the time series R, the sweep writes its packed
+// real DFT (the output of k_rfft, remark rem:parallel) to a.out: after a row batch the
+// workgroup holds the residual of nb x RB nodes in LDS, and S/4 lanes transform each of them
+// (nb RB S/4 = 256 lanes), so the series never goes through HBM.
 constexpr int kRowBatch = 4;
 enum ResKind { RK_WAVE = 0, RK_LOAD = 1, RK_SIGNAL = 2 };
 
-template <typename T, bool UNI, int KP, int RK>
+template <typename T, bool UNI, int KP, int RK, bool FUSE>
 __global__ void __launch_bounds__(kBlock)
 k_residual(FwdArgs a, void* rt_) {
     constexpr bool SIG = RK == RK_SIGNAL;
+    static_assert(!FUSE || (KP == 1 && !SIG), "the fused transform takes one pair per lane");
     using T2 = typename Vec2<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int RB = kRowBatch;
     const int TS = a.ts, S = a.S;
     const int lt = threadIdx.x % TS, team = threadIdx.x / TS;
-    // per team: rs [RB][S] double2 (residual without the mass term), me / xo [RB][S] double
-    // (even / odd time mass products)
-    double2* rs = (double2*)smem_raw + (size_t)team * RB * S * 2;
-    double* me = (double*)(rs + RB * S);
-    double* xo = me + RB * S;
+    // per team and row q of a batch, contiguous: rs [S] double2 (residual without the mass
+    // term), me / xo [S] double (even / odd time mass products); 32 S bytes
+    auto RSp = [&](int c, int q) { return (double2*)(smem_raw + ((size_t)c * RB + q) * 32 * S); };
+    auto MEp = [&](int c, int q) { return (double*)(RSp(c, q) + S); };
+    auto XOp = [&](int c, int q) { return MEp(c, q) + S; };
     T2* rt = (T2*)rt_;
+    // FUSE: the twiddle table (N values) in LDS after the row blocks, read by every stage
+    T2* twl = (T2*)(smem_raw + (size_t)a.nb * RB * 32 * S);
+    if constexpr (FUSE) {
+        for (int k = threadIdx.x; k < a.N; k += kBlock) twl[k] = ((const T2*)a.tw)[k];
+        // (the first use follows the barrier after the first row batch)
+    }
     const double2* U2 = (const double2*)a.U;
     const int vb = virtual_block(a.remap);
     const int side = a.side, n = a.n;
@@ -487,6 +570,7 @@ k_residual(FwdArgs a, void* rt_) {
             const int m = lt + TS * k;
             if (a.rout) ((double2*)a.rout)[(long)i * STp + bi * S + m] = make_double2(0.0, 0.0);
             if (rt) rt[(long)i * STp + bi * S + m] = mk2<T>((T)0, (T)0);
+            if constexpr (FUSE) ((T2*)a.out)[(long)i * STp + bi * S + m] = mk2<T>((T)0, (T)0);  // its spectrum
         }
     }
     // the source waveform at the lane's time pairs is the same on every row
@@ -582,9 +666,9 @@ k_residual(FwdArgs a, void* rt_) {
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
                 const int m = lt + TS * k;
-                rs[q * S + m] = r[k];
-                me[q * S + m] = mue[k];
-                xo[q * S + m] = muo[k];
+                RSp(team, q)[m] = r[k];
+                MEp(team, q)[m] = mue[k];
+                XOp(team, q)[m] = muo[k];
             }
         };
         static_assert(kRowBatch == 4, "the row window is kept in slots modulo 4");
@@ -604,19 +688,61 @@ k_residual(FwdArgs a, void* rt_) {
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
                 const int m = lt + TS * k;
-                double2 rv = rs[q * S + m];
+                double2 rv = RSp(team, q)[m];
                 if (mass) {
-                    double mue = me[q * S + m], muo = xo[q * S + m];
-                    double prev = xo[q * S + (m == 0 ? S - 1 : m - 1)];
+                    const double* xo = XOp(team, q);
+                    double mue = MEp(team, q)[m], muo = xo[m];
+                    double prev = xo[m == 0 ? S - 1 : m - 1];
                     rv.x -= (mue - prev) * a.inv_tau;
                     rv.y -= (muo - mue) * a.inv_tau;
                 }
                 if (interior) rr += rv.x * rv.x + rv.y * rv.y;
                 if (a.rout) ((double2*)a.rout)[(long)node * STp + bi * S + m] = rv;
-                if (rt) rt[(long)node * STp + bi * S + m] = mk2<T>((T)rv.x, (T)rv.y);
+                if constexpr (FUSE) {
+                    // the transform input z_m = (r_2m, r_2m+1) in the solver precision, over the
+                    // lane's own entry (FP32: me[m]; FP64: rs[m])
+                    if constexpr (sizeof(T) == 4) ((T2*)MEp(team, q))[m] = mk2<T>((T)rv.x, (T)rv.y);
+                    else RSp(team, q)[m] = rv;
+                } else if (rt) {
+                    rt[(long)node * STp + bi * S + m] = mk2<T>((T)rv.x, (T)rv.y);
+                }
             }
         }
         __syncthreads();
+        if constexpr (FUSE) {
+            // transform fid = (team fc, row fq) on lanes fl < S/4; scratch: FP32 xo, FP64 me + xo
+            // (the lane index is made opaque here so that the transform's addresses and
+            // twiddles are formed per batch instead of being kept live across the row walk)
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            const int F4 = S >> 2, H = S >> 1;
+            const int fid = tid / F4, fl = tid - fid * F4;
+            const int fc = fid / RB, fq = fid - fc * RB;
+            T2* fa = sizeof(T) == 4 ? (T2*)MEp(fc, fq) : (T2*)RSp(fc, fq);
+            T2* fb = sizeof(T) == 4 ? (T2*)XOp(fc, fq) : (T2*)MEp(fc, fq);
+            const T2* tw = twl;
+            const T2* res = fft_lane_tab<T2>(fa, fb, S, fl, F4, tw);
+            const int fvcol = sr.col0 + fc, fj = jb + fq;
+            if (fvcol < side * a.B && fj < sr.row1) {
+                const int fbi = fvcol / side, fi = fvcol - fbi * side;
+                const size_t chunk = ((size_t)fj * side + fi) * a.ST + (size_t)fbi * S;  // even
+                Pair<T2>* outp = (Pair<T2>*)a.out + chunk / 2;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int qq = fl + h * F4;
+                    if (qq < H) {
+                        const T2 pw[2] = {tw[2 * qq], tw[2 * qq + 1]};
+                        T2 X[2];
+                        rfft_split<T>(res, S, qq, pw, 0, X);
+                        Pair<T2> o;
+                        o.a = X[0];
+                        o.b = X[1];
+                        outp[qq] = o;
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
     // per-team reduction of the norm partials (fixed order): part[(vb nb + team) 2 + {0, 1}]
     // with vb the virtual workgroup index (column group vb % col_groups)
@@ -699,20 +825,7 @@ __global__ void __launch_bounds__(kBlock) k_rfft(RfftArgs a) {
                 const int q = lt + h * TS;
                 if (q < H) {
                     T2 X[2];
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int k = 2 * q + e;
-                        if (k == 0) {
-                            T2 z0 = res[0];
-                            X[e] = mk2<T>(z0.x + z0.y, z0.x - z0.y);
-                        } else {
-                            T2 zk = res[k], zc = conj2(res[S - k]);
-                            T2 E = scale2((T)0.5, add2(zk, zc));
-                            T2 O = scale2((T)0.5, mul_mi(sub2(zk, zc)));
-                            X[e] = add2(E, cmul(pw[h][e], O));
-                            if (a.conj) X[e] = conj2(X[e]);
-                        }
-                    }
+                    rfft_split<T>(res, S, q, pw[h], a.conj, X);
                     Pair<T2> o;
                     o.a = X[0];
                     o.b = X[1];
@@ -773,7 +886,33 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     void* rt = out ? (void*)(ws + p.off_P) : nullptr;  // R in solver precision, node-major
     tm_begin(p, KID_RESIDUAL, st);
     const int rk = mode == TM_SIGNAL ? RK_SIGNAL : (a.F ? RK_LOAD : RK_WAVE);
-#define PT_RES(TT, U, K, G) hipLaunchKernelGGL((k_residual<TT, U, K, G>), dim3(gf.blocks), blk, shm, st, a, rt)
+    // residual spectrum in one pass: transform fused into the sweep (see k_residual)
+    if (out && rk != RK_SIGNAL && KP == 1 && p.S >= 4) {
+        a.out = out;
+        shm += (size_t)p.N * p.elem;  // twiddle table
+#define PT_RESF(TT, U, G) hipLaunchKernelGGL((k_residual<TT, U, 1, G, true>), dim3(gf.blocks), blk, shm, st, a, nullptr)
+        if (p.fp32) {
+            if (uni) {
+                if (rk == RK_LOAD) PT_RESF(float, true, RK_LOAD);
+                else PT_RESF(float, true, RK_WAVE);
+            } else {
+                if (rk == RK_LOAD) PT_RESF(float, false, RK_LOAD);
+                else PT_RESF(float, false, RK_WAVE);
+            }
+        } else {
+            if (uni) {
+                if (rk == RK_LOAD) PT_RESF(double, true, RK_LOAD);
+                else PT_RESF(double, true, RK_WAVE);
+            } else {
+                if (rk == RK_LOAD) PT_RESF(double, false, RK_LOAD);
+                else PT_RESF(double, false, RK_WAVE);
+            }
+        }
+#undef PT_RESF
+        tm_end(p, KID_RESIDUAL, st);
+        return;
+    }
+#define PT_RES(TT, U, K, G) hipLaunchKernelGGL((k_residual<TT, U, K, G, false>), dim3(gf.blocks), blk, shm, st, a, rt)
 #define PT_RES_MODE(TT, U, K)               \
     do {                                    \
         if (rk == RK_SIGNAL)                \

@@ -50,6 +50,18 @@ template <> __device__ __forceinline__ double fast_rcp<double>(double x) {
     return __builtin_fma(r, e, r);
 }
 
+// gs_inv_diag without a branch: both forms computed, the dm = 0 one selected (same values).
+template <typename T> __device__ __forceinline__ GS<T> gs_inv_diag_sel(T dl, T idl, T dm, const GS<T>& z) {
+    const T P = dl + z.a * dm, Pp = dl + z.c * dm, Q = z.b * dm;
+    const T inv = fast_rcp<T>(P * Pp + Q * Q);
+    const bool zero = dm == (T)0;
+    GS<T> g;
+    g.a = zero ? idl : Pp * inv;
+    g.b = zero ? (T)0 : -Q * inv;
+    g.c = zero ? idl : P * inv;
+    return g;
+}
+
 // Inverse of D = dl + z (x) dm (z generic, dl > 0 and dm >= 0 real), in generic form;
 // idl = 1/dl is the inverse where dm = 0 (no conductivity near the node).
 template <typename T> __device__ __forceinline__ GS<T> gs_inv_diag(T dl, T idl, T dm, const GS<T>& z) {
