@@ -604,30 +604,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 walk(std::false_type());
         } else {
             // FP32 (two slots per lane): the coarse window would cost a wave of occupancy, so
-            // the interpolation inputs are loaded per point, one row ahead of their use (two rows
-            // ahead measured no faster at 165 VGPRs)
-            constexpr int AHEAD = 1;
-            UpIn<W> n0, n1, n2;
-            if constexpr (AHEAD == 2) {
-                n0 = load(0, j0 + 1);
-                n1 = load(1, j0 + 2);
-                n2 = load(2, j0 + 2);
-            }
+            // the interpolation inputs are loaded per point, one row ahead of their use
             for (int aj = j0; aj < sr.row1; ++aj) {
                 const bool more = aj + 1 < sr.row1;
-                UpIn<W> p0, p1, p2;
-                if constexpr (AHEAD == 2) {
-                    p0 = n0;
-                    p1 = n1;
-                    p2 = n2;
-                    n0 = load(0, aj + 2);
-                    n1 = load(1, aj + 3);
-                    n2 = load(2, aj + 3);
-                } else {
-                    p0 = load(0, aj + 1);
-                    p1 = load(1, aj + 2);
-                    p2 = load(2, aj + 2);
-                }
+                const UpIn<W> p0 = load(0, aj + 1), p1 = load(1, aj + 2), p2 = load(2, aj + 2);
                 issue_fence();
                 W out = sv_zero<T>();
                 if (aj > 0 && aj < nF) {
