@@ -219,6 +219,13 @@ __device__ __forceinline__ double rcp_ge1(double x) {
     return __builtin_fma(r, e, r);
 }
 
+// 1 / x for x >= 1 with one Newton step: the estimate's relative error (below 5e-8, measured)
+// squared, about 2e-15 -- a few units in the last place, far below the residual's own rounding.
+__device__ __forceinline__ double rcp_ge1_1(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
 // Reluctivity of one triangle from its scaled gradient G = h grad u: nu_a + nu_b s^2/(1+s^2)
 // = (nu_a + nu_b) - nu_b / (1 + s^2) with s^2 = n^2 |G|^2, times theta; nu_out outside iron.
 __device__ __forceinline__ double nu_tri(double gx, double gy, const FwdArgs& a, bool iron, double th) {
@@ -429,7 +436,7 @@ void launch_row_records(const Plan& p, char* ws, hipStream_t st) {
 template <bool NL>
 __device__ __forceinline__ double nu_law(double gx, double gy, double n2, const double law[2]) {
     if constexpr (!NL) return law[0];
-    return law[0] - law[1] * rcp_ge1(1.0 + n2 * (gx * gx + gy * gy));
+    return law[0] - law[1] * rcp_ge1_1(1.0 + n2 * (gx * gx + gy * gy));
 }
 
 // lower_three / upper_four with the reluctivity laws of a record: the record of node
