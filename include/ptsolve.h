@@ -116,7 +116,7 @@ typedef struct {
                               residual sweep aim for per slot chunk; 0 = 8192. Performance
                               only (>= 8). */
     int32_t grid_team;     /* workgroups the per-node time-axis sweeps (DFT, inverse DFT)
-                              aim for; 0 = 65536. Performance only (>= 8). */
+                              aim for; 0 = 262144. Performance only (>= 8). */
     int32_t adjoint;       /* 1: reserve the workspace of pt_adjoint_solve / pt_loss_gradients
                               (two more time fields and a per-triangle table); single-problem
                               plans only */

@@ -21,7 +21,7 @@ from typing import Callable, Dict, List, Optional, Sequence
 # predicts the rate of the whole solve poorly, so it is searched only on request.
 OMEGAS = (0.8,)
 GRID_SLOT = (1024, 2048, 4096, 8192, 16384)
-GRID_TEAM = (4096, 16384, 65536, 262144)
+GRID_TEAM = (16384, 65536, 262144, 1048576)
 
 
 def _probe(make_plan: Callable, kw: Dict, steps: int, tol: float) -> Dict:

@@ -955,7 +955,7 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     p.tm = nullptr;
     p.gr = nullptr;
     p.target_slot = opts->grid_slot > 0 ? opts->grid_slot : 8192;
-    p.target_team = opts->grid_team > 0 ? opts->grid_team : 65536;
+    p.target_team = opts->grid_team > 0 ? opts->grid_team : 262144;
     p.g_slot0 = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
     p.g_team = team_geom(p.side, p.S, p.B, p.target_team);
     p.g_fwd = fwd_geom(p.side, p.S, p.B, p.target_slot);
