@@ -283,8 +283,6 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     unsigned of[5];
 #pragma unroll
     for (int d = 0; d < 5; ++d) of[d] = (((unsigned)(c - 2 + d) << lgST) + L.s0) * E;
-    // x1 and r on fine row R, columns c-2..c+2 (r kept for the three centre columns)
-    W xa[5], xb[5], xq[5], rb[3], rq[3];
     // rows 2 cj0 - 2 .. 2 cj1 (all inside the grid, 0 <= R <= nF) are fetched
     auto fetch_row = [&](int R, W* rv, double* mv) {
         const W* fr = row_of(rin, R, sf, lgR);
@@ -310,24 +308,34 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
         for (int d = 1; d <= 3; ++d) rr[d - 1] = rv[d];
     };
     const int Rs = 2 * cj0 - 1, Re = 2 * cj1 - 1;
+    // x1 on rows R-1, R, R+1 and r on rows R, R+1 in rings over the row (row t in slot
+    // (t - Rs + 1) mod 3), the row loop unrolled by 3 so that no value is moved
+    W X[3][5], Rr[3][3];
     {
-        W rv[5], dummy[3];
+        W rv[5];
         double mv[5];
         fetch_row(Rs - 1, rv, mv);
-        eval_row(rv, mv, xa, dummy);
+        eval_row(rv, mv, X[0], Rr[0]);
         fetch_row(Rs, rv, mv);
-        eval_row(rv, mv, xb, rb);
+        eval_row(rv, mv, X[1], Rr[1]);
         fetch_row(Rs + 1, rv, mv);
-        eval_row(rv, mv, xq, rq);
+        eval_row(rv, mv, X[2], Rr[2]);
     }
     W acc = zero;
-    for (int R = Rs; R <= Re; ++R) {
+    auto step = [&](int R, auto u_) {
+        constexpr int u = decltype(u_)::value;  // (R - Rs) mod 3
+        constexpr int ia = u, ib = (u + 1) % 3, iq = (u + 2) % 3;
         W nr[5];
         double nm[5];
         // next row's inputs, loaded before this row is computed (unused after the last row)
         fetch_row(R + 2 < nF ? R + 2 : nF, nr, nm);
         issue_fence();
-        // s = r - A x1 at (c-1+k, R), k = 0..2; window rows: xa = R-1, xb = R, xq = R+1
+        if (R > Re) return;
+        const W* xa = X[ia];
+        const W* xb = X[ib];
+        const W* xq = X[iq];
+        const W* rb = Rr[ib];
+        // s = r - A x1 at (c-1+k, R), k = 0..2; rows: xa = R-1, xb = R, xq = R+1
         const long m0 = (long)R * sf + (c - 1);
         W sv[3];
         MRow mr3[3];
@@ -357,16 +365,12 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             acc = sv_add(acc, sv[1]);
             acc = sv_fma(half, sv[2], acc);
         }
-        if (R < Re) {
-#pragma unroll
-            for (int d = 0; d < 5; ++d) {
-                xa[d] = xb[d];
-                xb[d] = xq[d];
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) rb[d] = rq[d];
-            eval_row(nr, nm, xq, rq);
-        }
+        if (R < Re) eval_row(nr, nm, X[ia], Rr[ia]);  // row R+2 over row R-1
+    };
+    for (int R = Rs; R <= Re; R += 3) {
+        step(R, std::integral_constant<int, 0>());
+        step(R + 1, std::integral_constant<int, 1>());
+        step(R + 2, std::integral_constant<int, 2>());
     }
 }
 
