@@ -219,6 +219,15 @@ pt_status pt_solve_many(int32_t count, pt_plan* const* plans, void* const* d_ws,
 pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
                       double* d_r, void* stream, double* rel_out, double* fnorm_out);
 
+/* The first two steps of one outer iteration (eq. (iter1) with the DFT of remark
+ * rem:parallel): the residual R = F - A(U) of pt_residual and its packed real DFT along
+ * time, written to d_rhat (frequency-field layout, plan precision: what pt_time_rfft(R)
+ * gives, to rounding in the transform). For 4 <= N/2 <= 256 this is the fused sweep the
+ * solver runs in every step (the time-domain R never reaches memory); other N take the
+ * two-kernel path. rel_out / fnorm_out as in pt_residual. Blocks until done. */
+pt_status pt_residual_spectrum(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
+                               void* d_rhat, void* stream, double* rel_out, double* fnorm_out);
+
 /* d_ku[j] = K(d_u[j]) for j < nslices (time-field layout, 1 <= nslices <= N); the
  * nonlinear P1 operator of Sec. 4 with the plan's material law. */
 pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,

@@ -282,6 +282,17 @@ class Plan:
                                          self._stream(), C.byref(rel), C.byref(fn)), "pt_residual")
         return R, rel.value, fn.value
 
+    def residual_spectrum(self, U):
+        """Packed real DFT along time of R = F - A(U) (the frequency field the fixed-point step
+        feeds to the frequency solve), with ||R||/||F|| and ||F||."""
+        Rh = self.new_freq_field()
+        ws, nb = self.workspace()
+        rel, fn = C.c_double(), C.c_double()
+        self._check(self.lib.pt_residual_spectrum(self._h, ws, nb, self._time_field(U, "U"),
+                                                  C.c_void_p(Rh.data_ptr()), self._stream(), C.byref(rel),
+                                                  C.byref(fn)), "pt_residual_spectrum")
+        return Rh, rel.value, fn.value
+
     def apply_K(self, U, nslices=None):
         nslices = self.N if nslices is None else int(nslices)
         KU = self.new_time_field()
@@ -405,5 +416,5 @@ class BatchPlan(Plan):
     def _single(self, *a, **k):
         raise TypeError("component entry points take a single-problem plan")
 
-    residual = apply_K = rfft = irfft = shifted_apply = precond_apply = periodic_solve = _single
+    residual = residual_spectrum = apply_K = rfft = irfft = shifted_apply = precond_apply = periodic_solve = _single
     adjoint_solve = loss_gradients = newton_solve = jacobian_apply = _single

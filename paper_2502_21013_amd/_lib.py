@@ -92,6 +92,7 @@ def load():
                                 C.POINTER(C.c_void_p), C.POINTER(C.POINTER(Stats)), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_void_p), i32]),
         "pt_residual": (i32, [vp, vp, sz, vp, vp, vp, dp, dp]),
+        "pt_residual_spectrum": (i32, [vp, vp, sz, vp, vp, vp, dp, dp]),
         "pt_apply_K": (i32, [vp, vp, sz, vp, vp, i32, vp]),
         "pt_time_rfft": (i32, [vp, vp, sz, vp, vp, vp]),
         "pt_time_irfft": (i32, [vp, vp, sz, vp, vp, vp]),

@@ -1049,6 +1049,33 @@ pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* 
     return PT_OK;
 }
 
+pt_status pt_residual_spectrum(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, void* d_rhat,
+                               void* stream, double* rel_out, double* fnorm_out) {
+    if (!plan || !d_u || !d_rhat) return fail(PT_ERR_INVALID, "plan, d_u and d_rhat must not be NULL");
+    Plan& p = plan->p;
+    if (p.B != 1) return fail(PT_ERR_INVALID, "component entry points take a single-problem plan");
+    pt_status s = check_ws(&p, d_ws, ws_bytes);
+    if (s != PT_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    s = setup(p, ws, st);
+    if (s != PT_OK) return s;
+    double* U = (double*)(ws + p.off_U);
+    if (p.prob.d_load) launch_transpose_in(p, p.prob.d_load, (double*)(ws + p.off_F), st);
+    launch_transpose_in(p, d_u, U, st);
+    double* part = (double*)(ws + p.off_part);
+    double* scal = (double*)(ws + p.off_scal);
+    launch_forward(p, ws, TM_RESIDUAL, U, d_rhat, nullptr, part, st);
+    launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st);
+    double h[2];
+    PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    PT_HIP(hipStreamSynchronize(st));
+    PT_HIP(hipGetLastError());
+    if (fnorm_out) *fnorm_out = std::sqrt(h[1]);
+    if (rel_out) *rel_out = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+    return PT_OK;
+}
+
 pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, double* d_ku, int32_t nslices,
                      void* stream) {
     if (!plan || !d_u || !d_ku) return fail(PT_ERR_INVALID, "plan, d_u and d_ku must not be NULL");

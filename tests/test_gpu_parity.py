@@ -114,6 +114,35 @@ def test_time_dft_matches_definition(gpu, P, N, precision):
     assert rel_err(back.cpu().numpy(), X) <= tol
 
 
+# ---------------------------------------------------------------- residual spectrum (fused step)
+
+@pytest.mark.parametrize("n,N,seed", [(8, 8, 0), (16, 64, 1), (32, 128, 2), (8, 512, 3), (8, 1024, 4), (8, 4, 5)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_residual_spectrum_is_the_dft_of_the_residual(gpu, P, n, N, seed, precision):
+    # 4 <= N/2 <= 256 runs the fused sweep (residual and its DFT in one pass), N = 4 and 1024 the
+    # two-kernel path. Either way: the DFT entry point applied to the residual entry point to a
+    # few units in the last place (same twiddles and butterflies; the compiler may fuse a
+    # multiply-add differently in the two kernels), the same norms bit for bit, and the
+    # oracle's DFT of the oracle residual to the transform tolerance
+    say(f"residual spectrum n={n} N={N} {precision}")
+    p = W.with_size(W.config2(seed), n, N)
+    d = fem.discretise(p)
+    U = W.random_field(N, n, seed + 20, 0.1)
+    plan = P.Plan(p, precision=precision)
+    Rh, rel, fn = plan.residual_spectrum(dev(U))
+    R, rel2, fn2 = plan.residual(dev(U))
+    two = plan.rfft(R)
+    ulp = 8 * (2.0 ** -52 if precision == "fp64" else 2.0 ** -23)
+    assert float((Rh - two).abs().max()) <= ulp * float(two.abs().max())
+    assert rel == rel2 and fn == fn2
+    F = pp.load_series(d)
+    Rref = pp.to_full(d, pp.residual(d, pp.to_free(d, U), F))
+    ref = dft.rfft_packed(Rref.reshape(N, -1)).T            # (nodes, S)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert rel_err(Rh.cpu().numpy(), ref) <= tol
+    plan.close()
+
+
 # ---------------------------------------------------------------- frequency-domain operator
 
 @pytest.mark.parametrize("n,N", [(8, 8), (32, 32), (16, 128)])
