@@ -495,8 +495,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         // and the coarse rows R0, R0 + 1 with R0 = (aj + 1) >> 1, which hold every coarse value
         // that the P1 interpolation needs at the step's new points (ai-1, aj+1), (ai, aj+2),
         // (ai+1, aj+2). The window moves by one coarse row every second fine row, so each
-        // coarse value is loaded once per column walk instead of at every fine point (FP64
-        // mode). The parities of ai and aj (uniform) are compile-time in the code below.
+        // coarse value is loaded once per column walk instead of at every fine point (in FP32
+        // mode too: the loads saved outweigh the registers, 1.50 -> 1.24 ms at config 3). The
+        // parities of ai and aj (uniform) are compile-time in the code below.
         const int kc0 = (ai - 1) >> 1;
         const int nc = C.n;
         unsigned occ[3];
@@ -601,47 +602,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 step(aj + 1, std::true_type());
             }
         };
-        if constexpr (V == 1) {
-            if (ai & 1)
-                walk(std::true_type());
-            else
-                walk(std::false_type());
-        } else {
-            // FP32 (two slots per lane): the coarse window would cost a wave of occupancy, so
-            // the interpolation inputs are loaded per point, one row ahead of their use
-            for (int aj = j0; aj < sr.row1; ++aj) {
-                const bool more = aj + 1 < sr.row1;
-                const UpIn<W> p0 = load(0, aj + 1), p1 = load(1, aj + 2), p2 = load(2, aj + 2);
-                issue_fence();
-                W out = sv_zero<T>();
-                if (aj > 0 && aj < nF) {
-                    const MRow m = mrow<UNI>(F, (long)aj * sf + ai);
-                    if (m.any())
-                        out = post_smooth_t<T, true>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
-                    else
-                        out = post_smooth_t<T, false>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
-                    if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
-                }
-                *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
-                if (more) {
-                    xsw = xw;
-                    xs = xcn;
-                    xcn = xn;
-                    rc = rn;
-                    xe = xne;
-                    rn = p1.r;
-                    if (p0.mc != 0.0 || p1.mc != 0.0 || p2.mc != 0.0) {  // one branch per row
-                        xw = up_eval_t<T, true>(p0, dl, idl, om, L.z);
-                        xn = up_eval_t<T, true>(p1, dl, idl, om, L.z);
-                        xne = up_eval_t<T, true>(p2, dl, idl, om, L.z);
-                    } else {
-                        xw = up_eval_t<T, false>(p0, dl, idl, om, L.z);
-                        xn = up_eval_t<T, false>(p1, dl, idl, om, L.z);
-                        xne = up_eval_t<T, false>(p2, dl, idl, om, L.z);
-                    }
-                }
-            }
-        }
+        if (ai & 1)
+            walk(std::true_type());
+        else
+            walk(std::false_type());
     } else if (ai < sf) {
         const unsigned oc = (((unsigned)ai << lgST) + L.s0) * E;
         for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(xout, aj, sf, lgR), oc) = sv_zero<T>();
