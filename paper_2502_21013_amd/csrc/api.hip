@@ -85,15 +85,16 @@ static void sweep_geom(Geom& g, int side, int target_blocks, int cols = 0) {
     g.blocks = (int)blocks;
 }
 
-Geom slot_geom(int side, int S, int V, int target_blocks) {
+Geom slot_geom(int side, int S, int V, int target_blocks, int cols) {
     // S slots per node, V slots per lane: a workgroup row of slot_chunk lanes covers
-    // slot_chunk V slots; per_step columns per workgroup
+    // slot_chunk V slots; per_step column units (cols of them, default: the grid's columns)
+    // per workgroup
     Geom g;
     const int lanes = S / V;
     g.slot_chunk = lanes < kBlock ? lanes : kBlock;
     g.per_step = kBlock / g.slot_chunk;
     g.chunks = lanes / g.slot_chunk;
-    sweep_geom(g, side, target_blocks);
+    sweep_geom(g, side, target_blocks, cols);
     return g;
 }
 
@@ -232,7 +233,7 @@ static void layout(Plan& p) {
     p.off_zs = take(S * 3 * sizeof(double));
     p.off_wave = take(B * (size_t)p.N * sizeof(double));
     p.off_inst = take(B * 4 * sizeof(double));
-    size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows) * S * 3;
+    size_t part_slot = (size_t)(std::max(p.g_slot0.blocks, p.g_mv.blocks) + kReduceRows) * S * 3;
     size_t part_team = (size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2;
     size_t part_adj = p.opt.adjoint ? std::max<size_t>((size_t)kAdjBlocks * 2, (size_t)p.n * p.n * 2) : 0;
     if (p.opt.krylov_dim > 0) part_adj = std::max<size_t>(part_adj, (size_t)kAdjBlocks * 2);
@@ -364,9 +365,9 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
     void* P = ws + p.off_P;
     if (p.opt.inner == PT_INNER_GALERKIN1) {
         launch_vcycle(p, ws, R, P, DOT_HERM, part, st);
-        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_HERM, num, st));
+        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_slot0.blocks, DOT_HERM, num, st));
         TM(KID_MATVEC, launch_matvec(p, ws, P, nullptr, DOT_HERM, part, st));
-        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_HERM, den, st));
+        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_mv.blocks, DOT_HERM, den, st));
         TM(KID_REDUCE, launch_slot_div(p, num, den, alpha, nullptr, st));
         *X = P;
         *coef = alpha;
@@ -381,16 +382,16 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
     TM(KID_MEMSET, launch_zero16(x, p.nodes * S * p.elem, st));
     TM(KID_COCG, launch_copy_slots(p, R, r, st));
     launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
-    TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, rho, st));
+    TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_slot0.blocks, DOT_BILIN, rho, st));
     TM(KID_COCG, launch_copy_slots(p, z, pv, st));
     for (int it = 0; it < iters; ++it) {
         TM(KID_MATVEC, launch_matvec(p, ws, pv, q, DOT_BILIN, part, st));
-        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, den, st));
+        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_mv.blocks, DOT_BILIN, den, st));
         TM(KID_REDUCE, launch_slot_div(p, rho, den, alpha, flag, st));
         TM(KID_COCG, launch_cocg_xr(p, alpha, x, r, pv, q, st));
         if (it + 1 == iters) break;
         launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
-        TM(KID_REDUCE, launch_reduce_dots(p, part, DOT_BILIN, rho2, st));
+        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_slot0.blocks, DOT_BILIN, rho2, st));
         TM(KID_REDUCE, launch_slot_div(p, rho2, rho, beta, nullptr, st));
         TM(KID_COCG, launch_cocg_p(p, beta, z, pv, st));
         TM(KID_COCG, launch_copy16(rho2, rho, S * sizeof(double2), st));
@@ -957,6 +958,7 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     p.target_slot = opts->grid_slot > 0 ? opts->grid_slot : 8192;
     p.target_team = opts->grid_team > 0 ? opts->grid_team : 262144;
     p.g_slot0 = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
+    p.g_mv = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, p.target_slot, (p.side + 1) / 2);
     p.g_team = team_geom(p.side, p.S, p.B, p.target_team);
     p.g_fwd = fwd_geom(p.side, p.S, p.B, p.target_slot);
     layout(p);

@@ -615,9 +615,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
 
 // ---------------------------------------------------------------- operator apply
 
-// y = A x and the dot partials of (x, A x); rolling window along the column as in k_vc_up,
-// kept in row slots modulo 4 (row aj in slot (aj - j0 + 1) & 3) with the row loop unrolled
-// by 4, so that the window is addressed with compile-time slots and never moved.
+// y = A x and the dot partials of (x, A x) for the two adjacent columns a0 = 2 pc and a0 + 1
+// of a team (the grid's columns 0..n in pairs; the last pair has one column): the rolling
+// window spans columns a0-1 .. a0+2, so each row loads four new points for two outputs
+// instead of three for one. The window is kept in row slots modulo 4 (row aj in slot
+// (aj - j0 + 1) & 3) with the row loop unrolled by 4, so it is never moved between registers.
+// Boundary columns and rows give 0.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const void* x_, void* y_, int dotmode,
                                                    double* part) {
@@ -633,38 +636,57 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
     const unsigned E = sizeof(typename Vec2<T>::type);
     double acc[V][3] = {};
     const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, F.side);
-    int ai = sr.col0 + L.ln;
-    if (UNI) ai = __builtin_amdgcn_readfirstlane(ai);
-    if (ai > 0 && ai < nF && sr.row0 < sr.row1) {
-        const unsigned ow = (((unsigned)(ai - 1) << lgST) + L.s0) * E, oc = ow + (unsigned)ST * E,
-                       oe = oc + (unsigned)ST * E;
+    int pc = sr.col0 + L.ln;
+    if (UNI) pc = __builtin_amdgcn_readfirstlane(pc);
+    const int a0 = 2 * pc;
+    if (a0 <= nF && sr.row0 < sr.row1) {
+        const bool two = a0 + 1 <= nF;   // the pair's second column exists
+        // columns a0-1, a0, a0+1, a0+2, clamped onto the grid (values there never used)
+        unsigned oc[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) oc[d] = (((unsigned)clampi(a0 - 1 + d, 0, nF) << lgST) + L.s0) * E;
         // rows outside the grid are clamped onto it (loaded on every path, never used)
-        auto ld = [&](unsigned o, int bj) -> W { return *cboff(row_of(x, clampi(bj, 0, nF), sf, lgR), o); };
+        auto ld = [&](int d, int bj) -> W { return *cboff(row_of(x, clampi(bj, 0, nF), sf, lgR), oc[d]); };
         const int j0 = sr.row0;
-        W Wc[4], Cc[4], Ec[4];
-        Wc[0] = ld(ow, j0 - 1);
-        Cc[0] = ld(oc, j0 - 1);
-        Wc[1] = ld(ow, j0);
-        Cc[1] = ld(oc, j0);
-        Ec[1] = ld(oe, j0);
-        Cc[2] = ld(oc, j0 + 1);
-        Ec[2] = ld(oe, j0 + 1);
+        W Wc[4], C0[4], C1[4], Ec[4];
+        Wc[0] = ld(0, j0 - 1);
+        C0[0] = ld(1, j0 - 1);
+        C1[0] = ld(2, j0 - 1);
+        Wc[1] = ld(0, j0);
+        C0[1] = ld(1, j0);
+        C1[1] = ld(2, j0);
+        Ec[1] = ld(3, j0);
+        C0[2] = ld(1, j0 + 1);
+        C1[2] = ld(2, j0 + 1);
+        Ec[2] = ld(3, j0 + 1);
+        const bool in0 = a0 > 0 && a0 < nF, in1 = a0 + 1 < nF;
         auto row = [&](int aj, auto r_) {
             constexpr int r = decltype(r_)::value;  // slot of row aj - 1
             constexpr int s0 = r, s1 = (r + 1) & 3, s2 = (r + 2) & 3, s3 = (r + 3) & 3;
             // next row's new points, loaded before this row is computed (on every path)
-            Wc[s2] = ld(ow, aj + 1);
-            Cc[s3] = ld(oc, aj + 2);
-            Ec[s3] = ld(oe, aj + 2);
+            Wc[s2] = ld(0, aj + 1);
+            C0[s3] = ld(1, aj + 2);
+            C1[s3] = ld(2, aj + 2);
+            Ec[s3] = ld(3, aj + 2);
             issue_fence();
             if (aj >= sr.row1) return;
-            W out = sv_zero<T>();
+            W out0 = sv_zero<T>(), out1 = sv_zero<T>();
             if (aj > 0 && aj < nF) {
-                out = apply_A<T>(mrow<UNI>(F, (long)aj * sf + ai), nu, L.z, Cc[s1], Ec[s1], Wc[s1], Cc[s2], Cc[s0],
-                                 Ec[s2], Wc[s0]);
-                if (dotmode != DOT_NONE) sv_dot_acc(acc, Cc[s1], out, dotmode == DOT_HERM);
+                if (in0) {
+                    out0 = apply_A<T>(mrow<UNI>(F, (long)aj * sf + a0), nu, L.z, C0[s1], C1[s1], Wc[s1], C0[s2], C0[s0],
+                                      C1[s2], Wc[s0]);
+                    if (dotmode != DOT_NONE) sv_dot_acc(acc, C0[s1], out0, dotmode == DOT_HERM);
+                }
+                if (in1) {
+                    out1 = apply_A<T>(mrow<UNI>(F, (long)aj * sf + a0 + 1), nu, L.z, C1[s1], Ec[s1], C0[s1], C1[s2],
+                                      C1[s0], Ec[s2], C0[s0]);
+                    if (dotmode != DOT_NONE) sv_dot_acc(acc, C1[s1], out1, dotmode == DOT_HERM);
+                }
             }
-            if (y) *boff(row_of(y, aj, sf, lgR), oc) = out;
+            if (y) {
+                *boff(row_of(y, aj, sf, lgR), oc[1]) = out0;
+                if (two) *boff(row_of(y, aj, sf, lgR), oc[2]) = out1;
+            }
         };
         for (int aj = j0; aj < sr.row1; aj += 4) {
             row(aj, std::integral_constant<int, 0>());
@@ -672,9 +694,6 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
             row(aj + 2, std::integral_constant<int, 2>());
             row(aj + 3, std::integral_constant<int, 3>());
         }
-    } else if (ai < sf && y) {
-        const unsigned oc = (((unsigned)ai << lgST) + L.s0) * E;
-        for (int aj = sr.row0; aj < sr.row1; ++aj) *boff(row_of(y, aj, sf, lgR), oc) = sv_zero<T>();
     }
     if (dotmode != DOT_NONE) store_dot_partials<V>(acc, part, vb, ST, blockIdx.y, SC);
 }
@@ -908,7 +927,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
 }
 
 void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode, double* part, hipStream_t st) {
-    const Geom& g = p.g_slot0;
+    const Geom& g = p.g_mv;
     SlotArgs sa = mk_slot(p, ws, g);
     dim3 grid(g.blocks, g.chunks);
     LvArgs Fl = host_lv(p, ws, 0);
@@ -926,9 +945,8 @@ void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode,
     }
 }
 
-void launch_reduce_dots(const Plan& p, double* part, int dotmode, double* out, hipStream_t st) {
-    // stage 1 into the tail of the partial buffer, then stage 2
-    const int nblk = p.g_slot0.blocks;
+void launch_reduce_dots(const Plan& p, double* part, int nblk, int dotmode, double* out, hipStream_t st) {
+    // stage 1 into the tail of the partial buffer (after the nblk workgroups' partials), then stage 2
     const int RB = nblk < kReduceRows ? nblk : kReduceRows;
     const int SG = p.ST < 64 ? p.ST : 64;
     double* part2 = part + (size_t)nblk * p.ST * 3;

@@ -121,6 +121,7 @@ struct Plan {
     double* h_inst;     // B x 4: nu_a, nu_b, nu_out, 0 of each instance
     int target_slot, target_team;  // grid targets of the slot-vector and per-node kernels
     Geom g_slot0;       // slot-vector kernels on level 0
+    Geom g_mv;          // operator apply on level 0: two adjacent columns per team
     Geom g_team;        // per-node team kernels (inverse DFT)
     Geom g_fwd;         // residual sweep (team of min(S, 256) threads per column)
     Timer* tm;          // per-kernel event timer (owned by the plan)
@@ -132,7 +133,7 @@ void graph_release(Plan& p);
 // target = number of workgroups (per slot chunk) the sweeping kernels aim for. The
 // per-node team kernels sweep B (n+1) virtual columns (instance b, grid column i at
 // b (n+1) + i) over n+1 rows.
-Geom slot_geom(int side, int S, int V, int target);
+Geom slot_geom(int side, int S, int V, int target, int cols = 0);
 Geom team_geom(int side, int S, int B, int target);
 Geom fwd_geom(int side, int S, int B, int target);
 
@@ -182,7 +183,7 @@ enum DotMode { DOT_NONE = 0, DOT_HERM = 1, DOT_BILIN = 2 };
 void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode, double* part,
                    hipStream_t st);
 // reduce dot partials -> generic scalars out[S] (double2)
-void launch_reduce_dots(const Plan& p, double* part, int dotmode, double* out, hipStream_t st);
+void launch_reduce_dots(const Plan& p, double* part, int nblk, int dotmode, double* out, hipStream_t st);
 // coef = num / den (generic division), with breakdown flag written to flag (int) if |den| tiny
 void launch_slot_div(const Plan& p, const double* num, const double* den, double* coef,
                      int* flag, hipStream_t st);
