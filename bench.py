@@ -28,6 +28,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -161,12 +162,23 @@ def algorithmic_bytes(p, elem):
     }
 
 
-def kernel_source_hash():
+def _code_only(text):
+    """C++ source without comments and whitespace runs (a comment edit is not a kernel change)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(csrc=None):
+    """Hash of the kernel sources' code (comments and layout ignored)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2502_21013_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2502_21013_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        if not f.endswith((".hip", ".h")):
+            continue
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(f.encode())
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -431,8 +431,9 @@ __device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl,
 // dot partials of (x3, r). Each thread walks down one column: the seven x2 values of the
 // stencil of row j are kept in registers and only the three new ones of row j+1,
 // (i-1, j+1), (i, j+2) and (i+1, j+2), are evaluated per step; their inputs are loaded
-// before the current row is computed so that the loads overlap the arithmetic.
-// three waves per SIMD (at most 168 VGPRs): the FP64 coarse window would otherwise drop to two
+// before the current row is computed so that the loads overlap the arithmetic, and the
+// coarse values they interpolate from come from a window of coarse rows (below).
+// Three waves per SIMD (at most 168 VGPRs): the coarse window would otherwise drop to two.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
@@ -463,8 +464,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
             och[d] = (((unsigned)hi << lgST) + L.s0) * E;
             ocq[d] = (((unsigned)(hi + (bi & 1)) << lgST) + L.s0) * E;
         }
-        // inputs of fine point (ai-1+d, bj); every load is issued on every path (row clamped to
-        // the grid; c1 is the node of c0 again where the point coincides with a coarse node)
+        // inputs of fine point (ai-1+d, bj) for the first rows of the walk; every load is issued
+        // on every path (row clamped to the grid; c1 is the node of c0 again where the point
+        // coincides with a coarse node)
         auto load = [&](int d, int bj) -> UpIn<W> {
             UpIn<W> u;
             const int bc = clampi(bj, 0, nF);
