@@ -138,7 +138,7 @@ def test_config2_full_size_against_oracle_residual(gpu, P, precision):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
-@pytest.mark.parametrize("precision", ["fp32"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_config3_full_size_sampled_slices(gpu, P, precision):
     say(f"config3 full size {precision}")
     p = W.config3(0)
