@@ -161,27 +161,16 @@ __device__ __forceinline__ SV<T> apply_A(const MRow& m, T nu, const GS<T>* z, co
 template <typename T, bool MASS>
 __device__ __forceinline__ SV<T> jacobi_t(T dl, T idl, T om, double dm, const GS<T>* z, const SV<T>& r) {
     SV<T> out;
+    if constexpr (!MASS) {
+        // D = dl: a real scaling (omega / dl per component)
+        const T s = om * idl;
 #pragma unroll
-    for (int k = 0; k < SV<T>::V; ++k) {
-        GS<T> di;
-        if constexpr (MASS) {
-            di = gs_inv_diag_sel<T>(dl, idl, (T)dm, z[k]);
-        } else {
-            di.a = idl;
-            di.b = (T)0;
-            di.c = idl;
-        }
-        out.v[k] = scale2(om, gs_apply(di, r.v[k]));
+        for (int k = 0; k < SV<T>::V; ++k) out.v[k] = scale2(s, r.v[k]);
+        return out;
     }
-    return out;
-}
-
-template <typename T>
-__device__ __forceinline__ SV<T> jacobi(T dl, T idl, T om, double dm, const GS<T>* z, const SV<T>& r) {
-    SV<T> out;
 #pragma unroll
     for (int k = 0; k < SV<T>::V; ++k) {
-        GS<T> di = gs_inv_diag<T>(dl, idl, (T)dm, z[k]);
+        const GS<T> di = gs_inv_diag_sel<T>(dl, idl, (T)dm, z[k]);
         out.v[k] = scale2(om, gs_apply(di, r.v[k]));
     }
     return out;
