@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                     const W p0 = px(std::integral_constant<int, 0>(), RW(), EW());
                     const W p1 = px(std::integral_constant<int, 1>(), RCE(), ECE());
                     const W p2 = px(std::integral_constant<int, 2>(), RCE(), ECE());
-                    if (m0 != 0.0 || m1 != 0.0 || m2 != 0.0) {  // one branch per row
+                    if ((nzbits(m0) | nzbits(m1) | nzbits(m2)) != 0) {  // one branch per row
                         xw = x2_at(aj + 1, r0, m0, p0, std::true_type());
                         xn = x2_at(aj + 2, r1, m1, p1, std::true_type());
                         xne = x2_at(aj + 2, r2, m2, p2, std::true_type());

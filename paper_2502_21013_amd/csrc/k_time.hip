@@ -452,7 +452,7 @@ __device__ __forceinline__ double lower_three_rec(const Win& v, double n2, const
 
 // whether any of the four laws of a record is nonlinear (uniform per row in a column walk)
 __device__ __forceinline__ bool rec_nonlinear(const NodeRec& r) {
-    return (r.law[0][1] != 0.0) || (r.law[1][1] != 0.0) || (r.law[2][1] != 0.0) || (r.law[3][1] != 0.0);
+    return (nzbits(r.law[0][1]) | nzbits(r.law[1][1]) | nzbits(r.law[2][1]) | nzbits(r.law[3][1])) != 0;
 }
 
 template <bool NL>
@@ -637,8 +637,8 @@ k_residual(FwdArgs a, void* rt_) {
                                  mNE = rc.m[5], mSW = rc.m[6];
                     const double bl = rc.bl;
                     const bool nl = rec_nonlinear(rc);
-                    const bool mass = (mc != 0.0) || (mE != 0.0) || (mW != 0.0) || (mN != 0.0) || (mS != 0.0) ||
-                                      (mNE != 0.0) || (mSW != 0.0);
+                    const bool mass = (nzbits(mc) | nzbits(mE) | nzbits(mW) | nzbits(mN) | nzbits(mS) |
+                                       nzbits(mNE) | nzbits(mSW)) != 0;
                     if (mass) mass_bits |= 1u << q;
 #pragma unroll
                     for (int k = 0; k < KP; ++k) {

@@ -188,6 +188,11 @@ __device__ __forceinline__ void consume(float2 x) {
     consume(x.y);
 }
 
+// Nonzero test on the raw bits (x != 0 exactly when the bits without the sign are nonzero,
+// NaN included): OR-ing several of them keeps a test of wave-uniform values on the scalar unit
+// instead of one vector compare per value.
+__device__ __forceinline__ unsigned long long nzbits(double x) { return __builtin_bit_cast(unsigned long long, x) << 1; }
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 }  // namespace pt
