@@ -110,21 +110,22 @@ __device__ __forceinline__ T2* fft_lane(T2* a, T2* b, int S, int lt, int TS, con
 }
 
 // fft_lane with the twiddles read from the table at each stage (the same entries as
-// lane_fft_twiddles), for kernels that cannot keep them in registers.
+// lane_fft_twiddles), for kernels that cannot keep them in registers; lgS = log2 S (the
+// index arithmetic is shifts).
 template <typename T2>
-__device__ __forceinline__ T2* fft_lane_tab(T2* a, T2* b, int S, int lt, int TS, const T2* tw) {
-    int Ns = 1;
+__device__ __forceinline__ T2* fft_lane_tab(T2* a, T2* b, int S, int lgS, int lt, int TS, const T2* tw) {
+    int Ns = 1, lgNs = 0;
     const int Q = S >> 2;
 #pragma unroll
     for (int st = 0; st < kFftMaxR4; ++st) {
         if (Ns * 4 > S) break;
         if (lt < Q) {
-            const int j = lt, k = j & (Ns - 1), stp = S / (2 * Ns);
+            const int j = lt, k = j & (Ns - 1), lgstp = lgS - 1 - lgNs;  // S / (2 Ns) = 2^lgstp
             T2 v0 = a[j], v1 = a[j + Q], v2 = a[j + 2 * Q], v3 = a[j + 3 * Q];
             if (st > 0) {
-                v1 = cmul(v1, tw[k * stp]);
-                v2 = cmul(v2, tw[2 * k * stp]);
-                v3 = cmul(v3, tw[3 * k * stp]);
+                v1 = cmul(v1, tw[k << lgstp]);
+                v2 = cmul(v2, tw[(2 * k) << lgstp]);
+                v3 = cmul(v3, tw[(3 * k) << lgstp]);
             }
             T2 t0 = add2(v0, v2), t1 = sub2(v0, v2), t2 = add2(v1, v3), t3 = mul_mi(sub2(v1, v3));
             const int idx = (j / Ns) * Ns * 4 + k;
@@ -138,6 +139,7 @@ __device__ __forceinline__ T2* fft_lane_tab(T2* a, T2* b, int S, int lt, int TS,
         a = b;
         b = t;
         Ns *= 4;
+        lgNs += 2;
     }
     if (Ns < S) {
         const int H = S >> 1;
@@ -147,7 +149,7 @@ __device__ __forceinline__ T2* fft_lane_tab(T2* a, T2* b, int S, int lt, int TS,
             if (j < H) {
                 const int k = j & (Ns - 1);
                 T2 v0 = a[j];
-                T2 v1 = cmul(a[j + H], tw[(k * (S / Ns)) & (2 * S - 1)]);
+                T2 v1 = cmul(a[j + H], tw[(k << (lgS - lgNs)) & (2 * S - 1)]);
                 const int idx = (j / Ns) * Ns * 2 + k;
                 b[idx] = add2(v0, v1);
                 b[idx + Ns] = sub2(v0, v1);
@@ -723,15 +725,15 @@ k_residual(FwdArgs a, void* rt_) {
             int tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
             const int F4 = S >> 2, H = S >> 1;
-            const int fid = tid / F4, fl = tid - fid * F4;
+            const int fid = tid >> (a.lgS - 2), fl = tid & (F4 - 1);
             const int fc = fid / RB, fq = fid - fc * RB;
             T2* fa = sizeof(T) == 4 ? (T2*)MEp(fc, fq) : (T2*)RSp(fc, fq);
             T2* fb = sizeof(T) == 4 ? (T2*)XOp(fc, fq) : (T2*)MEp(fc, fq);
             const T2* tw = twl;
-            const T2* res = fft_lane_tab<T2>(fa, fb, S, fl, F4, tw);
+            const T2* res = fft_lane_tab<T2>(fa, fb, S, a.lgS, fl, F4, tw);
             const int fvcol = sr.col0 + fc, fj = jb + fq;
             if (fvcol < side * a.B && fj < sr.row1) {
-                const int fbi = fvcol / side, fi = fvcol - fbi * side;
+                const int fbi = a.B == 1 ? 0 : fvcol / side, fi = fvcol - fbi * side;
                 const size_t chunk = ((size_t)fj * side + fi) * a.ST + (size_t)fbi * S;  // even
                 Pair<T2>* outp = (Pair<T2>*)a.out + chunk / 2;
 #pragma unroll
