@@ -240,7 +240,8 @@ __device__ __forceinline__ void store_dot_partials(const double (*acc)[3], doubl
 // contributes (c, c+1) x 1/2 (P1 interpolation on the SW-NE split grid). The inputs of
 // row R+2 are loaded before row R is computed, on every path (the row clamped to the grid
 // after the last one), and the mass rows of a uniform column come through the scalar unit,
-// so that the wait for a row's inputs never waits for the loads of the row after it.
+// so that the wait for a row's inputs never waits for the loads of the row after it. The
+// coarse residual is stored with streaming access (it is read back only by the next level).
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_, void* rout_) {
     using W = SV<T>;
@@ -346,7 +347,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
             if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
                 acc = sv_fma(half, sv[1], acc);
                 acc = sv_fma(half, sv[2], acc);
-                *boff(row_of(rout, (R - 1) / 2, sc, lgR), oco) = acc;
+                nt_store(boff(row_of(rout, (R - 1) / 2, sc, lgR), oco), acc);
             }
             acc = sv_scale(half, sv_add(sv[0], sv[1]));  // lower row of coarse row (R+1)/2
         } else {
@@ -423,6 +424,7 @@ __device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl,
 // before the current row is computed so that the loads overlap the arithmetic, and the
 // coarse values they interpolate from come from a window of coarse rows (below).
 // Three waves per SIMD (at most 168 VGPRs): the coarse window would otherwise drop to two.
+// x3 is stored with streaming access, keeping the caches for the neighbour columns' inputs.
 template <typename T, bool UNI>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
@@ -555,7 +557,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                         out = post_smooth_t<T, false>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
                 }
-                if (here) *boff(row_of(xout, aj, sf, lgR), ofn[1]) = out;
+                if (here) nt_store(boff(row_of(xout, aj, sf, lgR), ofn[1]), out);
                 if (more) {
                     // aj even: row aj + 1 (column ai-1) is odd on coarse row R0, row aj + 2 even on
                     // R0 + 1; aj odd: aj + 1 even on R0, aj + 2 odd on R0

@@ -109,32 +109,50 @@ __device__ __forceinline__ T2* fft_lane(T2* a, T2* b, int S, int lt, int TS, con
     return a;
 }
 
-// fft_lane with the twiddles read from the table at each stage (the same entries as
-// lane_fft_twiddles), for kernels that cannot keep them in registers; lgS = log2 S (the
-// index arithmetic is shifts).
+// Ordering point for LDS data exchanged between the lanes of one wavefront: LDS accesses of a
+// wavefront are carried out in issue order, so it is enough that the compiler keeps them in
+// program order here (no instruction is emitted and no other wavefront is waited for).
+__device__ __forceinline__ void wave_lds_sync() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// fft_lane on the S/4 lanes lt of one wavefront (S/4 <= 64 lanes per transform, so a
+// transform never spans two wavefronts), with the twiddles read from the table at each stage
+// (the same entries as lane_fft_twiddles; lgS = log2 S, the index arithmetic is shifts), the
+// input of the first radix-4 stage in registers, v[c] = z_{lt + c S/4}, and LDS-ordering
+// points instead of workgroup barriers between the stages. a and b hold S values each; the
+// result is in one of them.
 template <typename T2>
-__device__ __forceinline__ T2* fft_lane_tab(T2* a, T2* b, int S, int lgS, int lt, int TS, const T2* tw) {
-    int Ns = 1, lgNs = 0;
+__device__ __forceinline__ T2* fft_wave_tab(const T2 v[4], T2* a, T2* b, int S, int lgS, int lt, const T2* tw) {
     const int Q = S >> 2;
+    // every lane has read its inputs before any lane writes a buffer
+    wave_lds_sync();
+    {
+        T2 t0 = add2(v[0], v[2]), t1 = sub2(v[0], v[2]), t2 = add2(v[1], v[3]), t3 = mul_mi(sub2(v[1], v[3]));
+        const int idx = lt * 4;
+        a[idx] = add2(t0, t2);
+        a[idx + 1] = add2(t1, t3);
+        a[idx + 2] = sub2(t0, t2);
+        a[idx + 3] = sub2(t1, t3);
+    }
+    wave_lds_sync();
+    int Ns = 4, lgNs = 2;
 #pragma unroll
-    for (int st = 0; st < kFftMaxR4; ++st) {
+    for (int st = 1; st < kFftMaxR4; ++st) {
         if (Ns * 4 > S) break;
-        if (lt < Q) {
-            const int j = lt, k = j & (Ns - 1), lgstp = lgS - 1 - lgNs;  // S / (2 Ns) = 2^lgstp
-            T2 v0 = a[j], v1 = a[j + Q], v2 = a[j + 2 * Q], v3 = a[j + 3 * Q];
-            if (st > 0) {
-                v1 = cmul(v1, tw[k << lgstp]);
-                v2 = cmul(v2, tw[(2 * k) << lgstp]);
-                v3 = cmul(v3, tw[(3 * k) << lgstp]);
-            }
-            T2 t0 = add2(v0, v2), t1 = sub2(v0, v2), t2 = add2(v1, v3), t3 = mul_mi(sub2(v1, v3));
-            const int idx = (j / Ns) * Ns * 4 + k;
-            b[idx] = add2(t0, t2);
-            b[idx + Ns] = add2(t1, t3);
-            b[idx + 2 * Ns] = sub2(t0, t2);
-            b[idx + 3 * Ns] = sub2(t1, t3);
-        }
-        __syncthreads();
+        const int j = lt, k = j & (Ns - 1), lgstp = lgS - 1 - lgNs;  // S / (2 Ns) = 2^lgstp
+        T2 v0 = a[j], v1 = a[j + Q], v2 = a[j + 2 * Q], v3 = a[j + 3 * Q];
+        v1 = cmul(v1, tw[k << lgstp]);
+        v2 = cmul(v2, tw[(2 * k) << lgstp]);
+        v3 = cmul(v3, tw[(3 * k) << lgstp]);
+        T2 t0 = add2(v0, v2), t1 = sub2(v0, v2), t2 = add2(v1, v3), t3 = mul_mi(sub2(v1, v3));
+        const int idx = (j >> lgNs) * Ns * 4 + k;
+        b[idx] = add2(t0, t2);
+        b[idx + Ns] = add2(t1, t3);
+        b[idx + 2 * Ns] = sub2(t0, t2);
+        b[idx + 3 * Ns] = sub2(t1, t3);
+        wave_lds_sync();
         T2* t = a;
         a = b;
         b = t;
@@ -145,20 +163,18 @@ __device__ __forceinline__ T2* fft_lane_tab(T2* a, T2* b, int S, int lgS, int lt
         const int H = S >> 1;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int j = lt + h * TS;
+            const int j = lt + h * Q;
             if (j < H) {
                 const int k = j & (Ns - 1);
                 T2 v0 = a[j];
                 T2 v1 = cmul(a[j + H], tw[(k << (lgS - lgNs)) & (2 * S - 1)]);
-                const int idx = (j / Ns) * Ns * 2 + k;
+                const int idx = (j >> lgNs) * Ns * 2 + k;
                 b[idx] = add2(v0, v1);
                 b[idx + Ns] = sub2(v0, v1);
             }
         }
-        __syncthreads();
-        T2* t = a;
-        a = b;
-        b = t;
+        wave_lds_sync();
+        return b;
     }
     return a;
 }
@@ -491,7 +507,7 @@ constexpr int kRowBatch = 4;
 enum ResKind { RK_WAVE = 0, RK_LOAD = 1, RK_SIGNAL = 2 };
 
 template <typename T, bool UNI, int KP, int RK, bool FUSE>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FUSE && UNI ? 4 : 1)))
 k_residual(FwdArgs a, void* rt_) {
     constexpr bool SIG = RK == RK_SIGNAL;
     static_assert(!FUSE || (KP == 1 && !SIG), "the fused transform takes one pair per lane");
@@ -686,54 +702,72 @@ k_residual(FwdArgs a, void* rt_) {
         row(std::integral_constant<int, 2>());
         row(std::integral_constant<int, 3>());
         __syncthreads();
-        // M (u^n - u^{n-1}) = M u^n - M u^{n-1}: the odd-time product of pair m-1 (cyclic)
+        if constexpr (!FUSE) {
+            // M (u^n - u^{n-1}) = M u^n - M u^{n-1}: the odd-time product of pair m-1 (cyclic)
 #pragma unroll 1
-        for (int q = 0; q < RB; ++q) {
-            const int j = jb + q;
-            if (!colvalid || j >= sr.row1) continue;
-            const int node = j * side + i;
-            const bool interior = colint && j > 0 && j < n;
-            const bool mass = (mass_bits >> q) & 1u;
+            for (int q = 0; q < RB; ++q) {
+                const int j = jb + q;
+                if (!colvalid || j >= sr.row1) continue;
+                const int node = j * side + i;
+                const bool interior = colint && j > 0 && j < n;
+                const bool mass = (mass_bits >> q) & 1u;
 #pragma unroll
-            for (int k = 0; k < KP; ++k) {
-                const int m = lt + TS * k;
-                double2 rv = RSp(team, q)[m];
-                if (mass) {
-                    const double* xo = XOp(team, q);
-                    double mue = MEp(team, q)[m], muo = xo[m];
-                    double prev = xo[m == 0 ? S - 1 : m - 1];
-                    rv.x -= (mue - prev) * a.inv_tau;
-                    rv.y -= (muo - mue) * a.inv_tau;
-                }
-                if (interior) rr += rv.x * rv.x + rv.y * rv.y;
-                if (a.rout) ((double2*)a.rout)[(long)node * STp + bi * S + m] = rv;
-                if constexpr (FUSE) {
-                    // the transform input z_m = (r_2m, r_2m+1) in the solver precision, over the
-                    // lane's own entry (FP32: me[m]; FP64: rs[m])
-                    if constexpr (sizeof(T) == 4) ((T2*)MEp(team, q))[m] = mk2<T>((T)rv.x, (T)rv.y);
-                    else RSp(team, q)[m] = rv;
-                } else if (rt) {
-                    rt[(long)node * STp + bi * S + m] = mk2<T>((T)rv.x, (T)rv.y);
+                for (int k = 0; k < KP; ++k) {
+                    const int m = lt + TS * k;
+                    double2 rv = RSp(team, q)[m];
+                    if (mass) {
+                        const double* xo = XOp(team, q);
+                        double mue = MEp(team, q)[m], muo = xo[m];
+                        double prev = xo[m == 0 ? S - 1 : m - 1];
+                        rv.x -= (mue - prev) * a.inv_tau;
+                        rv.y -= (muo - mue) * a.inv_tau;
+                    }
+                    if (interior) rr += rv.x * rv.x + rv.y * rv.y;
+                    if (a.rout) ((double2*)a.rout)[(long)node * STp + bi * S + m] = rv;
+                    if (rt) rt[(long)node * STp + bi * S + m] = mk2<T>((T)rv.x, (T)rv.y);
                 }
             }
-        }
-        __syncthreads();
-        if constexpr (FUSE) {
-            // transform fid = (team fc, row fq) on lanes fl < S/4; scratch: FP32 xo, FP64 me + xo
-            // (the lane index is made opaque here so that the transform's addresses and
-            // twiddles are formed per batch instead of being kept live across the row walk)
+            __syncthreads();
+        } else {
+            // Node fid = (team fc, row fq) of the batch on the S/4 lanes fl of one wavefront
+            // (S/4 <= 64 divides the wavefront): each lane forms the residual, mass difference
+            // included, at the four time pairs m = fl + c S/4 that the first radix-4 stage takes
+            // from it, so the series goes straight from the row buffers into the butterflies.
+            // The node's buffers are touched by its wavefront only, which needs no workgroup
+            // barrier between the stages. The lanes of node (fc, fq) are lanes of team fc
+            // (TS = S), so the team's mass bits are in their registers. (The lane index is made opaque so that the transform's
+            // addresses and twiddles are formed per batch instead of being kept live across the
+            // row walk.)
             int tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
             const int F4 = S >> 2, H = S >> 1;
             const int fid = tid >> (a.lgS - 2), fl = tid & (F4 - 1);
             const int fc = fid / RB, fq = fid - fc * RB;
-            T2* fa = sizeof(T) == 4 ? (T2*)MEp(fc, fq) : (T2*)RSp(fc, fq);
-            T2* fb = sizeof(T) == 4 ? (T2*)XOp(fc, fq) : (T2*)MEp(fc, fq);
-            const T2* tw = twl;
-            const T2* res = fft_lane_tab<T2>(fa, fb, S, a.lgS, fl, F4, tw);
             const int fvcol = sr.col0 + fc, fj = jb + fq;
-            if (fvcol < side * a.B && fj < sr.row1) {
-                const int fbi = a.B == 1 ? 0 : fvcol / side, fi = fvcol - fbi * side;
+            const bool fvalid = fvcol < side * a.B && fj < sr.row1;
+            const int fbi = (a.B == 1 || !fvalid) ? 0 : fvcol / side, fi = fvcol - fbi * side;
+            const bool fint = fvalid && fi > 0 && fi < n && fj > 0 && fj < n;
+            const bool fmass = (mass_bits >> fq) & 1u;
+            const double2* rs = RSp(fc, fq);
+            const double* me = MEp(fc, fq);
+            const double* xo = XOp(fc, fq);
+            T2 z[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int m = fl + c * F4;
+                double2 rv = rs[m];
+                if (fmass) {
+                    const double mue = me[m], muo = xo[m], prev = xo[m == 0 ? S - 1 : m - 1];
+                    rv.x -= (mue - prev) * a.inv_tau;
+                    rv.y -= (muo - mue) * a.inv_tau;
+                }
+                if (fint) rr += rv.x * rv.x + rv.y * rv.y;
+                if (a.rout && fvalid) ((double2*)a.rout)[((long)fj * side + fi) * STp + fbi * S + m] = rv;
+                z[c] = mk2<T>((T)rv.x, (T)rv.y);
+            }
+            const T2* tw = twl;
+            const T2* res = fft_wave_tab<T2>(z, (T2*)RSp(fc, fq), (T2*)MEp(fc, fq), S, a.lgS, fl, tw);
+            if (fvalid) {
                 const size_t chunk = ((size_t)fj * side + fi) * a.ST + (size_t)fbi * S;  // even
                 Pair<T2>* outp = (Pair<T2>*)a.out + chunk / 2;
 #pragma unroll
@@ -754,8 +788,9 @@ k_residual(FwdArgs a, void* rt_) {
         }
     }
     // per-team reduction of the norm partials (fixed order): part[(vb nb + team) 2 + {0, 1}]
-    // with vb the virtual workgroup index (column group vb % col_groups)
-    __shared__ double red[2][kBlock];
+    // with vb the virtual workgroup index (column group vb % col_groups); in the row buffers,
+    // which are free after the last batch's barrier (the launch gives at least 2 kBlock doubles)
+    double (*red)[kBlock] = (double (*)[kBlock])smem_raw;
     red[0][threadIdx.x] = rr;
     red[1][threadIdx.x] = ff;
     __syncthreads();
@@ -890,6 +925,7 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.col_groups = gf.col_groups;
     a.rows_per_chunk = gf.rows_per_chunk;
     size_t shm = (size_t)nb * kRowBatch * p.S * 4 * sizeof(double);
+    if (shm < 2 * kBlock * sizeof(double)) shm = 2 * kBlock * sizeof(double);  // the norm reduction
     dim3 blk(nb * TS);
     bool uni = TS >= 64;
     void* rt = out ? (void*)(ws + p.off_P) : nullptr;  // R in solver precision, node-major
@@ -1034,7 +1070,9 @@ struct InvArgs {
 // chunk are software-pipelined: the spectrum of row j+1 and the field of row j are loaded
 // at the start of row j (on every path: indexes clamped to valid memory), so both overlap
 // the transform of row j; the results of row j are stored after the loads of row j+1 are
-// issued, so that no register reuse behind a store in flight stalls the next row.
+// issued, so that no register reuse behind a store in flight stalls the next row. The field
+// is read and written with streaming access: each value once per sweep (FP32 at 1024^2 x 512:
+// 2.03 -> 1.86 ms per launch).
 template <typename T, bool ACC>
 __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
     using T2 = typename Vec2<T>::type;
@@ -1095,7 +1133,7 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
 #pragma unroll
         for (int r = 0; r < kMaxPer; ++r) {
             const int m = lt + r * TS;
-            if (m < S) up[m] = op[r];
+            if (m < S) nt_store(&up[m], op[r]);
         }
     };
     for (int j = sr.row0; j < sr.row1; ++j) {
@@ -1109,7 +1147,7 @@ __global__ void __launch_bounds__(kBlock) k_inverse(InvArgs a) {
 #pragma unroll
             for (int r = 0; r < kMaxPer; ++r) {
                 const int m = lt + r * TS;
-                uo[r] = u2[m < S ? m : S - 1];
+                uo[r] = nt_load(&u2[m < S ? m : S - 1]);
             }
         }
         issue_fence();

@@ -195,4 +195,25 @@ __device__ __forceinline__ unsigned long long nzbits(double x) { return __builti
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Streaming (nontemporal) access for data touched once per sweep and far larger than the
+// caches: the lines are not kept in L2 / MALL at the expense of data that is reused (the
+// neighbour columns of the stencil sweeps). X is moved as 16-byte pieces.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+template <typename X>
+__device__ __forceinline__ X nt_load(const X* p) {
+    static_assert(sizeof(X) % 16 == 0, "moved in 16-byte pieces");
+    X x;
+    nt_f4* d = (nt_f4*)&x;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(X) / 16); ++k) d[k] = __builtin_nontemporal_load((const nt_f4*)p + k);
+    return x;
+}
+template <typename X>
+__device__ __forceinline__ void nt_store(X* p, const X& x) {
+    static_assert(sizeof(X) % 16 == 0, "moved in 16-byte pieces");
+    const nt_f4* s = (const nt_f4*)&x;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(X) / 16); ++k) __builtin_nontemporal_store(s[k], (nt_f4*)p + k);
+}
+
 }  // namespace pt

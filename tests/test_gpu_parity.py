@@ -122,8 +122,9 @@ def test_residual_spectrum_is_the_dft_of_the_residual(gpu, P, n, N, seed, precis
     # 4 <= N/2 <= 256 runs the fused sweep (residual and its DFT in one pass), N = 4 and 1024 the
     # two-kernel path. Either way: the DFT entry point applied to the residual entry point to a
     # few units in the last place (same twiddles and butterflies; the compiler may fuse a
-    # multiply-add differently in the two kernels), the same norms bit for bit, and the
-    # oracle's DFT of the oracle residual to the transform tolerance
+    # multiply-add differently in the two kernels), the same FP64 norms up to the order of
+    # their partial sums (the fused sweep adds each node's terms on the lanes that transform
+    # it), and the oracle's DFT of the oracle residual to the transform tolerance
     say(f"residual spectrum n={n} N={N} {precision}")
     p = W.with_size(W.config2(seed), n, N)
     d = fem.discretise(p)
@@ -134,7 +135,7 @@ def test_residual_spectrum_is_the_dft_of_the_residual(gpu, P, n, N, seed, precis
     two = plan.rfft(R)
     ulp = 8 * (2.0 ** -52 if precision == "fp64" else 2.0 ** -23)
     assert float((Rh - two).abs().max()) <= ulp * float(two.abs().max())
-    assert rel == rel2 and fn == fn2
+    assert abs(rel - rel2) <= 1e-13 * rel2 and fn == fn2
     F = pp.load_series(d)
     Rref = pp.to_full(d, pp.residual(d, pp.to_free(d, U), F))
     ref = dft.rfft_packed(Rref.reshape(N, -1)).T            # (nodes, S)
