@@ -706,11 +706,26 @@ __global__ void __launch_bounds__(kBlock) k_reduce_dots1(const double* part, int
     const int RB = gridDim.y;
     const int b0 = (int)((long)blockIdx.y * nblk / RB), b1 = (int)((long)(blockIdx.y + 1) * nblk / RB);
     double s1 = 0, s2 = 0, s3 = 0;
-    for (int b = b0 + rl; b < b1; b += RL) {
-        const double* o = part + ((size_t)b * S + s) * 3;
-        s1 += o[0];
-        s2 += o[1];
-        s3 += o[2];
+    // rows b0 + rl, b0 + rl + RL, ... added in that order; the loads of kReduceBatch rows are
+    // issued together (rows past b1 clamped onto the first one, loaded and not added)
+    for (int b = b0 + rl; b < b1; b += RL * kReduceBatch) {
+        double v[kReduceBatch][3];
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) {
+            const int bb = b + u * RL < b1 ? b + u * RL : b;
+            const double* o = part + ((size_t)bb * S + s) * 3;
+            v[u][0] = o[0];
+            v[u][1] = o[1];
+            v[u][2] = o[2];
+        }
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) {
+            if (b + u * RL < b1) {
+                s1 += v[u][0];
+                s2 += v[u][1];
+                s3 += v[u][2];
+            }
+        }
     }
     red[0][threadIdx.x] = s1;
     red[1][threadIdx.x] = s2;
@@ -735,11 +750,23 @@ __global__ void __launch_bounds__(kBlock) k_reduce_dots(const double* part, int 
                                                         double* out) {
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
         double s1 = 0, s2 = 0, s3 = 0;
-        for (int b = 0; b < nblk; ++b) {
-            const double* o = part + ((size_t)b * S + s) * 3;
-            s1 += o[0];
-            s2 += o[1];
-            s3 += o[2];
+        for (int b = 0; b < nblk; b += kReduceBatch) {  // rows in order, loads batched
+            double v[kReduceBatch][3];
+#pragma unroll
+            for (int u = 0; u < kReduceBatch; ++u) {
+                const double* o = part + ((size_t)(b + u < nblk ? b + u : b) * S + s) * 3;
+                v[u][0] = o[0];
+                v[u][1] = o[1];
+                v[u][2] = o[2];
+            }
+#pragma unroll
+            for (int u = 0; u < kReduceBatch; ++u) {
+                if (b + u < nblk) {
+                    s1 += v[u][0];
+                    s2 += v[u][1];
+                    s3 += v[u][2];
+                }
+            }
         }
         double2 r;
         if ((s & (Si - 1)) == 0) {

@@ -1021,11 +1021,24 @@ __global__ void __launch_bounds__(kBlock) k_reduce_norms(const double* part, int
     __shared__ double red[2][kBlock];
     const int b = blockIdx.x;
     double s0 = 0, s1 = 0;
-    for (int q = threadIdx.x; q < nparts; q += kBlock) {
-        const int vcol = ((q / nb) % col_groups) * nb + q % nb;
-        if (vcol / side != b) continue;
-        s0 += part[2 * q];
-        s1 += part[2 * q + 1];
+    // partials q = threadIdx.x + kBlock t in order of t; the loads of kReduceBatch of them are
+    // issued together (indexes past nparts clamped onto the first one, loaded and not added)
+    for (int q = threadIdx.x; q < nparts; q += kBlock * kReduceBatch) {
+        double2 v[kReduceBatch];
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) {
+            const int qq = q + u * kBlock < nparts ? q + u * kBlock : q;
+            v[u] = ((const double2*)part)[qq];
+        }
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) {
+            const int qq = q + u * kBlock;
+            if (qq >= nparts) continue;
+            const int vcol = ((qq / nb) % col_groups) * nb + qq % nb;
+            if (vcol / side != b) continue;
+            s0 += v[u].x;
+            s1 += v[u].y;
+        }
     }
     red[0][threadIdx.x] = s0;
     red[1][threadIdx.x] = s1;

@@ -24,6 +24,7 @@ constexpr int kBlock = 256;          // threads per workgroup in every kernel
 constexpr int kMaxLevels = 16;
 constexpr int kNumXcd = 8;
 constexpr int kReduceRows = 64;      // first-stage row groups of the dot-product reduction
+constexpr int kReduceBatch = 8;      // partials whose loads a reduction thread issues together
 constexpr int kAdjBlocks = 8192;     // workgroups of the grid-stride adjoint kernels
 constexpr int kRecDoubles = 16;      // residual-sweep record per node: mass row, load, reluctivity laws
 
