@@ -224,7 +224,9 @@ pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* 
  * time, written to d_rhat (frequency-field layout, plan precision: what pt_time_rfft(R)
  * gives, to rounding in the transform). For 4 <= N/2 <= 256 this is the fused sweep the
  * solver runs in every step (the time-domain R never reaches memory); other N take the
- * two-kernel path. rel_out / fnorm_out as in pt_residual. Blocks until done. */
+ * two-kernel path. rel_out / fnorm_out as in pt_residual (the fused sweep adds the norm
+ * terms in another order, so rel_out may differ from pt_residual's in the last bits). Blocks
+ * until done. */
 pt_status pt_residual_spectrum(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
                                void* d_rhat, void* stream, double* rel_out, double* fnorm_out);
 

@@ -502,7 +502,7 @@ __device__ __forceinline__ double upper_four_rec(const Win& v, double n2, const 
 // FUSE (KP = 1, 4 <= S <= 256): instead of the time series R, the sweep writes its packed
 // real DFT (the output of k_rfft, remark rem:parallel) to a.out: after a row batch the
 // workgroup holds the residual of nb x RB nodes in LDS, and S/4 lanes transform each of them
-// (nb RB S/4 = 256 lanes), so the series never goes through HBM.
+// (nb RB S/4 = 256 lanes), so the series never goes through HBM (a.rout is not written).
 constexpr int kRowBatch = 4;
 enum ResKind { RK_WAVE = 0, RK_LOAD = 1, RK_SIGNAL = 2 };
 
@@ -762,7 +762,6 @@ k_residual(FwdArgs a, void* rt_) {
                     rv.y -= (muo - mue) * a.inv_tau;
                 }
                 if (fint) rr += rv.x * rv.x + rv.y * rv.y;
-                if (a.rout && fvalid) ((double2*)a.rout)[((long)fj * side + fi) * STp + fbi * S + m] = rv;
                 z[c] = mk2<T>((T)rv.x, (T)rv.y);
             }
             const T2* tw = twl;
@@ -932,7 +931,7 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     tm_begin(p, KID_RESIDUAL, st);
     const int rk = mode == TM_SIGNAL ? RK_SIGNAL : (a.F ? RK_LOAD : RK_WAVE);
     // residual spectrum in one pass: transform fused into the sweep (see k_residual)
-    if (out && rk != RK_SIGNAL && KP == 1 && p.S >= 4) {
+    if (out && !rout && rk != RK_SIGNAL && KP == 1 && p.S >= 4) {
         a.out = out;
         shm += (size_t)p.N * p.elem;  // twiddle table
 #define PT_RESF(TT, U, G) hipLaunchKernelGGL((k_residual<TT, U, 1, G, true>), dim3(gf.blocks), blk, shm, st, a, nullptr)
