@@ -118,11 +118,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // fft_lane on the S/4 lanes lt of one wavefront (S/4 <= 64 lanes per transform, so a
-// transform never spans two wavefronts), with the twiddles read from the table at each stage
-// (the same entries as lane_fft_twiddles; lgS = log2 S, the index arithmetic is shifts), the
-// input of the first radix-4 stage in registers, v[c] = z_{lt + c S/4}, and LDS-ordering
-// points instead of workgroup barriers between the stages. a and b hold S values each; the
-// result is in one of them.
+// transform never spans two wavefronts), with the input of the first radix-4 stage in
+// registers, v[c] = z_{lt + c S/4}, and LDS-ordering points instead of workgroup barriers
+// between the stages. tw: the first S entries of the twiddle table w^i = exp(-2 pi i / N)
+// (read by a final radix-2 stage), followed by the stage runs of the radix-4 stages after the
+// first (w^(c k S/(2 Ns)) at [3 Ns-run offset + (c-1) Ns + k], the entries of
+// lane_fft_twiddles). lgS = log2 S. a and b hold S values each; the result is in one of them.
 template <typename T2>
 __device__ __forceinline__ T2* fft_wave_tab(const T2 v[4], T2* a, T2* b, int S, int lgS, int lt, const T2* tw) {
     const int Q = S >> 2;
@@ -138,14 +139,16 @@ __device__ __forceinline__ T2* fft_wave_tab(const T2 v[4], T2* a, T2* b, int S, 
     }
     wave_lds_sync();
     int Ns = 4, lgNs = 2;
+    const T2* ts = tw + S;  // the stage runs after the first S entries
 #pragma unroll
     for (int st = 1; st < kFftMaxR4; ++st) {
         if (Ns * 4 > S) break;
-        const int j = lt, k = j & (Ns - 1), lgstp = lgS - 1 - lgNs;  // S / (2 Ns) = 2^lgstp
+        const int j = lt, k = j & (Ns - 1);
         T2 v0 = a[j], v1 = a[j + Q], v2 = a[j + 2 * Q], v3 = a[j + 3 * Q];
-        v1 = cmul(v1, tw[k << lgstp]);
-        v2 = cmul(v2, tw[(2 * k) << lgstp]);
-        v3 = cmul(v3, tw[(3 * k) << lgstp]);
+        v1 = cmul(v1, ts[k]);
+        v2 = cmul(v2, ts[Ns + k]);
+        v3 = cmul(v3, ts[2 * Ns + k]);
+        ts += 3 * Ns;
         T2 t0 = add2(v0, v2), t1 = sub2(v0, v2), t2 = add2(v1, v3), t3 = mul_mi(sub2(v1, v3));
         const int idx = (j >> lgNs) * Ns * 4 + k;
         b[idx] = add2(t0, t2);
@@ -525,7 +528,21 @@ k_residual(FwdArgs a, void* rt_) {
     // FUSE: the twiddle table (N values) in LDS after the row blocks, read by every stage
     T2* twl = (T2*)(smem_raw + (size_t)a.nb * RB * 32 * S);
     if constexpr (FUSE) {
-        for (int k = threadIdx.x; k < a.N; k += kBlock) twl[k] = ((const T2*)a.tw)[k];
+        // entries 0..S-1 (the split and a final radix-2 stage read only these), then for each
+        // radix-4 stage after the first (Ns = 4, 16, ...) its three twiddles w^(c k S/(2 Ns)),
+        // c = 1, 2, 3, k < Ns, as three runs of Ns: the lanes of a stage read consecutive
+        // entries (at most S further entries, so the N-entry space suffices)
+        const T2* tg = (const T2*)a.tw;
+        for (int k = threadIdx.x; k < S; k += kBlock) twl[k] = tg[k];
+        int o = S;
+        for (int Ns = 4, lgNs = 2; Ns * 4 <= S; Ns *= 4, lgNs += 2) {
+            const int lgstp = a.lgS - 1 - lgNs;
+            for (int e = threadIdx.x; e < 3 * Ns; e += kBlock) {
+                const int c = e / Ns + 1, k = e - (c - 1) * Ns;
+                twl[o + e] = tg[(c * k) << lgstp];
+            }
+            o += 3 * Ns;
+        }
         // (the first use follows the barrier after the first row batch)
     }
     const double2* U2 = (const double2*)a.U;
