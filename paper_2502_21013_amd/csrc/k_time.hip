@@ -947,8 +947,9 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     void* rt = out ? (void*)(ws + p.off_P) : nullptr;  // R in solver precision, node-major
     tm_begin(p, KID_RESIDUAL, st);
     const int rk = mode == TM_SIGNAL ? RK_SIGNAL : (a.F ? RK_LOAD : RK_WAVE);
-    // residual spectrum in one pass: transform fused into the sweep (see k_residual)
-    if (out && !rout && rk != RK_SIGNAL && KP == 1 && p.S >= 4) {
+    // residual spectrum in one pass: transform fused into the sweep (see k_residual); its
+    // S/4 lanes per node must lie in one wavefront, so S <= 256
+    if (out && !rout && rk != RK_SIGNAL && KP == 1 && p.S >= 4 && p.S <= 256) {
         a.out = out;
         shm += (size_t)p.N * p.elem;  // twiddle table
 #define PT_RESF(TT, U, G) hipLaunchKernelGGL((k_residual<TT, U, 1, G, true>), dim3(gf.blocks), blk, shm, st, a, nullptr)
