@@ -134,7 +134,7 @@ void graph_release(Plan& p);
 // target = number of workgroups (per slot chunk) the sweeping kernels aim for. The
 // per-node team kernels sweep B (n+1) virtual columns (instance b, grid column i at
 // b (n+1) + i) over n+1 rows.
-Geom slot_geom(int side, int S, int V, int target, int cols = 0);
+Geom slot_geom(int side, int S, int V, int target, int cols = 0, int max_chunk = kBlock);
 Geom team_geom(int side, int S, int B, int target);
 Geom fwd_geom(int side, int S, int B, int target);
 
