@@ -31,6 +31,18 @@ struct SlotArgs {
     const double* zs;  // S x 3 generic (a, b, c) of the shifts
 };
 
+// The levels of at most kSmallSide points per side (33, 17, 9, 5 and 3: at most kMaxSmall of
+// them) run in one k_vc_small launch; r and x of level q at off_r[q], off_x[q], a scratch
+// vector of the first level's size at off_t (offsets in slot values of LDS).
+constexpr int kSmallSide = 33;
+constexpr int kMaxSmall = 5;
+struct SmallArgs {
+    int count;
+    int side[kMaxSmall];
+    const double* mt[kMaxSmall];
+    int off_r[kMaxSmall], off_x[kMaxSmall], off_t;
+};
+
 template <typename T> __device__ __forceinline__ GS<T> load_shift(const double* zs, int s) {
     GS<T> g;
     g.a = (T)zs[3 * s];
@@ -385,6 +397,128 @@ __global__ void __launch_bounds__(kBlock) k_vc_coarsest(SlotArgs sa, LvArgs C, c
             }
             xout[node * S + s] = v;
         }
+    }
+}
+
+// ---------------------------------------------------------------- V-cycle: small levels
+
+// The levels from l0 (side <= kSmallSide, l0 >= 1) to the coarsest in one launch. Workgroup s
+// takes slot s, keeps r and x of all these levels in LDS and runs the same V(1,1) cycle as
+// k_vc_down, k_vc_coarsest and k_vc_up: restriction of r - A x1 with x1 = omega D^{-1} r, the
+// exact solve on the 2 x 2-cell grid, then x2 = omega D^{-1} r + P x_c and
+// x3 = x2 + omega D^{-1} (r - A x2), phases separated by workgroup barriers. As separate
+// launches these levels cost a few microseconds each for very little work.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, const void* rin_, void* xout_) {
+    using T2 = typename Vec2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T2* sh = (T2*)smem_raw;
+    const T2* rin = (const T2*)rin_;
+    T2* xout = (T2*)xout_;
+    const int ST = sa.ST, s = blockIdx.x;
+    const GS<T> z = load_shift<T>(sa.zs, s);
+    const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl, half = (T)0.5;
+    const T2 zero = mk2<T>(0, 0);
+    // omega D^{-1} v at a node with diagonal mass dm (the forms of jacobi_t)
+    auto jac = [&](double dm, T2 v) -> T2 {
+        if (dm == 0.0) return scale2(om * idl, v);
+        return scale2(om, gs_apply(gs_inv_diag_sel<T>(dl, idl, (T)dm, z), v));
+    };
+    // (A x)_a at interior node a of a level with side sd and mass table mt (as apply_A_t)
+    auto applyA = [&](const double* mt, int sd, const T2* xv, int a) -> T2 {
+        const int nd = sd * sd;
+        const T2 xc = xv[a], xe = xv[a + 1], xw = xv[a - 1], xn = xv[a + sd], xs = xv[a - sd], xne = xv[a + sd + 1],
+                 xsw = xv[a - sd - 1];
+        T2 out;
+        out.x = nu * ((T)4 * xc.x - xe.x - xw.x - xn.x - xs.x);
+        out.y = nu * ((T)4 * xc.y - xe.y - xw.y - xn.y - xs.y);
+        const double mc = mt[a], me = mt[nd + a], mw = mt[nd + a - 1], mn = mt[2 * nd + a], ms = mt[2 * nd + a - sd],
+                     mne = mt[3 * nd + a], msw = mt[3 * nd + a - sd - 1];
+        if (mc != 0.0 || me != 0.0 || mw != 0.0 || mn != 0.0 || ms != 0.0 || mne != 0.0 || msw != 0.0) {
+            T2 Mx = scale2((T)mc, xc);
+            Mx = fma2((T)me, xe, Mx);
+            Mx = fma2((T)mw, xw, Mx);
+            Mx = fma2((T)mn, xn, Mx);
+            Mx = fma2((T)ms, xs, Mx);
+            Mx = fma2((T)mne, xne, Mx);
+            Mx = fma2((T)msw, xsw, Mx);
+            out = add2(out, gs_apply(z, Mx));
+        }
+        return out;
+    };
+    {
+        const int nodes = sm.side[0] * sm.side[0];
+        T2* r = sh + sm.off_r[0];
+        for (int a = threadIdx.x; a < nodes; a += kBlock) r[a] = rin[(size_t)a * ST + s];
+    }
+    __syncthreads();
+    // restriction sweeps: level q -> q + 1
+    for (int q = 0; q + 1 < sm.count; ++q) {
+        const int sd = sm.side[q], n = sd - 1, nodes = sd * sd, sc = sm.side[q + 1], nc = sc - 1;
+        const double* mt = sm.mt[q];
+        const T2* r = sh + sm.off_r[q];
+        T2* x1 = sh + sm.off_x[q];
+        T2* t = sh + sm.off_t;
+        T2* rc = sh + sm.off_r[q + 1];
+        for (int a = threadIdx.x; a < nodes; a += kBlock) x1[a] = jac(mt[a], r[a]);
+        __syncthreads();
+        for (int a = threadIdx.x; a < nodes; a += kBlock) {
+            const int j = a / sd, i = a - j * sd;
+            t[a] = (i > 0 && i < n && j > 0 && j < n) ? sub2(r[a], applyA(mt, sd, x1, a)) : zero;
+        }
+        __syncthreads();
+        for (int ca = threadIdx.x; ca < sc * sc; ca += kBlock) {
+            const int cj = ca / sc, ci = ca - cj * sc;
+            T2 acc = zero;
+            if (ci > 0 && ci < nc && cj > 0 && cj < nc) {
+                // P^T at fine node (2 ci, 2 cj): W, C, E of its row, (C, E) above, (W, C) below
+                const int a = 2 * cj * sd + 2 * ci;
+                acc = scale2(half, add2(t[a - sd - 1], t[a - sd]));
+                acc = fma2(half, t[a - 1], acc);
+                acc = add2(acc, t[a]);
+                acc = fma2(half, t[a + 1], acc);
+                acc = fma2(half, t[a + sd], acc);
+                acc = fma2(half, t[a + sd + 1], acc);
+            }
+            rc[ca] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        // the coarsest level: the single interior node (1, 1), 1 x 1 operator 4 nu_max + z M_c
+        const int q = sm.count - 1, sd = sm.side[q], nodes = sd * sd;
+        const T2* r = sh + sm.off_r[q];
+        T2* x = sh + sm.off_x[q];
+        for (int a = threadIdx.x; a < nodes; a += kBlock)
+            x[a] = (a == sd + 1) ? gs_apply(gs_inv_diag<T>(dl, (T)1 / dl, (T)sm.mt[q][a], z), r[a]) : zero;
+    }
+    __syncthreads();
+    // prolongation sweeps with post-smoothing: level q + 1 -> q
+    for (int q = sm.count - 2; q >= 0; --q) {
+        const int sd = sm.side[q], n = sd - 1, nodes = sd * sd, sc = sm.side[q + 1];
+        const double* mt = sm.mt[q];
+        const T2* r = sh + sm.off_r[q];
+        const T2* xc = sh + sm.off_x[q + 1];
+        T2* x2 = sh + sm.off_t;
+        T2* x3 = sh + sm.off_x[q];
+        for (int a = threadIdx.x; a < nodes; a += kBlock) {
+            const int j = a / sd, i = a - j * sd, hi = i >> 1, hj = j >> 1;
+            const T2 c0 = xc[hj * sc + hi];
+            const T2 p = ((i | j) & 1) ? scale2(half, add2(c0, xc[(hj + (j & 1)) * sc + hi + (i & 1)])) : c0;
+            x2[a] = add2(jac(mt[a], r[a]), p);
+        }
+        __syncthreads();
+        for (int a = threadIdx.x; a < nodes; a += kBlock) {
+            const int j = a / sd, i = a - j * sd;
+            x3[a] = (i > 0 && i < n && j > 0 && j < n) ? add2(x2[a], jac(mt[a], sub2(r[a], applyA(mt, sd, x2, a))))
+                                                       : zero;
+        }
+        __syncthreads();
+    }
+    {
+        const int nodes = sm.side[0] * sm.side[0];
+        const T2* x = sh + sm.off_x[0];
+        for (int a = threadIdx.x; a < nodes; a += kBlock) xout[(size_t)a * ST + s] = x[a];
     }
 }
 
@@ -877,8 +1011,16 @@ static int flat_grid(size_t total) {
 
 void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmode, double* part, hipStream_t st) {
     const int L = p.nlev;
+    // levels l0 .. L-1 (side <= kSmallSide, l0 >= 1) run in one k_vc_small launch
+    int l0 = L;
+    for (int l = 1; l < L; ++l)
+        if (p.lev[l].side <= kSmallSide) {
+            l0 = l;
+            break;
+        }
+    if (L - l0 > kMaxSmall) l0 = L;  // (sides 33, 17, 9, 5, 3: never more than kMaxSmall)
     // restriction sweep
-    for (int l = 0; l + 1 < L; ++l) {
+    for (int l = 0; l + 1 < L && l < l0; ++l) {
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* rout = ws + p.lev[l + 1].off_r;
         Geom g = slot_geom(p.lev[l + 1].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
@@ -901,7 +1043,32 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         }
         tm_end(p, kid, st);
     }
-    {
+    if (l0 < L) {
+        Geom g = slot_geom(p.lev[l0].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
+        SlotArgs sa = mk_slot(p, ws, g);
+        SmallArgs sm;
+        sm.count = L - l0;
+        int off = 0;
+        for (int q = 0; q < sm.count; ++q) {
+            const LevelDesc& d = p.lev[l0 + q];
+            sm.side[q] = d.side;
+            sm.mt[q] = (const double*)(ws + d.off_mt);
+            sm.off_r[q] = off;
+            sm.off_x[q] = off + (int)d.nodes;
+            off += 2 * (int)d.nodes;
+        }
+        sm.off_t = off;
+        off += (int)p.lev[l0].nodes;
+        const size_t shm = (size_t)off * p.elem;
+        tm_begin(p, KID_COARSEST, st);
+        if (p.fp32)
+            hipLaunchKernelGGL(k_vc_small<float>, dim3(p.ST), dim3(kBlock), shm, st, sa, sm, ws + p.lev[l0].off_r,
+                               ws + p.lev[l0].off_x);
+        else
+            hipLaunchKernelGGL(k_vc_small<double>, dim3(p.ST), dim3(kBlock), shm, st, sa, sm, ws + p.lev[l0].off_r,
+                               ws + p.lev[l0].off_x);
+        tm_end(p, KID_COARSEST, st);
+    } else {
         Geom g = slot_geom(p.lev[L - 1].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
         SlotArgs sa = mk_slot(p, ws, g);
         const void* rin = (L == 1) ? r0 : (const void*)(ws + p.lev[L - 1].off_r);
@@ -916,7 +1083,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         tm_end(p, KID_COARSEST, st);
     }
     // prolongation sweep
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = (l0 < L ? l0 : L - 1) - 1; l >= 0; --l) {
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* xout = (l == 0) ? x0 : (void*)(ws + p.lev[l].off_x);
         const void* xc = ws + p.lev[l + 1].off_x;
