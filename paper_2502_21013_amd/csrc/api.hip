@@ -233,7 +233,8 @@ static void layout(Plan& p) {
     p.off_zs = take(S * 3 * sizeof(double));
     p.off_wave = take(B * (size_t)p.N * sizeof(double));
     p.off_inst = take(B * 4 * sizeof(double));
-    size_t part_slot = (size_t)(std::max(p.g_slot0.blocks, p.g_mv.blocks) + kReduceRows) * S * 3;
+    // two sets of slot partials (V-cycle and operator sweep), each with its stage-1 tail
+    size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows + p.g_mv.blocks + kReduceRows) * S * 3;
     size_t part_team = (size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2;
     size_t part_adj = p.opt.adjoint ? std::max<size_t>((size_t)kAdjBlocks * 2, (size_t)p.n * p.n * 2) : 0;
     if (p.opt.krylov_dim > 0) part_adj = std::max<size_t>(part_adj, (size_t)kAdjBlocks * 2);
@@ -364,11 +365,13 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
     void* R = ws + p.lev[0].off_r;
     void* P = ws + p.off_P;
     if (p.opt.inner == PT_INNER_GALERKIN1) {
+        // p^H r partials from the V-cycle's last sweep, p^H A p partials after them; both reduced
+        // and divided in two launches
+        double* part_b = part + (size_t)(p.g_slot0.blocks + kReduceRows) * S * 3;
         launch_vcycle(p, ws, R, P, DOT_HERM, part, st);
-        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_slot0.blocks, DOT_HERM, num, st));
-        TM(KID_MATVEC, launch_matvec(p, ws, P, nullptr, DOT_HERM, part, st));
-        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_mv.blocks, DOT_HERM, den, st));
-        TM(KID_REDUCE, launch_slot_div(p, num, den, alpha, nullptr, st));
+        TM(KID_MATVEC, launch_matvec(p, ws, P, nullptr, DOT_HERM, part_b, st));
+        TM(KID_REDUCE, launch_reduce_ratio(p, part, p.g_slot0.blocks, part_b, p.g_mv.blocks, DOT_HERM, num, den, alpha,
+                                           st));
         *X = P;
         *coef = alpha;
         return PT_OK;

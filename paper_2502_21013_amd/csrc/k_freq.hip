@@ -832,12 +832,23 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
 // slot 0 the two real dot products (s1, s2).
 // Stage 1: workgroup (x, y) sums partial rows [y nblk / RB, (y+1) nblk / RB) for SG slots
 // (threads: SG slots x 256/SG row lanes, lanes combined in a fixed order) into part2[y][s].
-__global__ void __launch_bounds__(kBlock) k_reduce_dots1(const double* part, int nblk, int S, double* part2) {
+// Workgroups z = 1 do the same for a second set (part_b, nblk_b, RB_b, part2_b); each set
+// keeps its own RB (workgroups with y >= RB of their set have nothing to do).
+struct Dots1Set {
+    const double* part;
+    int nblk, RB;
+    double* part2;
+};
+__global__ void __launch_bounds__(kBlock) k_reduce_dots1(Dots1Set a, Dots1Set b, int S) {
     __shared__ double red[3][kBlock];
+    const Dots1Set& d = blockIdx.z == 0 ? a : b;
+    const double* part = d.part;
+    const int nblk = d.nblk, RB = d.RB;
+    double* part2 = d.part2;
+    if ((int)blockIdx.y >= RB) return;  // (uniform in the workgroup)
     const int SG = S < 64 ? S : 64, RL = kBlock / SG;
     const int sl = threadIdx.x % SG, rl = threadIdx.x / SG;
     const int s = blockIdx.x * SG + sl;
-    const int RB = gridDim.y;
     const int b0 = (int)((long)blockIdx.y * nblk / RB), b1 = (int)((long)(blockIdx.y + 1) * nblk / RB);
     double s1 = 0, s2 = 0, s3 = 0;
     // rows b0 + rl, b0 + rl + RL, ... added in that order; the loads of kReduceBatch rows are
@@ -878,52 +889,29 @@ __global__ void __launch_bounds__(kBlock) k_reduce_dots1(const double* part, int
     }
 }
 
-// Stage 2: sum the RB rows of part2 in order and combine into a generic scalar
-// (S = total slots, Si = slots per instance).
-__global__ void __launch_bounds__(kBlock) k_reduce_dots(const double* part, int nblk, int S, int Si, int herm,
-                                                        double* out) {
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
-        double s1 = 0, s2 = 0, s3 = 0;
-        for (int b = 0; b < nblk; b += kReduceBatch) {  // rows in order, loads batched
-            double v[kReduceBatch][3];
-#pragma unroll
-            for (int u = 0; u < kReduceBatch; ++u) {
-                const double* o = part + ((size_t)(b + u < nblk ? b + u : b) * S + s) * 3;
-                v[u][0] = o[0];
-                v[u][1] = o[1];
-                v[u][2] = o[2];
-            }
-#pragma unroll
-            for (int u = 0; u < kReduceBatch; ++u) {
-                if (b + u < nblk) {
-                    s1 += v[u][0];
-                    s2 += v[u][1];
-                    s3 += v[u][2];
-                }
-            }
-        }
-        double2 r;
-        if ((s & (Si - 1)) == 0) {
-            r.x = s1;
-            r.y = s2;
-        } else {
-            r.x = herm ? (s1 + s2) : (s1 - s2);
-            r.y = s3;
-        }
-        ((double2*)out)[s] = r;
+// Stage 2: the row sums of part2 per slot, combined into a generic scalar (S = total slots,
+// Si = slots per instance). kS2Lanes lanes per slot: lane l adds rows l, l + kS2Lanes, ... in
+// that order, then the lane sums are added in lane order.
+constexpr int kS2Lanes = 16;
+
+__device__ __forceinline__ double2 dots_combine(double s1, double s2, double s3, int s, int Si, int herm) {
+    double2 r;
+    if ((s & (Si - 1)) == 0) {
+        r.x = s1;
+        r.y = s2;
+    } else {
+        r.x = herm ? (s1 + s2) : (s1 - s2);
+        r.y = s3;
     }
+    return r;
 }
 
 // coef = num / den in generic arithmetic. A zero denominator with a zero numerator (a
 // frequency whose right-hand side vanishes) gives 0; a vanishing denominator with a
 // nonzero numerator sets *flag (COCG breakdown) and gives 0.
-__global__ void __launch_bounds__(kBlock) k_slot_div(const double* num_, const double* den_, double* coef_, int S,
-                                                     int Si, int* flag) {
-    const double2* num = (const double2*)num_;
-    const double2* den = (const double2*)den_;
-    double2* coef = (double2*)coef_;
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock) {
-        double2 a = num[s], b = den[s], r;
+__device__ __forceinline__ double2 slot_ratio(double2 a, double2 b, int s, int Si, int* flag) {
+    {
+        double2 r;
         if ((s & (Si - 1)) == 0) {
             r.x = (b.x != 0.0) ? a.x / b.x : 0.0;
             r.y = (b.y != 0.0) ? a.y / b.y : 0.0;
@@ -939,7 +927,60 @@ __global__ void __launch_bounds__(kBlock) k_slot_div(const double* num_, const d
                 if (flag && (a.x != 0.0 || a.y != 0.0)) *flag = 1;
             }
         }
-        coef[s] = r;
+        return r;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_slot_div(const double* num_, const double* den_, double* coef_, int S,
+                                                     int Si, int* flag) {
+    const double2* num = (const double2*)num_;
+    const double2* den = (const double2*)den_;
+    double2* coef = (double2*)coef_;
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock)
+        coef[s] = slot_ratio(num[s], den[s], s, Si, flag);
+}
+
+// Stage 2 of one reduction (out = rows of pa), or of two and their ratio in one launch (RATIO:
+// outa = rows of pa, outb = rows of pb, coef = outa / outb per slot, as k_slot_div without a
+// flag).
+template <bool RATIO>
+__global__ void __launch_bounds__(kBlock) k_reduce_dots2(const double* pa, int RBa, const double* pb, int RBb, int S,
+                                                         int Si, int herm, double* outa, double* outb, double* coef) {
+    __shared__ double red[6][kBlock];
+    const int ln = threadIdx.x % kS2Lanes;
+    const int s = blockIdx.x * (kBlock / kS2Lanes) + threadIdx.x / kS2Lanes;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (s < S) {
+        for (int b = ln; b < RBa; b += kS2Lanes) {
+            const double* o = pa + ((size_t)b * S + s) * 3;
+            v[0] += o[0];
+            v[1] += o[1];
+            v[2] += o[2];
+        }
+        if (RATIO) {
+            for (int b = ln; b < RBb; b += kS2Lanes) {
+                const double* o = pb + ((size_t)b * S + s) * 3;
+                v[3] += o[0];
+                v[4] += o[1];
+                v[5] += o[2];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    if (ln == 0 && s < S) {
+        double t[6] = {0, 0, 0, 0, 0, 0};
+        for (int l = 0; l < kS2Lanes; ++l)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) t[c] += red[c][threadIdx.x + l];
+        const double2 a = dots_combine(t[0], t[1], t[2], s, Si, herm);
+        ((double2*)outa)[s] = a;
+        if (RATIO) {
+            const double2 b = dots_combine(t[3], t[4], t[5], s, Si, herm);
+            ((double2*)outb)[s] = b;
+            ((double2*)coef)[s] = slot_ratio(a, b, s, Si, nullptr);
+        }
     }
 }
 
@@ -1132,16 +1173,36 @@ void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode,
     }
 }
 
+static Dots1Set dots1_set(const Plan& p, double* part, int nblk) {
+    // stage 1 writes into the tail of the partial buffer (after the nblk workgroups' partials)
+    Dots1Set d;
+    d.part = part;
+    d.nblk = nblk;
+    d.RB = nblk < kReduceRows ? nblk : kReduceRows;
+    d.part2 = part + (size_t)nblk * p.ST * 3;
+    return d;
+}
+
 void launch_reduce_dots(const Plan& p, double* part, int nblk, int dotmode, double* out, hipStream_t st) {
-    // stage 1 into the tail of the partial buffer (after the nblk workgroups' partials), then stage 2
-    const int RB = nblk < kReduceRows ? nblk : kReduceRows;
+    const Dots1Set d = dots1_set(p, part, nblk);
+    const int RB = d.RB;
     const int SG = p.ST < 64 ? p.ST : 64;
-    double* part2 = part + (size_t)nblk * p.ST * 3;
-    hipLaunchKernelGGL(k_reduce_dots1, dim3((p.ST + SG - 1) / SG, RB), dim3(kBlock), 0, st, (const double*)part, nblk,
-                       p.ST, part2);
-    int grid = (p.ST + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_reduce_dots, dim3(grid), dim3(kBlock), 0, st, (const double*)part2, RB, p.ST, p.S,
-                       dotmode == DOT_HERM ? 1 : 0, out);
+    const double* part2 = d.part2;
+    hipLaunchKernelGGL(k_reduce_dots1, dim3((p.ST + SG - 1) / SG, RB, 1), dim3(kBlock), 0, st, d, d, p.ST);
+    const int grid = (p.ST + kBlock / kS2Lanes - 1) / (kBlock / kS2Lanes);
+    hipLaunchKernelGGL(k_reduce_dots2<false>, dim3(grid), dim3(kBlock), 0, st, part2, RB, (const double*)nullptr, 0,
+                       p.ST, p.S, dotmode == DOT_HERM ? 1 : 0, out, (double*)nullptr, (double*)nullptr);
+}
+
+void launch_reduce_ratio(const Plan& p, double* pa, int na, double* pb, int nb, int dotmode, double* num, double* den,
+                         double* coef, hipStream_t st) {
+    const Dots1Set a = dots1_set(p, pa, na), b = dots1_set(p, pb, nb);
+    const int SG = p.ST < 64 ? p.ST : 64;
+    hipLaunchKernelGGL(k_reduce_dots1, dim3((p.ST + SG - 1) / SG, a.RB > b.RB ? a.RB : b.RB, 2), dim3(kBlock), 0, st, a, b,
+                       p.ST);
+    const int grid = (p.ST + kBlock / kS2Lanes - 1) / (kBlock / kS2Lanes);
+    hipLaunchKernelGGL(k_reduce_dots2<true>, dim3(grid), dim3(kBlock), 0, st, (const double*)a.part2, a.RB,
+                       (const double*)b.part2, b.RB, p.ST, p.S, dotmode == DOT_HERM ? 1 : 0, num, den, coef);
 }
 
 void launch_slot_div(const Plan& p, const double* num, const double* den, double* coef, int* flag, hipStream_t st) {

@@ -185,6 +185,9 @@ void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode,
                    hipStream_t st);
 // reduce dot partials -> generic scalars out[S] (double2)
 void launch_reduce_dots(const Plan& p, double* part, int nblk, int dotmode, double* out, hipStream_t st);
+// num, den = the reductions of the partials pa (na workgroups) and pb (nb workgroups); coef = num / den
+void launch_reduce_ratio(const Plan& p, double* pa, int na, double* pb, int nb, int dotmode, double* num, double* den,
+                         double* coef, hipStream_t st);
 // coef = num / den (generic division), with breakdown flag written to flag (int) if |den| tiny
 void launch_slot_div(const Plan& p, const double* num, const double* den, double* coef,
                      int* flag, hipStream_t st);
