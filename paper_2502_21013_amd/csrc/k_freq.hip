@@ -623,7 +623,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         // that the P1 interpolation needs at the step's new points (ai-1, aj+1), (ai, aj+2),
         // (ai+1, aj+2). The window moves by one coarse row every second fine row, so each
         // coarse value is loaded once per column walk instead of at every fine point (in FP32
-        // mode too: the loads saved outweigh the registers, 1.50 -> 1.24 ms at config 3). The
+        // mode too: the loads saved outweigh the registers, 1.50 -> 1.24 ms at 1024^2 x 512). The
         // parities of ai and aj (uniform) are compile-time in the code below.
         const int kc0 = (ai - 1) >> 1;
         const int nc = C.n;
