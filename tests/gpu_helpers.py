@@ -48,3 +48,73 @@ def oracle_shifted(d, Xh):
 def rel_err(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _prolongation(nc):
+    """P1 interpolation from the (nc+1)^2 grid to the (2 nc + 1)^2 grid on the SW-NE split
+    (full grids, node id = j * side + i): coarse nodes are copied, edge midpoints (horizontal,
+    vertical and the SW-NE diagonal) take the mean of their two coarse ends."""
+    import scipy.sparse as sp
+    sc, nf = nc + 1, 2 * nc
+    sf = nf + 1
+    rows, cols, vals = [], [], []
+    for j in range(sf):
+        for i in range(sf):
+            a = j * sf + i
+            hi, hj = i // 2, j // 2
+            if i % 2 == 0 and j % 2 == 0:
+                rows.append(a), cols.append(hj * sc + hi), vals.append(1.0)
+            else:
+                for (ci, cj) in ((hi, hj), (hi + i % 2, hj + j % 2)):
+                    rows.append(a), cols.append(cj * sc + ci), vals.append(0.5)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(sf * sf, sc * sc))
+
+
+def vcycle_reference(d, omega, R):
+    """One V(1,1) cycle B_s r_s per frequency slot, written out from its definition on the
+    interior nodes of each level: x1 = omega D^{-1} r, r_c = P^T (r - A x1), x_c = the cycle on
+    the next level (exact on the 2 x 2-cell grid), x2 = x1 + P x_c,
+    x3 = x2 + omega D^{-1} (r - A x2), with A = Khat + z M, Khat = nu_max * (5-point stencil),
+    D = 4 nu_max + z diag(M), P the P1 interpolation and the coarse mass P^T M P.
+    R: (nodes, S) complex; slot 0 holds the k = 0 system on the real part and k = N/2 on the
+    imaginary part."""
+    p = d.p
+    N, S, nu = p.N, p.N // 2, p.nu_max
+    z = dft.shifts(N, p.tau)
+    levels = []
+    n = p.n
+    Mf = fem.mass_full(d.mesh, d.mat.sigma).tocsr()
+    while True:
+        m = fem.build_mesh(n)
+        free = np.flatnonzero(m.free)
+        Kh = nu * fem.stiffness_full(m)[free][:, free].tocsr()
+        M = Mf[free][:, free].tocsr()
+        lev = {"n": n, "free": free, "Kh": Kh, "M": M, "dM": M.diagonal(), "nodes": (n + 1) ** 2}
+        levels.append(lev)
+        if n == 2:
+            break
+        Pf = _prolongation(n // 2)               # coarse (n/2) -> this level
+        lev["P"] = Pf[free][:, np.flatnonzero(fem.build_mesh(n // 2).free)].tocsr()
+        Mf = (Pf.T @ Mf @ Pf).tocsr()
+        n //= 2
+
+    def cycle(l, zz, r):
+        L = levels[l]
+        A = L["Kh"] + zz * L["M"]
+        D = 4 * nu + zz * L["dM"]
+        if L["n"] == 2:
+            return r / D
+        x1 = omega * r / D
+        rc = L["P"].T @ (r - A @ x1)
+        x2 = x1 + L["P"] @ cycle(l + 1, zz, rc)
+        return x2 + omega * (r - A @ x2) / D
+
+    fi = levels[0]["free"]
+    out = np.zeros_like(R, dtype=np.complex128)
+    for s in range(S):
+        r = R[fi, s].astype(np.complex128)
+        if s == 0:
+            out[fi, 0] = cycle(0, 0.0, r.real) + 1j * cycle(0, z[N // 2].real, r.imag)
+        else:
+            out[fi, s] = cycle(0, z[s], r)
+    return out

@@ -13,7 +13,7 @@ import pytest
 
 import workloads as W
 from oracle import dft, fem, periodic as pp
-from tests.gpu_helpers import say, oracle_K_full, oracle_shifted, rel_err
+from tests.gpu_helpers import say, oracle_K_full, oracle_shifted, rel_err, vcycle_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -203,6 +203,28 @@ def test_vcycle_is_symmetric_and_contracts(gpu, P, n, N, grid, precision):
         rn.append(np.linalg.norm(r1 - plan.shifted_apply(dev(x)).cpu().numpy(), axis=0))
     rate = (rn[-1] / rn[0]) ** (1 / 6)
     assert np.all(rate < 0.5), rate.max()
+
+
+# n = 16: the finest level in the per-level sweeps, the rest (9, 5, 3 points per side) in the
+# small-level kernel; n = 64 and 128: two and three levels in the per-level sweeps
+@pytest.mark.parametrize("n,N", [(16, 8), (64, 8), (128, 4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vcycle_matches_its_definition(gpu, P, n, N, precision):
+    say(f"vcycle definition n={n} N={N} {precision}")
+    p = W.with_size(W.config2(2), n, N)
+    d = fem.discretise(p)
+    plan = P.Plan(p, precision=precision, vc_omega=0.8)
+    rng = np.random.default_rng(n + N)
+    nodes = (n + 1) ** 2
+    R = rng.standard_normal((nodes, N // 2)) + 1j * rng.standard_normal((nodes, N // 2))
+    R[~d.mesh.free] = 0
+    cd = np.complex128 if precision == "fp64" else np.complex64
+    R = R.astype(cd)
+    B = plan.precond_apply(dev(R)).cpu().numpy().astype(np.complex128)
+    ref = vcycle_reference(d, 0.8, R.astype(np.complex128))
+    tol = 1e-12 if precision == "fp64" else 5e-5
+    assert rel_err(B, ref) <= tol
+    plan.close()
 
 
 # ---------------------------------------------------------------- periodic linear solve

@@ -1,0 +1,82 @@
+"""Pins of the test-side V(1,1) reference (tests/gpu_helpers.vcycle_reference) against facts
+that do not depend on it: P1 interpolation is exact on linear functions, the Galerkin coarse
+mass equals the mass assembled on the coarse mesh when the conductivity is constant on coarse
+triangles, the cycle is symmetric in the bilinear form, it is the exact solve on the 2 x 2-cell
+grid, and as a stationary iteration it contracts at a mesh-independent rate."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import dft, fem
+from tests.gpu_helpers import _prolongation, vcycle_reference
+
+
+def test_prolongation_is_exact_on_linear_functions():
+    for nc in (1, 2, 8):
+        P = _prolongation(nc)
+        c = np.arange(nc + 1)
+        X, Y = np.meshgrid(c, c)
+        f = np.arange(2 * nc + 1) / 2
+        FX, FY = np.meshgrid(f, f)
+        assert np.abs(P @ (3 * X - 2 * Y + 1).ravel() - (3 * FX - 2 * FY + 1).ravel()).max() == 0.0
+
+
+def test_galerkin_coarse_mass_is_the_coarse_assembly():
+    # the conductivity block [0.25, 0.75]^2 is a union of coarse triangles on both grids
+    p = W.with_size(W.config2(0), 16, 8)
+    pc = W.with_size(W.config2(0), 8, 8)
+    Mf = fem.mass_full(fem.build_mesh(16), fem.discretise(p).mat.sigma)
+    Mc = fem.mass_full(fem.build_mesh(8), fem.discretise(pc).mat.sigma)
+    P = _prolongation(8)
+    assert abs(P.T @ Mf @ P - Mc).max() <= 1e-15 * abs(Mc).max()
+
+
+def _setup(n, N, seed):
+    p = W.with_size(W.config2(seed), n, N)
+    d = fem.discretise(p)
+    rng = np.random.default_rng(seed)
+    R = rng.standard_normal(((n + 1) ** 2, N // 2)) + 1j * rng.standard_normal(((n + 1) ** 2, N // 2))
+    R[~d.mesh.free] = 0
+    return d, R
+
+
+def test_reference_cycle_is_symmetric():
+    d, R1 = _setup(16, 8, 1)
+    _, R2 = _setup(16, 8, 2)
+    B1, B2 = vcycle_reference(d, 0.8, R1), vcycle_reference(d, 0.8, R2)
+    for s in range(1, 4):
+        a, b = np.sum(B1[:, s] * R2[:, s]), np.sum(R1[:, s] * B2[:, s])
+        assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_reference_cycle_is_exact_on_the_coarsest_grid():
+    d, R = _setup(2, 8, 3)
+    B = vcycle_reference(d, 0.8, R)
+    z = dft.shifts(8, d.p.tau)
+    A = lambda zz: (d.Khat + zz * d.M).toarray()
+    fi = d.free_idx
+    for s in range(1, 4):
+        assert np.allclose(A(z[s]) @ B[fi, s], R[fi, s], rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_reference_cycle_contracts(n):
+    d, R = _setup(n, 8, 4)
+    z = dft.shifts(8, d.p.tau)
+    fi = d.free_idx
+    for s in (1, 3):
+        A = (d.Khat + z[s] * d.M).tocsr()
+        x = np.zeros(fi.size, complex)
+        r0 = np.linalg.norm(R[fi, s])
+        for _ in range(6):
+            res = np.zeros_like(R[:, :1].ravel())
+            res[fi] = R[fi, s] - A @ x
+            Rs = np.zeros_like(R)
+            Rs[:, s] = res
+            x = x + vcycle_reference(d, 0.8, Rs)[fi, s]
+        rate = (np.linalg.norm(R[fi, s] - A @ x) / r0) ** (1 / 6)
+        assert rate < 0.5
+        # and the iterate approaches the direct solution
+        xs = spla.spsolve(A.tocsc(), R[fi, s])
+        assert np.linalg.norm(x - xs) <= 0.05 * np.linalg.norm(xs)
