@@ -709,8 +709,10 @@ k_residual(FwdArgs a, void* rt_) {
             for (int k = 0; k < KP; ++k) {
                 const int m = lt + TS * k;
                 RSp(team, q)[m] = r[k];
-                MEp(team, q)[m] = mue[k];
-                XOp(team, q)[m] = muo[k];
+                if ((mass_bits >> q) & 1u) {  // (read only for rows with a mass term)
+                    MEp(team, q)[m] = mue[k];
+                    XOp(team, q)[m] = muo[k];
+                }
             }
         };
         static_assert(kRowBatch == 4, "the row window is kept in slots modulo 4");
