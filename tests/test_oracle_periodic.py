@@ -75,6 +75,33 @@ def test_single_mode_closed_form():
     assert np.allclose(Uh[1], np.linalg.solve(A, bh1), rtol=1e-11, atol=1e-14)
 
 
+def test_load_series_samples_the_new_time_level():
+    # Problem 1 evaluates f^n at t_n = n tau, n = 1..N, and row j of the series holds f^{j+1}.
+    # With N divisible by 4 the sin source takes closed values at quarter periods:
+    # f^{N/4} = b (t = T/4), f^{N/2} = 0 (t = T/2), f^{3N/4} = -b, f^N = 0 (t = T); the cos
+    # source has f^N = b and f^{N/2} = -b. Sampling at t_{n-1} instead would give
+    # sin(2 pi (N/4 - 1)/N) b in row N/4 - 1 and b in row 0 of the cos series.
+    for T in (1.0, 0.02):
+        d = small(8, 16, T=T)
+        b = d.b
+        N = d.p.N
+        assert np.linalg.norm(b) > 0
+        F = pp.load_series(d)
+        assert F.shape == (N, d.nfree)
+        tol = 1e-15 * np.max(np.abs(b))
+        assert np.max(np.abs(F[N // 4 - 1] - b)) <= tol
+        assert np.max(np.abs(F[N // 2 - 1])) <= 1e-14 * np.max(np.abs(b))
+        assert np.max(np.abs(F[3 * N // 4 - 1] + b)) <= tol
+        assert np.max(np.abs(F[N - 1])) <= 1e-14 * np.max(np.abs(b))
+        # the first row is the source one step into the period
+        assert np.allclose(F[0], np.sin(2 * np.pi / N) * b, rtol=0, atol=tol)
+        C = pp.load_series(d, "cos")
+        assert np.max(np.abs(C[N - 1] - b)) <= tol
+        assert np.max(np.abs(C[N // 2 - 1] + b)) <= tol
+        assert np.max(np.abs(C[N // 4 - 1])) <= 1e-14 * np.max(np.abs(b))
+        assert np.allclose(C[0], np.cos(2 * np.pi / N) * b, rtol=0, atol=tol)
+
+
 def test_period_sweep_solver_matches_spacetime_lu():
     d = small(8, 8)
     rng = np.random.default_rng(3)
