@@ -162,8 +162,10 @@ class FixedPointResult:
 
 def fixed_point(d: fem.Discretisation, tol: float = 1e-10, max_iter: int = 2000,
                 solver: str = "spacetime", U0: Optional[np.ndarray] = None,
-                F: Optional[np.ndarray] = None, lin=None) -> FixedPointResult:
-    """Fixed-point iteration (eqs. (iter1)-(iter2)) with Khat = nu_max S and an exact inner solve."""
+                F: Optional[np.ndarray] = None, lin=None, callback=None) -> FixedPointResult:
+    """Fixed-point iteration (eqs. (iter1)-(iter2)) with Khat = nu_max S and an exact inner solve.
+    callback(k, rel, U), if given, is called after the residual of every iterate U^k (progress
+    reports and checkpoints of long runs; it does not change the iteration)."""
     if F is None:
         F = load_series(d)
     if lin is None:
@@ -179,6 +181,8 @@ def fixed_point(d: fem.Discretisation, tol: float = 1e-10, max_iter: int = 2000,
         R = residual(d, U, F)
         rel = np.linalg.norm(R) / fnorm if fnorm > 0 else np.linalg.norm(R)
         rels.append(float(rel))
+        if callback is not None:
+            callback(k, float(rel), U)
         if not np.isfinite(rel):
             break
         if rel <= tol:
