@@ -25,7 +25,8 @@
  * Memory and ownership. Every device buffer (solution, workspace, optional
  * tables) is allocated and owned by the caller and must stay valid until the
  * stream-ordered work of the call has completed. The library allocates no device
- * memory; a plan owns only small host state. All entry points are stream-ordered
+ * memory at run time (the one device array it holds, the 64 MiB scratch of
+ * pt_solve_noalloc, is part of its code object); a plan owns only small host state. All entry points are stream-ordered
  * on the given HIP stream (hipStream_t passed as void*, NULL = default stream);
  * pt_solve and pt_residual additionally synchronise that stream before returning
  * because they read scalars back to the host.
@@ -177,6 +178,19 @@ pt_status pt_plan_workspace_bytes(const pt_plan* plan, size_t* bytes);
  * iterate and stats are filled. Blocks until the stream has finished. */
 pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream,
                    pt_stats* stats);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pt_solve_batch (and so pt_solve for a single-problem
+ * plan) with the workspace in a static device array of 64 MiB that the library holds on every
+ * GPU it runs on until the process ends, instead of a caller-owned workspace. d_u, stats,
+ * statuses and blocking as pt_solve_batch; time_ms is host wall time. Calls no allocating
+ * routine and creates no HIP object: plans with options.timing or options.graph are rejected
+ * (PT_ERR_INVALID), and plans whose pt_plan_workspace_bytes exceeds 64 MiB get
+ * PT_ERR_WORKSPACE before anything is launched. Every call on one GPU uses the same array,
+ * which keeps the previous call's contents (the solve initialises everything it reads):
+ * calls that overlap on one GPU, from any thread or stream, race and must be serialised by
+ * the caller. */
+pt_status pt_solve_noalloc(pt_plan* plan, double* d_u, void* stream, pt_stats* stats);
 
 /* Batching: count independent instances of Problem 1 that share the grid (n), the
  * period (N, T), the conductivity (sigma_in, sigma_rect) and nu_max -- hence M, Khat and

@@ -218,6 +218,23 @@ class Plan:
             raise PTError(st, "pt_solve")
         return U, stats
 
+    def solve_noalloc(self, U=None, history_cap: int = 4096, raise_on_error: bool = True):
+        """pt_solve_noalloc: the solve with the library's static device scratch as its workspace
+        (no workspace tensor is allocated or passed)."""
+        if U is None:
+            U = self.new_time_field()
+        buf = _StatsBuf(history_cap)
+        s = L.Stats()
+        buf.fill(s)
+        st = self.lib.pt_solve_noalloc(self._h, self._solution_field(U, "U"), self._stream(), C.byref(s))
+        stats = buf.result(self.lib, st, s)
+        if raise_on_error and st != L.PT_OK:
+            raise PTError(st, "pt_solve_noalloc")
+        return U, stats
+
+    def _solution_field(self, t, name):
+        return self._time_field(t, name)
+
     def adjoint_solve(self, U, Lam=None, history_cap: int = 4096, raise_on_error: bool = True):
         """Adjoint state lambda of the eddy-current loss at the state U (pt_adjoint_solve);
         Lam is the output (and the initial guess if the plan uses one)."""
@@ -411,6 +428,23 @@ class BatchPlan(Plan):
         stats = [b.result(self.lib, st, s) for b, s in zip(bufs, sa)]
         if raise_on_error and st != L.PT_OK:
             raise PTError(st, "pt_solve_batch")
+        return U, stats
+
+    def _solution_field(self, t, name):
+        return self._batch_field(t, name)
+
+    def solve_noalloc(self, U=None, history_cap: int = 4096, raise_on_error: bool = True):
+        """pt_solve_noalloc for the batch: U [count, N, n+1, n+1] and one SolveStats per instance."""
+        if U is None:
+            U = self.new_time_field()
+        bufs = [_StatsBuf(history_cap) for _ in range(self.count)]
+        sa = (L.Stats * self.count)()
+        for b, buf in zip(bufs, sa):
+            b.fill(buf)
+        st = self.lib.pt_solve_noalloc(self._h, self._batch_field(U, "U"), self._stream(), sa)
+        stats = [b.result(self.lib, st, s) for b, s in zip(bufs, sa)]
+        if raise_on_error and st != L.PT_OK:
+            raise PTError(st, "pt_solve_noalloc")
         return U, stats
 
     def _single(self, *a, **k):

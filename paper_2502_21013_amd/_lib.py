@@ -85,6 +85,7 @@ def load():
         "pt_plan_destroy": (None, [vp]),
         "pt_plan_workspace_bytes": (i32, [vp, C.POINTER(C.c_size_t)]),
         "pt_solve": (i32, [vp, vp, sz, vp, vp, C.POINTER(Stats)]),
+        "pt_solve_noalloc": (i32, [vp, vp, vp, C.POINTER(Stats)]),
         "pt_plan_create_batch": (i32, [C.POINTER(Problem), i32, C.POINTER(Options), pplan]),
         "pt_plan_batch_size": (i32, [vp, C.POINTER(C.c_int32)]),
         "pt_solve_batch": (i32, [vp, vp, sz, vp, vp, C.POINTER(Stats)]),

@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <mutex>
 #include <thread>
 #include <cstring>
 #include <new>
@@ -508,18 +510,22 @@ struct EventPair {
 // when every instance's relative residual is at most tol. d_u: [B][N][n+1][n+1];
 // stats: NULL or an array of B. Adjoint (B = 1): the same iteration for J^T lambda = dl/dU
 // at the state d_u, lambda in and out through d_lambda.
+// no_alloc: create no HIP object (events), time the call on the host clock (it blocks anyway).
 static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, hipStream_t st, pt_stats* stats,
-                            bool adjoint = false, double* d_lambda = nullptr) {
+                            bool adjoint = false, double* d_lambda = nullptr, bool no_alloc = false) {
     pt_status s = check_ws(&p, d_ws, ws_bytes);
     if (s != PT_OK) return s;
     char* ws = (char*)d_ws;
     const int B = p.B;
     EventPair ev;
-    PT_HIP(hipEventCreate(&ev.e0));
-    PT_HIP(hipEventCreate(&ev.e1));
+    const auto host_t0 = std::chrono::steady_clock::now();
+    if (!no_alloc) {
+        PT_HIP(hipEventCreate(&ev.e0));
+        PT_HIP(hipEventCreate(&ev.e1));
+    }
     s = timer_start(p);
     if (s != PT_OK) return s;
-    PT_HIP(hipEventRecord(ev.e0, st));
+    if (!no_alloc) PT_HIP(hipEventRecord(ev.e0, st));
     s = setup(p, ws, st);
     if (s != PT_OK) return s;
     double* U = (double*)(ws + p.off_U);
@@ -639,12 +645,18 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
         if (s != PT_OK) return s;
     }
     TM(KID_TRANSPOSE, launch_transpose_out(p, X0, d_x, st));
-    PT_HIP(hipEventRecord(ev.e1, st));
-    PT_HIP(hipEventSynchronize(ev.e1));
-    PT_HIP(hipGetLastError());
-    tm_flush(p);
     float ms = 0.f;
-    PT_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    if (no_alloc) {
+        PT_HIP(hipStreamSynchronize(st));
+        PT_HIP(hipGetLastError());
+        ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - host_t0).count();
+    } else {
+        PT_HIP(hipEventRecord(ev.e1, st));
+        PT_HIP(hipEventSynchronize(ev.e1));
+        PT_HIP(hipGetLastError());
+        PT_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    }
+    tm_flush(p);
     if (stats) {
         for (int b = 0; b < B; ++b) {
             pt_stats& o = stats[b];
@@ -867,6 +879,39 @@ static pt_status newton_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, 
     return result;
 }
 
+// ---------------------------------------------------------------- allocation-free solve
+
+// Device scratch of pt_solve_noalloc: the solver's whole workspace lives here. Every GPU the
+// library runs on holds its own copy until the process ends. In host code the name only
+// stands for the symbol: kernels and copies get the device address that hipGetSymbolAddress
+// returns for the current device (scratch_address).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of scratch on the current device, looked up once per device (with that
+// device current) and kept.
+static pt_status scratch_address(void** out) {
+    int dev = -1;
+    PT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PT_ERR_INVALID, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return fail(PT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        if (!ptr || ((uintptr_t)ptr & 255) != 0)
+            return fail(PT_ERR_HIP, "scratch has no 256-byte aligned device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PT_OK;
+}
+
 }  // namespace pt
 
 using namespace pt;
@@ -1021,6 +1066,22 @@ pt_status pt_solve(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void
 pt_status pt_solve_batch(pt_plan* plan, void* d_ws, size_t ws_bytes, double* d_u, void* stream, pt_stats* stats) {
     if (!plan || !d_u) return fail(PT_ERR_INVALID, "plan and d_u must not be NULL");
     return solve_impl(plan->p, d_ws, ws_bytes, d_u, (hipStream_t)stream, stats);
+}
+
+pt_status pt_solve_noalloc(pt_plan* plan, double* d_u, void* stream, pt_stats* stats) {
+    if (!plan || !d_u) return fail(PT_ERR_INVALID, "plan and d_u must not be NULL");
+    Plan& p = plan->p;
+    if (p.opt.timing || p.opt.graph)
+        return fail(PT_ERR_INVALID, "pt_solve_noalloc: options.timing and options.graph create HIP objects; "
+                                    "use pt_solve / pt_solve_batch");
+    if (p.ws_bytes > kScratchBytes)
+        return fail(PT_ERR_WORKSPACE, "pt_solve_noalloc: the plan needs " + std::to_string(p.ws_bytes) +
+                                          " bytes of workspace, more than the " + std::to_string(kScratchBytes) +
+                                          " bytes of the static device scratch; use pt_solve with a workspace");
+    void* ws = nullptr;
+    pt_status s = scratch_address(&ws);
+    if (s != PT_OK) return s;
+    return solve_impl(p, ws, kScratchBytes, d_u, (hipStream_t)stream, stats, false, nullptr, true);
 }
 
 pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u, double* d_r, void* stream,

@@ -210,3 +210,19 @@ def test_newton_entry_points_need_a_newton_plan(P):
     assert nplan.workspace_bytes > plan.workspace_bytes + 14 * 81 * 8 * 8
     with pytest.raises(P.PTError):
         P.BatchPlan([W.with_size(p, 8, 8) for p in W.config4(0, 2)], krylov_dim=4)
+
+
+def test_noalloc_solve_rejects_before_any_device_work(P):
+    """pt_solve_noalloc validates on the host: a plan whose workspace exceeds the 64 MiB static
+    scratch gets PT_ERR_WORKSPACE, timing or graph plans PT_ERR_INVALID (d_u is never touched)."""
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    dummy = (C.c_double * 1)()
+    big = P.Plan(W.with_size(W.config1(), 256, 64))
+    assert big.workspace_bytes > 64 << 20
+    st = lib.pt_solve_noalloc(big._h, C.cast(dummy, C.c_void_p), None, None)
+    assert st == L.PT_ERR_WORKSPACE and b"static device scratch" in lib.pt_last_error()
+    for kw in (dict(timing=True), dict(graph=True)):
+        pl = P.Plan(W.config1(), **kw)
+        assert lib.pt_solve_noalloc(pl._h, C.cast(dummy, C.c_void_p), None, None) == L.PT_ERR_INVALID
+    assert lib.pt_solve_noalloc(None, C.cast(dummy, C.c_void_p), None, None) == L.PT_ERR_INVALID
