@@ -10,17 +10,23 @@ inputs (problem tables, workspace) are resident in HBM before timing starts.
 Workload: 1024 x 1024 cells (1,050,625 nodes), N = 512 time steps, seeded materials
 (J0 and iron jitter from seed 0), 535,822,848 space-time DoFs (free nodes x N). Both the
 FP32+refinement mode (reported as `value`) and the plain FP64 path are timed; both stop
-on the same FP64 residual.
+on the same FP64 residual. The line states the error of each result: the relative L2
+difference of the FP32+refinement and FP64 solutions, and of both against the FP64 CPU
+oracle's solution on the 2x-coarsened copy (512 x 512 cells, N = 256, stored by
+tests/golden/make_oracle_solutions.py) when that file is present.
 
 Per-kernel durations come from HIP events that the library records around every launch on
 the solve stream over the timed region; the roofline entry uses the dominant kernel.
-The CPU baseline is the FP64 oracle on a bounded sample of the same workload family.
+The CPU baseline is the FP64 oracle on a bounded sample of the same workload family, one
+copy per host core, run before the GPU is touched.
 
-Batching workload (--workload c4): the 64 seeded instances of uneven grid and period
-(n in {64,128,256,512}, N in {64,128,256}, J0 and iron corners seeded), grouped into batch
-plans and solved by the concurrent work-list runner with graph replay; one step solves
-all 64 to 1e-8. It is compared with the plain FP64 path (each instance alone, one after
-the other, eager launches).
+Batching sub-record (`batching`, skipped with --no-batching; alone with --workload c4): the
+64 seeded instances of uneven grid and period (n in {64,128,256,512}, N in {64,128,256},
+J0 and iron corners seeded), grouped into batch plans and solved by the concurrent
+work-list runner with graph replay; one step solves all 64 to 1e-8, in FP32+refinement and
+FP64. It is compared with the plain FP64 path (each instance alone, eager launches, one
+after the other; plans, workspaces and fields built and warmed up before timing), with its
+own roofline (a serial pass with per-kernel events) and CPU baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c4]
 """
@@ -55,16 +61,21 @@ def workload(name, seed):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_many(P, problems, mode, steps, warmup, tol, nstreams, graph, tuning):
+def run_many(P, problems, mode, steps, warmup, tol, nstreams, graph, tuning, trace_gap=0.0, **opts):
+    """Time `steps` solves of all problems by the work-list runner; returns (timings, solver,
+    last result). The solver is left open (its fields hold the last solutions). trace_gap: idle
+    seconds between the warmup and the timed solves (marks the timed window in a kernel trace)."""
     import torch
     from paper_2502_21013_amd.batch import ManySolver
     ms = ManySolver(problems, precision=mode, tol=tol, max_outer=2000, graph=graph, nstreams=nstreams,
-                    tuning=tuning)
+                    tuning=tuning, **opts)
     for w in range(warmup):
         r = ms.solve()
         log(f"{mode} many warmup {w}: {len(ms.plans)} plans, max outer "
             f"{max(s.outer_iters for s in r.stats)}")
     torch.cuda.synchronize()
+    if trace_gap > 0:
+        time.sleep(trace_gap)
     t0 = time.perf_counter()
     for k in range(steps):
         r = ms.solve()
@@ -74,67 +85,141 @@ def run_many(P, problems, mode, steps, warmup, tol, nstreams, graph, tuning):
            "batch_sizes": [len(b) for b in ms.batches],
            "outer_iters_max": max(s.outer_iters for s in r.stats),
            "rel_residual_max": max(s.rel_residual for s in r.stats)}
-    ms.close()
-    del ms
-    torch.cuda.empty_cache()
-    return out
+    return out, ms, r
 
 
-def run_plain_each(P, problems, tol):
-    """The plain FP64 path: each instance alone, eager launches, one after the other."""
+def run_plain_each(P, problems, steps, warmup, tol):
+    """The plain FP64 path: each instance alone, eager launches, one after the other. Plans,
+    workspaces and output fields are built, and every plan solved once, before the timer."""
     import torch
+    plans = [P.Plan(p, tol=tol, precision="fp64", max_outer=2000) for p in problems]
+    fields = [pl.new_time_field() for pl in plans]
+    for pl in plans:
+        pl.workspace()
+    for w in range(warmup):
+        for pl, U in zip(plans, fields):
+            pl.solve(U)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     outer = []
-    for p in problems:
-        plan = P.Plan(p, tol=tol, precision="fp64", max_outer=2000)
-        _, st = plan.solve()
-        outer.append(st.outer_iters)
-        plan.close()
+    for k in range(steps):
+        outer = []
+        for pl, U in zip(plans, fields):
+            _, st = pl.solve(U)
+            outer.append(st.outer_iters)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    for pl in plans:
+        pl.close()
+    del plans, fields
     torch.cuda.empty_cache()
-    return {"ms_per_step": 1e3 * wall, "outer_iters_max": max(outer)}
+    return {"ms_per_step": 1e3 * wall / steps, "outer_iters_max": max(outer)}
 
 
-def main_many(args, P):
+def batch_roofline(P, problems, tol, tuning):
+    """Per-kernel-class device time of one serial pass (one stream, eager launches with events)
+    of the batching workload, against the algorithmic bytes of every launch: the dominant
+    class's achieved bandwidth = its bytes over all plans / its time over all plans."""
+    import torch
+    _, ms, r = run_many(P, problems, "fp32", 1, 1, tol, 1, False, tuning, timing=True)
+    by_cls_ms, by_cls_bytes, by_cls_n = {}, {}, {}
+    for k, ix in enumerate(r.batches):
+        st = r.stats[ix[0]]                      # every instance of a plan carries the plan's totals
+        pr = problems[ix[0]]
+        ab = algorithmic_bytes(pr, 8, len(ix))
+        for name, b in ab.items():
+            if name in st.kernel_ms:
+                n = st.kernel_launches[name]
+                by_cls_ms[name] = by_cls_ms.get(name, 0.0) + st.kernel_ms[name]
+                by_cls_bytes[name] = by_cls_bytes.get(name, 0.0) + b * n
+                by_cls_n[name] = by_cls_n.get(name, 0) + n
+    ms.close()
+    del ms
+    torch.cuda.empty_cache()
+    dom = max(by_cls_ms, key=by_cls_ms.get)
+    gbs = by_cls_bytes[dom] / (by_cls_ms[dom] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "launches": by_cls_n[dom], "alg_bytes_all_launches": by_cls_bytes[dom],
+            "avg_launch_ms": round(by_cls_ms[dom] / by_cls_n[dom], 4),
+            "note": "FP32+refinement, one stream, per-kernel HIP events; bytes and time summed over the "
+                    "launches of all batch plans"}
+
+
+def rel_l2_pairs(A, B):
+    """max over instance pairs of ||a - b|| / ||b|| (device tensors)."""
+    worst = 0.0
+    for a, b in zip(A, B):
+        nb = float(b.norm())
+        worst = max(worst, float((a - b).norm()) / nb if nb > 0 else float((a - b).norm()))
+    return worst
+
+
+def batching_record(args, P, cpu=None):
+    import torch
     import workloads as W
     from paper_2502_21013_amd import autotune as AT
     problems = W.config4(args.seed)
     total = sum(p.st_dofs for p in problems)
-    log(f"workload c4: {len(problems)} instances, {total} space-time DoFs in total")
+    log(f"batching workload: {len(problems)} instances, {total} space-time DoFs in total")
     tuning = AT.load_table(args.tuning) if args.tuning else None
-    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
-    res = {m: run_many(P, problems, m, args.steps, args.warmup, args.tol, args.streams, not args.no_graph, tuning)
-           for m in modes}
-    for m in modes:
+    steps, warmup = args.c4_steps, args.c4_warmup
+    res, sols = {}, {}
+    for m in [x.strip() for x in args.c4_modes.split(",") if x.strip()]:
+        res[m], ms, r = run_many(P, problems, m, steps, warmup, args.tol, args.streams, not args.no_graph, tuning,
+                                 trace_gap=args.trace_gap)
+        sols[m] = (ms, r)
         log(f"{m}: {res[m]['ms_per_step']:.1f} ms for all instances")
-    plain = None
+    err = rel_l2_pairs(sols["fp32"][1].U, sols["fp64"][1].U) if len(sols) == 2 else None
+    for m in sols:
+        sols[m][0].close()
+    del sols
+    torch.cuda.empty_cache()
+    plain = roof = None
     if not args.no_plain:
         log("plain FP64 path, instance by instance")
-        plain = run_plain_each(P, problems, args.tol)
+        plain = run_plain_each(P, problems, steps, warmup, args.tol)
         log(f"plain fp64: {plain['ms_per_step']:.1f} ms")
-    r0 = res[modes[0]]
+        plain["value"] = total / (plain["ms_per_step"] * 1e-3)
+    if not args.no_batch_roofline:
+        log("batching roofline pass (one stream, per-kernel events)")
+        roof = batch_roofline(P, problems, args.tol, tuning)
+    first = next(iter(res))
+    return {
+        "workload": "64 seeded instances, n in {64,128,256,512}, N in {64,128,256}, J0 log-uniform in "
+                    "[1,100], iron corners in [0.2,0.8]^2",
+        "seed": args.seed, "st_dofs": total, "tol": args.tol, "steps": steps, "warmup": warmup,
+        "streams": args.streams, "graph": not args.no_graph, "tuned": bool(tuning),
+        "value": total / (res[first]["ms_per_step"] * 1e-3), "unit": "space-time DoFs/s",
+        "ms_per_step": res[first]["ms_per_step"],
+        "modes": {m: dict(res[m], value=total / (res[m]["ms_per_step"] * 1e-3)) for m in res},
+        "plain_fp64_each": plain,
+        "err_fp32_vs_fp64_max_rel_l2": err,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
+def main_many(args, P, cpu=None):
+    rec = batching_record(args, P, cpu)
     out = {
         "metric": "space-time DoFs/s to rel. residual 1e-8 (FP32+refine vs FP64); % HBM peak",
-        "value": total / (r0["ms_per_step"] * 1e-3),
-        "unit": "space-time DoFs/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r0["ms_per_step"],
+        "value": rec["value"], "unit": "space-time DoFs/s",
+        "n_gpus": 1, "steps": rec["steps"], "warmup": rec["warmup"], "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if modes[0] == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": "batching: 64 seeded instances, n in {64,128,256,512}, N in {64,128,256}",
-                   "seed": args.seed, "st_dofs": total, "tol": args.tol, "streams": args.streams,
-                   "graph": not args.no_graph, "tuned": bool(tuning)},
-        "roofline": None,
-        "cpu_baseline": None,
-        "modes": {m: dict(res[m], value=total / (res[m]["ms_per_step"] * 1e-3)) for m in modes},
-        "plain_fp64_each": None if plain is None else dict(plain, value=total / (plain["ms_per_step"] * 1e-3)),
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batching: " + rec["workload"], "seed": args.seed, "st_dofs": rec["st_dofs"],
+                   "tol": args.tol, "streams": args.streams, "graph": rec["graph"], "tuned": rec["tuned"]},
+        "roofline": rec["roofline"], "cpu_baseline": cpu,
+        "modes": rec["modes"], "plain_fp64_each": rec["plain_fp64_each"],
+        "err_fp32_vs_fp64_max_rel_l2": rec["err_fp32_vs_fp64_max_rel_l2"],
     }
     print(json.dumps(out), flush=True)
 
 
-def algorithmic_bytes(p, elem):
-    """Bytes each dominant kernel must move per launch (all (n+1)^2 grid nodes).
+def algorithmic_bytes(p, elem, count=1):
+    """Bytes each dominant kernel must move per launch (all (n+1)^2 grid nodes, `count`
+    instances of the grid and period of p stacked in one batch plan).
 
     residual_sweep:           read U (8 B per node-time), write the residual spectrum R^ (its
                               packed DFT, fused into the sweep: elem per node-slot)
@@ -146,12 +231,12 @@ def algorithmic_bytes(p, elem):
     inverse (DFT + update):   read p, read U, write U
     """
     n, N = p.n, p.N
-    S = N // 2
+    S = N // 2 * count
     nodes = (n + 1) ** 2
     nc = (n // 2 + 1) ** 2
     slot = nodes * S * elem
     cslot = nc * S * elem
-    tfield = nodes * N * 8
+    tfield = nodes * N * count * 8
     return {
         "residual_sweep": tfield + slot,
         "rfft": 2 * slot,
@@ -222,7 +307,112 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None):
     del plan
     torch.cuda.empty_cache()
     return {"ms_per_step": 1e3 * wall / steps, "kernel_ms": kms, "kernel_launches": kcnt,
-            "outer_iters": outer, "rel_residual": st.rel_residual}
+            "outer_iters": outer, "rel_residual": st.rel_residual, "U": U}
+
+
+GOLDEN_HALF = os.path.join(ROOT, "tests", "golden", "oracle_c3half_seed0_n512_N256.npz")
+
+
+def error_vs_oracle(P, seed, path=GOLDEN_HALF, tol=1e-11):
+    """Relative L2 error of both modes against the FP64 CPU oracle's solution of the
+    2x-coarsened copy of the workload (512^2 cells, N = 256; stored sampled slices and
+    full-field sums), each mode solved on the GPU to `tol`. None when the file is absent."""
+    import numpy as np
+    import torch
+    import workloads as W
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    meta = json.loads(str(z["meta"]))
+    pr = meta["problem"]
+    if pr["seed"] != seed:
+        return None
+    prob = W.with_size(W.config3(seed), pr["n"], pr["N"])
+    idx, s = [int(j) for j in z["slice_idx"]], int(z["stride"])
+    ref = z["slices"]
+    out = {"workload": f"{pr['n']}x{pr['n']} cells, N={pr['N']} (2x-coarsened copy), seed {seed}",
+           "oracle": meta["solver"], "oracle_rel_residual": meta["rel_final"], "gpu_tol": tol}
+    for m in ("fp32", "fp64"):
+        plan = P.Plan(prob, tol=tol, precision=m, max_outer=4000)
+        U, st = plan.solve()
+        g = U.cpu().numpy()
+        plan.close()
+        sl = np.stack([g[j, ::s, ::s] for j in idx])
+        e_sl = float(np.linalg.norm(sl - ref) / np.linalg.norm(ref))
+        nrm = float(np.sqrt(float((U * U).sum())))
+        e_nrm = abs(nrm - float(np.sqrt(z["u_sq_sum"]))) / float(np.sqrt(z["u_sq_sum"]))
+        out[m] = {"rel_l2_sampled_slices": e_sl, "rel_diff_full_norm": e_nrm, "outer_iters": st.outer_iters,
+                  "rel_residual": st.rel_residual}
+        del U
+        torch.cuda.empty_cache()
+    return out
+
+
+PAPER_CONTEXT = {
+    "note": "the paper's own timings of its method (M1): the same outer fixed-point iteration with "
+            "multigrid in time for the periodic linear solves, on an unstructured transformer mesh "
+            "with the exp-capped law, tol 1e-4 relative to a static start; a different problem, "
+            "tolerance, inner solver and machine, quoted as context only",
+    "hardware": "one node of LLNL Dane, 112-core Intel Sapphire Rapids; (M1) on 8 MPI ranks (tab:runtime), "
+                "16-512 ranks over several nodes (tab:scaling)",
+    "tab_runtime_M1": [
+        {"N": 128, "N_V": 8208, "iters": 13, "seconds": 8.25036},
+        {"N": 128, "N_V": 32451, "iters": 10, "seconds": 24.6771},
+        {"N": 256, "N_V": 8208, "iters": 13, "seconds": 16.0703},
+        {"N": 256, "N_V": 32451, "iters": 10, "seconds": 49.6497},
+        {"N": 512, "N_V": 8208, "iters": 13, "seconds": 30.3863},
+        {"N": 512, "N_V": 32451, "iters": 10, "seconds": 98.5296},
+    ],
+    "tab_scaling_M1_best": {"N": 2048, "N_V": 8208, "ranks": 512, "seconds": 5.04528},
+    "derived_st_dofs_per_s": {"tab_runtime_max": 1.69e5, "tab_scaling_best": 3.3e6},
+}
+
+
+def _oracle_sample_worker(job):
+    """One oracle solve of a bounded sample (one host thread); returns (DoFs, seconds, outer steps)."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import fem, periodic as pp
+    kind, seed, n, N, tol = job
+    if kind == "c4":
+        base = W.config4(seed)[0]
+    else:
+        base = W.config3(seed)
+    p = W.with_size(base, n, N)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        d = fem.discretise(p)
+        r = pp.fixed_point(d, tol=tol, max_iter=2000)
+        dt = time.perf_counter() - t0
+    return p.st_dofs, dt, r.iters
+
+
+def host_cores():
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:
+        c = os.cpu_count() or 1
+    return max(1, min(16, c))
+
+
+def cpu_baseline(kind, seed, n=32, N=64, tol=1e-8):
+    """The FP64 oracle (space-time sparse LU inside the same fixed-point loop) on a bounded
+    sample: one copy of the sample problem per host core (at most 16), run concurrently, each
+    on one thread. Throughput = total DoFs / the longest solve time."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    cores = host_cores()
+    jobs = [(kind, seed, n, N, tol)] * cores
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_sample_worker, jobs))
+    dofs = sum(r[0] for r in res)
+    tmax = max(r[1] for r in res)
+    what = "config-4 instance 0's materials and source" if kind == "c4" else "the same seeded materials/source"
+    return {"value": dofs / tmax, "unit": "space-time DoFs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} concurrent copies (one per host core, one thread each) of {n}x{n} cells, N={N}, "
+                      f"{what}, tol {tol:g}, {res[0][2]} outer steps, longest {tmax:.1f} s "
+                      f"(sparse LU of the space-time matrix + fixed point)"}
 
 
 # ---------------------------------------------------------------- HBM traffic from rocprofv3 counters
@@ -256,6 +446,37 @@ def _per_class(rows, counter):
         vals = [v for v, d in ds if d >= 0.5 * dmax]
         res[cls] = sum(vals) / len(vals)
     return res
+
+
+def trace_idle(csv_path, gap_ns=0.5e9):
+    """Device busy time of the kernels of a rocprofv3 kernel trace (csv) in the window after the
+    last idle gap of at least gap_ns: the union of the kernels' [start, end] intervals over the
+    window's span (first start to last end). Kernels on different streams may overlap; the union
+    counts the device as busy while any kernel runs."""
+    import csv
+    with open(csv_path, newline="") as fh:
+        rows = list(csv.DictReader(fh))
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
+    cut = 0
+    reach = iv[0][1]
+    for k in range(1, len(iv)):
+        if iv[k][0] - reach >= gap_ns:
+            cut = k
+        reach = max(reach, iv[k][1])
+    win = iv[cut:]
+    busy, cs, ce = 0, win[0][0], win[0][1]
+    for a, b, _ in win[1:]:
+        if a > ce:
+            busy += ce - cs
+            cs, ce = a, b
+        else:
+            ce = max(ce, b)
+    busy += ce - cs
+    span = max(b for _, b, _ in win) - win[0][0]
+    out = {"trace": os.path.basename(csv_path), "kernels_in_window": len(win), "window_ms": span / 1e6,
+           "busy_ms": busy / 1e6, "idle_frac": 1.0 - busy / span}
+    print(json.dumps(out), flush=True)
+    return out
 
 
 def copy_calibration(gib=1.0, reps=3):
@@ -295,25 +516,6 @@ def pmc_summary(fetch_db, write_db, cal_fetch_db, cal_write_db, workload, mode, 
     print(json.dumps(data), flush=True)
 
 
-def cpu_baseline(seed, n=32, N=64, tol=1e-8):
-    """FP64 oracle (space-time sparse LU inside the same fixed-point loop) on a bounded sample:
-    the same materials and source at n x n cells and N steps, one thread."""
-    from threadpoolctl import threadpool_limits
-
-    import workloads as W
-    from oracle import fem, periodic as pp
-    p = W.with_size(W.config3(seed), n, N)
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        d = fem.discretise(p)
-        r = pp.fixed_point(d, tol=tol, max_iter=2000)
-        dt = time.perf_counter() - t0
-    return {"value": p.st_dofs / dt, "unit": "space-time DoFs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n}x{n} cells, N={N}, same seeded materials/source, tol {tol:g}, "
-                      f"{r.iters} outer steps, {dt:.1f} s on 1 host thread (sparse LU of the "
-                      f"space-time matrix + fixed point)"}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,9 +526,20 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--modes", default="fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--streams", type=int, default=4, help="c4: host threads / HIP streams of the work list")
-    ap.add_argument("--no-graph", action="store_true", help="c4: eager launches instead of graph replay")
-    ap.add_argument("--no-plain", action="store_true", help="c4: skip the instance-by-instance FP64 run")
+    ap.add_argument("--no-batching", action="store_true", help="skip the batching sub-record")
+    ap.add_argument("--no-oracle-error", action="store_true", help="skip the error against the oracle solution")
+    ap.add_argument("--c4-modes", default="fp32,fp64", help="batching: modes (FP32+refinement first)")
+    ap.add_argument("--no-plain", action="store_true", help="batching: skip the instance-by-instance FP64 run")
+    ap.add_argument("--no-batch-roofline", action="store_true", help="batching: skip the per-kernel event pass")
+    ap.add_argument("--trace-gap", type=float, default=0.0,
+                    help="batching: idle seconds before the timed solves (marks them in a kernel trace)")
+    ap.add_argument("--trace-idle", default="", metavar="KERNEL_TRACE_CSV",
+                    help="only summarise a rocprofv3 kernel trace (csv): device busy and idle time of the "
+                         "window after the last gap of at least 0.5 s")
+    ap.add_argument("--c4-steps", type=int, default=2, help="batching: timed steps")
+    ap.add_argument("--c4-warmup", type=int, default=1, help="batching: warmup steps")
+    ap.add_argument("--streams", type=int, default=4, help="batching: host threads / HIP streams of the work list")
+    ap.add_argument("--no-graph", action="store_true", help="batching: eager launches instead of graph replay")
     ap.add_argument("--tuning", default="", help="autotuner table (JSON) to apply")
     ap.add_argument("--max-outer", type=int, default=2000,
                     help="cap on outer steps per solve; below the count needed for 1e-8 the run is a "
@@ -338,6 +551,9 @@ def main():
     ap.add_argument("--pmc-out", default=os.path.join(ROOT, "profiles", "pmc_counters.json"))
     ap.add_argument("--pmc-commands", default="", help="the profiling commands, recorded in the table")
     args = ap.parse_args()
+    if args.trace_idle:
+        trace_idle(args.trace_idle)
+        return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, workload=args.workload, mode=args.modes.split(",")[0], out=args.pmc_out,
                     commands=args.pmc_commands)
@@ -346,6 +562,18 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU sharding of this "
               "solver is a design note, not an implementation", file=sys.stderr)
         sys.exit(2)
+
+    # CPU baselines first, in worker processes started before anything touches the GPU
+    cpu = cpu4 = None
+    want_batch = args.workload == "c4" or (args.workload == "c3" and not args.no_batching)
+    if not args.no_cpu_baseline and not args.calibrate_copy:
+        if args.workload != "c4":
+            log("cpu baseline (oracle on a bounded sample, one copy per host core)")
+            cpu = cpu_baseline("c3", args.seed)
+            log(f"cpu baseline {cpu['value']:.1f} DoFs/s on {cpu['cores']} cores")
+        if want_batch:
+            cpu4 = cpu_baseline("c4", args.seed)
+            log(f"batching cpu baseline {cpu4['value']:.1f} DoFs/s on {cpu4['cores']} cores")
 
     import torch
     import paper_2502_21013_amd as P
@@ -356,7 +584,7 @@ def main():
         return
     P.library()
     if args.workload == "c4":
-        main_many(args, P)
+        main_many(args, P, cpu4)
         return
     prob, desc = workload(args.workload, args.seed)
     log(f"workload {args.workload}: {desc}, {prob.st_dofs} space-time DoFs")
@@ -373,6 +601,20 @@ def main():
         res[m] = run_mode(P, prob, m, args.steps, args.warmup, args.tol, args.max_outer, tuned)
         res[m]["tuned"] = tuned
         log(f"{m}: {res[m]['ms_per_step']:.1f} ms per solve")
+    errors = {}
+    if "fp32" in res and "fp64" in res:
+        a, b = res["fp32"]["U"], res["fp64"]["U"]
+        errors["fp32_vs_fp64_rel_l2"] = float((a - b).norm() / b.norm())
+        log(f"rel L2 (FP32+refine vs FP64) {errors['fp32_vs_fp64_rel_l2']:.3e}")
+    for m in res:
+        res[m].pop("U")
+    torch.cuda.empty_cache()
+    if args.workload == "c3" and not args.no_oracle_error:
+        ev = error_vs_oracle(P, args.seed)
+        if ev:
+            errors["vs_oracle_coarsened_copy"] = ev
+            log(f"vs oracle (512^2 x 256): fp32 {ev['fp32']['rel_l2_sampled_slices']:.3e}, "
+                f"fp64 {ev['fp64']['rel_l2_sampled_slices']:.3e}")
 
     primary = modes[0]
     r0 = res[primary]
@@ -391,11 +633,10 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(dk["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_ms": round(dk["avg_ms"], 4)}
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a bounded sample)")
-        cpu = cpu_baseline(args.seed)
-        log(f"cpu baseline {cpu['value']:.1f} DoFs/s")
+
+    batching = None
+    if want_batch:
+        batching = batching_record(args, P, cpu4)
 
     value = prob.st_dofs / (r0["ms_per_step"] * 1e-3)
     out = {
@@ -418,9 +659,12 @@ def main():
         "modes": {m: {"value": prob.st_dofs / (res[m]["ms_per_step"] * 1e-3), "ms_per_step": res[m]["ms_per_step"],
                       "outer_iters": res[m]["outer_iters"], "rel_residual": res[m]["rel_residual"],
                       "tuned": res[m]["tuned"]} for m in modes},
+        "errors": errors,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "kernel_ms_all": {k: round(v, 3) for k, v in r0["kernel_ms"].items()},
+        "batching": batching,
+        "paper_context": PAPER_CONTEXT,
     }
     if args.max_outer < 2000:
         out["profiling_run"] = f"outer steps capped at {args.max_outer}: not a metric measurement"
