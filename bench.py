@@ -283,9 +283,9 @@ def load_traffic(kernel, mode, wl):
     return ent.get("hbm_bytes_per_launch")
 
 
-def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None):
+def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inner=None):
     import torch
-    plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer, **(tuned or {}))
+    plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer, **(inner or {}), **(tuned or {}))
     U = plan.new_time_field()
     plan.workspace()
     for w in range(warmup):
@@ -526,6 +526,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--modes", default="fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inner", default="galerkin1", choices=["galerkin1", "cocg"],
+                    help="inner method of every periodic solve (default: the one-step Galerkin V-cycle)")
+    ap.add_argument("--inner-iters", type=int, default=1, help="COCG steps per outer step (at most)")
+    ap.add_argument("--inner-rtol", type=float, default=0.0, help="COCG per-frequency relative tolerance")
     ap.add_argument("--no-batching", action="store_true", help="skip the batching sub-record")
     ap.add_argument("--no-oracle-error", action="store_true", help="skip the error against the oracle solution")
     ap.add_argument("--c4-modes", default="fp32,fp64", help="batching: modes (FP32+refinement first)")
@@ -593,12 +597,13 @@ def main():
     from paper_2502_21013_amd import autotune as AT
     from paper_2502_21013_amd.batch import tune_key
     table = AT.load_table(args.tuning) if args.tuning else {}
+    inner = {"inner": args.inner, "inner_iters": args.inner_iters, "inner_rtol": args.inner_rtol}
     res = {}
     for m in modes:
         tuned = table.get(tune_key(prob, 1, m))
         if tuned:
             log(f"{m}: tuned setting {tuned}")
-        res[m] = run_mode(P, prob, m, args.steps, args.warmup, args.tol, args.max_outer, tuned)
+        res[m] = run_mode(P, prob, m, args.steps, args.warmup, args.tol, args.max_outer, tuned, inner)
         res[m]["tuned"] = tuned
         log(f"{m}: {res[m]['ms_per_step']:.1f} ms per solve")
     errors = {}
@@ -653,7 +658,8 @@ def main():
         "dtype": "f32+f64" if primary == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": prob.n, "N": prob.N, "seed": args.seed, "st_dofs": prob.st_dofs,
-                   "tol": args.tol, "mode": "fp32_refine" if primary == "fp32" else "fp64"},
+                   "tol": args.tol, "mode": "fp32_refine" if primary == "fp32" else "fp64",
+                   "inner": inner},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": {m: {"value": prob.st_dofs / (res[m]["ms_per_step"] * 1e-3), "ms_per_step": res[m]["ms_per_step"],

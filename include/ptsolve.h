@@ -58,7 +58,8 @@ typedef enum {
     PT_ERR_INVALID = -1,        /* an argument or option is out of range */
     PT_ERR_HIP = -3,            /* a HIP runtime call failed (message in pt_last_error) */
     PT_ERR_NOT_CONVERGED = -4,  /* max_outer reached; the solution holds the last iterate */
-    PT_ERR_BREAKDOWN = -5,      /* COCG bilinear form vanished for some frequency */
+    PT_ERR_BREAKDOWN = -5,      /* COCG bilinear form p^T A p vanished (to breakdown_tol) for an
+                                   active frequency */
     PT_ERR_NONFINITE = -6,      /* residual norm is NaN or Inf */
     PT_ERR_DIVERGED = -7,       /* residual grew by diverge_factor over its minimum */
     PT_ERR_WORKSPACE = -8       /* workspace NULL, too small or not 256-byte aligned */
@@ -70,8 +71,12 @@ typedef enum { PT_FP64 = 0, PT_FP32_REFINE = 1 } pt_precision;
  *  PT_INNER_GALERKIN1: one V-cycle p = B_k r, then x = alpha p with
  *                      alpha = (p^H r) / (p^H A_k p) (Galerkin condition in the
  *                      Hermitian inner product; p^H A_k p has positive real part).
- *  PT_INNER_COCG:      inner_iters steps of COCG (unconjugated bilinear form
- *                      x^T y, preconditioned by the same V-cycle) from zero.   */
+ *  PT_INNER_COCG:      COCG (unconjugated bilinear form x^T y, preconditioned by
+ *                      the same V-cycle) from zero, per frequency until
+ *                      ||r_k|| <= inner_rtol ||R_k|| (that frequency is then
+ *                      masked: its iterate no longer changes) or inner_iters
+ *                      steps. A frequency whose right-hand side is zero is
+ *                      masked from the start.                                   */
 typedef enum { PT_INNER_GALERKIN1 = 0, PT_INNER_COCG = 1 } pt_inner;
 
 typedef enum { PT_WAVE_SIN = 0, PT_WAVE_COS = 1 } pt_waveform;
@@ -134,6 +139,14 @@ typedef struct {
     int32_t graph;         /* 1: capture the kernels of check_every outer steps into a HIP
                               graph on the first call (per plan and workspace address) and
                               replay it; same iterates as 0. Cannot be combined with timing. */
+    double inner_rtol;     /* PT_INNER_COCG: relative residual at which a frequency stops, in
+                              [0, 1); 0 = run inner_iters steps on every frequency with a nonzero
+                              residual. Eager launches end the inner loop once every frequency has
+                              stopped (one host read-back per step); graph replay runs inner_iters
+                              steps with the stopped frequencies masked (the same iterates). */
+    double breakdown_tol;  /* PT_INNER_COCG: PT_ERR_BREAKDOWN when an active frequency has
+                              |p^T A p| <= breakdown_tol Re(p^H A p) (the bilinear form vanishes to
+                              rounding); 0 = 64 units in the last place of the solver precision */
 } pt_options;
 
 typedef struct {
@@ -151,6 +164,9 @@ typedef struct {
     int32_t init_iters;         /* steps of the static start (options.init_static) */
     double rel_initial;         /* ||F - A(U^0)|| / ||F|| of the iteration's starting iterate */
     int32_t krylov_iters;       /* pt_newton_solve: Krylov steps over all Newton steps */
+    int32_t inner_iters_max;    /* most inner steps (COCG steps; 1 for the Galerkin step) taken by
+                                   one periodic solve of the call */
+    int64_t inner_iters_sum;    /* inner steps over all periodic solves of the call */
 } pt_stats;
 
 /* Kernel classes reported by the per-kernel timer; pt_kernel_class_name() names them. */

@@ -76,12 +76,14 @@ class SolveStats:
     init_iters: int = 0
     rel_initial: float = float("nan")
     krylov_iters: int = 0
+    inner_iters_max: int = 0
+    inner_iters_sum: int = 0
 
 
 def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega, use_initial_guess,
              diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0, adjoint=False,
              init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0, forcing=1e-2,
-             max_krylov=100) -> L.Options:
+             max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0) -> L.Options:
     o = L.Options()
     lib.pt_options_default(C.byref(o))
     o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
@@ -98,6 +100,7 @@ def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc
     o.init_tol = float(init_tol)
     o.stop_relative_initial = 1 if stop_relative_initial else 0
     o.krylov_dim, o.forcing, o.max_krylov = int(krylov_dim), float(forcing), int(max_krylov)
+    o.inner_rtol, o.breakdown_tol = float(inner_rtol), float(breakdown_tol)
     return o
 
 
@@ -124,7 +127,8 @@ class _StatsBuf:
                           kernel_ms={names[i]: self.kms[i] for i in range(n) if self.kcnt[i]},
                           kernel_launches={names[i]: int(self.kcnt[i]) for i in range(n) if self.kcnt[i]},
                           converged_at=s.converged_at, init_iters=s.init_iters, rel_initial=s.rel_initial,
-                          krylov_iters=s.krylov_iters)
+                          krylov_iters=s.krylov_iters, inner_iters_max=s.inner_iters_max,
+                          inner_iters_sum=s.inner_iters_sum)
 
 
 class Plan:
@@ -134,7 +138,8 @@ class Plan:
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
                  adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0,
-                 forcing=1e-2, max_krylov=100, theta=None, sigma=None, load=None, device=None):
+                 forcing=1e-2, max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, theta=None, sigma=None,
+                 load=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -146,7 +151,8 @@ class Plan:
         self._ps = problem_struct(problem, theta, sigma, load)
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
                      use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
-                     init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov)
+                     init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov, inner_rtol,
+                     breakdown_tol)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -373,7 +379,7 @@ class BatchPlan(Plan):
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
                  adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0,
-                 forcing=1e-2, max_krylov=100, device=None):
+                 forcing=1e-2, max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, device=None):
         import torch
         problems = list(problems)
         self.lib = L.load()
@@ -388,7 +394,8 @@ class BatchPlan(Plan):
         self._pa = (L.Problem * self.count)(*[problem_struct(p) for p in problems])
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
                      use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
-                     init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov)
+                     init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov, inner_rtol,
+                     breakdown_tol)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create_batch(self._pa, self.count, C.byref(o), C.byref(h))

@@ -48,7 +48,7 @@ class Options(C.Structure):
         ("grid_slot", C.c_int32), ("grid_team", C.c_int32), ("adjoint", C.c_int32),
         ("init_static", C.c_int32), ("init_tol", C.c_double), ("stop_relative_initial", C.c_int32),
         ("krylov_dim", C.c_int32), ("forcing", C.c_double), ("max_krylov", C.c_int32),
-        ("graph", C.c_int32),
+        ("graph", C.c_int32), ("inner_rtol", C.c_double), ("breakdown_tol", C.c_double),
     ]
 
 
@@ -59,7 +59,7 @@ class Stats(C.Structure):
         ("history_cap", C.c_int32), ("history_len", C.c_int32),
         ("kernel_ms", C.POINTER(C.c_double)), ("kernel_launches", C.POINTER(C.c_int64)),
         ("converged_at", C.c_int32), ("init_iters", C.c_int32), ("rel_initial", C.c_double),
-        ("krylov_iters", C.c_int32),
+        ("krylov_iters", C.c_int32), ("inner_iters_max", C.c_int32), ("inner_iters_sum", C.c_int64),
     ]
 
 

@@ -150,6 +150,9 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (o->inner != PT_INNER_GALERKIN1 && o->inner != PT_INNER_COCG) return fail(PT_ERR_INVALID, "unknown inner method");
     if (o->inner_iters < 1 || o->inner_iters > 64) return fail(PT_ERR_INVALID, "inner_iters must be in [1, 64]");
     if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused V(1,1) cycle)");
+    if (!(o->inner_rtol >= 0 && o->inner_rtol < 1)) return fail(PT_ERR_INVALID, "inner_rtol must be in [0, 1)");
+    if (!(o->breakdown_tol >= 0) || !std::isfinite(o->breakdown_tol))
+        return fail(PT_ERR_INVALID, "breakdown_tol must be finite and >= 0");
     if (!(o->vc_omega > 0 && o->vc_omega < 1)) return fail(PT_ERR_INVALID, "vc_omega must be in (0, 1)");
     if (o->adjoint != 0 && o->adjoint != 1) return fail(PT_ERR_INVALID, "adjoint must be 0 or 1");
     if (o->init_static != 0 && o->init_static != 1) return fail(PT_ERR_INVALID, "init_static must be 0 or 1");
@@ -224,8 +227,13 @@ static void layout(Plan& p) {
         p.off_cr = take(v);
         p.off_cq = take(v);
         p.off_cp = take(v);
+        // r^H r partials of the vector kernels with their stage-1 tail; five per-slot double2
+        // arrays (nr, thr, act, rho, coef) and the active-component counter
+        p.off_npart = take((size_t)(cocg_rows(p) + kReduceRows) * S * 3 * sizeof(double));
+        p.off_caux = take(5 * S * 2 * sizeof(double) + 16);
     } else {
         p.off_cx = p.off_cr = p.off_cq = p.off_cp = 0;
+        p.off_npart = p.off_caux = 0;
     }
     p.off_flags = take(B * 2 * (size_t)p.n * p.n);
     p.off_b = take(B * p.nodes * sizeof(double));
@@ -353,16 +361,14 @@ static pt_status setup(Plan& p, char* ws, hipStream_t st) {
 
 // Approximate X = (Khat + z M)^{-1} Rhat for every slot. On return *X and *coef describe
 // the correction coef (x) X (coef NULL means identity).
-static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const void** X, const double** coef) {
+static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const void** X, const double** coef,
+                             bool capture = false) {
     double* part = (double*)(ws + p.off_part);
     double2* cf = (double2*)(ws + p.off_coef);
     const size_t S = p.ST;
     double* num = (double*)(cf + 0 * S);
     double* den = (double*)(cf + 1 * S);
     double* alpha = (double*)(cf + 2 * S);
-    double* rho = (double*)(cf + 3 * S);
-    double* rho2 = (double*)(cf + 4 * S);
-    double* beta = (double*)(cf + 5 * S);
     int* flag = (int*)(ws + p.off_flag);
     void* R = ws + p.lev[0].off_r;
     void* P = ws + p.off_P;
@@ -374,33 +380,59 @@ static pt_status inner_solve(Plan& p, char* ws, hipStream_t st, int iters, const
         TM(KID_MATVEC, launch_matvec(p, ws, P, nullptr, DOT_HERM, part_b, st));
         TM(KID_REDUCE, launch_reduce_ratio(p, part, p.g_slot0.blocks, part_b, p.g_mv.blocks, DOT_HERM, num, den, alpha,
                                            st));
+        p.inner_done = 1;
         *X = P;
         *coef = alpha;
         return PT_OK;
     }
-    // COCG from zero: x = 0, r = Rhat, z = B r, p = z, rho = r^T z
+    // COCG from zero (x = 0, r = Rhat, z = B r, p = z, rho = r^T z), per frequency until
+    // ||r_k|| <= inner_rtol ||Rhat_k|| (then masked: alpha = beta = 0, so x_k and r_k stay as
+    // they are) or `iters` steps. Slot 0's two real systems are tested and masked apart.
     void* x = ws + p.off_cx;
     void* r = ws + p.off_cr;
     void* q = ws + p.off_cq;
     void* pv = ws + p.off_cp;
     void* z = P;
+    double* npart = (double*)(ws + p.off_npart);
+    double2* aux = (double2*)(ws + p.off_caux);
+    CocgScalars cs;
+    cs.nr = (double*)(aux + 0 * S);
+    cs.thr = (double*)(aux + 1 * S);
+    cs.act = (double*)(aux + 2 * S);
+    cs.rho = (double*)(aux + 3 * S);
+    cs.coef = (double*)(aux + 4 * S);
+    cs.count = (int*)(aux + 5 * S);
+    cs.flag = flag;
+    cs.eta2 = p.opt.inner_rtol * p.opt.inner_rtol;
+    cs.btol = p.opt.breakdown_tol > 0 ? p.opt.breakdown_tol : (p.fp32 ? 64.0 * 5.96e-8 : 64.0 * 1.11e-16);
+    const int nrows = cocg_rows(p);
+    const bool early = p.opt.inner_rtol > 0 && !capture;  // host test between steps (not in a graph)
     TM(KID_MEMSET, launch_zero16(x, p.nodes * S * p.elem, st));
-    TM(KID_COCG, launch_copy_slots(p, R, r, st));
+    TM(KID_COCG, launch_cocg_vec(p, 1, nullptr, nullptr, r, R, nullptr, npart, st));
+    TM(KID_REDUCE, launch_cocg_reduce(p, npart, nrows, COCG_NORM0, cs, st));
     launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
-    TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_slot0.blocks, DOT_BILIN, rho, st));
+    TM(KID_REDUCE, launch_cocg_reduce(p, part, p.g_slot0.blocks, COCG_RHO, cs, st));
     TM(KID_COCG, launch_copy_slots(p, z, pv, st));
+    int done = 0;
     for (int it = 0; it < iters; ++it) {
         TM(KID_MATVEC, launch_matvec(p, ws, pv, q, DOT_BILIN, part, st));
-        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_mv.blocks, DOT_BILIN, den, st));
-        TM(KID_REDUCE, launch_slot_div(p, rho, den, alpha, flag, st));
-        TM(KID_COCG, launch_cocg_xr(p, alpha, x, r, pv, q, st));
+        TM(KID_REDUCE, launch_cocg_reduce(p, part, p.g_mv.blocks, COCG_ALPHA, cs, st));
+        TM(KID_COCG, launch_cocg_vec(p, 0, cs.coef, x, r, pv, q, npart, st));
+        TM(KID_MEMSET, launch_zero16(cs.count, 16, st));
+        TM(KID_REDUCE, launch_cocg_reduce(p, npart, nrows, COCG_NORM, cs, st));
+        done = it + 1;
+        if (early) {
+            int active = 0;
+            PT_HIP(hipMemcpyAsync(&active, cs.count, sizeof(int), hipMemcpyDeviceToHost, st));
+            PT_HIP(hipStreamSynchronize(st));
+            if (active == 0) break;
+        }
         if (it + 1 == iters) break;
         launch_vcycle(p, ws, r, z, DOT_BILIN, part, st);
-        TM(KID_REDUCE, launch_reduce_dots(p, part, p.g_slot0.blocks, DOT_BILIN, rho2, st));
-        TM(KID_REDUCE, launch_slot_div(p, rho2, rho, beta, nullptr, st));
-        TM(KID_COCG, launch_cocg_p(p, beta, z, pv, st));
-        TM(KID_COCG, launch_copy16(rho2, rho, S * sizeof(double2), st));
+        TM(KID_REDUCE, launch_cocg_reduce(p, part, p.g_slot0.blocks, COCG_BETA, cs, st));
+        TM(KID_COCG, launch_cocg_p(p, cs.coef, z, pv, st));
     }
+    p.inner_done = done;
     *X = x;
     *coef = nullptr;
     PT_HIP(hipGetLastError());
@@ -417,6 +449,8 @@ struct GraphCache {
     char* ws = nullptr;  // workspace the graph's kernel arguments point into
     int steps = 0;
     bool adjoint = false;
+    long long inner_per_launch = 0;  // inner steps of the captured segment
+    int inner_max = 0;
 };
 
 void graph_release(Plan& p) {
@@ -449,12 +483,14 @@ static void residual_step(Plan& p, char* ws, bool adjoint, hipStream_t st) {
 // One fixed-point update once the residual of the iterate is in Rhat (eq. (iter2) in
 // correction form, U^{k+1} = U^k + P^{-1} R^k; for the adjoint with the transposed P),
 // followed by the residual of the new iterate and its norm partials.
-static pt_status outer_segment(Plan& p, char* ws, bool adjoint, hipStream_t st) {
+static pt_status outer_segment(Plan& p, char* ws, bool adjoint, hipStream_t st, bool capture = false) {
     double* X0 = (double*)(ws + (adjoint ? p.off_L : p.off_U));
     const void* X = nullptr;
     const double* coef = nullptr;
-    pt_status s = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
+    pt_status s = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef, capture);
     if (s != PT_OK) return s;
+    p.inner_max = std::max(p.inner_max, p.inner_done);
+    p.inner_sum += p.inner_done;
     TM(KID_INVERSE, launch_inverse(p, ws, X, coef, X0, 1, st, adjoint ? 1 : 0));
     residual_step(p, ws, adjoint, st);
     return PT_OK;
@@ -477,7 +513,16 @@ static pt_status graph_get(Plan& p, char* ws, int steps, bool adjoint, hipGraphE
     g->graph = nullptr;
     PT_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
     pt_status s = PT_OK;
-    for (int i = 0; i < steps && s == PT_OK; ++i) s = outer_segment(p, ws, adjoint, g->cap);
+    // the capture only records the launches: the inner-step counters are restored and every
+    // replay adds the captured segment's steps
+    const long long sum0 = p.inner_sum;
+    const int max0 = p.inner_max;
+    p.inner_max = 0;
+    for (int i = 0; i < steps && s == PT_OK; ++i) s = outer_segment(p, ws, adjoint, g->cap, true);
+    g->inner_per_launch = p.inner_sum - sum0;
+    g->inner_max = p.inner_max;
+    p.inner_sum = sum0;
+    p.inner_max = max0;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(g->cap, &graph);
     if (s != PT_OK) {
@@ -525,6 +570,8 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
     }
     s = timer_start(p);
     if (s != PT_OK) return s;
+    p.inner_max = 0;
+    p.inner_sum = 0;
     if (!no_alloc) PT_HIP(hipEventRecord(ev.e0, st));
     s = setup(p, ws, st);
     if (s != PT_OK) return s;
@@ -616,6 +663,8 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
                 pt_status g = graph_get(p, ws, ce, adjoint, &exec);
                 if (g != PT_OK) return g;
                 PT_HIP(hipGraphLaunch(exec, st));
+                p.inner_sum += p.gr->inner_per_launch;
+                p.inner_max = std::max(p.inner_max, p.gr->inner_max);
                 k += ce;
             } else {
                 pt_status g = outer_segment(p, ws, adjoint, st);
@@ -668,6 +717,8 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
             o.converged_at = conv[b];
             o.init_iters = init_iters;
             o.rel_initial = fnorm[b] > 0 ? d0[b] / fnorm[b] : d0[b];
+            o.inner_iters_max = p.inner_max;
+            o.inner_iters_sum = p.inner_sum;
             for (int c = 0; c < KID_COUNT; ++c) {
                 if (o.kernel_ms) o.kernel_ms[c] = p.tm ? p.tm->ms[c] : 0.0;
                 if (o.kernel_launches) o.kernel_launches[c] = p.tm ? p.tm->cnt[c] : 0;
@@ -692,6 +743,8 @@ static pt_status newton_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, 
     PT_HIP(hipEventCreate(&ev.e1));
     s = timer_start(p);
     if (s != PT_OK) return s;
+    p.inner_max = 0;
+    p.inner_sum = 0;
     PT_HIP(hipEventRecord(ev.e0, st));
     s = setup(p, ws, st);
     if (s != PT_OK) return s;
@@ -739,6 +792,8 @@ static pt_status newton_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, 
         const double* coef = nullptr;
         pt_status q = inner_solve(p, ws, st, p.opt.inner_iters, &X, &coef);
         if (q != PT_OK) return q;
+        p.inner_max = std::max(p.inner_max, p.inner_done);
+        p.inner_sum += p.inner_done;
         launch_inverse(p, ws, X, coef, z, 0, st);
         return PT_OK;
     };
@@ -870,6 +925,8 @@ static pt_status newton_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, 
         stats->init_iters = 0;
         stats->rel_initial = f > 0 ? d0 / f : d0;
         stats->krylov_iters = kry;
+        stats->inner_iters_max = p.inner_max;
+        stats->inner_iters_sum = p.inner_sum;
         for (int c = 0; c < KID_COUNT; ++c) {
             if (stats->kernel_ms) stats->kernel_ms[c] = p.tm ? p.tm->ms[c] : 0.0;
             if (stats->kernel_launches) stats->kernel_launches[c] = p.tm ? p.tm->cnt[c] : 0;

@@ -906,43 +906,24 @@ __device__ __forceinline__ double2 dots_combine(double s1, double s2, double s3,
     return r;
 }
 
-// coef = num / den in generic arithmetic. A zero denominator with a zero numerator (a
-// frequency whose right-hand side vanishes) gives 0; a vanishing denominator with a
-// nonzero numerator sets *flag (COCG breakdown) and gives 0.
-__device__ __forceinline__ double2 slot_ratio(double2 a, double2 b, int s, int Si, int* flag) {
-    {
-        double2 r;
-        if ((s & (Si - 1)) == 0) {
-            r.x = (b.x != 0.0) ? a.x / b.x : 0.0;
-            r.y = (b.y != 0.0) ? a.y / b.y : 0.0;
-            if (flag && ((b.x == 0.0 && a.x != 0.0) || (b.y == 0.0 && a.y != 0.0))) *flag = 1;
-        } else {
-            double d = b.x * b.x + b.y * b.y;
-            if (d != 0.0) {
-                r.x = (a.x * b.x + a.y * b.y) / d;
-                r.y = (a.y * b.x - a.x * b.y) / d;
-            } else {
-                r.x = 0.0;
-                r.y = 0.0;
-                if (flag && (a.x != 0.0 || a.y != 0.0)) *flag = 1;
-            }
-        }
-        return r;
+// coef = num / den in generic arithmetic (the Galerkin step's ratio p^H r / p^H A p, whose
+// denominator has a positive real part for a nonzero p). A zero denominator gives 0: it occurs
+// only for p = 0, i.e. a frequency whose right-hand side vanishes.
+__device__ __forceinline__ double2 slot_ratio(double2 a, double2 b, int s, int Si) {
+    double2 r;
+    if ((s & (Si - 1)) == 0) {
+        r.x = (b.x != 0.0) ? a.x / b.x : 0.0;
+        r.y = (b.y != 0.0) ? a.y / b.y : 0.0;
+    } else {
+        double d = b.x * b.x + b.y * b.y;
+        r.x = d != 0.0 ? (a.x * b.x + a.y * b.y) / d : 0.0;
+        r.y = d != 0.0 ? (a.y * b.x - a.x * b.y) / d : 0.0;
     }
-}
-
-__global__ void __launch_bounds__(kBlock) k_slot_div(const double* num_, const double* den_, double* coef_, int S,
-                                                     int Si, int* flag) {
-    const double2* num = (const double2*)num_;
-    const double2* den = (const double2*)den_;
-    double2* coef = (double2*)coef_;
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < S; s += gridDim.x * kBlock)
-        coef[s] = slot_ratio(num[s], den[s], s, Si, flag);
+    return r;
 }
 
 // Stage 2 of one reduction (out = rows of pa), or of two and their ratio in one launch (RATIO:
-// outa = rows of pa, outb = rows of pb, coef = outa / outb per slot, as k_slot_div without a
-// flag).
+// outa = rows of pa, outb = rows of pb, coef = outa / outb per slot).
 template <bool RATIO>
 __global__ void __launch_bounds__(kBlock) k_reduce_dots2(const double* pa, int RBa, const double* pb, int RBb, int S,
                                                          int Si, int herm, double* outa, double* outb, double* coef) {
@@ -979,26 +960,61 @@ __global__ void __launch_bounds__(kBlock) k_reduce_dots2(const double* pa, int R
         if (RATIO) {
             const double2 b = dots_combine(t[3], t[4], t[5], s, Si, herm);
             ((double2*)outb)[s] = b;
-            ((double2*)coef)[s] = slot_ratio(a, b, s, Si, nullptr);
+            ((double2*)coef)[s] = slot_ratio(a, b, s, Si);
         }
     }
 }
 
 // ---------------------------------------------------------------- COCG vector updates
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cocg_xr(int S, int Si, size_t total, const double* coef, void* x_,
-                                                    void* r_, const void* p_, const void* q_) {
+// Workgroup (bx, cy) of the COCG vector kernels covers the slots [cy SC, cy SC + SC) with
+// SC = min(ST, kBlock), at the nodes bx NL + nl + k Gx NL (NL = kBlock / SC node lanes per
+// slot, Gx = gridDim.x), so every thread keeps one slot. The kernel leaves the squares of the
+// new r per slot in part[(bx ST + s) 3 + {0, 1, 2}] = (sum r.x^2, sum r.y^2, 0): the
+// Hermitian partials of r^H r (slot 0: the two real systems' squares apart), reduced like the
+// other dot partials. CV_XR: x += a (x) p, r -= a (x) q. CV_COPY: r = p.
+enum CocgVecMode { CV_XR = 0, CV_COPY = 1 };
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_cocg_vec(int ST, int Si, size_t nodes, const double* coef, void* x_,
+                                                     void* r_, const void* p_, const void* q_, double* part) {
     using T2 = typename Vec2<T>::type;
+    __shared__ double red[2][kBlock];
+    const int SC = ST < kBlock ? ST : kBlock, NL = kBlock / SC;
+    const int ls = threadIdx.x % SC, nl = threadIdx.x / SC;
+    const int s = blockIdx.y * SC + ls;
     T2* x = (T2*)x_;
     T2* r = (T2*)r_;
     const T2* p = (const T2*)p_;
     const T2* q = (const T2*)q_;
-    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
-        int s = (int)(id % S);
-        GS<T> g = gs_from<T>(((const double2*)coef)[s], (s & (Si - 1)) == 0);
-        x[id] = add2(x[id], gs_apply(g, p[id]));
-        r[id] = sub2(r[id], gs_apply(g, q[id]));
+    GS<T> g{};
+    if (MODE == CV_XR) g = gs_from<T>(((const double2*)coef)[s], (s & (Si - 1)) == 0);
+    double a0 = 0.0, a1 = 0.0;
+    for (size_t nd = (size_t)blockIdx.x * NL + nl; nd < nodes; nd += (size_t)gridDim.x * NL) {
+        const size_t id = nd * ST + s;
+        T2 rn;
+        if (MODE == CV_XR) {
+            x[id] = add2(x[id], gs_apply(g, p[id]));
+            rn = sub2(r[id], gs_apply(g, q[id]));
+        } else {
+            rn = p[id];
+        }
+        r[id] = rn;
+        a0 += (double)rn.x * (double)rn.x;
+        a1 += (double)rn.y * (double)rn.y;
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    __syncthreads();
+    if (nl == 0) {
+        for (int l = 1; l < NL; ++l) {  // node lanes added in lane order
+            a0 += red[0][l * SC + ls];
+            a1 += red[1][l * SC + ls];
+        }
+        double* o = part + ((size_t)blockIdx.x * ST + s) * 3;
+        o[0] = a0;
+        o[1] = a1;
+        o[2] = 0.0;
     }
 }
 
@@ -1012,6 +1028,114 @@ __global__ void __launch_bounds__(kBlock) k_cocg_p(int S, int Si, size_t total, 
         int s = (int)(id % S);
         GS<T> g = gs_from<T>(((const double2*)coef)[s], (s & (Si - 1)) == 0);
         p[id] = add2(z[id], gs_apply(g, p[id]));
+    }
+}
+
+// Stage 2 of the COCG reductions: the rows of part2 summed per slot as in k_reduce_dots2
+// (kS2Lanes lanes per slot, lane sums added in lane order), then per slot s, with the
+// components c = .x, .y of slot 0 (the real systems k = 0 and k = N/2) treated apart and one
+// complex value for s >= 1:
+//   COCG_NORM0: nr = r^H r, thr = eta2 nr, act = [nr > 0]           (start: r = the right-hand side)
+//   COCG_NORM:  act = act and [nr > thr]; *count += active components (the caller zeroes it)
+//   COCG_ALPHA: den = p^T A p, alpha = rho / den where active, 0 elsewhere; *flag = 1 if an active
+//             component has |den| <= btol Re(p^H A p) (breakdown of the bilinear form)
+//   COCG_RHO:   rho = r^T z
+//   COCG_BETA:  beta = r^T z / rho where active, 0 elsewhere; rho = r^T z
+// v holds (nr, thr, act) for the norm ops and (rho, alpha or beta) otherwise.
+
+struct CocgScal {
+    double2* nr;     // r^H r per component
+    double2* thr;    // eta^2 ||Rhat||^2 per component
+    double2* act;    // 1 = active, 0 = converged (masked)
+    double2* rho;    // r^T z
+    double2* coef;   // alpha or beta
+    int* count;      // active components after COCG_NORM
+    int* flag;       // breakdown
+    double eta2, btol;
+};
+
+__device__ __forceinline__ double2 gen_div(double2 a, double2 b, bool s0) {
+    double2 r;
+    if (s0) {
+        r.x = b.x != 0.0 ? a.x / b.x : 0.0;
+        r.y = b.y != 0.0 ? a.y / b.y : 0.0;
+    } else {
+        const double d = b.x * b.x + b.y * b.y;
+        r.x = d != 0.0 ? (a.x * b.x + a.y * b.y) / d : 0.0;
+        r.y = d != 0.0 ? (a.y * b.x - a.x * b.y) / d : 0.0;
+    }
+    return r;
+}
+
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_cocg_stage2(const double* pa, int RB, int S, int Si, CocgScal c) {
+    __shared__ double red[3][kBlock];
+    const int ln = threadIdx.x % kS2Lanes;
+    const int s = blockIdx.x * (kBlock / kS2Lanes) + threadIdx.x / kS2Lanes;
+    double v[3] = {0, 0, 0};
+    if (s < S) {
+        for (int b = ln; b < RB; b += kS2Lanes) {
+            const double* o = pa + ((size_t)b * S + s) * 3;
+            v[0] += o[0];
+            v[1] += o[1];
+            v[2] += o[2];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    if (ln != 0 || s >= S) return;
+    double t[3] = {0, 0, 0};
+    for (int l = 0; l < kS2Lanes; ++l)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t[k] += red[k][threadIdx.x + l];
+    const bool s0 = (s & (Si - 1)) == 0;
+    if (OP == COCG_NORM0 || OP == COCG_NORM) {
+        const double2 nr = s0 ? make_double2(t[0], t[1]) : make_double2(t[0] + t[1], t[0] + t[1]);
+        c.nr[s] = nr;
+        double2 act;
+        if (OP == COCG_NORM0) {
+            c.thr[s] = make_double2(c.eta2 * nr.x, c.eta2 * nr.y);
+            act = make_double2(nr.x > 0.0 ? 1.0 : 0.0, nr.y > 0.0 ? 1.0 : 0.0);
+        } else {
+            const double2 th = c.thr[s], a = c.act[s];
+            act = make_double2((a.x != 0.0 && nr.x > th.x) ? 1.0 : 0.0, (a.y != 0.0 && nr.y > th.y) ? 1.0 : 0.0);
+            const int n = s0 ? (int)act.x + (int)act.y : (int)act.x;
+            if (n) atomicAdd(c.count, n);
+        }
+        if (!s0) act.y = act.x;
+        c.act[s] = act;
+        return;
+    }
+    // bilinear combine of the partials (slot 0: the two real dot products)
+    const double2 bl = s0 ? make_double2(t[0], t[1]) : make_double2(t[0] - t[1], t[2]);
+    const double2 act = c.act[s];
+    if (OP == COCG_ALPHA) {
+        double2 al = gen_div(c.rho[s], bl, s0);
+        if (s0) {
+            const bool bx = act.x != 0.0 && fabs(bl.x) <= c.btol * fabs(t[0]);
+            const bool by = act.y != 0.0 && fabs(bl.y) <= c.btol * fabs(t[1]);
+            if (bx || by) *c.flag = 1;
+            al.x = (act.x != 0.0 && !bx) ? al.x : 0.0;
+            al.y = (act.y != 0.0 && !by) ? al.y : 0.0;
+        } else {
+            const bool bk = act.x != 0.0 && sqrt(bl.x * bl.x + bl.y * bl.y) <= c.btol * (t[0] + t[1]);
+            if (bk) *c.flag = 1;
+            if (act.x == 0.0 || bk) al = make_double2(0.0, 0.0);
+        }
+        c.coef[s] = al;
+    } else if (OP == COCG_RHO) {
+        c.rho[s] = bl;
+    } else {
+        double2 be = gen_div(bl, c.rho[s], s0);
+        if (s0) {
+            be.x = act.x != 0.0 ? be.x : 0.0;
+            be.y = act.y != 0.0 ? be.y : 0.0;
+        } else if (act.x == 0.0) {
+            be = make_double2(0.0, 0.0);
+        }
+        c.coef[s] = be;
+        c.rho[s] = bl;
     }
 }
 
@@ -1205,20 +1329,70 @@ void launch_reduce_ratio(const Plan& p, double* pa, int na, double* pb, int nb, 
                        (const double*)b.part2, b.RB, p.ST, p.S, dotmode == DOT_HERM ? 1 : 0, num, den, coef);
 }
 
-void launch_slot_div(const Plan& p, const double* num, const double* den, double* coef, int* flag, hipStream_t st) {
-    int grid = (p.ST + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_slot_div, dim3(grid), dim3(kBlock), 0, st, num, den, coef, p.ST, p.S, flag);
+// Workgroups along the nodes of the COCG vector kernels (rows of their norm partials).
+int cocg_rows(const Plan& p) {
+    const int SC = p.ST < kBlock ? p.ST : kBlock, NL = kBlock / SC, CY = p.ST / SC;
+    long gx = 8192 / CY;
+    const long need = (long)((p.nodes + NL - 1) / NL);
+    if (gx > need) gx = need;
+    if (gx > kCocgRows) gx = kCocgRows;
+    return gx < 1 ? 1 : (int)gx;
 }
 
-void launch_cocg_xr(const Plan& p, const double* coef, void* x, void* r, const void* pv, const void* q,
-                    hipStream_t st) {
-    size_t total = p.nodes * (size_t)p.ST;
-    if (p.fp32)
-        hipLaunchKernelGGL(k_cocg_xr<float>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.ST, p.S, total, coef, x, r,
-                           pv, q);
-    else
-        hipLaunchKernelGGL(k_cocg_xr<double>, dim3(flat_grid(total)), dim3(kBlock), 0, st, p.ST, p.S, total, coef, x,
-                           r, pv, q);
+void launch_cocg_vec(const Plan& p, int mode, const double* coef, void* x, void* r, const void* src, const void* q,
+                     double* part, hipStream_t st) {
+    const int SC = p.ST < kBlock ? p.ST : kBlock;
+    dim3 grid(cocg_rows(p), p.ST / SC);
+    if (p.fp32) {
+        if (mode == CV_XR)
+            hipLaunchKernelGGL((k_cocg_vec<float, CV_XR>), grid, dim3(kBlock), 0, st, p.ST, p.S, p.nodes, coef, x, r,
+                               src, q, part);
+        else
+            hipLaunchKernelGGL((k_cocg_vec<float, CV_COPY>), grid, dim3(kBlock), 0, st, p.ST, p.S, p.nodes, coef, x,
+                               r, src, q, part);
+    } else {
+        if (mode == CV_XR)
+            hipLaunchKernelGGL((k_cocg_vec<double, CV_XR>), grid, dim3(kBlock), 0, st, p.ST, p.S, p.nodes, coef, x, r,
+                               src, q, part);
+        else
+            hipLaunchKernelGGL((k_cocg_vec<double, CV_COPY>), grid, dim3(kBlock), 0, st, p.ST, p.S, p.nodes, coef, x,
+                               r, src, q, part);
+    }
+}
+
+void launch_cocg_reduce(const Plan& p, double* part, int nblk, int op, const CocgScalars& cs, hipStream_t st) {
+    const Dots1Set d = dots1_set(p, part, nblk);
+    const int SG = p.ST < 64 ? p.ST : 64;
+    hipLaunchKernelGGL(k_reduce_dots1, dim3((p.ST + SG - 1) / SG, d.RB, 1), dim3(kBlock), 0, st, d, d, p.ST);
+    CocgScal c;
+    c.nr = (double2*)cs.nr;
+    c.thr = (double2*)cs.thr;
+    c.act = (double2*)cs.act;
+    c.rho = (double2*)cs.rho;
+    c.coef = (double2*)cs.coef;
+    c.count = cs.count;
+    c.flag = cs.flag;
+    c.eta2 = cs.eta2;
+    c.btol = cs.btol;
+    const int grid = (p.ST + kBlock / kS2Lanes - 1) / (kBlock / kS2Lanes);
+    const double* p2 = d.part2;
+    switch (op) {
+        case COCG_NORM0:
+            hipLaunchKernelGGL(k_cocg_stage2<COCG_NORM0>, dim3(grid), dim3(kBlock), 0, st, p2, d.RB, p.ST, p.S, c);
+            break;
+        case COCG_NORM:
+            hipLaunchKernelGGL(k_cocg_stage2<COCG_NORM>, dim3(grid), dim3(kBlock), 0, st, p2, d.RB, p.ST, p.S, c);
+            break;
+        case COCG_ALPHA:
+            hipLaunchKernelGGL(k_cocg_stage2<COCG_ALPHA>, dim3(grid), dim3(kBlock), 0, st, p2, d.RB, p.ST, p.S, c);
+            break;
+        case COCG_RHO:
+            hipLaunchKernelGGL(k_cocg_stage2<COCG_RHO>, dim3(grid), dim3(kBlock), 0, st, p2, d.RB, p.ST, p.S, c);
+            break;
+        default:
+            hipLaunchKernelGGL(k_cocg_stage2<COCG_BETA>, dim3(grid), dim3(kBlock), 0, st, p2, d.RB, p.ST, p.S, c);
+            break;
+    }
 }
 
 void launch_cocg_p(const Plan& p, const double* coef, const void* z, void* pv, hipStream_t st) {

@@ -26,6 +26,7 @@ constexpr int kNumXcd = 8;
 constexpr int kReduceRows = 64;      // first-stage row groups of the dot-product reduction
 constexpr int kReduceBatch = 8;      // partials whose loads a reduction thread issues together
 constexpr int kAdjBlocks = 8192;     // workgroups of the grid-stride adjoint kernels
+constexpr int kCocgRows = 4096;      // workgroups along the nodes of the COCG vector kernels, at most
 constexpr int kRecDoubles = 16;      // residual-sweep record per node: mass row, load, reluctivity laws
 
 // Per-slot scalar in "generic" form: for slot s >= 1 a complex number (x + i y);
@@ -108,6 +109,10 @@ struct Plan {
     size_t off_U, off_F, off_P, off_cx, off_cr, off_cq, off_cp;
     size_t off_flags, off_b, off_tw64, off_tw32, off_zs, off_wave;
     size_t off_rec;     // per-instance, per-node records of the residual sweep (kRecDoubles doubles)
+    size_t off_npart, off_caux;  // COCG plans: r^H r partials, per-slot scalars and counter
+    int inner_done;              // inner steps of the last inner solve
+    int inner_max;               // most inner steps of one outer step in the current call
+    long long inner_sum;         // inner steps over the current call
     size_t off_part, part_bytes, off_scal, off_flag, off_coef, off_coef2, off_hist, off_inst;
     size_t off_L, off_G, off_sig;   // adjoint plans: adjoint iterate, dl/dU, per-triangle sigma
     size_t off_R, off_Ut, off_D, off_V, off_Z;  // Newton plans: residual, trial, step, Krylov bases
@@ -188,12 +193,19 @@ void launch_reduce_dots(const Plan& p, double* part, int nblk, int dotmode, doub
 // num, den = the reductions of the partials pa (na workgroups) and pb (nb workgroups); coef = num / den
 void launch_reduce_ratio(const Plan& p, double* pa, int na, double* pb, int nb, int dotmode, double* num, double* den,
                          double* coef, hipStream_t st);
-// coef = num / den (generic division), with breakdown flag written to flag (int) if |den| tiny
-void launch_slot_div(const Plan& p, const double* num, const double* den, double* coef,
-                     int* flag, hipStream_t st);
-// x += a (x) p ; r -= a (x) q
-void launch_cocg_xr(const Plan& p, const double* coef, void* x, void* r, const void* pv,
-                    const void* q, hipStream_t st);
+// COCG vector kernels: mode 0 (x += a (x) p, r -= a (x) q) or 1 (r = src), both leaving the
+// Hermitian partials of r^H r in part (cocg_rows(p) rows)
+void launch_cocg_vec(const Plan& p, int mode, const double* coef, void* x, void* r, const void* src,
+                     const void* q, double* part, hipStream_t st);
+int cocg_rows(const Plan& p);
+// per-slot COCG scalars (double2 arrays of ST entries) and their stage-2 reductions
+struct CocgScalars {
+    double *nr, *thr, *act, *rho, *coef;
+    int *count, *flag;
+    double eta2, btol;
+};
+enum CocgReduceOp { COCG_NORM0 = 0, COCG_NORM = 1, COCG_ALPHA = 2, COCG_RHO = 3, COCG_BETA = 4 };
+void launch_cocg_reduce(const Plan& p, double* part, int nblk, int op, const CocgScalars& cs, hipStream_t st);
 // p = z + b (x) p
 void launch_cocg_p(const Plan& p, const double* coef, const void* z, void* pv, hipStream_t st);
 void launch_copy_slots(const Plan& p, const void* src, void* dst, hipStream_t st);

@@ -226,3 +226,11 @@ def test_noalloc_solve_rejects_before_any_device_work(P):
         pl = P.Plan(W.config1(), **kw)
         assert lib.pt_solve_noalloc(pl._h, C.cast(dummy, C.c_void_p), None, None) == L.PT_ERR_INVALID
     assert lib.pt_solve_noalloc(None, C.cast(dummy, C.c_void_p), None, None) == L.PT_ERR_INVALID
+
+
+@pytest.mark.parametrize("kw", [dict(inner_rtol=-1e-3), dict(inner_rtol=1.0), dict(breakdown_tol=-1.0),
+                                dict(breakdown_tol=float("inf"))])
+def test_plan_rejects_invalid_inner_tolerances(P, kw):
+    with pytest.raises(P.PTError) as e:
+        P.Plan(W.config1(), inner="cocg", **kw)
+    assert e.value.status == -1
