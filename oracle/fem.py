@@ -96,16 +96,31 @@ class Materials:
     iron: np.ndarray      # (ntri,) bool: nonlinear law applies
     theta: np.ndarray     # (ntri,) nu scale
     J: np.ndarray         # (ntri,) current density amplitude
+    # Region mode: the law and its per-triangle parameters (None: the rectangle problem's law,
+    # nu_a + nu_b s^2/(1+s^2) in iron and nu_out elsewhere, from the Problem)
+    law: str = "rational"
+    a: np.ndarray = None
+    b: np.ndarray = None
+    c: np.ndarray = None
+    d: np.ndarray = None
 
 
 def materials(p: Problem, m: Mesh) -> Materials:
     ntri = m.tri.shape[0]
-    sigma = np.where(in_rect(m.centroid, p.sigma_rect), p.sigma_in, 0.0)
-    iron = in_rect(m.centroid, p.nu_rect)
-    J = np.where(in_rect(m.centroid, p.coil_rect), p.J0, 0.0)
     theta = np.ones(ntri) if p.theta is None else np.asarray(p.theta, dtype=np.float64)
     if theta.shape != (ntri,):
         raise ValueError("theta must have one entry per triangle")
+    if p.regions is not None:
+        # region mode (Sec. 4, "Test problem": sigma, the law and j piecewise constant per region)
+        from workloads import region_ids
+        rid = region_ids(p).astype(np.int64)
+        tab = lambda f: np.array([getattr(r, f) for r in p.regions], dtype=np.float64)[rid]
+        a = tab("a")
+        return Materials(sigma=tab("sigma"), iron=a != 0.0, theta=theta, J=tab("j"), law=p.law,
+                         a=a, b=tab("b"), c=tab("c"), d=tab("d"))
+    sigma = np.where(in_rect(m.centroid, p.sigma_rect), p.sigma_in, 0.0)
+    iron = in_rect(m.centroid, p.nu_rect)
+    J = np.where(in_rect(m.centroid, p.coil_rect), p.J0, 0.0)
     return Materials(sigma=sigma, iron=iron, theta=theta, J=J)
 
 
@@ -145,22 +160,58 @@ def restrict(A: sp.spmatrix, free: np.ndarray) -> sp.csr_matrix:
 
 # ---------------------------------------------------------------- nonlinear law
 
+def _saturation(mat: Materials) -> np.ndarray:
+    """s^2 at which exp(b s^2) reaches c (the exp-capped law saturates beyond it): ln(c)/b,
+    +inf where b = 0 (the law is the constant a + d there)."""
+    with np.errstate(divide="ignore"):
+        return np.where(mat.b > 0, np.log(mat.c) / np.where(mat.b > 0, mat.b, 1.0), np.inf)
+
+
 def nu_of_s2(s2: np.ndarray, mat: Materials, p: Problem) -> np.ndarray:
-    """Reluctivity per triangle: theta (nu_a + nu_b s^2/(1+s^2)) in iron, theta nu_out elsewhere."""
-    inside = p.nu_a + p.nu_b * s2 / (1.0 + s2)
-    return mat.theta * np.where(mat.iron, inside, p.nu_out)
+    """Reluctivity per triangle, theta times
+    rectangle problems:  nu_a + nu_b s^2/(1+s^2) in iron, nu_out elsewhere;
+    region "rational":   a + b s^2/(1+s^2);
+    region "expcap":     a min(exp(b s^2), c) + d (the law of Sec. 4)."""
+    if mat.a is None:
+        inside = p.nu_a + p.nu_b * s2 / (1.0 + s2)
+        return mat.theta * np.where(mat.iron, inside, p.nu_out)
+    if mat.law == "rational":
+        return mat.theta * (mat.a + mat.b * s2 / (1.0 + s2))
+    z = np.minimum(s2, _saturation(mat))
+    return mat.theta * (mat.a * np.minimum(np.exp(mat.b * z), mat.c) + mat.d)
 
 
 def dnu_ds2(s2: np.ndarray, mat: Materials, p: Problem) -> np.ndarray:
-    """d nu / d(s^2): theta nu_b / (1+s^2)^2 in iron, 0 elsewhere."""
-    return mat.theta * np.where(mat.iron, p.nu_b / (1.0 + s2) ** 2, 0.0)
+    """d nu / d(s^2): theta nu_b / (1+s^2)^2 in iron (rectangle problems), theta b / (1+s^2)^2
+    (region "rational"), theta a b exp(b s^2) below saturation and 0 from it on (region "expcap",
+    the right derivative at the kink)."""
+    if mat.a is None:
+        return mat.theta * np.where(mat.iron, p.nu_b / (1.0 + s2) ** 2, 0.0)
+    if mat.law == "rational":
+        return mat.theta * mat.b / (1.0 + s2) ** 2
+    below = s2 < _saturation(mat)
+    z = np.where(below, s2, 0.0)
+    return mat.theta * np.where(below, mat.a * mat.b * np.exp(mat.b * z), 0.0)
 
 
 def energy_density(s2: np.ndarray, mat: Materials, p: Problem) -> np.ndarray:
-    """W(s^2) with dW/d(s^2) = nu/2:  theta ((a+b) s^2/2 - (b/2) ln(1+s^2)) in iron,
-    theta nu_out s^2 / 2 elsewhere."""
-    inside = 0.5 * (p.nu_a + p.nu_b) * s2 - 0.5 * p.nu_b * np.log1p(s2)
-    return mat.theta * np.where(mat.iron, inside, 0.5 * p.nu_out * s2)
+    """W(s^2) with dW/d(s^2) = nu/2, W(0) = 0:
+    rectangle problems:  theta ((a+b) s^2/2 - (b/2) ln(1+s^2)) in iron, theta nu_out s^2/2 elsewhere;
+    region "rational":   theta ((a+b) s^2/2 - (b/2) ln(1+s^2));
+    region "expcap":     theta (d s^2 + a (exp(b z) - 1)/b + a c (s^2 - z)) / 2, z = min(s^2, ln(c)/b)
+                         (a s^2/2 in place of the exp term where b = 0)."""
+    if mat.a is None:
+        inside = 0.5 * (p.nu_a + p.nu_b) * s2 - 0.5 * p.nu_b * np.log1p(s2)
+        return mat.theta * np.where(mat.iron, inside, 0.5 * p.nu_out * s2)
+    if mat.law == "rational":
+        return mat.theta * (0.5 * (mat.a + mat.b) * s2 - 0.5 * mat.b * np.log1p(s2))
+    zs = _saturation(mat)
+    z = np.minimum(s2, zs)
+    bpos = mat.b > 0
+    bb = np.where(bpos, mat.b, 1.0)
+    expint = np.where(bpos, np.expm1(bb * np.where(bpos, z, 0.0)) / bb, z)   # int_0^z exp(b t) dt
+    cap = np.where(np.isfinite(zs), mat.c * (s2 - z), 0.0)     # int_z^s2 c dt
+    return mat.theta * 0.5 * (mat.d * s2 + mat.a * (expint + cap))
 
 
 def gradients(m: Mesh, U: np.ndarray) -> np.ndarray:
@@ -217,9 +268,15 @@ class Discretisation:
     M: sp.csr_matrix      # free x free, sigma mass
     b: np.ndarray         # free, load amplitude
     free_idx: np.ndarray
+    # per-triangle coefficient of Khat (None: Khat = nu_max S, the constant coefficient)
+    khat_coef: np.ndarray = None
 
     @property
     def Khat(self) -> sp.csr_matrix:
+        """The linear operator of eqs. (iter1)-(iter2): nu_max S, or the stiffness with the
+        per-triangle coefficient khat_coef (a per-region choice in the family of Thm. thm:iter)."""
+        if self.khat_coef is not None:
+            return restrict(stiffness_full(self.mesh, self.khat_coef), self.mesh.free)
         return (self.p.nu_max * self.S).tocsr()
 
     @property

@@ -32,8 +32,8 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "Rect", "Problem", "config1", "config2", "config3", "config4", "config5",
-    "with_size", "random_field", "manufactured_coeffs", "CONFIG1_TOL",
+    "Rect", "Region", "Problem", "config1", "config2", "config3", "config4", "config5", "transformer",
+    "region_ids", "with_size", "random_field", "manufactured_coeffs", "CONFIG1_TOL",
 ]
 
 
@@ -47,6 +47,19 @@ class Rect:
 
     def as_tuple(self) -> Tuple[float, float, float, float]:
         return (self.x0, self.y0, self.x1, self.y1)
+
+
+@dataclass(frozen=True)
+class Region:
+    """Material of one region of a cross-section (Sec. 4, table tab:coef): conductivity sigma,
+    parameters a, b, c, d of the reluctivity law and current-density amplitude j."""
+    name: str
+    sigma: float = 0.0
+    a: float = 0.0
+    b: float = 0.0
+    c: float = 1.0
+    d: float = 1.0
+    j: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -71,6 +84,14 @@ class Problem:
     nu_max: float = 10.0
     # Optional per-triangle nu scale theta (length 2 n^2, ordering tri = 2 (j n + i) + {0, 1}).
     theta: Optional[np.ndarray] = field(default=None, compare=False, repr=False)
+    # Region mode (when `regions` is set): the rectangles above are not used; each triangle
+    # belongs to the region of the last rectangle of `layout` containing its centroid, and takes
+    # that region's conductivity, current amplitude and law parameters. `law` selects the
+    # reluctivity law of every region: "rational" nu = a + b s^2/(1+s^2), "expcap"
+    # nu = a min(exp(b s^2), c) + d (the law of Sec. 4).
+    law: str = "rational"
+    regions: Optional[Tuple[Region, ...]] = None
+    layout: Optional[Tuple[Tuple[Rect, int], ...]] = None
 
     @property
     def tau(self) -> float:
@@ -145,6 +166,75 @@ def config5(seed: int = 0, n: int = 256, N: int = 256) -> Problem:
     cell = np.exp(rng.normal(0.0, 0.1, n * n))
     theta = np.repeat(cell, 2)
     return Problem(n=n, N=N, theta=theta)
+
+
+def region_ids(p: Problem) -> np.ndarray:
+    """Region of every triangle (uint8, ordering tri = 2 (j n + i) + {0, 1}) of a region-mode
+    problem: the last rectangle of p.layout that contains the triangle's centroid (closed
+    rectangles; centroids ((3i+2)/(3n), (3j+1)/(3n)) for T_a and ((3i+1)/(3n), (3j+2)/(3n)) for
+    T_b). The first layout entry must cover the whole square."""
+    if p.regions is None or p.layout is None:
+        raise ValueError("not a region-mode problem")
+    n = p.n
+    cj, ci = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ci, cj = ci.ravel(), cj.ravel()
+    cx = np.empty(2 * n * n)
+    cy = np.empty(2 * n * n)
+    cx[0::2] = (3 * ci + 2) / (3.0 * n)
+    cy[0::2] = (3 * cj + 1) / (3.0 * n)
+    cx[1::2] = (3 * ci + 1) / (3.0 * n)
+    cy[1::2] = (3 * cj + 2) / (3.0 * n)
+    rid = np.full(2 * n * n, 255, dtype=np.uint8)
+    for r, k in p.layout:
+        inside = (cx >= r.x0) & (cx <= r.x1) & (cy >= r.y0) & (cy <= r.y1)
+        rid[inside] = k
+    if np.any(rid == 255):
+        raise ValueError("the layout does not cover every triangle")
+    return rid
+
+
+# Transformer cross-section of Sec. 4 (figure fig:domain, table tab:coef): a 355 mm x 466 mm
+# tank whose 10 mm steel wall encloses air, an iron core [60, 295] x [28, 438] mm with the window
+# [140, 215] x [108, 358] mm, and four windings 13 mm x 220 mm starting at y = 123 mm, at
+# x = 28 and 183 mm (winding-) and x = 159 and 314 mm (winding+).
+TRANSFORMER_MM = (355.0, 466.0)
+TRANSFORMER_REGIONS = (
+    Region("air", sigma=0.0, a=0.0, b=0.0, c=1.0, d=1e7 / (4.0 * np.pi), j=0.0),
+    Region("iron", sigma=0.0, a=5.85, b=2.196, c=136026.0, d=23.15, j=0.0),
+    Region("steel", sigma=1e7, a=130.171, b=1.102, c=6112.97, d=43.742, j=0.0),
+    Region("winding+", sigma=0.0, a=0.0, b=0.0, c=1.0, d=1e7 / (4.0 * np.pi), j=1.9e4),
+    Region("winding-", sigma=0.0, a=0.0, b=0.0, c=1.0, d=1e7 / (4.0 * np.pi), j=-1.9e4),
+)
+
+
+def _mm_rect(x0, y0, x1, y1) -> Rect:
+    """A rectangle of the cross-section in mm, its axes scaled independently onto [0, 1]."""
+    lx, ly = TRANSFORMER_MM
+    return Rect(x0 / lx, y0 / ly, x1 / lx, y1 / ly)
+
+
+def transformer(n: int = 128, N: int = 64, law: str = "expcap", nu_max: Optional[float] = None,
+                j_scale: float = 1.0) -> Problem:
+    """The transformer cross-section of Sec. 4 drawn on the unit square (each axis scaled onto
+    [0, 1], so the grid stays uniform and square: a transformer-like geometry with the paper's
+    layout and materials, not its exact aspect ratio), with the law nu = a min(exp(b s^2), c) + d
+    of table tab:coef, T = 0.02 s, the cos source j_i cos(2 pi t / T) (j_i scaled by j_scale) and
+    Khat = nu_max S, nu_max = max_i (a_i c_i + d_i) by default (the largest reluctivity the law
+    takes)."""
+    regs = tuple(replace(r, j=r.j * j_scale) for r in TRANSFORMER_REGIONS)
+    layout = (
+        (Rect(0.0, 0.0, 1.0, 1.0), 2),                 # steel tank wall ...
+        (_mm_rect(10, 10, 345, 456), 0),               # ... around the air inside it
+        (_mm_rect(60, 28, 295, 438), 1),               # iron core
+        (_mm_rect(140, 108, 215, 358), 0),             # core window (air)
+        (_mm_rect(28, 123, 41, 343), 4),               # winding-
+        (_mm_rect(183, 123, 196, 343), 4),             # winding-
+        (_mm_rect(159, 123, 172, 343), 3),             # winding+
+        (_mm_rect(314, 123, 327, 343), 3),             # winding+
+    )
+    if nu_max is None:
+        nu_max = max(r.a * r.c + r.d for r in regs)
+    return Problem(n=n, N=N, T=0.02, waveform="cos", nu_max=float(nu_max), law=law, regions=regs, layout=layout)
 
 
 def with_size(p: Problem, n: int, N: int) -> Problem:
