@@ -81,6 +81,22 @@ typedef enum { PT_INNER_GALERKIN1 = 0, PT_INNER_COCG = 1 } pt_inner;
 
 typedef enum { PT_WAVE_SIN = 0, PT_WAVE_COS = 1 } pt_waveform;
 
+/* Reluctivity law of every region of a problem:
+ *  PT_NU_RATIONAL: nu(s) = a + b s^2/(1 + s^2) (the synthetic iron law; rectangle problems use it
+ *                  with a = nu_a, b = nu_b in nu_rect and a = nu_out, b = 0 elsewhere)
+ *  PT_NU_EXPCAP:   nu(s) = a min(exp(b s^2), c) + d, the law of Sec. 4 ("Test problem"); region
+ *                  mode only. Evaluated in FP64 in both precision modes.                          */
+typedef enum { PT_NU_RATIONAL = 0, PT_NU_EXPCAP = 1 } pt_nu_law;
+
+/* Material of one region (region mode; Sec. 4, table tab:coef): conductivity, law parameters
+ * (b, c, d unused by PT_NU_RATIONAL: nu = a + b s^2/(1+s^2) there) and the amplitude j of the
+ * current density j w(2 pi t / T). */
+typedef struct {
+    double sigma;          /* >= 0 */
+    double a, b, c, d;     /* PT_NU_RATIONAL: a > 0, a + b > 0; PT_NU_EXPCAP: a, b >= 0, c >= 1, d > 0 */
+    double j;
+} pt_region;
+
 typedef struct { double x0, y0, x1, y1; } pt_rect;   /* closed rectangle */
 
 typedef struct {
@@ -101,6 +117,14 @@ typedef struct {
                               NULL = sigma_in on sigma_rect */
     const double* d_load;  /* optional device time field [N][n+1][n+1]: f^n given
                               explicitly (replaces J0 w b); NULL = built-in source */
+    int32_t law;           /* pt_nu_law; PT_NU_EXPCAP requires region mode */
+    int32_t nregions;      /* 0: rectangle mode (sigma_in/sigma_rect, nu_a/nu_b/nu_out/nu_rect,
+                              J0/coil_rect above); 1..16: region mode, where every triangle takes
+                              the conductivity, law and current of its region and those fields are
+                              not used (single-problem plans; d_sigma must be NULL) */
+    const uint8_t* d_region;     /* region mode: device [2 n^2], the region (< nregions) of every
+                                    triangle, ids as for d_theta */
+    const pt_region* regions;    /* region mode: host [nregions], copied by pt_plan_create */
 } pt_problem;
 
 typedef struct {

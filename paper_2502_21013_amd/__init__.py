@@ -36,10 +36,12 @@ def _rect(r) -> L.Rect:
     return L.Rect(x0, y0, x1, y1)
 
 
-def problem_struct(p, theta=None, sigma=None, load=None) -> L.Problem:
+def problem_struct(p, theta=None, sigma=None, load=None, region=None) -> L.Problem:
     """Fill the C problem struct from any object with the fields of a problem description
     (n, N, T, sigma_in, sigma_rect, nu_a, nu_b, nu_out, nu_rect, J0, coil_rect, waveform,
-    nu_max). theta / sigma / load are optional device tensors (float64, contiguous)."""
+    nu_max; region mode: law and regions, each with sigma, a, b, c, d, j). theta / sigma / load
+    are optional device tensors (float64, contiguous); region is the device uint8 tensor of the
+    triangles' regions, required in region mode. The struct keeps its regions array alive."""
     s = L.Problem()
     s.n, s.N, s.T = int(p.n), int(p.N), float(p.T)
     s.sigma_in, s.sigma_rect = float(p.sigma_in), _rect(p.sigma_rect)
@@ -50,6 +52,18 @@ def problem_struct(p, theta=None, sigma=None, load=None) -> L.Problem:
     s.d_theta = _ptr(theta, "theta", 2 * p.n * p.n)
     s.d_sigma = _ptr(sigma, "sigma", 2 * p.n * p.n)
     s.d_load = _ptr(load, "load", p.N * (p.n + 1) ** 2)
+    regs = getattr(p, "regions", None)
+    s.law = {"rational": L.PT_NU_RATIONAL, "expcap": L.PT_NU_EXPCAP}[getattr(p, "law", "rational")]
+    if regs is not None:
+        import torch
+        if region is None or region.dtype != torch.uint8 or not region.is_cuda or not region.is_contiguous() or \
+                region.numel() != 2 * p.n * p.n:
+            raise ValueError(f"region mode needs a contiguous uint8 device tensor of {2 * p.n * p.n} region ids")
+        arr = (L.Region * len(regs))(*[L.Region(r.sigma, r.a, r.b, r.c, r.d, r.j) for r in regs])
+        s._regions = arr
+        s.nregions = len(regs)
+        s.d_region = region.data_ptr()
+        s.regions = arr
     return s
 
 
@@ -139,7 +153,7 @@ class Plan:
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
                  adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0,
                  forcing=1e-2, max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, theta=None, sigma=None,
-                 load=None, device=None):
+                 load=None, region=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -147,8 +161,8 @@ class Plan:
         self.S = self.N // 2
         self.nodes = (self.n + 1) ** 2
         self.precision = precision
-        self._keep = (theta, sigma, load)  # device tables must outlive the plan's calls
-        self._ps = problem_struct(problem, theta, sigma, load)
+        self._keep = (theta, sigma, load, region)  # device tables must outlive the plan's calls
+        self._ps = problem_struct(problem, theta, sigma, load, region)
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
                      use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
                      init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov, inner_rtol,

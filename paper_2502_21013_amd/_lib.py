@@ -22,10 +22,17 @@ PT_INNER_GALERKIN1 = 0
 PT_INNER_COCG = 1
 PT_WAVE_SIN = 0
 PT_WAVE_COS = 1
+PT_NU_RATIONAL = 0
+PT_NU_EXPCAP = 1
 
 
 class Rect(C.Structure):
     _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("x1", C.c_double), ("y1", C.c_double)]
+
+
+class Region(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("d", C.c_double), ("j", C.c_double)]
 
 
 class Problem(C.Structure):
@@ -36,6 +43,7 @@ class Problem(C.Structure):
         ("J0", C.c_double), ("coil_rect", Rect), ("waveform", C.c_int32),
         ("nu_max", C.c_double),
         ("d_theta", C.c_void_p), ("d_sigma", C.c_void_p), ("d_load", C.c_void_p),
+        ("law", C.c_int32), ("nregions", C.c_int32), ("d_region", C.c_void_p), ("regions", C.POINTER(Region)),
     ]
 
 

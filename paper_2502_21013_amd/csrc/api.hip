@@ -143,6 +143,23 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (!rect_ok(pr->sigma_rect) || !rect_ok(pr->nu_rect) || !rect_ok(pr->coil_rect))
         return fail(PT_ERR_INVALID, "rectangles must be finite");
     if (pr->waveform != PT_WAVE_SIN && pr->waveform != PT_WAVE_COS) return fail(PT_ERR_INVALID, "unknown waveform");
+    if (pr->law != PT_NU_RATIONAL && pr->law != PT_NU_EXPCAP) return fail(PT_ERR_INVALID, "unknown reluctivity law");
+    if (pr->nregions < 0 || pr->nregions > kMaxRegions) return fail(PT_ERR_INVALID, "nregions must be in [0, 16]");
+    if (pr->nregions == 0 && pr->law != PT_NU_RATIONAL)
+        return fail(PT_ERR_INVALID, "the exp-capped law needs region mode (nregions > 0)");
+    if (pr->nregions > 0) {
+        if (!pr->d_region || !pr->regions) return fail(PT_ERR_INVALID, "region mode needs d_region and regions");
+        if (pr->d_sigma) return fail(PT_ERR_INVALID, "region mode takes the conductivity from the regions (d_sigma NULL)");
+        for (int r = 0; r < pr->nregions; ++r) {
+            const pt_region& g = pr->regions[r];
+            if (!std::isfinite(g.sigma) || !std::isfinite(g.a) || !std::isfinite(g.b) || !std::isfinite(g.c) ||
+                !std::isfinite(g.d) || !std::isfinite(g.j) || !(g.sigma >= 0))
+                return fail(PT_ERR_INVALID, "region " + std::to_string(r) + ": parameters must be finite, sigma >= 0");
+            const bool ok = pr->law == PT_NU_RATIONAL ? (g.a > 0 && g.a + g.b > 0)
+                                                      : (g.a >= 0 && g.b >= 0 && g.c >= 1 && g.d > 0);
+            if (!ok) return fail(PT_ERR_INVALID, "region " + std::to_string(r) + ": the law's parameters are out of range");
+        }
+    }
     if (!(o->tol > 0) || !std::isfinite(o->tol)) return fail(PT_ERR_INVALID, "tol must be positive");
     if (o->max_outer < 1) return fail(PT_ERR_INVALID, "max_outer must be >= 1");
     if (o->check_every < 1) return fail(PT_ERR_INVALID, "check_every must be >= 1");
@@ -194,6 +211,8 @@ static pt_status validate_batch(const pt_problem* pr, int count, const pt_option
             return fail(PT_ERR_INVALID, "batch instances must share sigma_in, sigma_rect and nu_max");
     }
     if (o->adjoint) return fail(PT_ERR_INVALID, "adjoint plans take a single problem");
+    for (int b = 0; b < count; ++b)
+        if (pr[b].nregions > 0) return fail(PT_ERR_INVALID, "region mode takes a single problem");
     if (o->krylov_dim) return fail(PT_ERR_INVALID, "Newton plans take a single problem");
     for (int b = 0; b < count; ++b)
         if (pr[b].d_theta || pr[b].d_sigma || pr[b].d_load)
@@ -243,9 +262,11 @@ static void layout(Plan& p) {
     p.off_zs = take(S * 3 * sizeof(double));
     p.off_wave = take(B * (size_t)p.N * sizeof(double));
     p.off_inst = take(B * 4 * sizeof(double));
+    p.off_regp = take(B * kMaxRegions * 4 * sizeof(double));
+    p.off_rsj = take(kMaxRegions * 2 * sizeof(double));
     // two sets of slot partials (V-cycle and operator sweep), each with its stage-1 tail
     size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows + p.g_mv.blocks + kReduceRows) * S * 3;
-    size_t part_team = (size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2;
+    size_t part_team = std::max((size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2, (size_t)4096 * 2);
     size_t part_adj = p.opt.adjoint ? std::max<size_t>((size_t)kAdjBlocks * 2, (size_t)p.n * p.n * 2) : 0;
     if (p.opt.krylov_dim > 0) part_adj = std::max<size_t>(part_adj, (size_t)kAdjBlocks * 2);
     p.part_bytes = std::max(std::max(part_slot, part_team), part_adj) * sizeof(double);
@@ -318,6 +339,30 @@ static void host_tables(Plan& p) {
         p.h_inst[4 * b + 2] = q.nu_out;
         p.h_inst[4 * b + 3] = 0.0;
     }
+    // law parameters per region (see law_nu): rectangle problems have region 0 (outside nu_rect:
+    // nu_out) and region 1 (inside: nu_a + nu_b s^2/(1+s^2)), both of the rational law
+    p.h_regp = new double[(size_t)p.B * kMaxRegions * 4]();
+    p.h_rsj = new double[(size_t)kMaxRegions * 2]();
+    for (int b = 0; b < p.B; ++b) {
+        double* q = p.h_regp + (size_t)b * kMaxRegions * 4;
+        if (!p.region_mode) {
+            q[0] = p.probs[b].nu_out;
+            q[4] = p.probs[b].nu_a;
+            q[5] = p.probs[b].nu_b;
+            continue;
+        }
+        for (int r = 0; r < p.nreg; ++r) {
+            const pt_region& g = p.regions[r];
+            q[4 * r] = g.a;
+            q[4 * r + 1] = g.b;
+            if (p.law == PT_NU_EXPCAP) {
+                q[4 * r + 2] = g.b > 0 ? std::log(g.c) / g.b : 1e300;  // s^2 at which exp(b s^2) = c
+                q[4 * r + 3] = g.d;
+            }
+            p.h_rsj[2 * r] = g.sigma;
+            p.h_rsj[2 * r + 1] = g.j;
+        }
+    }
 }
 
 static pt_status check_ws(const Plan* p, void* ws, size_t bytes) {
@@ -352,6 +397,9 @@ static pt_status setup(Plan& p, char* ws, hipStream_t st) {
     PT_HIP(hipMemcpyAsync(ws + p.off_zs, p.h_zs, (size_t)p.ST * 3 * sizeof(double), hipMemcpyHostToDevice, st));
     PT_HIP(hipMemcpyAsync(ws + p.off_wave, p.h_wave, (size_t)p.B * p.N * sizeof(double), hipMemcpyHostToDevice, st));
     PT_HIP(hipMemcpyAsync(ws + p.off_inst, p.h_inst, (size_t)p.B * 4 * sizeof(double), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_regp, p.h_regp, (size_t)p.B * kMaxRegions * 4 * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_rsj, p.h_rsj, (size_t)kMaxRegions * 2 * sizeof(double), hipMemcpyHostToDevice, st));
     TM(KID_SETUP, launch_setup_fine(p, ws, st));
     for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin(p, ws, l, st));
     TM(KID_SETUP, launch_row_records(p, ws, st));
@@ -470,8 +518,9 @@ static void residual_step(Plan& p, char* ws, bool adjoint, hipStream_t st) {
     double* part = (double*)(ws + p.off_part);
     double* scal = (double*)(ws + p.off_scal);
     if (!adjoint) {
-        launch_forward(p, ws, TM_RESIDUAL, (double*)(ws + p.off_U), ws + p.lev[0].off_r, nullptr, part, st);
-        TM(KID_REDUCE, launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st));
+        const int flat = launch_forward(p, ws, TM_RESIDUAL, (double*)(ws + p.off_U), ws + p.lev[0].off_r, nullptr,
+                                        part, st);
+        TM(KID_REDUCE, launch_reduce_norms(p, ws, part, flat, scal, st));
         return;
     }
     int nparts = 0;
@@ -771,8 +820,8 @@ static pt_status newton_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, 
     };
     // ||F - A(X)|| and ||F|| with the residual (FP64, node-major) into Rout
     auto residual = [&](const double* X, double* Rout, double& r, double& f) -> pt_status {
-        launch_forward(p, ws, TM_RESIDUAL, X, nullptr, Rout, part, st);
-        launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st);
+        const int flat = launch_forward(p, ws, TM_RESIDUAL, X, nullptr, Rout, part, st);
+        launch_reduce_norms(p, ws, part, flat, scal, st);
         pt_status q = fetch2();
         r = std::sqrt(h2[0]);
         f = std::sqrt(h2[1]);
@@ -1041,6 +1090,12 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     p.B = count;
     p.probs = new pt_problem[count];
     for (int b = 0; b < count; ++b) p.probs[b] = probs[b];
+    p.law = prob->law;
+    p.region_mode = prob->nregions > 0;
+    p.nreg = p.region_mode ? prob->nregions : 2;
+    if (p.region_mode) std::copy(prob->regions, prob->regions + prob->nregions, p.regions);
+    p.prob.regions = nullptr;  // the caller's array need not outlive the plan
+    for (int b = 0; b < count; ++b) p.probs[b].regions = nullptr;
     p.n = prob->n;
     p.N = prob->N;
     p.S = prob->N / 2;
@@ -1104,6 +1159,8 @@ void pt_plan_destroy(pt_plan* plan) {
     delete[] plan->p.h_zs;
     delete[] plan->p.h_wave;
     delete[] plan->p.h_inst;
+    delete[] plan->p.h_regp;
+    delete[] plan->p.h_rsj;
     delete[] plan->p.probs;
     delete plan;
 }
@@ -1159,8 +1216,8 @@ pt_status pt_residual(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* 
     double* scal = (double*)(ws + p.off_scal);
     // R is first written node-major into d_r (same size), then moved through U and
     // transposed back into d_r in the time-field layout.
-    launch_forward(p, ws, TM_RESIDUAL, U, nullptr, d_r, part, st);
-    launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st);
+    const int flat = launch_forward(p, ws, TM_RESIDUAL, U, nullptr, d_r, part, st);
+    launch_reduce_norms(p, ws, part, flat, scal, st);
     double h[2];
     PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     PT_HIP(hipStreamSynchronize(st));
@@ -1190,8 +1247,8 @@ pt_status pt_residual_spectrum(pt_plan* plan, void* d_ws, size_t ws_bytes, const
     launch_transpose_in(p, d_u, U, st);
     double* part = (double*)(ws + p.off_part);
     double* scal = (double*)(ws + p.off_scal);
-    launch_forward(p, ws, TM_RESIDUAL, U, d_rhat, nullptr, part, st);
-    launch_reduce_norms(p, ws, part, p.g_fwd.blocks, scal, st);
+    const int flat = launch_forward(p, ws, TM_RESIDUAL, U, d_rhat, nullptr, part, st);
+    launch_reduce_norms(p, ws, part, flat, scal, st);
     double h[2];
     PT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     PT_HIP(hipStreamSynchronize(st));

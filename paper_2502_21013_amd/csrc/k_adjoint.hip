@@ -8,7 +8,9 @@
 //   (M/tau)(lambda^n - lambda^{n+1}) + K'(u^n) lambda^n = g^n,  lambda^{N+1} = lambda^1,
 // with g^n = dl/du^n = (2/tau) M (2 u^n - u^{n-1} - u^{n+1}): backward in time, periodic.
 // K'(u) is symmetric (K is the gradient of an energy); per triangle it is
-//   |T| grad phi_a . (nu I + 2 dnu/d(s^2) grad u grad u^T) grad phi_b.
+//   |T| grad phi_a . (nu I + 2 dnu/d(s^2) grad u grad u^T) grad phi_b,
+// with the law of the triangle's region (law_nu_dn; dnu/d(s^2) the right derivative at the kink
+// of the exp-capped law).
 //
 // Layout as everywhere on the time axis: node-major [nodes][N] doubles, boundary nodes 0.
 // Scaled gradients G = h grad (differences of nodal values) as in the forward sweep, so
@@ -21,12 +23,12 @@ struct AdjArgs {
     int n, side, N, lgN;
     size_t nodes;
     double tau, inv_tau, n2;
-    double nu_a, nu_b, nu_out;
+    const double4* regp;   // [kMaxRegions] law parameters of each region (law_nu)
     const double* U;       // primal solution [nodes][N]
     const double* L;       // adjoint iterate [nodes][N]
     const double* G;       // dl/dU [nodes][N]
     const double* mt;      // fine mass stencil [4][nodes]
-    const uint8_t* flags;  // [2 n^2] bit 0: iron
+    const uint8_t* flags;  // [2 n^2] region of every triangle
     const double* theta;   // [2 n^2] or null
     const double* sig;     // [2 n^2] per-triangle conductivity
     double* part;          // norm / loss partials, two per workgroup
@@ -37,17 +39,13 @@ struct Law {
     double nu, dn;
 };
 
-__device__ __forceinline__ Law tri_law(const AdjArgs& a, bool iron, double th, double gx, double gy) {
+template <int LAW>
+__device__ __forceinline__ Law tri_law(const AdjArgs& a, int region, double th, double gx, double gy) {
     Law L;
-    if (!iron) {
-        L.nu = th * a.nu_out;
-        L.dn = 0.0;
-        return L;
-    }
     const double s2 = a.n2 * (gx * gx + gy * gy);
-    const double r = fast_rcp<double>(1.0 + s2);
-    L.nu = th * ((a.nu_a + a.nu_b) - a.nu_b * r);
-    L.dn = 2.0 * a.n2 * th * a.nu_b * r * r;
+    double dn;
+    L.nu = th * law_nu_dn<LAW>(a.regp[region], s2, dn);
+    L.dn = 2.0 * a.n2 * th * dn;
     return L;
 }
 
@@ -144,7 +142,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_source(AdjArgs a, double* g) {
 
 // R^n = g^n - (M/tau)(lambda^n - lambda^{n+1}) - K'(u^n) lambda^n at interior nodes (0 on the
 // boundary), written in the solver precision T for the time DFT; norm partials of R and g.
-template <typename T>
+template <typename T, int LAW>
 __global__ void __launch_bounds__(kBlock) k_adj_residual(AdjArgs a, T* rt) {
     const size_t total = a.nodes * (size_t)a.N;
     const size_t sd = a.side;
@@ -170,9 +168,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_residual(AdjArgs a, T* rt) {
             double Kl = 0.0;
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const bool iron = a.flags[tri[k]] & 1;
                 const double th = a.theta ? a.theta[tri[k]] : 1.0;
-                const Law L = tri_law(a, iron, th, gux[k], guy[k]);
+                const Law L = tri_law<LAW>(a, a.flags[tri[k]], th, gux[k], guy[k]);
                 Kl += tri_lin(L, gux[k], guy[k], glx[k], gly[k], px[k], py[k]);
             }
             R = g - Kl;
@@ -194,6 +191,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_residual(AdjArgs a, T* rt) {
 // dir = +1 (J, eqs. (disc1)-(disc2) linearised) or -1 (J^T: the time coupling runs the other
 // way, K' being symmetric). Writes out = J v when b is null and out = b - J v otherwise;
 // boundary entries are 0. FP64 throughout.
+template <int LAW>
 __global__ void __launch_bounds__(kBlock) k_jac_apply(AdjArgs a, const double* v, const double* b, double* out,
                                                       int dir) {
     const size_t total = a.nodes * (size_t)a.N;
@@ -217,9 +215,8 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(AdjArgs a, const double* v
             const int py[6] = {0, -1, -1, 1, 1, 0};
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const bool iron = a.flags[tri[k]] & 1;
                 const double th = a.theta ? a.theta[tri[k]] : 1.0;
-                const Law L = tri_law(a, iron, th, gux[k], guy[k]);
+                const Law L = tri_law<LAW>(a, a.flags[tri[k]], th, gux[k], guy[k]);
                 Jv += tri_lin(L, gux[k], guy[k], glx[k], gly[k], px[k], py[k]);
             }
             const MassRow m = mass_row(a, node);
@@ -239,13 +236,14 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(AdjArgs a, const double* v
 //   loss_T   = sigma_T tau sum_n du^T M_T du
 // with the unit-conductivity element mass |T|/12 (sum v w + sum v sum w), |T| = h^2 / 2.
 // per_cell: write the sums over the two triangles of the cell instead of one value each.
+template <int LAW>
 __global__ void __launch_bounds__(kBlock) k_adj_grad(AdjArgs a, double* gth, double* gsg, int per_cell) {
     const int c = blockIdx.x;
     const int ci = c % a.n, cj = c / a.n;
     const size_t sd = a.side;
     const size_t v00 = (size_t)cj * sd + ci, v10 = v00 + 1, v11 = v00 + sd + 1, v01 = v00 + sd;
     const size_t NN = a.N;
-    const bool ir_a = a.flags[2 * c] & 1, ir_b = a.flags[2 * c + 1] & 1;
+    const int rg_a = a.flags[2 * c], rg_b = a.flags[2 * c + 1];
     const double h2_24 = 1.0 / (24.0 * a.n2);  // |T| / 12
     double th_acc[2] = {0.0, 0.0}, ss[2] = {0.0, 0.0}, ls[2] = {0.0, 0.0};
     for (int t = threadIdx.x; t < a.N; t += kBlock) {
@@ -267,7 +265,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_grad(AdjArgs a, double* gth, dou
             ls[1] += h2_24 * (l00 * d00 + l11 * d11 + l01 * d01 + (l00 + l11 + l01) * dsb);
             const double uax = u10 - u00, uay = u11 - u10, ubx = u11 - u01, uby = u01 - u00;
             const double lax = l10 - l00, lay = l11 - l10, lbx = l11 - l01, lby = l01 - l00;
-            const Law La = tri_law(a, ir_a, 1.0, uax, uay), Lb = tri_law(a, ir_b, 1.0, ubx, uby);
+            const Law La = tri_law<LAW>(a, rg_a, 1.0, uax, uay), Lb = tri_law<LAW>(a, rg_b, 1.0, ubx, uby);
             th_acc[0] += 0.5 * La.nu * (uax * lax + uay * lay);
             th_acc[1] += 0.5 * Lb.nu * (ubx * lbx + uby * lby);
         }
@@ -319,9 +317,7 @@ static AdjArgs mk_adj(const Plan& p, char* ws) {
     a.tau = p.tau;
     a.inv_tau = 1.0 / p.tau;
     a.n2 = (double)p.n * (double)p.n;
-    a.nu_a = p.prob.nu_a;
-    a.nu_b = p.prob.nu_b;
-    a.nu_out = p.prob.nu_out;
+    a.regp = (const double4*)(ws + p.off_regp);
     a.U = (const double*)(ws + p.off_U);
     a.L = (const double*)(ws + p.off_L);
     a.G = (const double*)(ws + p.off_G);
@@ -348,10 +344,15 @@ void launch_adj_source(const Plan& p, char* ws, hipStream_t st) {
 int launch_adj_residual(const Plan& p, char* ws, void* rt, hipStream_t st) {
     AdjArgs a = mk_adj(p, ws);
     const int grid = adj_grid(p.nodes * p.N);
-    if (p.fp32)
-        hipLaunchKernelGGL(k_adj_residual<float>, dim3(grid), dim3(kBlock), 0, st, a, (float*)rt);
-    else
-        hipLaunchKernelGGL(k_adj_residual<double>, dim3(grid), dim3(kBlock), 0, st, a, (double*)rt);
+    const bool ex = p.law == PT_NU_EXPCAP;
+    if (p.fp32) {
+        if (ex) hipLaunchKernelGGL((k_adj_residual<float, PT_NU_EXPCAP>), dim3(grid), dim3(kBlock), 0, st, a, (float*)rt);
+        else hipLaunchKernelGGL((k_adj_residual<float, PT_NU_RATIONAL>), dim3(grid), dim3(kBlock), 0, st, a, (float*)rt);
+    } else {
+        if (ex) hipLaunchKernelGGL((k_adj_residual<double, PT_NU_EXPCAP>), dim3(grid), dim3(kBlock), 0, st, a, (double*)rt);
+        else hipLaunchKernelGGL((k_adj_residual<double, PT_NU_RATIONAL>), dim3(grid), dim3(kBlock), 0, st, a,
+                                (double*)rt);
+    }
     return grid;
 }
 
@@ -359,13 +360,21 @@ void launch_adj_grad(const Plan& p, char* ws, bool with_lambda, double* gth, dou
                      hipStream_t st) {
     AdjArgs a = mk_adj(p, ws);
     if (!with_lambda) a.L = nullptr;
-    hipLaunchKernelGGL(k_adj_grad, dim3((unsigned)p.n * (unsigned)p.n), dim3(kBlock), 0, st, a, gth, gsg, per_cell);
+    const dim3 grid((unsigned)p.n * (unsigned)p.n);
+    if (p.law == PT_NU_EXPCAP)
+        hipLaunchKernelGGL(k_adj_grad<PT_NU_EXPCAP>, grid, dim3(kBlock), 0, st, a, gth, gsg, per_cell);
+    else
+        hipLaunchKernelGGL(k_adj_grad<PT_NU_RATIONAL>, grid, dim3(kBlock), 0, st, a, gth, gsg, per_cell);
 }
 
 void launch_jac_apply(const Plan& p, char* ws, const double* v, const double* b, double* out, int dir,
                       hipStream_t st) {
     AdjArgs a = mk_adj(p, ws);
-    hipLaunchKernelGGL(k_jac_apply, dim3(adj_grid(p.nodes * p.N)), dim3(kBlock), 0, st, a, v, b, out, dir);
+    const dim3 grid(adj_grid(p.nodes * p.N));
+    if (p.law == PT_NU_EXPCAP)
+        hipLaunchKernelGGL(k_jac_apply<PT_NU_EXPCAP>, grid, dim3(kBlock), 0, st, a, v, b, out, dir);
+    else
+        hipLaunchKernelGGL(k_jac_apply<PT_NU_RATIONAL>, grid, dim3(kBlock), 0, st, a, v, b, out, dir);
 }
 
 }  // namespace pt

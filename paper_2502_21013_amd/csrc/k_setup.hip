@@ -16,7 +16,9 @@ struct SetupArgs {
     pt_rect sig, nu, coil;
     double sigma_in, J0;
     const double* d_sigma;  // optional per-triangle conductivity
-    uint8_t* flags;         // [2 n^2] bit 0: nonlinear (iron) law applies
+    const uint8_t* region;  // region mode: [2 n^2] region of every triangle (null: rectangles)
+    const double* rsj;      // region mode: [kMaxRegions][2] conductivity and current amplitude
+    uint8_t* flags;         // [2 n^2] region of every triangle (rectangles: 1 inside nu_rect, else 0)
     double* sig_out;        // [2 n^2] per-triangle conductivity (written if non-null)
     double* mt;             // [4][nodes] fine mass stencil
     double* b;              // [nodes] load amplitude
@@ -35,6 +37,7 @@ __device__ __forceinline__ void centroid(int n, int i, int j, int t, double& cx,
 
 __device__ __forceinline__ double tri_sigma(const SetupArgs& a, int i, int j, int t) {
     if (i < 0 || j < 0 || i >= a.n || j >= a.n) return 0.0;
+    if (a.region) return a.rsj[2 * a.region[2 * (j * a.n + i) + t]];
     if (a.d_sigma) return a.d_sigma[2 * (j * a.n + i) + t];
     double cx, cy;
     centroid(a.n, i, j, t, cx, cy);
@@ -43,6 +46,7 @@ __device__ __forceinline__ double tri_sigma(const SetupArgs& a, int i, int j, in
 
 __device__ __forceinline__ double tri_J(const SetupArgs& a, int i, int j, int t) {
     if (i < 0 || j < 0 || i >= a.n || j >= a.n) return 0.0;
+    if (a.region) return a.rsj[2 * a.region[2 * (j * a.n + i) + t] + 1];
     double cx, cy;
     centroid(a.n, i, j, t, cx, cy);
     return in_rect(a.coil, cx, cy) ? a.J0 : 0.0;
@@ -56,7 +60,7 @@ __global__ void __launch_bounds__(kBlock) k_tri_flags(SetupArgs a) {
         int i = (int)(c % a.n), j = (int)(c / a.n);
         double cx, cy;
         centroid(a.n, i, j, typ, cx, cy);
-        a.flags[t] = in_rect(a.nu, cx, cy) ? 1 : 0;
+        a.flags[t] = a.region ? a.region[t] : (in_rect(a.nu, cx, cy) ? 1 : 0);
         if (a.sig_out) a.sig_out[t] = tri_sigma(a, i, j, typ);
     }
 }
@@ -160,6 +164,8 @@ void launch_setup_fine(const Plan& p, char* ws, hipStream_t st) {
         a.sigma_in = q.sigma_in;
         a.J0 = q.J0;
         a.d_sigma = q.d_sigma;
+        a.region = p.region_mode ? q.d_region : nullptr;
+        a.rsj = (const double*)(ws + p.off_rsj);
         a.flags = (uint8_t*)(ws + p.off_flags) + (size_t)inst * 2 * p.n * p.n;
         a.mt = (double*)(ws + p.lev[0].off_mt);
         a.b = (double*)(ws + p.off_b) + (size_t)inst * p.nodes;

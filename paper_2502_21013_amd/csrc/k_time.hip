@@ -214,8 +214,7 @@ struct FwdArgs {
     int B, ST, lgST;       // instances in the batch, slots per node over all instances (2^lgST)
     size_t nodes;
     double inv_tau, n2;
-    double nu_a, nu_b, nu_out;
-    const double* inst;    // [B][4] per-instance nu_a, nu_b, nu_out (batch); null for one instance
+    const double4* regp;   // [B][kMaxRegions] law parameters of each region (law_nu)
     const double* U;       // [nodes][N]
     const double* F;       // [nodes][N] explicit load or null
     const double* bload;   // [nodes]
@@ -230,93 +229,11 @@ struct FwdArgs {
     double* part;          // [gridDim.x][2]
 };
 
-// 1 / x for x >= 1 to full double precision: hardware reciprocal estimate refined by two
-// Newton steps r <- r + r (1 - x r) (each step squares the relative error).
-__device__ __forceinline__ double rcp_ge1(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-
 // 1 / x for x >= 1 with one Newton step: the estimate's relative error (below 5e-8, measured)
 // squared, about 2e-15 -- a few units in the last place, far below the residual's own rounding.
 __device__ __forceinline__ double rcp_ge1_1(double x) {
     const double r = __builtin_amdgcn_rcp(x);
     return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
-}
-
-// Reluctivity of one triangle from its scaled gradient G = h grad u: nu_a + nu_b s^2/(1+s^2)
-// = (nu_a + nu_b) - nu_b / (1 + s^2) with s^2 = n^2 |G|^2, times theta; nu_out outside iron.
-__device__ __forceinline__ double nu_tri(double gx, double gy, const FwdArgs& a, bool iron, double th) {
-    if (!iron) return th * a.nu_out;
-    double s2 = a.n2 * (gx * gx + gy * gy);
-    return th * ((a.nu_a + a.nu_b) - a.nu_b * rcp_ge1(1.0 + s2));
-}
-
-// K(u)_i at an interior node from the values of u at the node and its six neighbours
-// (triangles T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i,j-1), T_a(i-1,j-1), T_b(i-1,j-1);
-// the node is vertex 0, 0, 1, 2, 2, 1 of them, with scaled basis gradients (-1,0),
-// (0,-1), (1,-1), (-1,1), (0,1), (1,0)).
-struct NodeMat {
-    bool ir[6];
-    double th[6];
-};
-
-__device__ __forceinline__ double k_node(const FwdArgs& a, const NodeMat& m, double uc, double ue, double uw,
-                                         double un, double us, double une, double usw) {
-    double g1x = ue - uc, g1y = une - ue;   // T_a(i,j)
-    double g2x = une - un, g2y = un - uc;   // T_b(i,j)
-    double g3x = uc - uw, g3y = un - uc;    // T_a(i-1,j)
-    double g4x = ue - uc, g4y = uc - us;    // T_b(i,j-1)
-    double g5x = us - usw, g5y = uc - us;   // T_a(i-1,j-1)
-    double g6x = uc - uw, g6y = uw - usw;   // T_b(i-1,j-1)
-    double K = nu_tri(g1x, g1y, a, m.ir[0], m.th[0]) * (-g1x) + nu_tri(g2x, g2y, a, m.ir[1], m.th[1]) * (-g2y) +
-               nu_tri(g3x, g3y, a, m.ir[2], m.th[2]) * (g3x - g3y) +
-               nu_tri(g4x, g4y, a, m.ir[3], m.th[3]) * (g4y - g4x) + nu_tri(g5x, g5y, a, m.ir[4], m.th[4]) * g5y +
-               nu_tri(g6x, g6y, a, m.ir[5], m.th[5]) * g6x;
-    return 0.5 * K;
-}
-
-__device__ __forceinline__ NodeMat node_materials(const FwdArgs& a, int i, int j) {
-    NodeMat m;
-    size_t c_ij = (size_t)j * a.n + i, c_w = c_ij - 1, c_s = c_ij - a.n, c_sw = c_ij - a.n - 1;
-    m.ir[0] = a.flags[2 * c_ij] & 1;
-    m.ir[1] = a.flags[2 * c_ij + 1] & 1;
-    m.ir[2] = a.flags[2 * c_w] & 1;
-    m.ir[3] = a.flags[2 * c_s + 1] & 1;
-    m.ir[4] = a.flags[2 * c_sw] & 1;
-    m.ir[5] = a.flags[2 * c_sw + 1] & 1;
-    if (a.theta) {
-        m.th[0] = a.theta[2 * c_ij];
-        m.th[1] = a.theta[2 * c_ij + 1];
-        m.th[2] = a.theta[2 * c_w];
-        m.th[3] = a.theta[2 * c_s + 1];
-        m.th[4] = a.theta[2 * c_sw];
-        m.th[5] = a.theta[2 * c_sw + 1];
-    } else {
-        for (int t = 0; t < 6; ++t) m.th[t] = 1.0;
-    }
-    return m;
-}
-
-// Material flags and scales of the two triangles T_a (t = 0) and T_b (t = 1) of cell (ci, cj).
-// The two flag bytes of a cell share one aligned dword (the flag table of an instance starts
-// at a multiple of 2 n^2 bytes, n >= 4).
-template <bool UNI = false>
-__device__ __forceinline__ void cell_mat(const FwdArgs& a, int ci, int cj, bool ir[2], double th[2]) {
-    size_t c = (size_t)cj * a.n + ci;
-    if constexpr (UNI) {
-        const uint32_t w = ((ConstPtr<uint32_t>)a.flags)[c >> 1] >> (16 * (c & 1));
-        ir[0] = w & 1u;
-        ir[1] = (w >> 8) & 1u;
-    } else {
-        ir[0] = a.flags[2 * c] & 1;
-        ir[1] = a.flags[2 * c + 1] & 1;
-    }
-    th[0] = a.theta ? uload<UNI>(a.theta, 2 * c) : 1.0;
-    th[1] = a.theta ? uload<UNI>(a.theta, 2 * c + 1) : 1.0;
 }
 
 // Per-lane state of the column walk for one time value: u on the rows j-1 (s, sw), j
@@ -326,42 +243,14 @@ struct Win {
     double sw, s, w, c, e, nw, n, ne, carry;
 };
 
-// The three triangles of the cells of row j-1 that touch node (i, j): T_b(i,j-1),
-// T_a(i-1,j-1), T_b(i-1,j-1) (node = vertex 2, 2, 1; scaled gradients (-1,1), (0,1), (1,0)).
-__device__ __forceinline__ double lower_three(const FwdArgs& a, const Win& v, const bool ir_s[2], const double th_s[2],
-                                              const bool ir_sw[2], const double th_sw[2]) {
-    double g4x = v.e - v.c, g4y = v.c - v.s;
-    double g5x = v.s - v.sw, g5y = v.c - v.s;
-    double g6x = v.c - v.w, g6y = v.w - v.sw;
-    return 0.5 * (nu_tri(g4x, g4y, a, ir_s[1], th_s[1]) * (g4y - g4x) + nu_tri(g5x, g5y, a, ir_sw[0], th_sw[0]) * g5y +
-                  nu_tri(g6x, g6y, a, ir_sw[1], th_sw[1]) * g6x);
-}
-
-// K at node (i, j) from the four triangles of the cells of row j (T_a(i,j), T_b(i,j),
-// T_a(i-1,j), T_b(i-1,j)) plus the carried lower part; also returns the carried part
-// for node (i, j+1): T_b(i,j) (vertex 2, (-1,1)), T_a(i-1,j) (vertex 2, (0,1)),
-// T_b(i-1,j) (vertex 1, (1,0)).
-__device__ __forceinline__ double upper_four(const FwdArgs& a, const Win& v, const bool ir_c[2], const double th_c[2],
-                                             const bool ir_w[2], const double th_w[2], double& carry_up) {
-    double g1x = v.e - v.c, g1y = v.ne - v.e;    // T_a(i,j)
-    double g2x = v.ne - v.n, g2y = v.n - v.c;    // T_b(i,j)
-    double g3x = v.c - v.w, g3y = v.n - v.c;     // T_a(i-1,j)
-    double g4x = v.n - v.nw, g4y = v.nw - v.w;   // T_b(i-1,j)
-    double nu1 = nu_tri(g1x, g1y, a, ir_c[0], th_c[0]);
-    double nu2 = nu_tri(g2x, g2y, a, ir_c[1], th_c[1]);
-    double nu3 = nu_tri(g3x, g3y, a, ir_w[0], th_w[0]);
-    double nu4 = nu_tri(g4x, g4y, a, ir_w[1], th_w[1]);
-    carry_up = 0.5 * (nu2 * (g2y - g2x) + nu3 * g3y + nu4 * g4x);
-    return 0.5 * (nu1 * (-g1x) + nu2 * (-g2y) + nu3 * (g3x - g3y)) + v.carry;
-}
-
 // ---------------------------------------------------------------- residual-sweep records
 
 // Everything the residual sweep needs at node (i, j) besides u, in one record read through the
 // scalar unit: the seven mass-stencil coefficients (centre, E, W, N, S, NE, SW), the load
 // amplitude b, and for the triangles T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i-1,j) the pair (A, B)
-// of the reluctivity law nu = A - B / (1 + s^2): A = theta (nu_a + nu_b), B = theta nu_b in
-// iron, A = theta nu_out and B = 0 elsewhere (Sec. 4, "Test problem": the same law as nu_tri).
+// of the rational reluctivity law nu = theta (a + b s^2/(1+s^2)) = A - B / (1 + s^2) of the
+// triangle's region: A = theta (a + b), B = theta b (rectangle problems: a = nu_a, b = nu_b in
+// nu_rect, a = nu_out, b = 0 elsewhere). The exp-capped law takes the generic residual kernel.
 struct NodeRec {
     double m[7];
     double bl;
@@ -388,7 +277,7 @@ struct RecArgs {
     const double* bload;   // [B][nodes]
     const uint8_t* flags;  // [B][2 n^2]
     const double* theta;   // [2 n^2] or null (one instance)
-    const double* inst;    // [B][4] nu_a, nu_b, nu_out
+    const double4* regp;   // [B][kMaxRegions] law parameters of each region (rational law)
     NodeRec* rec;          // [B][nodes]
 };
 
@@ -413,19 +302,15 @@ __global__ void __launch_bounds__(kBlock) k_row_records(RecArgs a) {
             for (int k = 0; k < 7; ++k) r.m[k] = 0.0;
         }
         r.bl = a.bload[id];
-        const double nu_a = a.inst[4 * b], nu_b = a.inst[4 * b + 1], nu_out = a.inst[4 * b + 2];
         for (int t = 0; t < 4; ++t) {
             const int ci = i - (t >> 1), typ = t & 1;   // cells (i, j), (i, j), (i-1, j), (i-1, j)
             double A = 0.0, Bv = 0.0;
             if (ci >= 0 && ci < a.n && j < a.n) {
                 const size_t tri = 2 * ((size_t)j * a.n + ci) + typ;
                 const double th = a.theta ? a.theta[tri] : 1.0;
-                if (a.flags[(size_t)b * nt + tri] & 1) {
-                    A = th * (nu_a + nu_b);
-                    Bv = th * nu_b;
-                } else {
-                    A = th * nu_out;
-                }
+                const double4 q = a.regp[(size_t)b * kMaxRegions + a.flags[(size_t)b * nt + tri]];
+                A = th * (q.x + q.y);   // nu = q.x + q.y s^2/(1+s^2) = A - B / (1 + s^2)
+                Bv = th * q.y;
             }
             r.law[t][0] = A;
             r.law[t][1] = Bv;
@@ -444,7 +329,7 @@ void launch_row_records(const Plan& p, char* ws, hipStream_t st) {
     a.bload = (const double*)(ws + p.off_b);
     a.flags = (const uint8_t*)(ws + p.off_flags);
     a.theta = p.prob.d_theta;
-    a.inst = (const double*)(ws + p.off_inst);
+    a.regp = (const double4*)(ws + p.off_regp);
     a.rec = (NodeRec*)(ws + p.off_rec);
     size_t g = ((size_t)p.B * p.nodes + kBlock - 1) / kBlock;
     if (g > 65536) g = 65536;
@@ -899,8 +784,130 @@ __global__ void __launch_bounds__(kBlock) k_rfft(RfftArgs a) {
     }
 }
 
-void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* out, double* rout, double* part,
-                    hipStream_t st) {
+// Scaled gradients G = h grad u of the six triangles around interior node (i, j) from the values
+// of u at the node and its neighbours, with the scaled gradient of the node's hat function on
+// each: T_a(i,j) (-1,0), T_b(i,j) (0,-1), T_a(i-1,j) (1,-1), T_b(i,j-1) (-1,1),
+// T_a(i-1,j-1) (0,1), T_b(i-1,j-1) (1,0); and the six triangle ids.
+struct Six {
+    double gx[6], gy[6];
+    size_t tri[6];
+};
+
+__device__ __forceinline__ Six six_triangles(int n, int i, int j, double uc, double ue, double uw, double un,
+                                             double us, double une, double usw) {
+    Six t;
+    t.gx[0] = ue - uc;   t.gy[0] = une - ue;    // T_a(i,j)
+    t.gx[1] = une - un;  t.gy[1] = un - uc;     // T_b(i,j)
+    t.gx[2] = uc - uw;   t.gy[2] = un - uc;     // T_a(i-1,j)
+    t.gx[3] = ue - uc;   t.gy[3] = uc - us;     // T_b(i,j-1)
+    t.gx[4] = us - usw;  t.gy[4] = uc - us;     // T_a(i-1,j-1)
+    t.gx[5] = uc - uw;   t.gy[5] = uw - usw;    // T_b(i-1,j-1)
+    const size_t c = (size_t)j * n + i;
+    t.tri[0] = 2 * c;
+    t.tri[1] = 2 * c + 1;
+    t.tri[2] = 2 * (c - 1);
+    t.tri[3] = 2 * (c - n) + 1;
+    t.tri[4] = 2 * (c - n - 1);
+    t.tri[5] = 2 * (c - n - 1) + 1;
+    return t;
+}
+
+// K(u)_i = sum_T |T| nu_T grad u_T . grad phi_i = (1/2) sum_T nu_T G_T . g~_T with the law of each
+// triangle's region (times theta), s^2 = n^2 |G|^2.
+template <int LAW>
+__device__ __forceinline__ double k_six(const Six& t, const FwdArgs& a, const double4* regp) {
+    const int px[6] = {-1, 0, 1, -1, 0, 1};
+    const int py[6] = {0, -1, -1, 1, 1, 0};
+    double K = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double th = a.theta ? a.theta[t.tri[k]] : 1.0;
+        const double s2 = a.n2 * (t.gx[k] * t.gx[k] + t.gy[k] * t.gy[k]);
+        const double nu = th * law_nu<LAW>(regp[a.flags[t.tri[k]]], s2);
+        K += nu * (t.gx[k] * px[k] + t.gy[k] * py[k]);
+    }
+    return 0.5 * K;
+}
+
+template <int LAW>
+__global__ void __launch_bounds__(kBlock) k_apply_K(FwdArgs a, int nslices, double* ku) {
+    size_t total = (size_t)nslices * a.nodes;
+    const size_t sd = a.side;
+    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
+        size_t node = id % a.nodes;
+        int i = (int)(node % sd), j = (int)(node / sd);
+        if (!(i > 0 && j > 0 && i < a.n && j < a.n)) {
+            ku[id] = 0.0;
+            continue;
+        }
+        const double* u = a.U + id;
+        const Six t = six_triangles(a.n, i, j, u[0], u[1], u[-1], u[sd], u[-(long)sd], u[sd + 1], u[-(long)sd - 1]);
+        ku[id] = k_six<LAW>(t, a, a.regp);
+    }
+}
+
+// Residual R^n = f^n - M (u^n - u^{n-1}) / tau - K(u^n) (eq. (disc1), u^0 = u^N) of a single
+// instance, one thread per node and time level on the node-major layout, for any law (the
+// exp-capped law of Sec. 4 takes this path: the record sweep holds the rational law only).
+// Writes R in double (rout, if non-null) and in the solver precision (rt, if non-null), and the
+// FP64 norm partials of R and F over interior nodes, two per workgroup.
+template <typename T, int LAW, bool LOAD>
+__global__ void __launch_bounds__(kBlock) k_residual_gen(FwdArgs a, T* rt) {
+    const size_t total = a.nodes * (size_t)a.N;
+    const size_t sd = a.side;
+    const size_t NN = a.N;
+    double rr = 0.0, ff = 0.0;
+    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
+        const size_t node = id / NN;
+        const int t = (int)(id - node * NN);
+        const int i = (int)(node % sd), j = (int)(node / sd);
+        double R = 0.0;
+        if (i > 0 && j > 0 && i < a.n && j < a.n) {
+            const double* u = a.U + id;
+            const long s = (long)sd * (long)NN, e = (long)NN;
+            const double uc = u[0], ue = u[e], uw = u[-e], un = u[s], us = u[-s], une = u[s + e], usw = u[-s - e];
+            const Six g = six_triangles(a.n, i, j, uc, ue, uw, un, us, une, usw);
+            const double K = k_six<LAW>(g, a, a.regp);
+            const double f = LOAD ? a.F[id] : a.bload[node] * a.wave[t];
+            // mass stencil (centre, E, W, N, S, NE, SW) applied to u^n - u^{n-1}
+            const long pt = t == 0 ? (long)NN - 1 : -1;   // offset of u^{n-1} (cyclic: u^0 = u^N)
+            const size_t nd = a.nodes;
+            const double mc = a.mt[node], mE = a.mt[nd + node], mW = a.mt[nd + node - 1], mN = a.mt[2 * nd + node],
+                         mS = a.mt[2 * nd + node - sd], mNE = a.mt[3 * nd + node], mSW = a.mt[3 * nd + node - sd - 1];
+            double Mu = 0.0;
+            if (mc != 0.0 || mE != 0.0 || mW != 0.0 || mN != 0.0 || mS != 0.0 || mNE != 0.0 || mSW != 0.0) {
+                const double* v = u + pt;
+                Mu = mc * (uc - v[0]) + mE * (ue - v[e]) + mW * (uw - v[-e]) + mN * (un - v[s]) + mS * (us - v[-s]) +
+                     mNE * (une - v[s + e]) + mSW * (usw - v[-s - e]);
+            }
+            R = f - Mu * a.inv_tau - K;
+            rr += R * R;
+            ff += f * f;
+        }
+        if (a.rout) a.rout[id] = R;
+        if (rt) rt[id] = (T)R;
+    }
+    __shared__ double red[2][kBlock];
+    red[0][threadIdx.x] = rr;
+    red[1][threadIdx.x] = ff;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.part[2 * (size_t)blockIdx.x] = red[0][0];
+        a.part[2 * (size_t)blockIdx.x + 1] = red[1][0];
+    }
+}
+
+constexpr int kGenBlocks = 4096;  // workgroups of the generic residual kernel, at most
+
+int launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* out, double* rout, double* part,
+                   hipStream_t st) {
     FwdArgs a;
     a.n = p.n;
     a.side = p.side;
@@ -912,15 +919,12 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     a.ST = p.ST;
     a.lgST = 0;
     while ((1 << a.lgST) < p.ST) ++a.lgST;
-    a.inst = p.B > 1 ? (const double*)(ws + p.off_inst) : nullptr;
+    a.regp = (const double4*)(ws + p.off_regp);
     a.remap = p.opt.xcd_remap;
     a.mode = mode;
     a.nodes = p.nodes;
     a.inv_tau = 1.0 / p.tau;
     a.n2 = (double)p.n * (double)p.n;
-    a.nu_a = p.prob.nu_a;
-    a.nu_b = p.prob.nu_b;
-    a.nu_out = p.prob.nu_out;
     a.U = Uw;
     a.F = p.prob.d_load ? (const double*)(ws + p.off_F) : nullptr;
     a.bload = (const double*)(ws + p.off_b);
@@ -949,6 +953,23 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
     void* rt = out ? (void*)(ws + p.off_P) : nullptr;  // R in solver precision, node-major
     tm_begin(p, KID_RESIDUAL, st);
     const int rk = mode == TM_SIGNAL ? RK_SIGNAL : (a.F ? RK_LOAD : RK_WAVE);
+    if (p.law == PT_NU_EXPCAP && rk != RK_SIGNAL) {
+        // the exp-capped law: generic residual kernel (single instance), then the DFT
+        size_t g = (p.nodes * (size_t)p.N + kBlock - 1) / kBlock;
+        if (g > (size_t)kGenBlocks) g = kGenBlocks;
+        const bool ld = rk == RK_LOAD;
+#define PT_GEN(TT) \
+    do { \
+        if (ld) hipLaunchKernelGGL((k_residual_gen<TT, PT_NU_EXPCAP, true>), dim3(g), dim3(kBlock), 0, st, a, (TT*)rt); \
+        else hipLaunchKernelGGL((k_residual_gen<TT, PT_NU_EXPCAP, false>), dim3(g), dim3(kBlock), 0, st, a, (TT*)rt); \
+    } while (0)
+        if (p.fp32) PT_GEN(float);
+        else PT_GEN(double);
+#undef PT_GEN
+        tm_end(p, KID_RESIDUAL, st);
+        if (out) launch_rfft(p, ws, rt, out, 0, st);
+        return (int)g;
+    }
     // residual spectrum in one pass: transform fused into the sweep (see k_residual); its
     // S/4 lanes per node must lie in one wavefront, so S <= 256
     if (out && !rout && rk != RK_SIGNAL && KP == 1 && p.S >= 4 && p.S <= 256) {
@@ -974,7 +995,7 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
         }
 #undef PT_RESF
         tm_end(p, KID_RESIDUAL, st);
-        return;
+        return 0;
     }
 #define PT_RES(TT, U, K, G) hipLaunchKernelGGL((k_residual<TT, U, K, G, false>), dim3(gf.blocks), blk, shm, st, a, rt)
 #define PT_RES_MODE(TT, U, K)               \
@@ -998,8 +1019,8 @@ void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* o
 #undef PT_RES_MODE
 #undef PT_RES
     tm_end(p, KID_RESIDUAL, st);
-    if (!out) return;
-    launch_rfft(p, ws, rt, out, 0, st);
+    if (out) launch_rfft(p, ws, rt, out, 0, st);
+    return 0;
 }
 
 void launch_rfft(const Plan& p, char* ws, const void* rt, void* out, int conj, hipStream_t st) {
@@ -1079,10 +1100,14 @@ void launch_reduce_pairs(const Plan& p, const double* part, int nparts, double* 
     hipLaunchKernelGGL(k_reduce_norms, dim3(1), dim3(kBlock), 0, st, part, nparts, 1, 1, p.side, out2);
 }
 
-void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, double* out2, hipStream_t st) {
+void launch_reduce_norms(const Plan& p, char* ws, double* part, int flat, double* out2, hipStream_t st) {
     (void)ws;
+    if (flat > 0) {  // one pair of partials per workgroup of a single-instance kernel
+        launch_reduce_pairs(p, part, flat, out2, st);
+        return;
+    }
     const Geom& g = p.g_fwd;
-    hipLaunchKernelGGL(k_reduce_norms, dim3(p.B), dim3(kBlock), 0, st, (const double*)part, nparts * g.per_step,
+    hipLaunchKernelGGL(k_reduce_norms, dim3(p.B), dim3(kBlock), 0, st, (const double*)part, g.blocks * g.per_step,
                        g.per_step, g.col_groups, p.side, out2);
 }
 
@@ -1337,60 +1362,23 @@ void launch_transpose_out(const Plan& p, const double* src, double* dst, hipStre
 
 // ---------------------------------------------------------------- K(u) on slices
 
-__global__ void __launch_bounds__(kBlock) k_apply_K(FwdArgs a, int nslices, double* ku) {
-    size_t total = (size_t)nslices * a.nodes;
-    const size_t sd = a.side;
-    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
-        size_t node = id % a.nodes;
-        int i = (int)(node % sd), j = (int)(node / sd);
-        if (!(i > 0 && j > 0 && i < a.n && j < a.n)) {
-            ku[id] = 0.0;
-            continue;
-        }
-        const double* u = a.U + id;
-        double uc = u[0], ue = u[1], uw = u[-1], un = u[sd], us = u[-(long)sd], une = u[sd + 1],
-               usw = u[-(long)sd - 1];
-        size_t c_ij = (size_t)j * a.n + i, c_w = c_ij - 1, c_s = c_ij - a.n, c_sw = c_ij - a.n - 1;
-        bool ir1 = a.flags[2 * c_ij] & 1, ir2 = a.flags[2 * c_ij + 1] & 1, ir3 = a.flags[2 * c_w] & 1,
-             ir4 = a.flags[2 * c_s + 1] & 1, ir5 = a.flags[2 * c_sw] & 1, ir6 = a.flags[2 * c_sw + 1] & 1;
-        double th1 = 1, th2 = 1, th3 = 1, th4 = 1, th5 = 1, th6 = 1;
-        if (a.theta) {
-            th1 = a.theta[2 * c_ij];
-            th2 = a.theta[2 * c_ij + 1];
-            th3 = a.theta[2 * c_w];
-            th4 = a.theta[2 * c_s + 1];
-            th5 = a.theta[2 * c_sw];
-            th6 = a.theta[2 * c_sw + 1];
-        }
-        double g1x = ue - uc, g1y = une - ue;
-        double g2x = une - un, g2y = un - uc;
-        double g3x = uc - uw, g3y = un - uc;
-        double g4x = ue - uc, g4y = uc - us;
-        double g5x = us - usw, g5y = uc - us;
-        double g6x = uc - uw, g6y = uw - usw;
-        double K = nu_tri(g1x, g1y, a, ir1, th1) * (-g1x) + nu_tri(g2x, g2y, a, ir2, th2) * (-g2y) +
-                   nu_tri(g3x, g3y, a, ir3, th3) * (g3x - g3y) + nu_tri(g4x, g4y, a, ir4, th4) * (g4y - g4x) +
-                   nu_tri(g5x, g5y, a, ir5, th5) * g5y + nu_tri(g6x, g6y, a, ir6, th6) * g6x;
-        ku[id] = 0.5 * K;
-    }
-}
-
 void launch_apply_K(const Plan& p, char* ws, const double* u, double* ku, int nslices, hipStream_t st) {
     FwdArgs a = {};
     a.n = p.n;
     a.side = p.side;
     a.nodes = p.nodes;
     a.n2 = (double)p.n * (double)p.n;
-    a.nu_a = p.prob.nu_a;
-    a.nu_b = p.prob.nu_b;
-    a.nu_out = p.prob.nu_out;
+    a.regp = (const double4*)(ws + p.off_regp);
     a.U = u;
     a.flags = (const uint8_t*)(ws + p.off_flags);
     a.theta = p.prob.d_theta;
     size_t total = (size_t)nslices * p.nodes;
     size_t g = (total + kBlock - 1) / kBlock;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_apply_K, dim3((unsigned)g), dim3(kBlock), 0, st, a, nslices, ku);
+    if (p.law == PT_NU_EXPCAP)
+        hipLaunchKernelGGL(k_apply_K<PT_NU_EXPCAP>, dim3((unsigned)g), dim3(kBlock), 0, st, a, nslices, ku);
+    else
+        hipLaunchKernelGGL(k_apply_K<PT_NU_RATIONAL>, dim3((unsigned)g), dim3(kBlock), 0, st, a, nslices, ku);
 }
 
 }  // namespace pt

@@ -216,4 +216,29 @@ __device__ __forceinline__ void nt_store(X* p, const X& x) {
     for (int k = 0; k < (int)(sizeof(X) / 16); ++k) __builtin_nontemporal_store(s[k], (nt_f4*)p + k);
 }
 
+// ---------------------------------------------------------------- reluctivity laws (Sec. 4)
+
+// Law of one region, parameters q = (q.x, q.y, q.z, q.w), before the triangle's scale theta:
+//   PT_NU_RATIONAL  nu = q.x + q.y s^2 / (1 + s^2)
+//   PT_NU_EXPCAP    nu = q.x exp(q.y min(s^2, q.z)) + q.w, q.z = ln(c)/b: a min(exp(b s^2), c) + d
+//                   (q.z huge when b = 0, the constant a + d)
+// with s^2 = |grad u|^2. law_nu_dn also gives dnu/d(s^2): q.y / (1+s^2)^2, resp. a b exp(b s^2)
+// below the saturation kink and 0 from it on (the right derivative).
+template <int LAW> __device__ __forceinline__ double law_nu(const double4 q, double s2) {
+    if constexpr (LAW == PT_NU_RATIONAL) return (q.x + q.y) - q.y / (1.0 + s2);
+    else return q.x * exp(q.y * fmin(s2, q.z)) + q.w;
+}
+
+template <int LAW> __device__ __forceinline__ double law_nu_dn(const double4 q, double s2, double& dn) {
+    if constexpr (LAW == PT_NU_RATIONAL) {
+        const double r = 1.0 / (1.0 + s2);
+        dn = q.y * r * r;
+        return (q.x + q.y) - q.y * r;
+    } else {
+        const double e = exp(q.y * fmin(s2, q.z));
+        dn = s2 < q.z ? q.x * q.y * e : 0.0;
+        return q.x * e + q.w;
+    }
+}
+
 }  // namespace pt

@@ -28,6 +28,7 @@ constexpr int kReduceBatch = 8;      // partials whose loads a reduction thread 
 constexpr int kAdjBlocks = 8192;     // workgroups of the grid-stride adjoint kernels
 constexpr int kCocgRows = 4096;      // workgroups along the nodes of the COCG vector kernels, at most
 constexpr int kRecDoubles = 16;      // residual-sweep record per node: mass row, load, reluctivity laws
+constexpr int kMaxRegions = 16;      // material regions of a problem (the triangles' region ids)
 
 // Per-slot scalar in "generic" form: for slot s >= 1 a complex number (x + i y);
 // for slot 0 two reals, x acting on the real part (k = 0) and y on the imaginary
@@ -125,6 +126,13 @@ struct Plan {
     double* h_zs;       // ST x 3: generic (a, b, c) of the shift z_s, repeated per instance
     double* h_wave;     // B x N: w(2 pi t_{j+1} / T) of each instance
     double* h_inst;     // B x 4: nu_a, nu_b, nu_out, 0 of each instance
+    int law;            // pt_nu_law of every region
+    int nreg;           // regions (2 in rectangle mode: 0 outside, 1 the nu rectangle)
+    bool region_mode;   // materials from d_region and the region table
+    pt_region regions[kMaxRegions];  // region mode: host copy of the regions
+    double* h_regp;     // B x kMaxRegions x 4: law parameters of each region (see law_nu)
+    double* h_rsj;      // kMaxRegions x 2: conductivity and current amplitude (region mode)
+    size_t off_regp, off_rsj;
     int target_slot, target_team;  // grid targets of the slot-vector and per-node kernels
     Geom g_slot0;       // slot-vector kernels on level 0
     Geom g_mv;          // operator apply on level 0: two adjacent columns per team
@@ -153,10 +161,12 @@ void launch_transpose_in(const Plan& p, const double* src, double* dst, hipStrea
 void launch_transpose_out(const Plan& p, const double* src, double* dst, hipStream_t st);
 enum TimeMode { TM_RESIDUAL = 0, TM_SIGNAL = 1 };
 // forward: residual (or the field itself) per node, packed real DFT to slot vector
-// out (if non-null), real residual to rout (if non-null), norm partials to part.
-void launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* out, double* rout,
-                    double* part, hipStream_t st);
-void launch_reduce_norms(const Plan& p, char* ws, double* part, int nparts, double* out2,
+// out (if non-null), real residual to rout (if non-null), norm partials to part. Returns the
+// partial layout for launch_reduce_norms: 0 for the column sweeps' layout, else the number of
+// partial pairs of the generic kernel (one per workgroup).
+int launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* out, double* rout,
+                   double* part, hipStream_t st);
+void launch_reduce_norms(const Plan& p, char* ws, double* part, int flat, double* out2,
                          hipStream_t st);
 // packed real DFT of rt (T2 [nodes][ST], solver precision) into out; conj: conjugate the
 // result (every slot but the packed real slot 0)
