@@ -208,6 +208,13 @@ void pt_options_default(pt_options* o);
 pt_status pt_plan_create(const pt_problem* prob, const pt_options* opts, pt_plan** out);
 void pt_plan_destroy(pt_plan* plan);
 
+/* Host-only check of a plan before any launch: walks every workgroup of every sweeping kernel
+ * with the kernels' own range helpers and checks that each index range, partial-sum slot and
+ * LDS request it can address lies within its buffer, and that the workspace buffers are
+ * aligned, inside the workspace and disjoint. PT_OK, or PT_ERR_INVALID with the first violation
+ * in msg (caller-owned, cap bytes, may be NULL) and pt_last_error. No device work. */
+pt_status pt_plan_check_bounds(const pt_plan* plan, char* msg, size_t cap);
+
 /* Bytes of device workspace every entry point below needs (256-byte aligned base). */
 pt_status pt_plan_workspace_bytes(const pt_plan* plan, size_t* bytes);
 

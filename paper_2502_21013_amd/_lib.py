@@ -92,6 +92,7 @@ def load():
         "pt_plan_create": (i32, [C.POINTER(Problem), C.POINTER(Options), pplan]),
         "pt_plan_destroy": (None, [vp]),
         "pt_plan_workspace_bytes": (i32, [vp, C.POINTER(C.c_size_t)]),
+        "pt_plan_check_bounds": (i32, [vp, C.c_char_p, sz]),
         "pt_solve": (i32, [vp, vp, sz, vp, vp, C.POINTER(Stats)]),
         "pt_solve_noalloc": (i32, [vp, vp, vp, C.POINTER(Stats)]),
         "pt_plan_create_batch": (i32, [C.POINTER(Problem), i32, C.POINTER(Options), pplan]),

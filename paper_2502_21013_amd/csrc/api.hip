@@ -26,6 +26,25 @@ static pt_status fail(pt_status s, const std::string& msg) {
     return s;
 }
 
+// Diagnostic output on stderr, chosen by the environment variable PT_LOG (read once):
+// 0 or unset: none; 1: one line per plan and per solve (sizes, status, steps, residual, time);
+// 2: also the relative residual at every check of the outer loop.
+static int log_level() {
+    static const int level = [] {
+        const char* e = std::getenv("PT_LOG");
+        return e ? std::atoi(e) : 0;
+    }();
+    return level;
+}
+
+#define PT_LOG(lvl, ...)                              \
+    do {                                              \
+        if (log_level() >= (lvl)) {                   \
+            std::fprintf(stderr, "[ptsolve] " __VA_ARGS__); \
+            std::fputc('\n', stderr);                 \
+        }                                             \
+    } while (0)
+
 #define PT_HIP(call)                                                                               \
     do {                                                                                           \
         hipError_t e_ = (call);                                                                    \
@@ -678,6 +697,10 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
                     }
                 }
                 if (record) ++hist;
+                if (log_level() >= 2)
+                    for (int b = 0; b < B; ++b)
+                        PT_LOG(2, "%s step %d%s: rel %.6e", adjoint ? "adjoint" : "outer", k,
+                               B > 1 ? (" instance " + std::to_string(b)).c_str() : "", rel[b]);
                 auto inst = [&](int b) { return B > 1 ? " (instance " + std::to_string(b) + ")" : std::string(); };
                 if (bad >= 0) {
                     result = fail(PT_ERR_NONFINITE,
@@ -755,6 +778,9 @@ static pt_status solve_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, h
         PT_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
     }
     tm_flush(p);
+    PT_LOG(1, "%s n=%d N=%d B=%d %s: %s after %d steps (static start %d), rel %.3e, inner steps %lld (max %d), %.2f ms",
+           adjoint ? "adjoint" : "solve", p.n, p.N, B, p.fp32 ? "fp32+refine" : "fp64", pt_status_string(result), k,
+           init_iters, *std::max_element(rel.begin(), rel.end()), p.inner_sum, p.inner_max, ms);
     if (stats) {
         for (int b = 0; b < B; ++b) {
             pt_stats& o = stats[b];
@@ -985,6 +1011,8 @@ static pt_status newton_impl(Plan& p, void* d_ws, size_t ws_bytes, double* d_u, 
     return result;
 }
 
+pt_status check_bounds(const Plan& p, std::string& msg);
+
 // ---------------------------------------------------------------- allocation-free solve
 
 // Device scratch of pt_solve_noalloc: the solver's whole workspace lives here. Every GPU the
@@ -1125,6 +1153,9 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     p.g_fwd = fwd_geom(p.side, p.S, p.B, p.target_slot);
     layout(p);
     host_tables(p);
+    PT_LOG(1, "plan n=%d N=%d B=%d %s%s: %d levels, workspace %.1f MiB", p.n, p.N, p.B,
+           p.fp32 ? "fp32+refine" : "fp64", p.region_mode ? (p.law == PT_NU_EXPCAP ? " regions, exp-capped law" : " regions") : "",
+           p.nlev, (double)p.ws_bytes / (1 << 20));
     *out = h;
     return PT_OK;
 }
@@ -1163,6 +1194,17 @@ void pt_plan_destroy(pt_plan* plan) {
     delete[] plan->p.h_rsj;
     delete[] plan->p.probs;
     delete plan;
+}
+
+pt_status pt_plan_check_bounds(const pt_plan* plan, char* msg, size_t cap) {
+    if (!plan) return fail(PT_ERR_INVALID, "plan must not be NULL");
+    std::string m;
+    pt_status s = check_bounds(plan->p, m);
+    if (msg && cap > 0) {
+        std::snprintf(msg, cap, "%s", m.c_str());
+    }
+    if (s != PT_OK) return fail(s, "launch bounds: " + m);
+    return PT_OK;
 }
 
 pt_status pt_plan_workspace_bytes(const pt_plan* plan, size_t* bytes) {

@@ -131,30 +131,33 @@ template <typename T2> __device__ __forceinline__ void dot3_acc(double* s, T2 u,
     s[2] += conj ? (cr - rc) : (cr + rc);
 }
 
-// Virtual workgroup index: workgroups are dispatched round-robin over the XCDs, so
-// this gives every XCD a contiguous range of node groups (its own L2 sees the
-// stencil neighbours of what it processes). blocks is a multiple of kNumXcd.
-__device__ __forceinline__ int virtual_block(int remap) {
-    int b = blockIdx.x;
-    if (!remap) return b;
-    int per = gridDim.x / kNumXcd;
-    return (b % kNumXcd) * per + b / kNumXcd;
-}
-
 // Column and row range of this workgroup in a sweeping kernel (see Geom).
 struct SweepRange {
     int col0, row0, row1;
 };
 
-__device__ __forceinline__ SweepRange sweep_range(int vb, int col_groups, int per_step, int rows_per_chunk, int side) {
+// (also compiled for the host: the launch-bounds check walks the same ranges)
+__host__ __device__ __forceinline__ SweepRange sweep_range(int vb, int col_groups, int per_step, int rows_per_chunk,
+                                                           int side) {
     SweepRange r;
     int g = vb % col_groups, c = vb / col_groups;
     r.col0 = g * per_step;
     r.row0 = c * rows_per_chunk;
-    r.row1 = min(r.row0 + rows_per_chunk, side);
+    r.row1 = r.row0 + rows_per_chunk < side ? r.row0 + rows_per_chunk : side;
     if (r.row0 > side) r.row0 = side;
     return r;
 }
+
+// Virtual workgroup index of workgroup b of a launch of `blocks` workgroups: workgroups are
+// dispatched round-robin over the XCDs, so this gives every XCD a contiguous range of node
+// groups (its own L2 sees the stencil neighbours of what it processes). blocks is a multiple of
+// kNumXcd. virtual_block is the same for the calling workgroup.
+__host__ __device__ __forceinline__ int virtual_block_of(int b, int blocks, int remap) {
+    if (!remap) return b;
+    const int per = blocks / kNumXcd;
+    return (b % kNumXcd) * per + b / kNumXcd;
+}
+__device__ __forceinline__ int virtual_block(int remap) { return virtual_block_of(blockIdx.x, gridDim.x, remap); }
 
 // Read-only table entry at an index that is the same on every lane of the wavefront (UNI):
 // read through the scalar unit (constant address space), so that the wait for it does not

@@ -234,3 +234,18 @@ def test_plan_rejects_invalid_inner_tolerances(P, kw):
     with pytest.raises(P.PTError) as e:
         P.Plan(W.config1(), inner="cocg", **kw)
     assert e.value.status == -1
+
+
+def test_pt_log_reports_plans_on_stderr():
+    """PT_LOG=1 makes the library describe each plan on stderr; unset, it prints nothing."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); import paper_2502_21013_amd as P, workloads as W; "
+            "P.Plan(W.config1(), precision='fp32')" % ROOT)
+    env = dict(os.environ, PT_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "[ptsolve] plan n=32 N=32 B=1 fp32+refine" in r.stderr
+    env.pop("PT_LOG")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert "[ptsolve]" not in r.stderr
