@@ -285,7 +285,9 @@ def load_traffic(kernel, mode, wl):
 
 def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inner=None):
     import torch
-    plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer, **(inner or {}), **(tuned or {}))
+    kw = dict(inner or {})
+    kw.update(tuned or {})   # a tuning table entry overrides the inner method given on the command line
+    plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer, **kw)
     U = plan.new_time_field()
     plan.workspace()
     for w in range(warmup):
@@ -544,7 +546,8 @@ def main():
     ap.add_argument("--c4-warmup", type=int, default=1, help="batching: warmup steps")
     ap.add_argument("--streams", type=int, default=4, help="batching: host threads / HIP streams of the work list")
     ap.add_argument("--no-graph", action="store_true", help="batching: eager launches instead of graph replay")
-    ap.add_argument("--tuning", default="", help="autotuner table (JSON) to apply")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2502_21013_amd", "tuning_mi355x.json"),
+                    help="autotuner table (JSON) to apply ('' for the library defaults)")
     ap.add_argument("--max-outer", type=int, default=2000,
                     help="cap on outer steps per solve; below the count needed for 1e-8 the run is a "
                          "profiling run (marked in the output), not a metric measurement")
