@@ -532,6 +532,8 @@ def main():
                     help="inner method of every periodic solve (default: the one-step Galerkin V-cycle)")
     ap.add_argument("--inner-iters", type=int, default=1, help="COCG steps per outer step (at most)")
     ap.add_argument("--inner-rtol", type=float, default=0.0, help="COCG per-frequency relative tolerance")
+    ap.add_argument("--cycle", default="default", choices=["default", "v11", "v01"],
+                    help="multigrid cycle (default: V(0,1) with the Galerkin step, V(1,1) with COCG)")
     ap.add_argument("--no-batching", action="store_true", help="skip the batching sub-record")
     ap.add_argument("--no-oracle-error", action="store_true", help="skip the error against the oracle solution")
     ap.add_argument("--c4-modes", default="fp32,fp64", help="batching: modes (FP32+refinement first)")
@@ -600,7 +602,7 @@ def main():
     from paper_2502_21013_amd import autotune as AT
     from paper_2502_21013_amd.batch import tune_key
     table = AT.load_table(args.tuning) if args.tuning else {}
-    inner = {"inner": args.inner, "inner_iters": args.inner_iters, "inner_rtol": args.inner_rtol}
+    inner = {"inner": args.inner, "inner_iters": args.inner_iters, "inner_rtol": args.inner_rtol, "cycle": args.cycle}
     res = {}
     for m in modes:
         tuned = table.get(tune_key(prob, 1, m))

@@ -79,6 +79,17 @@ typedef enum { PT_FP64 = 0, PT_FP32_REFINE = 1 } pt_precision;
  *                      masked from the start.                                   */
 typedef enum { PT_INNER_GALERKIN1 = 0, PT_INNER_COCG = 1 } pt_inner;
 
+/* Shape of the multigrid cycle B_k (P1 interpolation P, restriction P^T, damped Jacobi with
+ * D = 4 nu_max + z_k diag(M), exact solve on the 2 x 2-cell grid), the same on every level:
+ *  PT_VC_V11: V(1,1): x1 = omega D^{-1} r, coarse cycle on P^T (r - A x1), x2 = x1 + P x_c,
+ *             x3 = x2 + omega D^{-1} (r - A x2). Symmetric in the bilinear form x^T y, as
+ *             COCG requires.
+ *  PT_VC_V01: V(0,1): coarse cycle on P^T r, x2 = P x_c, x3 = x2 + omega D^{-1} (r - A x2).
+ *             Not symmetric; PT_INNER_GALERKIN1 only. Per cycle it skips the pre-smoothing
+ *             sweep and its operator evaluation on every level.
+ *  PT_VC_DEFAULT: V(0,1) with PT_INNER_GALERKIN1, V(1,1) with PT_INNER_COCG.            */
+typedef enum { PT_VC_DEFAULT = 0, PT_VC_V11 = 1, PT_VC_V01 = 2 } pt_vcycle;
+
 typedef enum { PT_WAVE_SIN = 0, PT_WAVE_COS = 1 } pt_waveform;
 
 /* Reluctivity law of every region of a problem:
@@ -134,8 +145,8 @@ typedef struct {
     int32_t precision;     /* pt_precision */
     int32_t inner;         /* pt_inner */
     int32_t inner_iters;   /* COCG steps per outer step (PT_INNER_COCG), 1..64 */
-    int32_t vc_sweeps;     /* damped-Jacobi sweeps before and after the coarse correction;
-                              must be 1 (the fused V(1,1) cycle) */
+    int32_t vc_sweeps;     /* damped-Jacobi sweeps per smoothing step of the cycle (vc_cycle);
+                              must be 1 (the fused sweeps) */
     double vc_omega;       /* Jacobi damping, 0 < omega < 1 */
     int32_t use_initial_guess; /* 0: U^0 = 0; 1: start from the contents of d_u */
     double diverge_factor; /* PT_ERR_DIVERGED if rel > diverge_factor * min(rel) (0 = off) */
@@ -171,6 +182,7 @@ typedef struct {
     double breakdown_tol;  /* PT_INNER_COCG: PT_ERR_BREAKDOWN when an active frequency has
                               |p^T A p| <= breakdown_tol Re(p^H A p) (the bilinear form vanishes to
                               rounding); 0 = 64 units in the last place of the solver precision */
+    int32_t vc_cycle;      /* pt_vcycle; PT_VC_V01 requires PT_INNER_GALERKIN1 */
 } pt_options;
 
 typedef struct {
@@ -199,7 +211,7 @@ typedef struct {
 typedef struct pt_plan pt_plan;
 
 /* Fill *o with the defaults (tol 1e-8, max_outer 1000, check_every 1, FP64,
- * PT_INNER_GALERKIN1, inner_iters 1, vc_sweeps 1, vc_omega 0.8, no initial guess,
+ * PT_INNER_GALERKIN1, inner_iters 1, vc_sweeps 1, vc_omega 0.8, PT_VC_DEFAULT, no initial guess,
  * diverge_factor 1e3, xcd_remap 1, timing 0, default grid targets, adjoint 0, no static start
  * (init_tol 1e-8), stop relative to ||F||, graph 0). */
 void pt_options_default(pt_options* o);
@@ -309,7 +321,7 @@ pt_status pt_time_irfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* 
 pt_status pt_shifted_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_x,
                            void* d_y, void* stream);
 
-/* x_s = B_s r_s: one V-cycle of the multigrid preconditioner for every slot. */
+/* x_s = B_s r_s: one cycle of the multigrid preconditioner (the plan's vc_cycle) for every slot. */
 pt_status pt_precond_apply(pt_plan* plan, void* d_ws, size_t ws_bytes, const void* d_r,
                            void* d_x, void* stream);
 

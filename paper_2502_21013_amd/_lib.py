@@ -20,6 +20,9 @@ PT_FP64 = 0
 PT_FP32_REFINE = 1
 PT_INNER_GALERKIN1 = 0
 PT_INNER_COCG = 1
+PT_VC_DEFAULT = 0
+PT_VC_V11 = 1
+PT_VC_V01 = 2
 PT_WAVE_SIN = 0
 PT_WAVE_COS = 1
 PT_NU_RATIONAL = 0
@@ -57,6 +60,7 @@ class Options(C.Structure):
         ("init_static", C.c_int32), ("init_tol", C.c_double), ("stop_relative_initial", C.c_int32),
         ("krylov_dim", C.c_int32), ("forcing", C.c_double), ("max_krylov", C.c_int32),
         ("graph", C.c_int32), ("inner_rtol", C.c_double), ("breakdown_tol", C.c_double),
+        ("vc_cycle", C.c_int32),
     ]
 
 

@@ -185,7 +185,11 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (o->precision != PT_FP64 && o->precision != PT_FP32_REFINE) return fail(PT_ERR_INVALID, "unknown precision");
     if (o->inner != PT_INNER_GALERKIN1 && o->inner != PT_INNER_COCG) return fail(PT_ERR_INVALID, "unknown inner method");
     if (o->inner_iters < 1 || o->inner_iters > 64) return fail(PT_ERR_INVALID, "inner_iters must be in [1, 64]");
-    if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused V(1,1) cycle)");
+    if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused smoothing sweeps)");
+    if (o->vc_cycle != PT_VC_DEFAULT && o->vc_cycle != PT_VC_V11 && o->vc_cycle != PT_VC_V01)
+        return fail(PT_ERR_INVALID, "unknown vc_cycle");
+    if (o->vc_cycle == PT_VC_V01 && o->inner == PT_INNER_COCG)
+        return fail(PT_ERR_INVALID, "COCG needs the symmetric V(1,1) cycle (vc_cycle PT_VC_V11)");
     if (!(o->inner_rtol >= 0 && o->inner_rtol < 1)) return fail(PT_ERR_INVALID, "inner_rtol must be in [0, 1)");
     if (!(o->breakdown_tol >= 0) || !std::isfinite(o->breakdown_tol))
         return fail(PT_ERR_INVALID, "breakdown_tol must be finite and >= 0");
@@ -259,6 +263,7 @@ static void layout(Plan& p) {
     }
     p.off_P = p.lev[0].off_x;
     p.has_cocg_vectors = p.opt.inner == PT_INNER_COCG;
+    p.vc_pre = p.opt.vc_cycle == PT_VC_V11 || (p.opt.vc_cycle == PT_VC_DEFAULT && p.opt.inner == PT_INNER_COCG);
     if (p.has_cocg_vectors) {
         size_t v = p.nodes * S * p.elem;
         p.off_cx = take(v);

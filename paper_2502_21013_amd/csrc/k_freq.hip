@@ -37,7 +37,7 @@ struct SlotArgs {
 constexpr int kSmallSide = 33;
 constexpr int kMaxSmall = 5;
 struct SmallArgs {
-    int count;
+    int count, pre;   // pre: V(1,1) (pre-smoothing), else V(0,1)
     int side[kMaxSmall];
     const double* mt[kMaxSmall];
     int off_r[kMaxSmall], off_x[kMaxSmall], off_t;
@@ -376,6 +376,81 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     }
 }
 
+// ---------------------------------------------------------------- V(0,1) cycle: restriction
+
+// r_c = P^T r, the restriction of the V(0,1) cycle (no pre-smoothing, so the fine residual is r
+// itself; r is zero on the boundary). Thread (coarse column ci, slots) walks the coarse rows of
+// its chunk with the P^T weights of k_vc_down: fine row 2cj contributes (c-1, c, c+1) x
+// (1/2, 1, 1/2), row 2cj+1 contributes (c, c+1) x 1/2 to coarse row cj and (c-1, c) x 1/2 to
+// coarse row cj+1 (carried), so each fine row is loaded once per walk (three columns). The two
+// fine rows of the next coarse row are loaded before the current one is computed, on every path
+// (rows clamped to the grid past the last one). Little arithmetic: the sweep streams r.
+template <typename T, bool UNI>
+__global__ void __launch_bounds__(kBlock) k_vc_restrict(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
+                                                        void* rout_) {
+    using W = SV<T>;
+    const W* rin = (const W*)rin_;
+    W* rout = (W*)rout_;
+    const int lgST = sa.lgST, lgR = lgST - (W::V - 1);
+    const SlotLane<T> L = slot_lane<T>(sa);
+    const int vb = virtual_block(sa.remap);
+    const int sf = F.side, nF = F.n, sc = C.side, nc = C.n;
+    const T half = (T)0.5;
+    const unsigned E = sizeof(typename Vec2<T>::type);
+    const SweepRange sr = sweep_range(vb, sa.col_groups, sa.per_step, sa.rows_per_chunk, sc);
+    int ci = sr.col0 + L.ln;
+    if (UNI) ci = __builtin_amdgcn_readfirstlane(ci);
+    if (ci >= sc || sr.row0 >= sr.row1) return;
+    const W zero = sv_zero<T>();
+    const unsigned oco = (((unsigned)ci << lgST) + L.s0) * E;
+    if (ci == 0 || ci == nc) {
+        for (int cj = sr.row0; cj < sr.row1; ++cj) nt_store(boff(row_of(rout, cj, sc, lgR), oco), zero);
+        return;
+    }
+    const int c = 2 * ci;
+    unsigned of[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) of[d] = (((unsigned)(c - 1 + d) << lgST) + L.s0) * E;
+    // fine rows 2 cj and 2 cj + 1 (clamped onto the grid) at columns c-1, c, c+1
+    auto fetch = [&](int cj, W* a, W* b) {
+        const W* ra = row_of(rin, clampi(2 * cj, 0, nF), sf, lgR);
+        const W* rb = row_of(rin, clampi(2 * cj + 1, 0, nF), sf, lgR);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            a[d] = *cboff(ra, of[d]);
+            b[d] = *cboff(rb, of[d]);
+        }
+    };
+    // (c-1, c) x 1/2 of fine row 2 row0 - 1 (the part of the first coarse row from below)
+    W carry = zero;
+    if (sr.row0 > 0) {
+        const W* rp = row_of(rin, 2 * sr.row0 - 1, sf, lgR);
+        carry = sv_scale(half, sv_add(*cboff(rp, of[0]), *cboff(rp, of[1])));
+    }
+    W A0[3], B0[3], A1[3], B1[3];
+    fetch(sr.row0, A0, B0);
+    auto step = [&](int cj, W* a, W* b, W* na, W* nb) {
+        fetch(cj + 1, na, nb);
+        issue_fence();
+        W acc = zero;
+        if (cj > 0 && cj < nc) {
+            acc = sv_fma(half, a[0], carry);
+            acc = sv_add(acc, a[1]);
+            acc = sv_fma(half, a[2], acc);
+            acc = sv_fma(half, b[1], acc);
+            acc = sv_fma(half, b[2], acc);
+        }
+        nt_store(boff(row_of(rout, cj, sc, lgR), oco), acc);
+        carry = sv_scale(half, sv_add(b[0], b[1]));
+    };
+    int cj = sr.row0;
+    for (; cj + 1 < sr.row1; cj += 2) {
+        step(cj, A0, B0, A1, B1);
+        step(cj + 1, A1, B1, A0, B0);
+    }
+    if (cj < sr.row1) step(cj, A0, B0, A1, B1);
+}
+
 // ---------------------------------------------------------------- V-cycle: coarsest
 
 // Exact solve on the 2 x 2-cell grid: the single interior node (1, 1) has the 1 x 1
@@ -406,7 +481,8 @@ __global__ void __launch_bounds__(kBlock) k_vc_coarsest(SlotArgs sa, LvArgs C, c
 // takes slot s, keeps r and x of all these levels in LDS and runs the same V(1,1) cycle as
 // k_vc_down, k_vc_coarsest and k_vc_up: restriction of r - A x1 with x1 = omega D^{-1} r, the
 // exact solve on the 2 x 2-cell grid, then x2 = omega D^{-1} r + P x_c and
-// x3 = x2 + omega D^{-1} (r - A x2), phases separated by workgroup barriers. As separate
+// x3 = x2 + omega D^{-1} (r - A x2), phases separated by workgroup barriers (sm.pre = 0: the
+// V(0,1) cycle of k_vc_restrict and k_vc_up, x1 = 0 and x2 = P x_c). As separate
 // launches these levels cost a few microseconds each for very little work.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, const void* rin_, void* xout_) {
@@ -458,15 +534,19 @@ __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, 
         const double* mt = sm.mt[q];
         const T2* r = sh + sm.off_r[q];
         T2* x1 = sh + sm.off_x[q];
-        T2* t = sh + sm.off_t;
-        T2* rc = sh + sm.off_r[q + 1];
-        for (int a = threadIdx.x; a < nodes; a += kBlock) x1[a] = jac(mt[a], r[a]);
-        __syncthreads();
-        for (int a = threadIdx.x; a < nodes; a += kBlock) {
-            const int j = a / sd, i = a - j * sd;
-            t[a] = (i > 0 && i < n && j > 0 && j < n) ? sub2(r[a], applyA(mt, sd, x1, a)) : zero;
+        const T2* t = r;   // the fine residual (V(0,1): r itself)
+        if (sm.pre) {
+            T2* tw = sh + sm.off_t;
+            for (int a = threadIdx.x; a < nodes; a += kBlock) x1[a] = jac(mt[a], r[a]);
+            __syncthreads();
+            for (int a = threadIdx.x; a < nodes; a += kBlock) {
+                const int j = a / sd, i = a - j * sd;
+                tw[a] = (i > 0 && i < n && j > 0 && j < n) ? sub2(r[a], applyA(mt, sd, x1, a)) : zero;
+            }
+            __syncthreads();
+            t = tw;
         }
-        __syncthreads();
+        T2* rc = sh + sm.off_r[q + 1];
         for (int ca = threadIdx.x; ca < sc * sc; ca += kBlock) {
             const int cj = ca / sc, ci = ca - cj * sc;
             T2 acc = zero;
@@ -505,7 +585,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, 
             const int j = a / sd, i = a - j * sd, hi = i >> 1, hj = j >> 1;
             const T2 c0 = xc[hj * sc + hi];
             const T2 p = ((i | j) & 1) ? scale2(half, add2(c0, xc[(hj + (j & 1)) * sc + hi + (i & 1)])) : c0;
-            x2[a] = add2(jac(mt[a], r[a]), p);
+            x2[a] = sm.pre ? add2(jac(mt[a], r[a]), p) : p;
         }
         __syncthreads();
         for (int a = threadIdx.x; a < nodes; a += kBlock) {
@@ -532,11 +612,12 @@ template <typename W> struct UpIn {
     int kind;  // 0: outside the grid rows, 1: coincides with a coarse node, 2: edge midpoint
 };
 
-// x2 at one fine point (the kind is uniform in a column walk); MASS as in jacobi_t
-template <typename T, bool MASS>
+// x2 at one fine point (the kind is uniform in a column walk); MASS as in jacobi_t; PRE: the
+// pre-smoothed omega D^{-1} r is part of x2 (V(1,1)), otherwise x2 = P x_c (V(0,1))
+template <typename T, bool MASS, bool PRE>
 __device__ __forceinline__ SV<T> up_eval_t(const UpIn<SV<T>>& u, T dl, T idl, T om, const GS<T>* z) {
     if (u.kind == 0) return sv_zero<T>();
-    const SV<T> v = jacobi_t<T, MASS>(dl, idl, om, u.mc, z, u.r);
+    const SV<T> v = PRE ? jacobi_t<T, MASS>(dl, idl, om, u.mc, z, u.r) : sv_zero<T>();
     if (u.kind == 1) return sv_add(v, u.c0);
     return sv_fma((T)0.5, sv_add(u.c0, u.c1), v);
 }
@@ -550,7 +631,8 @@ __device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl,
     return sv_add(xc, jacobi_t<T, MASS>(dl, idl, om, m.c, z, sv_sub(r, Ax)));
 }
 
-// x2 = omega D^{-1} r + P x_c (pre-smoothed iterate plus coarse correction), then one
+// x2 = omega D^{-1} r + P x_c (pre-smoothed iterate plus coarse correction; PRE = false, the
+// V(0,1) cycle: x2 = P x_c, and r is read on the centre column only), then one
 // post-smoothing sweep x3 = x2 + omega D^{-1} (r - A x2). Optionally accumulates the
 // dot partials of (x3, r). Each thread walks down one column: the seven x2 values of the
 // stencil of row j are kept in registers and only the three new ones of row j+1,
@@ -559,7 +641,7 @@ __device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl,
 // coarse values they interpolate from come from a window of coarse rows (below).
 // Three waves per SIMD (at most 168 VGPRs): the coarse window would otherwise drop to two.
 // x3 is stored with streaming access, keeping the caches for the neighbour columns' inputs.
-template <typename T, bool UNI>
+template <typename T, bool UNI, bool PRE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
     using W = SV<T>;
@@ -595,8 +677,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         auto load = [&](int d, int bj) -> UpIn<W> {
             UpIn<W> u;
             const int bc = clampi(bj, 0, nF);
-            u.r = *cboff(row_of(rin, bc, sf, lgR), ofn[d]);
-            u.mc = uload<UNI>(F.mt, (long)bc * sf + ai - 1 + d);
+            u.r = (PRE || d == 1) ? *cboff(row_of(rin, bc, sf, lgR), ofn[d]) : sv_zero<T>();
+            u.mc = PRE ? uload<UNI>(F.mt, (long)bc * sf + ai - 1 + d) : 0.0;
             const int hj = bc >> 1, oj = bc & 1;
             u.c0 = *cboff(row_of(xc, hj, sc, lgR), och[d]);
             u.c1 = *cboff(row_of(xc, hj + oj, sc, lgR), ocq[d]);
@@ -608,13 +690,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         {
             const UpIn<W> q0 = load(0, j0 - 1), q1 = load(1, j0 - 1), q2 = load(0, j0), q3 = load(1, j0),
                           q4 = load(2, j0), q5 = load(1, j0 + 1), q6 = load(2, j0 + 1);
-            xsw = up_eval_t<T, true>(q0, dl, idl, om, L.z);
-            xs = up_eval_t<T, true>(q1, dl, idl, om, L.z);
-            xw = up_eval_t<T, true>(q2, dl, idl, om, L.z);
-            xcn = up_eval_t<T, true>(q3, dl, idl, om, L.z);
-            xe = up_eval_t<T, true>(q4, dl, idl, om, L.z);
-            xn = up_eval_t<T, true>(q5, dl, idl, om, L.z);
-            xne = up_eval_t<T, true>(q6, dl, idl, om, L.z);
+            xsw = up_eval_t<T, true, PRE>(q0, dl, idl, om, L.z);
+            xs = up_eval_t<T, true, PRE>(q1, dl, idl, om, L.z);
+            xw = up_eval_t<T, true, PRE>(q2, dl, idl, om, L.z);
+            xcn = up_eval_t<T, true, PRE>(q3, dl, idl, om, L.z);
+            xe = up_eval_t<T, true, PRE>(q4, dl, idl, om, L.z);
+            xn = up_eval_t<T, true, PRE>(q5, dl, idl, om, L.z);
+            xne = up_eval_t<T, true, PRE>(q6, dl, idl, om, L.z);
             rc = q3.r;
             rn = q5.r;
         }
@@ -667,6 +749,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
             auto x2_at = [&](int bj, const W& r, double mc, const W& pxv, auto mass_) -> W {
                 constexpr bool MASS = decltype(mass_)::value;
                 if (bj < 0 || bj > nF) return sv_zero<T>();
+                if constexpr (!PRE) return pxv;
                 return sv_add(jacobi_t<T, MASS>(dl, idl, om, mc, L.z, r), pxv);
             };
             // one fine row aj < row1 (inside the chunk: computed and stored; past it: loads only)
@@ -679,8 +762,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                     R0 += 1;
                     load_crow(R0 + 1, std::integral_constant<int, 1>());
                 }
-                const W r0 = rload(0, aj + 1), r1 = rload(1, aj + 2), r2 = rload(2, aj + 2);
-                const double m0 = mload(0, aj + 1), m1 = mload(1, aj + 2), m2 = mload(2, aj + 2);
+                // (PRE = false: only the centre column's r, for the post-smoothing)
+                const W r1 = rload(1, aj + 2);
+                const W r0 = PRE ? rload(0, aj + 1) : sv_zero<T>(), r2 = PRE ? rload(2, aj + 2) : sv_zero<T>();
+                const double m0 = PRE ? mload(0, aj + 1) : 0.0, m1 = PRE ? mload(1, aj + 2) : 0.0,
+                             m2 = PRE ? mload(2, aj + 2) : 0.0;
                 issue_fence();
                 W out = sv_zero<T>();
                 if (here && aj > 0 && aj < nF) {
@@ -708,7 +794,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                     const W p0 = px(std::integral_constant<int, 0>(), RW(), EW());
                     const W p1 = px(std::integral_constant<int, 1>(), RCE(), ECE());
                     const W p2 = px(std::integral_constant<int, 2>(), RCE(), ECE());
-                    if ((nzbits(m0) | nzbits(m1) | nzbits(m2)) != 0) {  // one branch per row
+                    if (PRE && (nzbits(m0) | nzbits(m1) | nzbits(m2)) != 0) {  // one branch per row
                         xw = x2_at(aj + 1, r0, m0, p0, std::true_type());
                         xn = x2_at(aj + 2, r1, m1, p1, std::true_type());
                         xne = x2_at(aj + 2, r2, m2, p2, std::true_type());
@@ -1195,7 +1281,20 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         tm_begin(p, kid, st);
         LvArgs Fl = host_lv(p, ws, l), Cl = host_lv(p, ws, l + 1);
         bool uni = g.slot_chunk >= 64;
-        if (p.fp32) {
+        if (!p.vc_pre) {
+            if (p.fp32) {
+                if (uni)
+                    hipLaunchKernelGGL((k_vc_restrict<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+                else
+                    hipLaunchKernelGGL((k_vc_restrict<float, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+            } else {
+                if (uni)
+                    hipLaunchKernelGGL((k_vc_restrict<double, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+                else
+                    hipLaunchKernelGGL((k_vc_restrict<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin,
+                                       rout);
+            }
+        } else if (p.fp32) {
             if (uni)
                 hipLaunchKernelGGL((k_vc_down<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
             else
@@ -1213,6 +1312,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         SlotArgs sa = mk_slot(p, ws, g);
         SmallArgs sm;
         sm.count = L - l0;
+        sm.pre = p.vc_pre ? 1 : 0;
         int off = 0;
         for (int q = 0; q < sm.count; ++q) {
             const LevelDesc& d = p.lev[l0 + q];
@@ -1259,21 +1359,27 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         int kid = (l == 0) ? KID_UP0 : KID_UPC;
         tm_begin(p, kid, st);
         LvArgs Fl = host_lv(p, ws, l), Cl = host_lv(p, ws, l + 1);
-        bool uni = g.slot_chunk >= 64;
-        if (p.fp32) {
-            if (uni)
-                hipLaunchKernelGGL((k_vc_up<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm, part);
-            else
-                hipLaunchKernelGGL((k_vc_up<float, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
-                                   part);
-        } else {
-            if (uni)
-                hipLaunchKernelGGL((k_vc_up<double, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
-                                   part);
-            else
-                hipLaunchKernelGGL((k_vc_up<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
-                                   part);
-        }
+        const bool uni = g.slot_chunk >= 64;
+        auto up = [&](auto t_, auto uni_, auto pre_) {
+            using T = decltype(t_);
+            constexpr bool U = decltype(uni_)::value, PRE = decltype(pre_)::value;
+            hipLaunchKernelGGL((k_vc_up<T, U, PRE>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm, part);
+        };
+        auto up_t = [&](auto t_) {
+            using TT = std::true_type;
+            using FF = std::false_type;
+            if (uni) {
+                if (p.vc_pre) up(t_, TT(), TT());
+                else up(t_, TT(), FF());
+            } else {
+                if (p.vc_pre) up(t_, FF(), TT());
+                else up(t_, FF(), FF());
+            }
+        };
+        if (p.fp32)
+            up_t(0.0f);
+        else
+            up_t(0.0);
         tm_end(p, kid, st);
     }
 }

@@ -120,6 +120,7 @@ struct Plan {
     size_t tf_stride;                           // bytes between consecutive Krylov basis fields
     size_t ws_bytes;
     bool has_cocg_vectors;
+    bool vc_pre;        // the cycle pre-smooths (V(1,1)); otherwise V(0,1)
     // host copies of the small tables uploaded at every call
     double* h_tw64;     // N complex: exp(-2 pi i k / N)
     float* h_tw32;      // N complex, float

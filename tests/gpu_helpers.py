@@ -70,11 +70,12 @@ def _prolongation(nc):
     return sp.csr_matrix((vals, (rows, cols)), shape=(sf * sf, sc * sc))
 
 
-def vcycle_reference(d, omega, R):
-    """One V(1,1) cycle B_s r_s per frequency slot, written out from its definition on the
-    interior nodes of each level: x1 = omega D^{-1} r, r_c = P^T (r - A x1), x_c = the cycle on
-    the next level (exact on the 2 x 2-cell grid), x2 = x1 + P x_c,
-    x3 = x2 + omega D^{-1} (r - A x2), with A = Khat + z M, Khat = nu_max * (5-point stencil),
+def vcycle_reference(d, omega, R, pre=1, post=1):
+    """One V(pre,post) cycle B_s r_s per frequency slot (pre, post in {0, 1}; default V(1,1)),
+    written out from its definition on the interior nodes of each level: x1 = omega D^{-1} r
+    (x1 = 0 without pre-smoothing), r_c = P^T (r - A x1), x_c = the cycle on the next level
+    (exact on the 2 x 2-cell grid), x2 = x1 + P x_c, x3 = x2 + omega D^{-1} (r - A x2)
+    (x3 = x2 without post-smoothing), with A = Khat + z M, Khat = nu_max * (5-point stencil),
     D = 4 nu_max + z diag(M), P the P1 interpolation and the coarse mass P^T M P.
     R: (nodes, S) complex; slot 0 holds the k = 0 system on the real part and k = N/2 on the
     imaginary part."""
@@ -104,10 +105,10 @@ def vcycle_reference(d, omega, R):
         D = 4 * nu + zz * L["dM"]
         if L["n"] == 2:
             return r / D
-        x1 = omega * r / D
+        x1 = omega * r / D if pre else np.zeros_like(r)
         rc = L["P"].T @ (r - A @ x1)
         x2 = x1 + L["P"] @ cycle(l + 1, zz, rc)
-        return x2 + omega * (r - A @ x2) / D
+        return x2 + omega * (r - A @ x2) / D if post else x2
 
     fi = levels[0]["free"]
     out = np.zeros_like(R, dtype=np.complex128)

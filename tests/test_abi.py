@@ -54,6 +54,7 @@ def test_options_defaults(P):
     assert o.tol == 1e-8 and o.max_outer == 1000 and o.check_every == 1
     assert o.precision == L.PT_FP64 and o.inner == L.PT_INNER_GALERKIN1
     assert o.vc_sweeps == 1 and abs(o.vc_omega - 0.8) < 1e-15 and o.timing == 0
+    assert o.vc_cycle == L.PT_VC_DEFAULT
 
 
 @pytest.mark.parametrize("field,value", [("n", 30), ("n", 2), ("N", 3), ("N", 2048), ("T", 0.0),
@@ -69,10 +70,23 @@ def test_plan_rejects_invalid_problems(P, field, value):
 
 
 @pytest.mark.parametrize("kw", [dict(tol=0.0), dict(max_outer=0), dict(check_every=0), dict(inner_iters=0),
-                                dict(inner_iters=65), dict(vc_omega=1.0)])
+                                dict(inner_iters=65), dict(vc_omega=1.0), dict(inner="cocg", cycle="v01")])
 def test_plan_rejects_invalid_options(P, kw):
     with pytest.raises(P.PTError):
         P.Plan(W.config1(), **kw)
+
+
+def test_plan_rejects_unknown_cycle(P):
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    o = P._options(lib, 1e-8, 10, 1, "fp64", "galerkin1", 1, 0.8, False, 1e3, True, False, False)
+    o.vc_cycle = 3
+    ps = P.problem_struct(W.config1())
+    h = C.c_void_p()
+    assert lib.pt_plan_create(C.byref(ps), C.byref(o), C.byref(h)) == L.PT_ERR_INVALID
+    assert b"vc_cycle" in lib.pt_last_error()
+    for cyc, inner in (("v11", "galerkin1"), ("v01", "galerkin1"), ("v11", "cocg"), ("default", "cocg")):
+        P.Plan(W.config1(), inner=inner, cycle=cyc).close()
 
 
 def test_workspace_sizes_scale_with_problem_and_precision(P):

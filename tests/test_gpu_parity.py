@@ -174,7 +174,7 @@ def test_vcycle_is_symmetric_and_contracts(gpu, P, n, N, grid, precision):
     say(f"vcycle n={n} N={N} grid={grid} {precision}")
     p = W.with_size(W.config2(2), n, N)
     d = fem.discretise(p)
-    plan = P.Plan(p, grid_slot=grid, precision=precision)
+    plan = P.Plan(p, grid_slot=grid, precision=precision, cycle="v11")
     rng = np.random.default_rng(3)
     nodes = (n + 1) ** 2
     r1 = rng.standard_normal((nodes, N // 2)) + 1j * rng.standard_normal((nodes, N // 2))
@@ -206,14 +206,16 @@ def test_vcycle_is_symmetric_and_contracts(gpu, P, n, N, grid, precision):
 
 
 # n = 16: the finest level in the per-level sweeps, the rest (9, 5, 3 points per side) in the
-# small-level kernel; n = 64 and 128: two and three levels in the per-level sweeps
-@pytest.mark.parametrize("n,N", [(16, 8), (64, 8), (128, 4)])
+# small-level kernel; n = 64 and 128: two and three levels in the per-level sweeps; (64, 8, 66):
+# row chunks that start on odd rows. Both cycle shapes, V(1,1) and V(0,1).
+@pytest.mark.parametrize("n,N,grid", [(16, 8, 0), (64, 8, 0), (128, 4, 0), (64, 8, 66)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_vcycle_matches_its_definition(gpu, P, n, N, precision):
-    say(f"vcycle definition n={n} N={N} {precision}")
+@pytest.mark.parametrize("cycle", ["v11", "v01"])
+def test_vcycle_matches_its_definition(gpu, P, n, N, grid, precision, cycle):
+    say(f"vcycle definition n={n} N={N} grid={grid} {precision} {cycle}")
     p = W.with_size(W.config2(2), n, N)
     d = fem.discretise(p)
-    plan = P.Plan(p, precision=precision, vc_omega=0.8)
+    plan = P.Plan(p, precision=precision, vc_omega=0.8, cycle=cycle, grid_slot=grid)
     rng = np.random.default_rng(n + N)
     nodes = (n + 1) ** 2
     R = rng.standard_normal((nodes, N // 2)) + 1j * rng.standard_normal((nodes, N // 2))
@@ -221,10 +223,36 @@ def test_vcycle_matches_its_definition(gpu, P, n, N, precision):
     cd = np.complex128 if precision == "fp64" else np.complex64
     R = R.astype(cd)
     B = plan.precond_apply(dev(R)).cpu().numpy().astype(np.complex128)
-    ref = vcycle_reference(d, 0.8, R.astype(np.complex128))
+    ref = vcycle_reference(d, 0.8, R.astype(np.complex128), pre=1 if cycle == "v11" else 0)
     tol = 1e-12 if precision == "fp64" else 5e-5
     assert rel_err(B, ref) <= tol
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_v01_cycle_contracts(gpu, P, precision):
+    # the default cycle of the Galerkin step: x <- x + B (r - A x) converges at a
+    # mesh-independent rate (checked at two sizes)
+    for n in (32, 64):
+        say(f"v01 contraction n={n} {precision}")
+        p = W.with_size(W.config2(2), n, 16)
+        d = fem.discretise(p)
+        plan = P.Plan(p, precision=precision, cycle="v01")
+        rng = np.random.default_rng(5)
+        nodes = (n + 1) ** 2
+        r1 = rng.standard_normal((nodes, 8)) + 1j * rng.standard_normal((nodes, 8))
+        r1[~d.mesh.free] = 0
+        cd = np.complex128 if precision == "fp64" else np.complex64
+        r1 = r1.astype(cd)
+        x = np.zeros_like(r1)
+        rn0 = np.linalg.norm(r1, axis=0)
+        for _ in range(6):
+            Ax = plan.shifted_apply(dev(x)).cpu().numpy()
+            x = x + plan.precond_apply(dev((r1 - Ax).astype(cd))).cpu().numpy()
+        rn = np.linalg.norm(r1 - plan.shifted_apply(dev(x)).cpu().numpy(), axis=0)
+        rate = (rn / rn0) ** (1 / 6)
+        assert np.all(rate < 0.5), rate.max()
+        plan.close()
 
 
 # ---------------------------------------------------------------- periodic linear solve

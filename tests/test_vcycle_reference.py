@@ -1,8 +1,9 @@
-"""Pins of the test-side V(1,1) reference (tests/gpu_helpers.vcycle_reference) against facts
-that do not depend on it: P1 interpolation is exact on linear functions, the Galerkin coarse
-mass equals the mass assembled on the coarse mesh when the conductivity is constant on coarse
-triangles, the cycle is symmetric in the bilinear form, it is the exact solve on the 2 x 2-cell
-grid, and as a stationary iteration it contracts at a mesh-independent rate."""
+"""Pins of the test-side V-cycle reference (tests/gpu_helpers.vcycle_reference, V(1,1) and
+V(0,1)) against facts that do not depend on it: P1 interpolation is exact on linear functions,
+the Galerkin coarse mass equals the mass assembled on the coarse mesh when the conductivity is
+constant on coarse triangles, V(1,1) is symmetric in the bilinear form and V(0,1) is the
+transpose of V(1,0), both are the exact solve on the 2 x 2-cell grid, and as stationary
+iterations they contract at a mesh-independent rate."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -50,9 +51,28 @@ def test_reference_cycle_is_symmetric():
         assert abs(a - b) <= 1e-13 * abs(a)
 
 
-def test_reference_cycle_is_exact_on_the_coarsest_grid():
+def test_reference_v01_is_the_transpose_of_v10():
+    # The V(0,1) cycle smooths after the coarse correction only; its transpose in the bilinear
+    # form is the V(1,0) cycle that smooths before it only (A, D and P^T M P are symmetric), so
+    # r2^T B01 r1 = r1^T B10 r2. The two cycles run different code (no pre- / no post-smoothing).
+    d, R1 = _setup(16, 8, 1)
+    _, R2 = _setup(16, 8, 2)
+    B01 = vcycle_reference(d, 0.8, R1, pre=0, post=1)
+    B10 = vcycle_reference(d, 0.8, R2, pre=1, post=0)
+    for s in range(1, 4):
+        a, b = np.sum(B01[:, s] * R2[:, s]), np.sum(R1[:, s] * B10[:, s])
+        assert abs(a - b) <= 1e-13 * abs(a)
+    # and V(0,1) is not symmetric itself (the pins above and below would not see a cycle that
+    # ignored the pre flag)
+    B01b = vcycle_reference(d, 0.8, R2, pre=0, post=1)
+    a, b = np.sum(B01[:, 1] * R2[:, 1]), np.sum(R1[:, 1] * B01b[:, 1])
+    assert abs(a - b) > 1e-6 * abs(a)
+
+
+@pytest.mark.parametrize("pre", [1, 0])
+def test_reference_cycle_is_exact_on_the_coarsest_grid(pre):
     d, R = _setup(2, 8, 3)
-    B = vcycle_reference(d, 0.8, R)
+    B = vcycle_reference(d, 0.8, R, pre=pre)
     z = dft.shifts(8, d.p.tau)
     A = lambda zz: (d.Khat + zz * d.M).toarray()
     fi = d.free_idx
@@ -60,8 +80,8 @@ def test_reference_cycle_is_exact_on_the_coarsest_grid():
         assert np.allclose(A(z[s]) @ B[fi, s], R[fi, s], rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("n", [16, 32])
-def test_reference_cycle_contracts(n):
+@pytest.mark.parametrize("n,pre", [(16, 1), (32, 1), (32, 0)])
+def test_reference_cycle_contracts(n, pre):
     d, R = _setup(n, 8, 4)
     z = dft.shifts(8, d.p.tau)
     fi = d.free_idx
@@ -74,7 +94,7 @@ def test_reference_cycle_contracts(n):
             res[fi] = R[fi, s] - A @ x
             Rs = np.zeros_like(R)
             Rs[:, s] = res
-            x = x + vcycle_reference(d, 0.8, Rs)[fi, s]
+            x = x + vcycle_reference(d, 0.8, Rs, pre=pre)[fi, s]
         rate = (np.linalg.norm(R[fi, s] - A @ x) / r0) ** (1 / 6)
         assert rate < 0.5
         # and the iterate approaches the direct solution
