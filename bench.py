@@ -147,12 +147,14 @@ def batch_roofline(P, problems, tol, tuning):
 
 
 def rel_l2_pairs(A, B):
-    """max over instance pairs of ||a - b|| / ||b|| (device tensors)."""
-    worst = 0.0
-    for a, b in zip(A, B):
+    """(max over instance pairs of ||a - b|| / ||b||, index of that pair) (device tensors)."""
+    worst, at = 0.0, -1
+    for i, (a, b) in enumerate(zip(A, B)):
         nb = float(b.norm())
-        worst = max(worst, float((a - b).norm()) / nb if nb > 0 else float((a - b).norm()))
-    return worst
+        e = float((a - b).norm()) / nb if nb > 0 else float((a - b).norm())
+        if e > worst or at < 0:
+            worst, at = e, i
+    return worst, at
 
 
 def batching_record(args, P, cpu=None):
@@ -170,7 +172,12 @@ def batching_record(args, P, cpu=None):
                                  trace_gap=args.trace_gap)
         sols[m] = (ms, r)
         log(f"{m}: {res[m]['ms_per_step']:.1f} ms for all instances")
-    err = rel_l2_pairs(sols["fp32"][1].U, sols["fp64"][1].U) if len(sols) == 2 else None
+    err = worst = None
+    if len(sols) == 2:
+        err, at = rel_l2_pairs(sols["fp32"][1].U, sols["fp64"][1].U)
+        # the instance where the modes differ most: its outer steps and final residuals in both modes
+        worst = {"instance": at, **{m: {"outer_iters": sols[m][1].stats[at].outer_iters,
+                                         "rel_residual": sols[m][1].stats[at].rel_residual} for m in sols}}
     for m in sols:
         sols[m][0].close()
     del sols
@@ -195,6 +202,7 @@ def batching_record(args, P, cpu=None):
         "modes": {m: dict(res[m], value=total / (res[m]["ms_per_step"] * 1e-3)) for m in res},
         "plain_fp64_each": plain,
         "err_fp32_vs_fp64_max_rel_l2": err,
+        "err_fp32_vs_fp64_worst_instance": worst,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -213,6 +221,7 @@ def main_many(args, P, cpu=None):
         "roofline": rec["roofline"], "cpu_baseline": cpu,
         "modes": rec["modes"], "plain_fp64_each": rec["plain_fp64_each"],
         "err_fp32_vs_fp64_max_rel_l2": rec["err_fp32_vs_fp64_max_rel_l2"],
+        "err_fp32_vs_fp64_worst_instance": rec["err_fp32_vs_fp64_worst_instance"],
     }
     print(json.dumps(out), flush=True)
 
@@ -420,7 +429,8 @@ def cpu_baseline(kind, seed, n=32, N=64, tol=1e-8):
 # ---------------------------------------------------------------- HBM traffic from rocprofv3 counters
 
 KERNEL_CLASSES = [("k_residual", "residual_sweep"), ("k_rfft", "rfft"), ("k_vc_down", "vcycle_down_fine"),
-                  ("k_vc_up", "vcycle_up_fine"), ("k_matvec", "matvec_dot"), ("k_inverse", "inverse_rfft_update")]
+                  ("k_vc_restrict", "vcycle_down_fine"), ("k_vc_up", "vcycle_up_fine"), ("k_matvec", "matvec_dot"),
+                  ("k_inverse", "inverse_rfft_update")]
 
 
 def _pmc_rows(db_path):
@@ -440,8 +450,9 @@ def _per_class(rows, counter):
     """Average counter value (KiB) per dispatch of the finest-level launches of each kernel class:
     the dispatches lasting at least half as long as the longest one of that kernel."""
     res = {}
-    for key, cls in KERNEL_CLASSES:
-        ds = [(v, d) for (k, c, v, d) in rows if c == counter and key in k]
+    for cls in dict.fromkeys(c for _, c in KERNEL_CLASSES):
+        keys = [k for k, c in KERNEL_CLASSES if c == cls]
+        ds = [(v, d) for (k, c, v, d) in rows if c == counter and any(key in k for key in keys)]
         if not ds:
             continue
         dmax = max(d for _, d in ds)

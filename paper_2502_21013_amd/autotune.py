@@ -3,15 +3,16 @@
 The quantity minimised is the predicted time to tolerance: (device time per outer step)
 x (outer steps to reach tol at the contraction rate measured over a few probe steps).
 The grid targets change only how the sweeping kernels are cut into workgroups; the
-Jacobi damping omega of the V(1,1) cycle also changes the inner approximation and hence
-the contraction rate, which is why the rate is measured rather than assumed.
+Jacobi damping omega of the cycle also changes the inner approximation and hence the
+contraction rate, which is why the rate is measured rather than assumed.
 
 The search is coordinate-wise (the inner method, omega, then the slot-vector grid, then the
 time-axis grid), each over a short candidate list, starting from the library defaults. The
-inner method axis compares the one-step Galerkin V-cycle with COCG of a few steps and with
-COCG stopped per frequency at a relative tolerance: more inner work per step against fewer
-outer steps, which is what the predicted time to tolerance weighs. Results are kept in a
-plain JSON table keyed by grid, period, batch size and precision.
+inner method axis compares the one-step Galerkin step on a V(0,1) and on a V(1,1) cycle with
+COCG of a few steps and with COCG stopped per frequency at a relative tolerance: more inner
+work per step against fewer outer steps, which is what the predicted time to tolerance
+weighs. Results are kept in a plain JSON table keyed by grid, period, batch size and
+precision.
 """
 from __future__ import annotations
 
@@ -25,8 +26,9 @@ from typing import Callable, Dict, List, Optional, Sequence
 OMEGAS = (0.8,)
 GRID_SLOT = (1024, 2048, 4096, 8192, 16384)
 GRID_TEAM = (16384, 65536, 262144, 1048576)
-# inner methods: (inner, inner_iters, inner_rtol)
-INNER = (("galerkin1", 1, 0.0), ("cocg", 2, 0.0), ("cocg", 4, 0.1))
+# inner methods: (inner, inner_iters, inner_rtol, cycle); COCG needs the symmetric V(1,1)
+INNER = (("galerkin1", 1, 0.0, "v01"), ("galerkin1", 1, 0.0, "v11"), ("cocg", 2, 0.0, "v11"),
+         ("cocg", 4, 0.1, "v11"))
 
 
 def _probe(make_plan: Callable, kw: Dict, steps: int, tol: float) -> Dict:
@@ -61,9 +63,9 @@ def tune(make_plan: Callable, *, tol: float = 1e-8, steps: int = 12, omegas: Seq
          grid_slot: Sequence[int] = GRID_SLOT, grid_team: Sequence[int] = GRID_TEAM,
          inner: Sequence = INNER, log=None) -> Dict:
     """make_plan(max_outer=..., vc_omega=..., grid_slot=..., grid_team=..., inner=..., inner_iters=...,
-    inner_rtol=...) -> Plan or BatchPlan. Returns {"best": kwargs, "trials": [...]}."""
-    best = {"inner": "galerkin1", "inner_iters": 1, "inner_rtol": 0.0, "vc_omega": 0.8, "grid_slot": 0,
-            "grid_team": 0}
+    inner_rtol=..., cycle=...) -> Plan or BatchPlan. Returns {"best": kwargs, "trials": [...]}."""
+    best = {"inner": "galerkin1", "inner_iters": 1, "inner_rtol": 0.0, "cycle": "v01", "vc_omega": 0.8,
+            "grid_slot": 0, "grid_team": 0}
     trials: List[Dict] = []
     cache = {}
 
@@ -81,10 +83,10 @@ def tune(make_plan: Callable, *, tol: float = 1e-8, steps: int = 12, omegas: Seq
 
     scores = {}
     for c in inner:
-        kw = dict(best, inner=c[0], inner_iters=c[1], inner_rtol=c[2])
+        kw = dict(best, inner=c[0], inner_iters=c[1], inner_rtol=c[2], cycle=c[3])
         scores[c] = run(kw)
     c = min(scores, key=scores.get)
-    best.update(inner=c[0], inner_iters=c[1], inner_rtol=c[2])
+    best.update(inner=c[0], inner_iters=c[1], inner_rtol=c[2], cycle=c[3])
     for name, cands in (("vc_omega", omegas), ("grid_slot", grid_slot), ("grid_team", grid_team)):
         scores = {}
         for c in cands:

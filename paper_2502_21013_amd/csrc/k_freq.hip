@@ -10,7 +10,9 @@
 //   M x    = 7-point stencil from the level's table (c, e, n, ne, and symmetry)
 // Multigrid: damped Jacobi smoothing with D = 4 nu_max + z diag(M), P1 interpolation P
 // between nested grids, restriction P^T, Galerkin coarse mass (k_setup.hip), exact solve
-// on the 2 x 2-cell grid (one unknown). One V(1,1) cycle is symmetric (B^T = B).
+// on the 2 x 2-cell grid (one unknown). A V(1,1) cycle (k_vc_down, k_vc_up) is symmetric
+// (B^T = B, as COCG needs); a V(0,1) cycle (k_vc_restrict, k_vc_up without pre-smoothing)
+// skips the pre-smoothing sweep and its operator evaluation on every level.
 #include <type_traits>
 
 #include "pt_device.h"

@@ -174,7 +174,7 @@ def test_autotuner_picks_a_valid_setting(gpu, P):
     r = AT.tune(mk, tol=1e-10, steps=8, omegas=(0.7, 0.8), grid_slot=(256, 2048), grid_team=(1024, 16384))
     best = r["best"]
     assert best["vc_omega"] in (0.7, 0.8) and best["grid_slot"] in (256, 2048) and best["grid_team"] in (1024, 16384)
-    assert (best["inner"], best["inner_iters"], best["inner_rtol"]) in AT.INNER
+    assert (best["inner"], best["inner_iters"], best["inner_rtol"], best["cycle"]) in AT.INNER
     assert all(0 < t["rate"] < 1 and t["step_ms"] > 0 for t in r["trials"])
     # the tuned plan reaches the same solution
     U, st = P.BatchPlan(ps, tol=1e-12, max_outer=2000, **best).solve()
