@@ -293,10 +293,24 @@ def load_traffic(kernel, mode, wl):
 
 
 def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inner=None):
+    """Time `steps` solves after `warmup` untimed ones. Before them, one untimed solve with every
+    kernel class bracketed by HIP events gives the per-class device times; the timed solves then
+    bracket only the two classes with the most device time (two event records per launch of
+    those, instead of around every launch), which is where the roofline kernel comes from."""
     import torch
     kw = dict(inner or {})
     kw.update(tuned or {})   # a tuning table entry overrides the inner method given on the command line
     plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer, **kw)
+    U = plan.new_time_field()
+    plan.workspace()
+    _, st = plan.solve(U, raise_on_error=max_outer >= 2000)
+    all_ms, all_n = dict(st.kernel_ms), dict(st.kernel_launches)
+    top = sorted(all_ms, key=all_ms.get, reverse=True)[:2]
+    log(f"{mode} per-kernel pass: outer={st.outer_iters} {st.time_ms:.1f} ms; timed classes {top}")
+    plan.close()
+    del plan, U
+    torch.cuda.empty_cache()
+    plan = P.Plan(prob, tol=tol, precision=mode, timing=tuple(top), max_outer=max_outer, **kw)
     U = plan.new_time_field()
     plan.workspace()
     for w in range(warmup):
@@ -318,6 +332,7 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inne
     del plan
     torch.cuda.empty_cache()
     return {"ms_per_step": 1e3 * wall / steps, "kernel_ms": kms, "kernel_launches": kcnt,
+            "kernel_ms_pass": all_ms, "kernel_launches_pass": all_n,
             "outer_iters": outer, "rel_residual": st.rel_residual, "U": U}
 
 
@@ -641,13 +656,16 @@ def main():
     r0 = res[primary]
     elem = 8 if primary == "fp32" else 16
     ab = algorithmic_bytes(prob, elem)
-    kern = {}
-    for name, b in ab.items():
-        if name in r0["kernel_ms"]:
-            avg_ms = r0["kernel_ms"][name] / r0["kernel_launches"][name]
-            kern[name] = {"avg_ms": avg_ms, "launches": r0["kernel_launches"][name],
-                          "total_ms": r0["kernel_ms"][name], "alg_bytes": b,
-                          "achieved_gbs": b / (avg_ms * 1e-3) / 1e9}
+    def per_kernel(ms, cnt):
+        out = {}
+        for name, b in ab.items():
+            if name in ms:
+                avg_ms = ms[name] / cnt[name]
+                out[name] = {"avg_ms": avg_ms, "launches": cnt[name], "total_ms": ms[name], "alg_bytes": b,
+                             "achieved_gbs": b / (avg_ms * 1e-3) / 1e9}
+        return out
+    kern = per_kernel(r0["kernel_ms"], r0["kernel_launches"])              # timed region
+    kern_pass = per_kernel(r0["kernel_ms_pass"], r0["kernel_launches_pass"])  # per-kernel pass
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     dk = kern[dom]
     traffic = load_traffic(dom, primary, args.workload)
@@ -684,7 +702,12 @@ def main():
         "errors": errors,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
-        "kernel_ms_all": {k: round(v, 3) for k, v in r0["kernel_ms"].items()},
+        "kernels_per_kernel_pass": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                                    for k, v in kern_pass.items()},
+        "kernel_ms_all": {k: round(v, 3) for k, v in r0["kernel_ms_pass"].items()},
+        "timing_note": "the timed solves bracket only the two kernel classes of `kernels` with HIP events; "
+                       "`kernels_per_kernel_pass` and `kernel_ms_all` come from one untimed solve before "
+                       "them with every launch bracketed",
         "batching": batching,
         "paper_context": PAPER_CONTEXT,
     }

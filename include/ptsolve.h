@@ -183,6 +183,10 @@ typedef struct {
                               |p^T A p| <= breakdown_tol Re(p^H A p) (the bilinear form vanishes to
                               rounding); 0 = 64 units in the last place of the solver precision */
     int32_t vc_cycle;      /* pt_vcycle; PT_VC_V01 requires PT_INNER_GALERKIN1 */
+    int32_t timing_mask;   /* with timing = 1: bit k set = time the launches of kernel class k
+                              (pt_kernel_class_name(k)) only; 0 = every class. Each timed launch
+                              adds two event records to the stream, so timing fewer classes
+                              perturbs the timed solve less. Bits >= PT_KERNEL_CLASSES: invalid. */
 } pt_options;
 
 typedef struct {

@@ -106,7 +106,15 @@ def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc
     o.inner_iters, o.vc_omega = int(inner_iters), float(vc_omega)
     o.use_initial_guess = 1 if use_initial_guess else 0
     o.diverge_factor, o.xcd_remap = float(diverge_factor), 1 if xcd_remap else 0
-    o.timing = 1 if timing else 0
+    # timing: False, True (every kernel class) or a collection of class names to time alone
+    if isinstance(timing, (list, tuple, set, frozenset)):
+        names = {lib.pt_kernel_class_name(k).decode(): k for k in range(L.PT_KERNEL_CLASSES)}
+        unknown = [c for c in timing if c not in names]
+        if unknown or not timing:
+            raise ValueError(f"timing: unknown or no kernel classes {unknown}")
+        o.timing, o.timing_mask = 1, sum(1 << names[c] for c in set(timing))
+    else:
+        o.timing = 1 if timing else 0
     o.graph = 1 if graph else 0
     o.grid_slot, o.grid_team = int(grid_slot), int(grid_team)
     o.adjoint = 1 if adjoint else 0

@@ -60,7 +60,7 @@ class Options(C.Structure):
         ("init_static", C.c_int32), ("init_tol", C.c_double), ("stop_relative_initial", C.c_int32),
         ("krylov_dim", C.c_int32), ("forcing", C.c_double), ("max_krylov", C.c_int32),
         ("graph", C.c_int32), ("inner_rtol", C.c_double), ("breakdown_tol", C.c_double),
-        ("vc_cycle", C.c_int32),
+        ("vc_cycle", C.c_int32), ("timing_mask", C.c_int32),
     ]
 
 

@@ -68,16 +68,15 @@ static void tm_flush(const Plan& p) {
 }
 
 void tm_begin(const Plan& p, int kid, hipStream_t st) {
-    (void)kid;
     Timer* t = p.tm;
-    if (!t || !t->on) return;
+    if (!t || !t->on || !((t->mask >> kid) & 1u)) return;
     if (t->used == Timer::kCap) tm_flush(p);
     hipEventRecord(t->ev[2 * t->used], st);
 }
 
 void tm_end(const Plan& p, int kid, hipStream_t st) {
     Timer* t = p.tm;
-    if (!t || !t->on) return;
+    if (!t || !t->on || !((t->mask >> kid) & 1u)) return;
     hipEventRecord(t->ev[2 * t->used + 1], st);
     t->kid[t->used] = kid;
     t->used += 1;
@@ -188,6 +187,8 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
     if (o->vc_sweeps != 1) return fail(PT_ERR_INVALID, "vc_sweeps must be 1 (fused smoothing sweeps)");
     if (o->vc_cycle != PT_VC_DEFAULT && o->vc_cycle != PT_VC_V11 && o->vc_cycle != PT_VC_V01)
         return fail(PT_ERR_INVALID, "unknown vc_cycle");
+    if (o->timing_mask < 0 || o->timing_mask >= (1 << KID_COUNT))
+        return fail(PT_ERR_INVALID, "timing_mask has bits beyond the kernel classes");
     if (o->vc_cycle == PT_VC_V01 && o->inner == PT_INNER_COCG)
         return fail(PT_ERR_INVALID, "COCG needs the symmetric V(1,1) cycle (vc_cycle PT_VC_V11)");
     if (!(o->inner_rtol >= 0 && o->inner_rtol < 1)) return fail(PT_ERR_INVALID, "inner_rtol must be in [0, 1)");
@@ -406,6 +407,7 @@ static pt_status timer_start(Plan& p) {
         for (int i = 0; i < 2 * Timer::kCap; ++i) PT_HIP(hipEventCreate(&p.tm->ev[i]));
     }
     p.tm->on = true;
+    p.tm->mask = p.opt.timing_mask ? (unsigned)p.opt.timing_mask : ~0u;
     p.tm->used = 0;
     for (int c = 0; c < KID_COUNT; ++c) {
         p.tm->ms[c] = 0.0;

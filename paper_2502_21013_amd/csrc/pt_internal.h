@@ -83,6 +83,7 @@ enum KernelId {
 struct Timer {
     static constexpr int kCap = 256;
     bool on = false;
+    unsigned mask = ~0u;   // kernel classes that are timed (bit per class)
     int used = 0;
     hipEvent_t ev[2 * kCap];
     int kid[kCap];

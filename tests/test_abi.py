@@ -89,6 +89,26 @@ def test_plan_rejects_unknown_cycle(P):
         P.Plan(W.config1(), inner=inner, cycle=cyc).close()
 
 
+def test_timing_mask_validation(P):
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    ps = P.problem_struct(W.config1())
+    h = C.c_void_p()
+    o = P._options(lib, 1e-8, 10, 1, "fp64", "galerkin1", 1, 0.8, False, 1e3, True, True, False)
+    o.timing_mask = 1 << L.PT_KERNEL_CLASSES
+    assert lib.pt_plan_create(C.byref(ps), C.byref(o), C.byref(h)) == L.PT_ERR_INVALID
+    assert b"timing_mask" in lib.pt_last_error()
+    o.timing_mask = -1
+    assert lib.pt_plan_create(C.byref(ps), C.byref(o), C.byref(h)) == L.PT_ERR_INVALID
+    with pytest.raises(ValueError):
+        P.Plan(W.config1(), timing=("no_such_kernel",))
+    with pytest.raises(ValueError):
+        P.Plan(W.config1(), timing=())
+    pl = P.Plan(W.config1(), timing=("inverse_rfft_update", "residual_sweep"))
+    assert pl._opts.timing == 1 and pl._opts.timing_mask == (1 << 2) | (1 << 11)
+    pl.close()
+
+
 def test_workspace_sizes_scale_with_problem_and_precision(P):
     small = P.Plan(W.with_size(W.config1(), 16, 8)).workspace_bytes
     big = P.Plan(W.config1()).workspace_bytes

@@ -110,6 +110,29 @@ def test_checking_every_few_steps_gives_the_same_iterates(gpu, P):
     assert s4.rel_residual <= 1e-9
 
 
+def test_per_kernel_timer_counts_and_mask(gpu, P):
+    # The event timer sees every launch of the fixed-point step: one residual sweep per step plus
+    # the final one, one inverse per step, one restriction and one up sweep per step on the finest
+    # level. With a class mask only those classes are bracketed, with the same counts, and the
+    # iterates are bitwise those of an untimed solve.
+    say("per-kernel timer")
+    p = W.with_size(W.config2(3), 64, 16)
+    U0, s0 = P.Plan(p, tol=1e-9).solve()
+    Ua, sa = P.Plan(p, tol=1e-9, timing=True).solve()
+    k = sa.outer_iters
+    assert k == s0.outer_iters and torch.equal(Ua, U0)
+    n = sa.kernel_launches
+    assert n["residual_sweep"] == k + 1 and n["inverse_rfft_update"] == k
+    assert n["vcycle_down_fine"] == k and n["vcycle_up_fine"] == k and n["matvec_dot"] == k
+    assert all(v > 0 for v in sa.kernel_ms.values())
+    Ub, sb = P.Plan(p, tol=1e-9, timing=("inverse_rfft_update", "residual_sweep")).solve()
+    assert torch.equal(Ub, U0)
+    assert set(sb.kernel_ms) == {"inverse_rfft_update", "residual_sweep"}
+    assert sb.kernel_launches["residual_sweep"] == k + 1 and sb.kernel_launches["inverse_rfft_update"] == k
+    with pytest.raises(ValueError):
+        P.Plan(p, timing=("no_such_kernel",))
+
+
 # ---------------------------------------------------------------- full-size workloads
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
