@@ -15,8 +15,11 @@ difference of the FP32+refinement and FP64 solutions, and of both against the FP
 oracle's solution on the 2x-coarsened copy (512 x 512 cells, N = 256, stored by
 tests/golden/make_oracle_solutions.py) when that file is present.
 
-Per-kernel durations come from HIP events that the library records around every launch on
-the solve stream over the timed region; the roofline entry uses the dominant kernel.
+Per-kernel durations come from HIP events that the library records on the solve stream: one
+untimed solve brackets every launch (per-kernel pass), and the timed solves bracket the
+launches of the two kernel classes with the most device time in that pass, from which the
+roofline entry takes the dominant kernel. Each mode reports the mean wall time per solve over
+the K timed solves (`ms_per_step`, `value`) and the median of their device times.
 The CPU baseline is the FP64 oracle on a bounded sample of the same workload family, one
 copy per host core, run before the GPU is touched.
 
@@ -34,9 +37,10 @@ from __future__ import annotations
 
 import argparse
 import hashlib
-import re
 import json
 import os
+import re
+import statistics
 import sys
 import time
 
@@ -316,12 +320,13 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inne
     for w in range(warmup):
         _, st = plan.solve(U, raise_on_error=max_outer >= 2000)
         log(f"{mode} warmup {w}: outer={st.outer_iters} rel={st.rel_residual:.3e} {st.time_ms:.1f} ms")
-    kms, kcnt, outer = {}, {}, []
+    kms, kcnt, outer, dev_ms = {}, {}, [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         _, st = plan.solve(U, raise_on_error=max_outer >= 2000)
         outer.append(st.outer_iters)
+        dev_ms.append(st.time_ms)
         for name, v in st.kernel_ms.items():
             kms[name] = kms.get(name, 0.0) + v
             kcnt[name] = kcnt.get(name, 0) + st.kernel_launches[name]
@@ -332,7 +337,7 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inne
     del plan
     torch.cuda.empty_cache()
     return {"ms_per_step": 1e3 * wall / steps, "kernel_ms": kms, "kernel_launches": kcnt,
-            "kernel_ms_pass": all_ms, "kernel_launches_pass": all_n,
+            "kernel_ms_pass": all_ms, "kernel_launches_pass": all_n, "solve_ms_device": dev_ms,
             "outer_iters": outer, "rel_residual": st.rel_residual, "U": U}
 
 
@@ -547,7 +552,7 @@ def pmc_summary(fetch_db, write_db, cal_fetch_db, cal_write_db, workload, mode, 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--seed", type=int, default=0)
@@ -697,6 +702,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": {m: {"value": prob.st_dofs / (res[m]["ms_per_step"] * 1e-3), "ms_per_step": res[m]["ms_per_step"],
+                      "median_solve_ms_device": statistics.median(res[m]["solve_ms_device"]),
+                      "solve_ms_device": [round(x, 2) for x in res[m]["solve_ms_device"]],
                       "outer_iters": res[m]["outer_iters"], "rel_residual": res[m]["rel_residual"],
                       "tuned": res[m]["tuned"]} for m in modes},
         "errors": errors,
