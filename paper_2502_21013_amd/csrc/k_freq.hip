@@ -812,9 +812,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 step(aj, std::true_type());
                 ++aj;
             }
-            for (; aj < sr.row1; aj += 2) {
+            // four rows per iteration: the window's values then come back to the registers they
+            // started in after fewer register moves than with two (1.04 -> 1.00 ms at 1024^2 x 512)
+            for (; aj < sr.row1; aj += 4) {
                 step(aj, std::false_type());
                 step(aj + 1, std::true_type());
+                step(aj + 2, std::false_type());
+                step(aj + 3, std::true_type());
             }
         };
         if (ai & 1)
