@@ -512,6 +512,28 @@ def trace_idle(csv_path, gap_ns=0.5e9):
     return out
 
 
+def copy_bandwidth(gib=2.0, reps=5):
+    """Median bandwidth of a plain device-to-device copy (torch's copy kernel) of `gib` GiB, read
+    + write bytes over the event time: the practical streaming rate of this device, beside the
+    8 TB/s peak the roofline fractions use."""
+    import torch
+    n = int(gib * 2 ** 30)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rates = []
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        rates.append(2 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(statistics.median(rates), 1)
+
+
 def copy_calibration(gib=1.0, reps=3):
     """A plain device copy of a known size, for scaling FETCH_SIZE / WRITE_SIZE to bytes."""
     import torch
@@ -674,9 +696,11 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     dk = kern[dom]
     traffic = load_traffic(dom, primary, args.workload)
+    copy_gbs = copy_bandwidth()
     roofline = {"bound": "hbm", "achieved": round(dk["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dk["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_ms": round(dk["avg_ms"], 4)}
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_ms": round(dk["avg_ms"], 4),
+                "copy_measured_gbs": copy_gbs, "frac_of_copy": round(dk["achieved_gbs"] / copy_gbs, 4)}
 
     batching = None
     if want_batch:
