@@ -841,7 +841,12 @@ __global__ void __launch_bounds__(kBlock) k_apply_K(FwdArgs a, int nslices, doub
             continue;
         }
         const double* u = a.U + id;
-        const Six t = six_triangles(a.n, i, j, u[0], u[1], u[-1], u[sd], u[-(long)sd], u[sd + 1], u[-(long)sd - 1]);
+        // neighbours on the boundary are read as 0 (u = 0 there), whatever the field holds
+        auto at = [&](int di, int dj) -> double {
+            const int ii = i + di, jj = j + dj;
+            return (ii > 0 && jj > 0 && ii < a.n && jj < a.n) ? u[(long)dj * (long)sd + di] : 0.0;
+        };
+        const Six t = six_triangles(a.n, i, j, u[0], at(1, 0), at(-1, 0), at(0, 1), at(0, -1), at(1, 1), at(-1, -1));
         ku[id] = k_six<LAW>(t, a, a.regp);
     }
 }

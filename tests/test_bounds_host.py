@@ -41,7 +41,7 @@ def test_batching_plans_are_in_bounds(P, precision):
         check(P, P.BatchPlan([probs[i] for i in ix], precision=precision, inner="cocg", inner_iters=2))
 
 
-@pytest.mark.parametrize("n,N", [(4, 4), (4, 1024), (8, 2), (64, 1024), (4096, 4), (2048, 64)])
+@pytest.mark.parametrize("n,N", [(4, 4), (4, 1024), (8, 2), (64, 1024), (4096, 4), (2048, 64), (4096, 1024)])
 def test_extreme_sizes_are_in_bounds(P, n, N):
     if N < 4:
         pytest.skip("N >= 4 by the ABI")

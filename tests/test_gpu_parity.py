@@ -8,6 +8,8 @@ condition number at these sizes is below 1e3). FP32+refinement reaches the same 
 residual, so it meets the same solution bound; its FP32-only kernels (transforms,
 operator, preconditioner) are held to 2e-6 relative (a few float ulps times log N).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -343,6 +345,69 @@ def test_half_wave_symmetry_and_energy_balance(gpu, P):
 
 
 # ---------------------------------------------------------------- extreme sizes
+
+@pytest.mark.parametrize("law", ["rational", "expcap"])
+def test_apply_K_reads_boundary_entries_as_zero(gpu, P, law):
+    # the time-field convention: boundary entries of an input are read as 0, so K of a field
+    # with a nonzero boundary ring is K of the same field with the ring zeroed
+    say(f"apply_K boundary ring {law}")
+    n, N = 16, 4
+    p = W.transformer(n, N) if law == "expcap" else W.with_size(W.config2(4), n, N)
+    U = W.random_field(N, n, 13, 0.05)
+    V = U.copy()
+    rng = np.random.default_rng(14)
+    for sl in (np.s_[:, 0, :], np.s_[:, -1, :], np.s_[:, :, 0], np.s_[:, :, -1]):
+        V[sl] = rng.standard_normal(V[sl].shape)
+    kw = dict(region=dev(W.region_ids(p))) if law == "expcap" else {}
+    plan = P.Plan(p, **kw)
+    a, b = plan.apply_K(dev(U)), plan.apply_K(dev(V))
+    assert torch.equal(a, b)
+    r, _, _ = plan.residual(dev(U))
+    s, _, _ = plan.residual(dev(V))
+    assert torch.equal(r, s)
+    plan.close()
+
+
+def test_largest_grid_operator_and_solve(gpu, P):
+    # n = 4096, the ABI's largest grid (13 multigrid levels), N = 8.
+    # (a) With uniform nu (no iron) and no current, K annihilates an affine field at every node
+    # whose neighbours are all interior (P1 is exact on linear functions, and |grad u| is the same
+    # on every triangle, so the law gives one nu everywhere); boundary entries are read as 0, so
+    # the nodes next to the boundary see the jump. A time-constant field has no mass term: the
+    # operator, the residual sweep and its fused DFT all return zero there, up to rounding.
+    # (b) The seeded problem at this size converges in both precision modes to the same iterate.
+    n, N = 4096, 8
+    say(f"largest grid n={n} N={N}")
+    base = W.with_size(W.config2(5), n, N)
+    p = dataclasses.replace(base, nu_rect=W.Rect(0.0, 0.0, 0.0, 0.0), J0=0.0)
+    x = np.linspace(0.0, 1.0, n + 1)
+    u = 0.3 * x[None, :] - 0.7 * x[:, None] + 0.1          # u(x_i, y_j) = 0.3 x - 0.7 y + 0.1
+    u[0, :] = u[-1, :] = u[:, 0] = u[:, -1] = 0.0
+    U = dev(np.broadcast_to(u, (N, n + 1, n + 1)).copy())
+    scale = 4 * p.nu_out * float(np.abs(u).max())
+    plan = P.Plan(p, precision="fp64")
+    KU = plan.apply_K(U)
+    assert float(KU[:, 2:-2, 2:-2].abs().max()) <= 1e-12 * scale
+    assert float(KU[:, 1, 1:-1].abs().min()) >= 0.05 * p.nu_out     # the jump next to y = 0
+    R, _, fn = plan.residual(U)
+    assert fn == 0.0
+    assert float(R[:, 2:-2, 2:-2].abs().max()) <= 1e-12 * scale
+    assert torch.allclose(R[:, 1:-1, 1:-1], -KU[:, 1:-1, 1:-1], rtol=0, atol=1e-12 * scale)
+    Rh, _, _ = plan.residual_spectrum(U)
+    Rh = Rh.reshape(n + 1, n + 1, -1)
+    assert float(Rh[2:-2, 2:-2].abs().max()) <= 1e-11 * scale
+    plan.close()
+    del KU, R, Rh, U
+    sol = {}
+    for precision in ("fp64", "fp32"):
+        pl = P.Plan(base, tol=1e-8, precision=precision, max_outer=2000)
+        V, st = pl.solve()
+        assert st.rel_residual <= 1e-8
+        sol[precision] = (V, st.outer_iters)
+        pl.close()
+    (a, ka), (b, kb) = sol["fp32"], sol["fp64"]
+    assert abs(ka - kb) <= 8
+    assert float((a - b).norm() / b.norm()) <= 1e-6
 
 _extreme_ref = {}
 
