@@ -187,6 +187,10 @@ typedef struct {
                               (pt_kernel_class_name(k)) only; 0 = every class. Each timed launch
                               adds two event records to the stream, so timing fewer classes
                               perturbs the timed solve less. Bits >= PT_KERNEL_CLASSES: invalid. */
+    int32_t grid_restrict; /* workgroups the restriction sweeps aim for (every level); 0 = grid_slot */
+    int32_t grid_up;       /* workgroups the prolongation + smoothing sweeps aim for; 0 = grid_slot */
+    int32_t grid_matvec;   /* workgroups the operator sweep (p^H A p, COCG's A p) aims for; 0 =
+                              grid_slot. All three: performance only (>= 8). */
 } pt_options;
 
 typedef struct {

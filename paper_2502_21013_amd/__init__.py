@@ -97,7 +97,8 @@ class SolveStats:
 def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega, use_initial_guess,
              diverge_factor, xcd_remap, timing, graph, grid_slot=0, grid_team=0, adjoint=False,
              init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0, forcing=1e-2,
-             max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, cycle="default") -> L.Options:
+             max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, cycle="default", grid_restrict=0, grid_up=0,
+             grid_matvec=0) -> L.Options:
     o = L.Options()
     lib.pt_options_default(C.byref(o))
     o.tol, o.max_outer, o.check_every = float(tol), int(max_outer), int(check_every)
@@ -124,6 +125,7 @@ def _options(lib, tol, max_outer, check_every, precision, inner, inner_iters, vc
     o.krylov_dim, o.forcing, o.max_krylov = int(krylov_dim), float(forcing), int(max_krylov)
     o.inner_rtol, o.breakdown_tol = float(inner_rtol), float(breakdown_tol)
     o.vc_cycle = {"default": L.PT_VC_DEFAULT, "v11": L.PT_VC_V11, "v01": L.PT_VC_V01}[cycle]
+    o.grid_restrict, o.grid_up, o.grid_matvec = int(grid_restrict), int(grid_up), int(grid_matvec)
     return o
 
 
@@ -161,8 +163,8 @@ class Plan:
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
                  adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0,
-                 forcing=1e-2, max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, cycle="default", theta=None,
-                 sigma=None, load=None, region=None, device=None):
+                 forcing=1e-2, max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, cycle="default", grid_restrict=0,
+                 grid_up=0, grid_matvec=0, theta=None, sigma=None, load=None, region=None, device=None):
         import torch
         self.lib = L.load()
         self.problem = problem
@@ -175,7 +177,7 @@ class Plan:
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
                      use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
                      init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov, inner_rtol,
-                     breakdown_tol, cycle)
+                     breakdown_tol, cycle, grid_restrict, grid_up, grid_matvec)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create(C.byref(self._ps), C.byref(o), C.byref(h))
@@ -402,7 +404,8 @@ class BatchPlan(Plan):
                  inner="galerkin1", inner_iters=1, vc_omega=0.8, use_initial_guess=False,
                  diverge_factor=1e3, xcd_remap=True, timing=False, graph=False, grid_slot=0, grid_team=0,
                  adjoint=False, init_static=False, init_tol=1e-8, stop_relative_initial=False, krylov_dim=0,
-                 forcing=1e-2, max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, cycle="default", device=None):
+                 forcing=1e-2, max_krylov=100, inner_rtol=0.0, breakdown_tol=0.0, cycle="default", grid_restrict=0,
+                 grid_up=0, grid_matvec=0, device=None):
         import torch
         problems = list(problems)
         self.lib = L.load()
@@ -418,7 +421,7 @@ class BatchPlan(Plan):
         o = _options(self.lib, tol, max_outer, check_every, precision, inner, inner_iters, vc_omega,
                      use_initial_guess, diverge_factor, xcd_remap, timing, graph, grid_slot, grid_team, adjoint,
                      init_static, init_tol, stop_relative_initial, krylov_dim, forcing, max_krylov, inner_rtol,
-                     breakdown_tol, cycle)
+                     breakdown_tol, cycle, grid_restrict, grid_up, grid_matvec)
         self._opts = o
         h = C.c_void_p()
         st = self.lib.pt_plan_create_batch(self._pa, self.count, C.byref(o), C.byref(h))

@@ -61,6 +61,7 @@ class Options(C.Structure):
         ("krylov_dim", C.c_int32), ("forcing", C.c_double), ("max_krylov", C.c_int32),
         ("graph", C.c_int32), ("inner_rtol", C.c_double), ("breakdown_tol", C.c_double),
         ("vc_cycle", C.c_int32), ("timing_mask", C.c_int32),
+        ("grid_restrict", C.c_int32), ("grid_up", C.c_int32), ("grid_matvec", C.c_int32),
     ]
 
 

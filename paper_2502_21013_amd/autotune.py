@@ -6,8 +6,10 @@ The grid targets change only how the sweeping kernels are cut into workgroups; t
 Jacobi damping omega of the cycle also changes the inner approximation and hence the
 contraction rate, which is why the rate is measured rather than assumed.
 
-The search is coordinate-wise (the inner method, omega, then the slot-vector grid, then the
-time-axis grid), each over a short candidate list, starting from the library defaults. The
+The search is coordinate-wise (the inner method, omega, the slot-vector grid, the time-axis
+grid, then per-sweep overrides of the slot grid for the restriction, up and operator sweeps,
+whose best workgroup counts differ), each over a short candidate list, starting from the
+library defaults. The
 inner method axis compares the one-step Galerkin step on a V(0,1) and on a V(1,1) cycle with
 COCG of a few steps and with COCG stopped per frequency at a relative tolerance: more inner
 work per step against fewer outer steps, which is what the predicted time to tolerance
@@ -25,6 +27,8 @@ from typing import Callable, Dict, List, Optional, Sequence
 # predicts the rate of the whole solve poorly, so it is searched only on request.
 OMEGAS = (0.8,)
 GRID_SLOT = (1024, 2048, 4096, 8192, 16384)
+# per-sweep overrides of the slot grid (0 = the slot grid): restriction, up sweep, operator sweep
+GRID_SWEEP = (0, 2048, 4096, 16384)
 GRID_TEAM = (16384, 65536, 262144, 1048576)
 # inner methods: (inner, inner_iters, inner_rtol, cycle); COCG needs the symmetric V(1,1)
 INNER = (("galerkin1", 1, 0.0, "v01"), ("galerkin1", 1, 0.0, "v11"), ("cocg", 2, 0.0, "v11"),
@@ -61,11 +65,12 @@ def _probe(make_plan: Callable, kw: Dict, steps: int, tol: float) -> Dict:
 
 def tune(make_plan: Callable, *, tol: float = 1e-8, steps: int = 12, omegas: Sequence[float] = OMEGAS,
          grid_slot: Sequence[int] = GRID_SLOT, grid_team: Sequence[int] = GRID_TEAM,
-         inner: Sequence = INNER, log=None) -> Dict:
-    """make_plan(max_outer=..., vc_omega=..., grid_slot=..., grid_team=..., inner=..., inner_iters=...,
-    inner_rtol=..., cycle=...) -> Plan or BatchPlan. Returns {"best": kwargs, "trials": [...]}."""
+         grid_sweep: Sequence[int] = GRID_SWEEP, inner: Sequence = INNER, log=None) -> Dict:
+    """make_plan(max_outer=..., vc_omega=..., grid_slot=..., grid_team=..., grid_restrict=..., grid_up=...,
+    grid_matvec=..., inner=..., inner_iters=..., inner_rtol=..., cycle=...) -> Plan or BatchPlan.
+    Returns {"best": kwargs, "trials": [...]}."""
     best = {"inner": "galerkin1", "inner_iters": 1, "inner_rtol": 0.0, "cycle": "v01", "vc_omega": 0.8,
-            "grid_slot": 0, "grid_team": 0}
+            "grid_slot": 0, "grid_team": 0, "grid_restrict": 0, "grid_up": 0, "grid_matvec": 0}
     trials: List[Dict] = []
     cache = {}
 
@@ -87,7 +92,8 @@ def tune(make_plan: Callable, *, tol: float = 1e-8, steps: int = 12, omegas: Seq
         scores[c] = run(kw)
     c = min(scores, key=scores.get)
     best.update(inner=c[0], inner_iters=c[1], inner_rtol=c[2], cycle=c[3])
-    for name, cands in (("vc_omega", omegas), ("grid_slot", grid_slot), ("grid_team", grid_team)):
+    for name, cands in (("vc_omega", omegas), ("grid_slot", grid_slot), ("grid_team", grid_team),
+                        ("grid_restrict", grid_sweep), ("grid_up", grid_sweep), ("grid_matvec", grid_sweep)):
         scores = {}
         for c in cands:
             kw = dict(best)

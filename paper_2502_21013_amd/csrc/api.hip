@@ -204,9 +204,10 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
         return fail(PT_ERR_INVALID, "init_tol must be positive");
     if (o->init_static && o->use_initial_guess)
         return fail(PT_ERR_INVALID, "init_static and use_initial_guess cannot be combined");
-    if (o->grid_slot < 0 || (o->grid_slot > 0 && o->grid_slot < 8) || o->grid_slot > (1 << 22) || o->grid_team < 0 ||
-        (o->grid_team > 0 && o->grid_team < 8) || o->grid_team > (1 << 22))
-        return fail(PT_ERR_INVALID, "grid_slot and grid_team must be 0 or in [8, 4194304]");
+    for (int32_t g : {o->grid_slot, o->grid_team, o->grid_restrict, o->grid_up, o->grid_matvec})
+        if (g < 0 || (g > 0 && g < 8) || g > (1 << 22))
+            return fail(PT_ERR_INVALID, "grid targets (grid_slot, grid_team, grid_restrict, grid_up, grid_matvec) "
+                                        "must be 0 or in [8, 4194304]");
     if (!(o->diverge_factor >= 0) || !std::isfinite(o->diverge_factor))
         return fail(PT_ERR_INVALID, "diverge_factor must be >= 0");
     return PT_OK;
@@ -1152,10 +1153,13 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     p.gr = nullptr;
     p.target_slot = opts->grid_slot > 0 ? opts->grid_slot : 8192;
     p.target_team = opts->grid_team > 0 ? opts->grid_team : 262144;
-    p.g_slot0 = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
+    p.target_down = opts->grid_restrict > 0 ? opts->grid_restrict : p.target_slot;
+    p.target_up = opts->grid_up > 0 ? opts->grid_up : p.target_slot;
+    p.g_slot0 = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, p.target_up);
     // operator sweep: 64-lane slot chunks, so a workgroup holds four column pairs and their
     // shared halo columns come through L1 (1024^2 x 512: 0.508 -> 0.490 ms FP32, 0.930 -> 0.891 ms FP64)
-    p.g_mv = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, p.target_slot, (p.side + 1) / 2, 64);
+    p.g_mv = slot_geom(p.side, p.ST, p.fp32 ? 2 : 1, opts->grid_matvec > 0 ? opts->grid_matvec : p.target_slot,
+                       (p.side + 1) / 2, 64);
     p.g_team = team_geom(p.side, p.S, p.B, p.target_team);
     p.g_fwd = fwd_geom(p.side, p.S, p.B, p.target_slot);
     layout(p);

@@ -158,11 +158,18 @@ pt_status check_bounds(const Plan& p, std::string& msg) {
     const size_t set_a = (size_t)(p.g_slot0.blocks + kReduceRows) * p.ST * 3;
     const size_t set_b = (size_t)(p.g_mv.blocks + kReduceRows) * p.ST * 3;
     if (set_a + set_b > part_doubles) c.fail("the two dot-partial sets exceed the partial buffer");
-    check_slot(c, "V-cycle / operator level 0", p.g_slot0, p.side, p.side, V, p.nodes, (size_t)p.g_slot0.blocks);
+    const Geom up0 = slot_geom(p.side, p.ST, V, p.target_up);
+    if (up0.blocks != p.g_slot0.blocks || up0.rows_per_chunk != p.g_slot0.rows_per_chunk)
+        c.fail("level-0 up sweep geometry differs from the one its dot partials are sized for");
+    check_slot(c, "V-cycle up sweep level 0", p.g_slot0, p.side, p.side, V, p.nodes, (size_t)p.g_slot0.blocks);
     check_slot(c, "operator (column pairs)", p.g_mv, p.side, (p.side + 1) / 2, V, p.nodes, (size_t)p.g_mv.blocks);
     for (int l = 1; l < p.nlev && c.ok(); ++l) {
-        const Geom g = slot_geom(p.lev[l].side, p.ST, V, p.target_slot);
-        check_slot(c, ("V-cycle level " + std::to_string(l)).c_str(), g, p.lev[l].side, p.lev[l].side, V,
+        // the restriction into level l and the up sweep onto level l
+        const Geom gd = slot_geom(p.lev[l].side, p.ST, V, p.target_down);
+        check_slot(c, ("V-cycle restriction into level " + std::to_string(l)).c_str(), gd, p.lev[l].side,
+                   p.lev[l].side, V, p.lev[l].nodes, 0);
+        const Geom gu = slot_geom(p.lev[l].side, p.ST, V, p.target_up);
+        check_slot(c, ("V-cycle up sweep level " + std::to_string(l)).c_str(), gu, p.lev[l].side, p.lev[l].side, V,
                    p.lev[l].nodes, 0);
     }
     // residual sweep: TS = min(S, 256) threads per column, norm partials two per team

@@ -1280,7 +1280,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
     for (int l = 0; l + 1 < L && l < l0; ++l) {
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* rout = ws + p.lev[l + 1].off_r;
-        Geom g = slot_geom(p.lev[l + 1].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
+        Geom g = slot_geom(p.lev[l + 1].side, p.ST, p.fp32 ? 2 : 1, p.target_down);
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int kid = (l == 0) ? KID_DOWN0 : KID_DOWNC;
@@ -1358,7 +1358,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         const void* rin = (l == 0) ? r0 : (const void*)(ws + p.lev[l].off_r);
         void* xout = (l == 0) ? x0 : (void*)(ws + p.lev[l].off_x);
         const void* xc = ws + p.lev[l + 1].off_x;
-        Geom g = slot_geom(p.lev[l].side, p.ST, p.fp32 ? 2 : 1, p.target_slot);
+        Geom g = slot_geom(p.lev[l].side, p.ST, p.fp32 ? 2 : 1, p.target_up);   // level 0: p.g_slot0
         SlotArgs sa = mk_slot(p, ws, g);
         dim3 grid(g.blocks, g.chunks);
         int dm = (l == 0) ? dotmode : DOT_NONE;

@@ -136,7 +136,8 @@ struct Plan {
     double* h_rsj;      // kMaxRegions x 2: conductivity and current amplitude (region mode)
     size_t off_regp, off_rsj;
     int target_slot, target_team;  // grid targets of the slot-vector and per-node kernels
-    Geom g_slot0;       // slot-vector kernels on level 0
+    int target_down, target_up;    // grid targets of the restriction and up sweeps (all levels)
+    Geom g_slot0;       // up sweep on level 0 (its dot partials: one row per workgroup)
     Geom g_mv;          // operator apply on level 0: two adjacent columns per team
     Geom g_team;        // per-node team kernels (inverse DFT)
     Geom g_fwd;         // residual sweep (team of min(S, 256) threads per column)

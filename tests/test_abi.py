@@ -70,7 +70,8 @@ def test_plan_rejects_invalid_problems(P, field, value):
 
 
 @pytest.mark.parametrize("kw", [dict(tol=0.0), dict(max_outer=0), dict(check_every=0), dict(inner_iters=0),
-                                dict(inner_iters=65), dict(vc_omega=1.0), dict(inner="cocg", cycle="v01")])
+                                dict(inner_iters=65), dict(vc_omega=1.0), dict(inner="cocg", cycle="v01"),
+                                dict(grid_restrict=4), dict(grid_up=-1), dict(grid_matvec=(1 << 22) + 1)])
 def test_plan_rejects_invalid_options(P, kw):
     with pytest.raises(P.PTError):
         P.Plan(W.config1(), **kw)

@@ -28,7 +28,10 @@ def check(P, plan):
 def test_config_plans_are_in_bounds(P, name, precision):
     p = {"c1": W.config1(), "c2": W.config2(0), "c3": W.config3(0), "c5": W.config2(0)}[name]
     for kw in (dict(), dict(inner="cocg", inner_iters=3), dict(adjoint=True), dict(krylov_dim=8),
-               dict(grid_slot=8, grid_team=8), dict(grid_slot=4194304, grid_team=4194304), dict(xcd_remap=False)):
+               dict(grid_slot=8, grid_team=8), dict(grid_slot=4194304, grid_team=4194304), dict(xcd_remap=False),
+               dict(grid_restrict=16384, grid_up=4096, grid_matvec=4096),
+               dict(grid_restrict=8, grid_up=4194304, grid_matvec=8),
+               dict(inner="cocg", grid_restrict=2048, grid_up=8, grid_matvec=4194304)):
         check(P, P.Plan(p, precision=precision, **kw))
 
 

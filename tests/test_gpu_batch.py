@@ -171,9 +171,11 @@ def test_autotuner_picks_a_valid_setting(gpu, P):
     from paper_2502_21013_amd import autotune as AT
     ps = instances(31, 32, 16, 2)
     mk = lambda max_outer, **kw: P.BatchPlan(ps, tol=1e-10, max_outer=max_outer, **kw)
-    r = AT.tune(mk, tol=1e-10, steps=8, omegas=(0.7, 0.8), grid_slot=(256, 2048), grid_team=(1024, 16384))
+    r = AT.tune(mk, tol=1e-10, steps=8, omegas=(0.7, 0.8), grid_slot=(256, 2048), grid_team=(1024, 16384),
+                grid_sweep=(0, 512))
     best = r["best"]
     assert best["vc_omega"] in (0.7, 0.8) and best["grid_slot"] in (256, 2048) and best["grid_team"] in (1024, 16384)
+    assert all(best[k] in (0, 512) for k in ("grid_restrict", "grid_up", "grid_matvec"))
     assert (best["inner"], best["inner_iters"], best["inner_rtol"], best["cycle"]) in AT.INNER
     assert all(0 < t["rate"] < 1 and t["step_ms"] > 0 for t in r["trials"])
     # the tuned plan reaches the same solution
