@@ -100,12 +100,19 @@ typedef enum { PT_WAVE_SIN = 0, PT_WAVE_COS = 1 } pt_waveform;
 typedef enum { PT_NU_RATIONAL = 0, PT_NU_EXPCAP = 1 } pt_nu_law;
 
 /* Material of one region (region mode; Sec. 4, table tab:coef): conductivity, law parameters
- * (b, c, d unused by PT_NU_RATIONAL: nu = a + b s^2/(1+s^2) there) and the amplitude j of the
- * current density j w(2 pi t / T). */
+ * (b, c, d unused by PT_NU_RATIONAL: nu = a + b s^2/(1+s^2) there), the amplitude j of the
+ * current density j w(2 pi t / T), and the region's coefficient nu_hat of the linear operator
+ * Khat of the fixed-point iteration (eq. (iter1); Thm. thm:iter admits any Khat = S_nuhat with a
+ * piecewise-constant coefficient bounding the law's range suitably): Khat is the P1 stiffness
+ * with coefficient nu_hat on the region's triangles. nu_hat = 0 takes the problem's nu_max; when
+ * every region has nu_hat = 0, Khat = nu_max S (a constant stencil). A per-region Khat needs the
+ * Galerkin inner step with the V(0,1) cycle (options.inner = PT_INNER_GALERKIN1, vc_cycle
+ * PT_VC_DEFAULT or PT_VC_V01). */
 typedef struct {
     double sigma;          /* >= 0 */
     double a, b, c, d;     /* PT_NU_RATIONAL: a > 0, a + b > 0; PT_NU_EXPCAP: a, b >= 0, c >= 1, d > 0 */
     double j;
+    double nu_hat;         /* >= 0 (0: nu_max) */
 } pt_region;
 
 typedef struct { double x0, y0, x1, y1; } pt_rect;   /* closed rectangle */

@@ -290,4 +290,11 @@ def discretise(p: Problem) -> Discretisation:
     S = restrict(stiffness_full(m), m.free)
     M = restrict(mass_full(m, mat.sigma), m.free)
     b = load_full(m, mat.J)[m.free]
-    return Discretisation(p=p, mesh=m, mat=mat, S=S, M=M, b=b, free_idx=np.flatnonzero(m.free))
+    d = Discretisation(p=p, mesh=m, mat=mat, S=S, M=M, b=b, free_idx=np.flatnonzero(m.free))
+    if p.regions is not None and any(r.nu_hat > 0 for r in p.regions):
+        # Khat with a coefficient per region (Thm. thm:iter: any such Khat whose coefficient
+        # bounds the law suitably); a region without one takes nu_max
+        from workloads import region_ids
+        coef = np.array([r.nu_hat if r.nu_hat > 0 else p.nu_max for r in p.regions], dtype=np.float64)
+        d.khat_coef = coef[region_ids(p).astype(np.int64)]
+    return d

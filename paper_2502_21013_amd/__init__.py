@@ -59,7 +59,7 @@ def problem_struct(p, theta=None, sigma=None, load=None, region=None) -> L.Probl
         if region is None or region.dtype != torch.uint8 or not region.is_cuda or not region.is_contiguous() or \
                 region.numel() != 2 * p.n * p.n:
             raise ValueError(f"region mode needs a contiguous uint8 device tensor of {2 * p.n * p.n} region ids")
-        arr = (L.Region * len(regs))(*[L.Region(r.sigma, r.a, r.b, r.c, r.d, r.j) for r in regs])
+        arr = (L.Region * len(regs))(*[L.Region(r.sigma, r.a, r.b, r.c, r.d, r.j, r.nu_hat) for r in regs])
         s._regions = arr
         s.nregions = len(regs)
         s.d_region = region.data_ptr()

@@ -35,7 +35,7 @@ class Rect(C.Structure):
 
 class Region(C.Structure):
     _fields_ = [("sigma", C.c_double), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
-                ("d", C.c_double), ("j", C.c_double)]
+                ("d", C.c_double), ("j", C.c_double), ("nu_hat", C.c_double)]
 
 
 class Problem(C.Structure):

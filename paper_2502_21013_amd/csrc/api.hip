@@ -171,8 +171,13 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
         for (int r = 0; r < pr->nregions; ++r) {
             const pt_region& g = pr->regions[r];
             if (!std::isfinite(g.sigma) || !std::isfinite(g.a) || !std::isfinite(g.b) || !std::isfinite(g.c) ||
-                !std::isfinite(g.d) || !std::isfinite(g.j) || !(g.sigma >= 0))
-                return fail(PT_ERR_INVALID, "region " + std::to_string(r) + ": parameters must be finite, sigma >= 0");
+                !std::isfinite(g.d) || !std::isfinite(g.j) || !(g.sigma >= 0) || !std::isfinite(g.nu_hat) ||
+                !(g.nu_hat >= 0))
+                return fail(PT_ERR_INVALID, "region " + std::to_string(r) +
+                                                ": parameters must be finite, sigma >= 0 and nu_hat >= 0");
+            if (g.nu_hat > 0 && (o->inner != PT_INNER_GALERKIN1 || o->vc_cycle == PT_VC_V11))
+                return fail(PT_ERR_INVALID, "a per-region Khat (nu_hat > 0) needs the Galerkin inner step with the "
+                                            "V(0,1) cycle");
             const bool ok = pr->law == PT_NU_RATIONAL ? (g.a > 0 && g.a + g.b > 0)
                                                       : (g.a >= 0 && g.b >= 0 && g.c >= 1 && g.d > 0);
             if (!ok) return fail(PT_ERR_INVALID, "region " + std::to_string(r) + ": the law's parameters are out of range");
@@ -260,6 +265,7 @@ static void layout(Plan& p) {
     for (int l = 0; l < p.nlev; ++l) {
         LevelDesc& d = p.lev[l];
         d.off_mt = take(4 * d.nodes * sizeof(double));
+        d.off_kt = p.vk ? take(4 * d.nodes * sizeof(double)) : 0;
         d.off_r = take(d.nodes * S * p.elem);
         d.off_x = take(d.nodes * S * p.elem);
     }
@@ -290,6 +296,7 @@ static void layout(Plan& p) {
     p.off_inst = take(B * 4 * sizeof(double));
     p.off_regp = take(B * kMaxRegions * 4 * sizeof(double));
     p.off_rsj = take(kMaxRegions * 2 * sizeof(double));
+    p.off_rkh = take(kMaxRegions * sizeof(double));
     // two sets of slot partials (V-cycle and operator sweep), each with its stage-1 tail
     size_t part_slot = (size_t)(p.g_slot0.blocks + kReduceRows + p.g_mv.blocks + kReduceRows) * S * 3;
     size_t part_team = std::max((size_t)p.g_fwd.blocks * p.g_fwd.per_step * 2, (size_t)4096 * 2);
@@ -389,6 +396,8 @@ static void host_tables(Plan& p) {
             p.h_rsj[2 * r + 1] = g.j;
         }
     }
+    for (int r = 0; r < kMaxRegions; ++r)
+        p.h_rkh[r] = (p.region_mode && r < p.nreg && p.regions[r].nu_hat > 0) ? p.regions[r].nu_hat : p.prob.nu_max;
 }
 
 static pt_status check_ws(const Plan* p, void* ws, size_t bytes) {
@@ -427,8 +436,14 @@ static pt_status setup(Plan& p, char* ws, hipStream_t st) {
     PT_HIP(hipMemcpyAsync(ws + p.off_regp, p.h_regp, (size_t)p.B * kMaxRegions * 4 * sizeof(double),
                           hipMemcpyHostToDevice, st));
     PT_HIP(hipMemcpyAsync(ws + p.off_rsj, p.h_rsj, (size_t)kMaxRegions * 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    PT_HIP(hipMemcpyAsync(ws + p.off_rkh, p.h_rkh, (size_t)kMaxRegions * sizeof(double), hipMemcpyHostToDevice, st));
     TM(KID_SETUP, launch_setup_fine(p, ws, st));
     for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin(p, ws, l, st));
+    if (p.vk) {
+        // Khat = S_nuhat on the finest level and its Galerkin coarsening (same stencil layout)
+        TM(KID_SETUP, launch_setup_stiffness(p, ws, st));
+        for (int l = 0; l + 1 < p.nlev; ++l) TM(KID_SETUP, launch_galerkin_table(p, ws, l, true, st));
+    }
     TM(KID_SETUP, launch_row_records(p, ws, st));
     PT_HIP(hipGetLastError());
     return PT_OK;
@@ -1130,6 +1145,8 @@ static pt_status plan_create_impl(const pt_problem* probs, int count, const pt_o
     p.region_mode = prob->nregions > 0;
     p.nreg = p.region_mode ? prob->nregions : 2;
     if (p.region_mode) std::copy(prob->regions, prob->regions + prob->nregions, p.regions);
+    p.vk = false;
+    for (int r = 0; p.region_mode && r < p.nreg; ++r) p.vk = p.vk || p.regions[r].nu_hat > 0;
     p.prob.regions = nullptr;  // the caller's array need not outlive the plan
     for (int b = 0; b < count; ++b) p.probs[b].regions = nullptr;
     p.n = prob->n;

@@ -46,6 +46,7 @@ std::vector<Buf> buffers(const Plan& p) {
     for (int l = 0; l < p.nlev; ++l) {
         const LevelDesc& d = p.lev[l];
         v.push_back({"mass stencil", d.off_mt, dbl(4 * d.nodes)});
+        if (p.vk) v.push_back({"Khat stencil", d.off_kt, dbl(4 * d.nodes)});
         v.push_back({"level r", d.off_r, d.nodes * S * p.elem});
         v.push_back({"level x", d.off_x, d.nodes * S * p.elem});
     }
@@ -68,6 +69,7 @@ std::vector<Buf> buffers(const Plan& p) {
     v.push_back({"instances", p.off_inst, dbl(B * 4)});
     v.push_back({"region laws", p.off_regp, dbl(B * kMaxRegions * 4)});
     v.push_back({"region sigma/j", p.off_rsj, dbl(kMaxRegions * 2)});
+    v.push_back({"region nu_hat", p.off_rkh, dbl(kMaxRegions)});
     v.push_back({"partials", p.off_part, p.part_bytes});
     v.push_back({"norms", p.off_scal, dbl(2 * B)});
     v.push_back({"flag", p.off_flag, sizeof(int)});

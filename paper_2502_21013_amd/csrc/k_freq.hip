@@ -23,6 +23,7 @@ struct LvArgs {
     int n, side;
     size_t nodes;
     const double* mt;
+    const double* kt;  // Khat stencil table (per-region Khat), or null: Khat = nu_max * 5-point stencil
 };
 
 // S: slots per instance (a power of two; slot s with s % S == 0 packs k = 0 and k = N/2),
@@ -42,6 +43,7 @@ struct SmallArgs {
     int count, pre;   // pre: V(1,1) (pre-smoothing), else V(0,1)
     int side[kMaxSmall];
     const double* mt[kMaxSmall];
+    const double* kt[kMaxSmall];  // Khat stencil tables (per-region Khat), or null
     int off_r[kMaxSmall], off_x[kMaxSmall], off_t;
 };
 
@@ -75,18 +77,30 @@ struct MRow {
     }
 };
 
+// Row a of a symmetric 7-point stencil table in the layout [centre | E | N | NE][nodes] (the W,
+// S and SW couplings are the E, N and NE entries of the neighbours).
+template <bool UNI>
+__device__ __forceinline__ MRow stencil_row(const double* t, long nd, long sd, long a) {
+    MRow m;
+    m.c = uload<UNI>(t, a);
+    m.e = uload<UNI>(t, nd + a);
+    m.w = uload<UNI>(t, nd + a - 1);
+    m.n = uload<UNI>(t, 2 * nd + a);
+    m.s = uload<UNI>(t, 2 * nd + a - sd);
+    m.ne = uload<UNI>(t, 3 * nd + a);
+    m.sw = uload<UNI>(t, 3 * nd + a - sd - 1);
+    return m;
+}
+
 template <bool UNI>
 __device__ __forceinline__ MRow mrow(const LvArgs& L, long a) {
-    const long nd = (long)L.nodes, sd = L.side;
-    MRow m;
-    m.c = uload<UNI>(L.mt, a);
-    m.e = uload<UNI>(L.mt, nd + a);
-    m.w = uload<UNI>(L.mt, nd + a - 1);
-    m.n = uload<UNI>(L.mt, 2 * nd + a);
-    m.s = uload<UNI>(L.mt, 2 * nd + a - sd);
-    m.ne = uload<UNI>(L.mt, 3 * nd + a);
-    m.sw = uload<UNI>(L.mt, 3 * nd + a - sd - 1);
-    return m;
+    return stencil_row<UNI>(L.mt, (long)L.nodes, (long)L.side, a);
+}
+
+// the Khat row of node a (per-region Khat; the same layout as the mass)
+template <bool UNI>
+__device__ __forceinline__ MRow krow(const LvArgs& L, long a) {
+    return stencil_row<UNI>(L.kt, (long)L.nodes, (long)L.side, a);
 }
 
 // V consecutive slots of one node held by one lane: V = 2 in FP32 mode (one 16-byte
@@ -136,15 +150,30 @@ template <typename T> __device__ __forceinline__ SV<T> sv_fma(T s, const SV<T>& 
 // (A x)_a for interior node a with mass row m, given the 7 neighbour values of x; z[k] is
 // the shift of the lane's slot k. MASS = false: the mass row is zero (stiffness part only);
 // MASS = true: the mass part is added without a branch (no change where the row is zero).
-template <typename T, bool MASS>
+// VK = false: Khat = nu * (5-point stencil); VK = true: Khat from the stencil row kr.
+template <typename T, bool MASS, bool VK = false>
 __device__ __forceinline__ SV<T> apply_A_t(const MRow& m, T nu, const GS<T>* z, const SV<T>& xc, const SV<T>& xe,
                                            const SV<T>& xw, const SV<T>& xn, const SV<T>& xs, const SV<T>& xne,
-                                           const SV<T>& xsw) {
+                                           const SV<T>& xsw, const MRow& kr = MRow{}) {
     SV<T> out;
+    if constexpr (VK) {
+        const T kc = (T)kr.c, ke = (T)kr.e, kw = (T)kr.w, kn = (T)kr.n, ks = (T)kr.s, kne = (T)kr.ne, ksw = (T)kr.sw;
 #pragma unroll
-    for (int k = 0; k < SV<T>::V; ++k) {
-        out.v[k].x = nu * ((T)4 * xc.v[k].x - xe.v[k].x - xw.v[k].x - xn.v[k].x - xs.v[k].x);
-        out.v[k].y = nu * ((T)4 * xc.v[k].y - xe.v[k].y - xw.v[k].y - xn.v[k].y - xs.v[k].y);
+        for (int k = 0; k < SV<T>::V; ++k) {
+            auto Kx = scale2(kc, xc.v[k]);
+            Kx = fma2(ke, xe.v[k], Kx);
+            Kx = fma2(kw, xw.v[k], Kx);
+            Kx = fma2(kn, xn.v[k], Kx);
+            Kx = fma2(ks, xs.v[k], Kx);
+            Kx = fma2(kne, xne.v[k], Kx);
+            out.v[k] = fma2(ksw, xsw.v[k], Kx);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SV<T>::V; ++k) {
+            out.v[k].x = nu * ((T)4 * xc.v[k].x - xe.v[k].x - xw.v[k].x - xn.v[k].x - xs.v[k].x);
+            out.v[k].y = nu * ((T)4 * xc.v[k].y - xe.v[k].y - xw.v[k].y - xn.v[k].y - xs.v[k].y);
+        }
     }
     if constexpr (!MASS) return out;
     const T mc = (T)m.c, me = (T)m.e, mw = (T)m.w, mn = (T)m.n, ms = (T)m.s, mne = (T)m.ne, msw = (T)m.sw;
@@ -162,12 +191,12 @@ __device__ __forceinline__ SV<T> apply_A_t(const MRow& m, T nu, const GS<T>* z, 
     return out;
 }
 
-template <typename T>
+template <typename T, bool VK = false>
 __device__ __forceinline__ SV<T> apply_A(const MRow& m, T nu, const GS<T>* z, const SV<T>& xc, const SV<T>& xe,
                                          const SV<T>& xw, const SV<T>& xn, const SV<T>& xs, const SV<T>& xne,
-                                         const SV<T>& xsw) {
-    if (m.any()) return apply_A_t<T, true>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw);
-    return apply_A_t<T, false>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw);
+                                         const SV<T>& xsw, const MRow& kr = MRow{}) {
+    if (m.any()) return apply_A_t<T, true, VK>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw, kr);
+    return apply_A_t<T, false, VK>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw, kr);
 }
 
 // omega D^{-1} r with D = dl + z diag(M) (dm the node's diagonal mass entry). MASS = false:
@@ -468,7 +497,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_coarsest(SlotArgs sa, LvArgs C, c
         for (size_t node = 0; node < C.nodes; ++node) {
             T2 v = mk2<T>(0, 0);
             if (node == (size_t)C.side + 1) {
-                T dl = (T)4 * (T)sa.nu;
+                T dl = C.kt ? (T)C.kt[node] : (T)4 * (T)sa.nu;   // Khat's diagonal
                 GS<T> di = gs_inv_diag<T>(dl, (T)1 / dl, (T)C.mt[node], z);
                 v = gs_apply(di, rin[node * S + s]);
             }
@@ -497,19 +526,32 @@ __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, 
     const GS<T> z = load_shift<T>(sa.zs, s);
     const T nu = (T)sa.nu, om = (T)sa.omega, dl = (T)4 * nu, idl = (T)1 / dl, half = (T)0.5;
     const T2 zero = mk2<T>(0, 0);
-    // omega D^{-1} v at a node with diagonal mass dm (the forms of jacobi_t)
-    auto jac = [&](double dm, T2 v) -> T2 {
-        if (dm == 0.0) return scale2(om * idl, v);
-        return scale2(om, gs_apply(gs_inv_diag_sel<T>(dl, idl, (T)dm, z), v));
+    // omega D^{-1} v at node a of a level with mass table mt and Khat table kt (null: Khat = nu_max
+    // times the 5-point stencil), D = Khat_aa + z M_aa (the forms of jacobi_t)
+    auto jac = [&](const double* mt, const double* kt, int a, T2 v) -> T2 {
+        const double dm = mt[a];
+        const T dla = kt ? (T)kt[a] : dl, idla = kt ? (T)1 / dla : idl;
+        if (dm == 0.0) return scale2(om * idla, v);
+        return scale2(om, gs_apply(gs_inv_diag_sel<T>(dla, idla, (T)dm, z), v));
     };
-    // (A x)_a at interior node a of a level with side sd and mass table mt (as apply_A_t)
-    auto applyA = [&](const double* mt, int sd, const T2* xv, int a) -> T2 {
+    // (A x)_a at interior node a of a level with side sd and tables mt, kt (as apply_A_t)
+    auto applyA = [&](const double* mt, const double* kt, int sd, const T2* xv, int a) -> T2 {
         const int nd = sd * sd;
         const T2 xc = xv[a], xe = xv[a + 1], xw = xv[a - 1], xn = xv[a + sd], xs = xv[a - sd], xne = xv[a + sd + 1],
                  xsw = xv[a - sd - 1];
         T2 out;
-        out.x = nu * ((T)4 * xc.x - xe.x - xw.x - xn.x - xs.x);
-        out.y = nu * ((T)4 * xc.y - xe.y - xw.y - xn.y - xs.y);
+        if (kt) {
+            out = scale2((T)kt[a], xc);
+            out = fma2((T)kt[nd + a], xe, out);
+            out = fma2((T)kt[nd + a - 1], xw, out);
+            out = fma2((T)kt[2 * nd + a], xn, out);
+            out = fma2((T)kt[2 * nd + a - sd], xs, out);
+            out = fma2((T)kt[3 * nd + a], xne, out);
+            out = fma2((T)kt[3 * nd + a - sd - 1], xsw, out);
+        } else {
+            out.x = nu * ((T)4 * xc.x - xe.x - xw.x - xn.x - xs.x);
+            out.y = nu * ((T)4 * xc.y - xe.y - xw.y - xn.y - xs.y);
+        }
         const double mc = mt[a], me = mt[nd + a], mw = mt[nd + a - 1], mn = mt[2 * nd + a], ms = mt[2 * nd + a - sd],
                      mne = mt[3 * nd + a], msw = mt[3 * nd + a - sd - 1];
         if (mc != 0.0 || me != 0.0 || mw != 0.0 || mn != 0.0 || ms != 0.0 || mne != 0.0 || msw != 0.0) {
@@ -534,16 +576,17 @@ __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, 
     for (int q = 0; q + 1 < sm.count; ++q) {
         const int sd = sm.side[q], n = sd - 1, nodes = sd * sd, sc = sm.side[q + 1], nc = sc - 1;
         const double* mt = sm.mt[q];
+        const double* kt = sm.kt[q];
         const T2* r = sh + sm.off_r[q];
         T2* x1 = sh + sm.off_x[q];
         const T2* t = r;   // the fine residual (V(0,1): r itself)
         if (sm.pre) {
             T2* tw = sh + sm.off_t;
-            for (int a = threadIdx.x; a < nodes; a += kBlock) x1[a] = jac(mt[a], r[a]);
+            for (int a = threadIdx.x; a < nodes; a += kBlock) x1[a] = jac(mt, kt, a, r[a]);
             __syncthreads();
             for (int a = threadIdx.x; a < nodes; a += kBlock) {
                 const int j = a / sd, i = a - j * sd;
-                tw[a] = (i > 0 && i < n && j > 0 && j < n) ? sub2(r[a], applyA(mt, sd, x1, a)) : zero;
+                tw[a] = (i > 0 && i < n && j > 0 && j < n) ? sub2(r[a], applyA(mt, kt, sd, x1, a)) : zero;
             }
             __syncthreads();
             t = tw;
@@ -567,18 +610,21 @@ __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, 
         __syncthreads();
     }
     {
-        // the coarsest level: the single interior node (1, 1), 1 x 1 operator 4 nu_max + z M_c
+        // the coarsest level: the single interior node (1, 1), 1 x 1 operator Khat_c + z M_c
+        // (Khat_c = 4 nu_max for the constant stencil)
         const int q = sm.count - 1, sd = sm.side[q], nodes = sd * sd;
         const T2* r = sh + sm.off_r[q];
         T2* x = sh + sm.off_x[q];
+        const T dlq = sm.kt[q] ? (T)sm.kt[q][sd + 1] : dl;
         for (int a = threadIdx.x; a < nodes; a += kBlock)
-            x[a] = (a == sd + 1) ? gs_apply(gs_inv_diag<T>(dl, (T)1 / dl, (T)sm.mt[q][a], z), r[a]) : zero;
+            x[a] = (a == sd + 1) ? gs_apply(gs_inv_diag<T>(dlq, (T)1 / dlq, (T)sm.mt[q][a], z), r[a]) : zero;
     }
     __syncthreads();
     // prolongation sweeps with post-smoothing: level q + 1 -> q
     for (int q = sm.count - 2; q >= 0; --q) {
         const int sd = sm.side[q], n = sd - 1, nodes = sd * sd, sc = sm.side[q + 1];
         const double* mt = sm.mt[q];
+        const double* kt = sm.kt[q];
         const T2* r = sh + sm.off_r[q];
         const T2* xc = sh + sm.off_x[q + 1];
         T2* x2 = sh + sm.off_t;
@@ -587,13 +633,14 @@ __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, 
             const int j = a / sd, i = a - j * sd, hi = i >> 1, hj = j >> 1;
             const T2 c0 = xc[hj * sc + hi];
             const T2 p = ((i | j) & 1) ? scale2(half, add2(c0, xc[(hj + (j & 1)) * sc + hi + (i & 1)])) : c0;
-            x2[a] = sm.pre ? add2(jac(mt[a], r[a]), p) : p;
+            x2[a] = sm.pre ? add2(jac(mt, kt, a, r[a]), p) : p;
         }
         __syncthreads();
         for (int a = threadIdx.x; a < nodes; a += kBlock) {
             const int j = a / sd, i = a - j * sd;
-            x3[a] = (i > 0 && i < n && j > 0 && j < n) ? add2(x2[a], jac(mt[a], sub2(r[a], applyA(mt, sd, x2, a))))
-                                                       : zero;
+            x3[a] = (i > 0 && i < n && j > 0 && j < n)
+                        ? add2(x2[a], jac(mt, kt, a, sub2(r[a], applyA(mt, kt, sd, x2, a))))
+                        : zero;
         }
         __syncthreads();
     }
@@ -624,12 +671,14 @@ __device__ __forceinline__ SV<T> up_eval_t(const UpIn<SV<T>>& u, T dl, T idl, T 
     return sv_fma((T)0.5, sv_add(u.c0, u.c1), v);
 }
 
-// x3 = x2 + omega D^{-1} (r - A x2) at an interior node with mass row m (m.c its diagonal)
-template <typename T, bool MASS>
+// x3 = x2 + omega D^{-1} (r - A x2) at an interior node with mass row m (m.c its diagonal) and,
+// VK, Khat row kr (dl = kr.c then)
+template <typename T, bool MASS, bool VK = false>
 __device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl, T om, const GS<T>* z, const SV<T>& r,
                                                const SV<T>& xc, const SV<T>& xe, const SV<T>& xw, const SV<T>& xn,
-                                               const SV<T>& xs, const SV<T>& xne, const SV<T>& xsw) {
-    const SV<T> Ax = apply_A_t<T, MASS>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw);
+                                               const SV<T>& xs, const SV<T>& xne, const SV<T>& xsw,
+                                               const MRow& kr = MRow{}) {
+    const SV<T> Ax = apply_A_t<T, MASS, VK>(m, nu, z, xc, xe, xw, xn, xs, xne, xsw, kr);
     return sv_add(xc, jacobi_t<T, MASS>(dl, idl, om, m.c, z, sv_sub(r, Ax)));
 }
 
@@ -643,9 +692,10 @@ __device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl,
 // coarse values they interpolate from come from a window of coarse rows (below).
 // Three waves per SIMD (at most 168 VGPRs): the coarse window would otherwise drop to two.
 // x3 is stored with streaming access, keeping the caches for the neighbour columns' inputs.
-template <typename T, bool UNI, bool PRE>
+template <typename T, bool UNI, bool PRE, bool VK>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
+    static_assert(!(PRE && VK), "a per-region Khat runs the V(0,1) cycle");
     using W = SV<T>;
     constexpr int V = W::V;
     const W* rin = (const W*)rin_;
@@ -772,11 +822,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 issue_fence();
                 W out = sv_zero<T>();
                 if (here && aj > 0 && aj < nF) {
-                    const MRow m = mrow<UNI>(F, (long)aj * sf + ai);
+                    const long node = (long)aj * sf + ai;
+                    const MRow m = mrow<UNI>(F, node);
+                    MRow kr{};
+                    T dlc = dl, idlc = idl;
+                    if constexpr (VK) {  // the node's Khat row and diagonal
+                        kr = krow<UNI>(F, node);
+                        dlc = (T)kr.c;
+                        idlc = (T)1 / dlc;
+                    }
                     if (m.any())
-                        out = post_smooth_t<T, true>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
+                        out = post_smooth_t<T, true, VK>(m, nu, dlc, idlc, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw,
+                                                         kr);
                     else
-                        out = post_smooth_t<T, false>(m, nu, dl, idl, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw);
+                        out = post_smooth_t<T, false, VK>(m, nu, dlc, idlc, om, L.z, rc, xcn, xe, xw, xn, xs, xne, xsw,
+                                                          kr);
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, out, rc, dotmode == DOT_HERM);
                 }
                 if (here) nt_store(boff(row_of(xout, aj, sf, lgR), ofn[1]), out);
@@ -839,8 +899,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
 // window spans columns a0-1 .. a0+2, so each row loads four new points for two outputs
 // instead of three for one. The window is kept in row slots modulo 4 (row aj in slot
 // (aj - j0 + 1) & 3) with the row loop unrolled by 4, so it is never moved between registers.
-// Boundary columns and rows give 0.
-template <typename T, bool UNI>
+// Boundary columns and rows give 0. VK: Khat from the level's stencil table (per-region Khat).
+template <typename T, bool UNI, bool VK>
 __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const void* x_, void* y_, int dotmode,
                                                    double* part) {
     using W = SV<T>;
@@ -892,13 +952,15 @@ __global__ void __launch_bounds__(kBlock) k_matvec(SlotArgs sa, LvArgs F, const 
             W out0 = sv_zero<T>(), out1 = sv_zero<T>();
             if (aj > 0 && aj < nF) {
                 if (in0) {
-                    out0 = apply_A<T>(mrow<UNI>(F, (long)aj * sf + a0), nu, L.z, C0[s1], C1[s1], Wc[s1], C0[s2], C0[s0],
-                                      C1[s2], Wc[s0]);
+                    const long nd0 = (long)aj * sf + a0;
+                    out0 = apply_A<T, VK>(mrow<UNI>(F, nd0), nu, L.z, C0[s1], C1[s1], Wc[s1], C0[s2], C0[s0], C1[s2],
+                                          Wc[s0], VK ? krow<UNI>(F, nd0) : MRow{});
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, C0[s1], out0, dotmode == DOT_HERM);
                 }
                 if (in1) {
-                    out1 = apply_A<T>(mrow<UNI>(F, (long)aj * sf + a0 + 1), nu, L.z, C1[s1], Ec[s1], C0[s1], C1[s2],
-                                      C1[s0], Ec[s2], C0[s0]);
+                    const long nd1 = (long)aj * sf + a0 + 1;
+                    out1 = apply_A<T, VK>(mrow<UNI>(F, nd1), nu, L.z, C1[s1], Ec[s1], C0[s1], C1[s2], C1[s0], Ec[s2],
+                                          C0[s0], VK ? krow<UNI>(F, nd1) : MRow{});
                     if (dotmode != DOT_NONE) sv_dot_acc(acc, C1[s1], out1, dotmode == DOT_HERM);
                 }
             }
@@ -1256,6 +1318,7 @@ static LvArgs host_lv(const Plan& p, char* ws, int l) {
     L.side = p.lev[l].side;
     L.nodes = p.lev[l].nodes;
     L.mt = (const double*)(ws + p.lev[l].off_mt);
+    L.kt = p.vk ? (const double*)(ws + p.lev[l].off_kt) : nullptr;
     return L;
 }
 
@@ -1324,6 +1387,7 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
             const LevelDesc& d = p.lev[l0 + q];
             sm.side[q] = d.side;
             sm.mt[q] = (const double*)(ws + d.off_mt);
+            sm.kt[q] = p.vk ? (const double*)(ws + d.off_kt) : nullptr;
             sm.off_r[q] = off;
             sm.off_x[q] = off + (int)d.nodes;
             off += 2 * (int)d.nodes;
@@ -1366,21 +1430,23 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
         tm_begin(p, kid, st);
         LvArgs Fl = host_lv(p, ws, l), Cl = host_lv(p, ws, l + 1);
         const bool uni = g.slot_chunk >= 64;
-        auto up = [&](auto t_, auto uni_, auto pre_) {
+        auto up = [&](auto t_, auto uni_, auto pre_, auto vk_) {
             using T = decltype(t_);
-            constexpr bool U = decltype(uni_)::value, PRE = decltype(pre_)::value;
-            hipLaunchKernelGGL((k_vc_up<T, U, PRE>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm, part);
+            constexpr bool U = decltype(uni_)::value, PRE = decltype(pre_)::value, VK = decltype(vk_)::value;
+            hipLaunchKernelGGL((k_vc_up<T, U, PRE, VK>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
+                               part);
         };
-        auto up_t = [&](auto t_) {
+        // (a per-region Khat only with V(0,1): the plan validation guarantees !(p.vk && p.vc_pre))
+        auto up_u = [&](auto t_, auto uni_) {
             using TT = std::true_type;
             using FF = std::false_type;
-            if (uni) {
-                if (p.vc_pre) up(t_, TT(), TT());
-                else up(t_, TT(), FF());
-            } else {
-                if (p.vc_pre) up(t_, FF(), TT());
-                else up(t_, FF(), FF());
-            }
+            if (p.vc_pre) up(t_, uni_, TT(), FF());
+            else if (p.vk) up(t_, uni_, FF(), TT());
+            else up(t_, uni_, FF(), FF());
+        };
+        auto up_t = [&](auto t_) {
+            if (uni) up_u(t_, std::true_type());
+            else up_u(t_, std::false_type());
         };
         if (p.fp32)
             up_t(0.0f);
@@ -1395,18 +1461,24 @@ void launch_matvec(const Plan& p, char* ws, const void* x, void* y, int dotmode,
     SlotArgs sa = mk_slot(p, ws, g);
     dim3 grid(g.blocks, g.chunks);
     LvArgs Fl = host_lv(p, ws, 0);
-    bool uni = g.slot_chunk >= 64;
-    if (p.fp32) {
-        if (uni)
-            hipLaunchKernelGGL((k_matvec<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
-        else
-            hipLaunchKernelGGL((k_matvec<float, false>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
-    } else {
-        if (uni)
-            hipLaunchKernelGGL((k_matvec<double, true>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
-        else
-            hipLaunchKernelGGL((k_matvec<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
-    }
+    const bool uni = g.slot_chunk >= 64;
+    auto mv = [&](auto t_, auto uni_, auto vk_) {
+        using T = decltype(t_);
+        constexpr bool U = decltype(uni_)::value, VK = decltype(vk_)::value;
+        hipLaunchKernelGGL((k_matvec<T, U, VK>), grid, dim3(kBlock), 0, st, sa, Fl, x, y, dotmode, part);
+    };
+    auto mv_u = [&](auto t_, auto uni_) {
+        if (p.vk) mv(t_, uni_, std::true_type());
+        else mv(t_, uni_, std::false_type());
+    };
+    auto mv_t = [&](auto t_) {
+        if (uni) mv_u(t_, std::true_type());
+        else mv_u(t_, std::false_type());
+    };
+    if (p.fp32)
+        mv_t(0.0f);
+    else
+        mv_t(0.0);
 }
 
 static Dots1Set dots1_set(const Plan& p, double* part, int nblk) {

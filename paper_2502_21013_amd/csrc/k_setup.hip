@@ -175,11 +175,58 @@ void launch_setup_fine(const Plan& p, char* ws, hipStream_t st) {
     }
 }
 
-void launch_galerkin(const Plan& p, char* ws, int l, hipStream_t st) {
+void launch_galerkin_table(const Plan& p, char* ws, int l, bool khat, hipStream_t st) {
     const LevelDesc& f = p.lev[l];
     const LevelDesc& c = p.lev[l + 1];
-    hipLaunchKernelGGL(k_galerkin, dim3(grid_for(c.nodes)), dim3(kBlock), 0, st, (const double*)(ws + f.off_mt),
-                       f.side, (double*)(ws + c.off_mt), c.side);
+    const size_t fo = khat ? f.off_kt : f.off_mt, co = khat ? c.off_kt : c.off_mt;
+    hipLaunchKernelGGL(k_galerkin, dim3(grid_for(c.nodes)), dim3(kBlock), 0, st, (const double*)(ws + fo), f.side,
+                       (double*)(ws + co), c.side);
+}
+
+void launch_galerkin(const Plan& p, char* ws, int l, hipStream_t st) { launch_galerkin_table(p, ws, l, false, st); }
+
+// Khat = S_nuhat, the P1 stiffness with the per-triangle coefficient nu_hat of the triangle's
+// region, as a stencil table in the mass layout (centre, E, N, NE per node). On the SW-NE split
+// grid the P1 coupling of two nodes through a triangle is -nuhat_T cot(theta) / 2 with theta the
+// angle opposite their edge: 45 degrees for the axis edges (each in two triangles, one on either
+// side), 90 degrees for the diagonal ones (no coupling). So the east weight of node (i, j) is
+// (nuhat(T_a(i,j)) + nuhat(T_b(i,j-1))) / 2, the north weight (nuhat(T_b(i,j)) + nuhat(T_a(i-1,j))) / 2,
+// and the centre the sum of the four axis weights (a constant nu_hat gives 4 nu, -nu, -nu, 0).
+struct StiffArgs {
+    int n, side;
+    const uint8_t* region;  // [2 n^2]
+    const double* rkh;      // [kMaxRegions] nu_hat of each region
+    double* kt;             // [4][nodes]
+};
+
+__device__ __forceinline__ double tri_khat(const StiffArgs& a, int i, int j, int t) {
+    if (i < 0 || j < 0 || i >= a.n || j >= a.n) return 0.0;
+    return a.rkh[a.region[2 * (j * a.n + i) + t]];
+}
+
+__global__ void __launch_bounds__(kBlock) k_fine_stiffness(StiffArgs a) {
+    const size_t nodes = (size_t)a.side * a.side;
+    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < nodes; id += (size_t)gridDim.x * kBlock) {
+        const int i = (int)(id % a.side), j = (int)(id / a.side);
+        const double we = 0.5 * (tri_khat(a, i, j, 0) + tri_khat(a, i, j - 1, 1));
+        const double ww = 0.5 * (tri_khat(a, i - 1, j, 0) + tri_khat(a, i - 1, j - 1, 1));
+        const double wn = 0.5 * (tri_khat(a, i, j, 1) + tri_khat(a, i - 1, j, 0));
+        const double ws = 0.5 * (tri_khat(a, i, j - 1, 1) + tri_khat(a, i - 1, j - 1, 0));
+        a.kt[id] = we + ww + wn + ws;
+        a.kt[nodes + id] = -we;
+        a.kt[2 * nodes + id] = -wn;
+        a.kt[3 * nodes + id] = 0.0;
+    }
+}
+
+void launch_setup_stiffness(const Plan& p, char* ws, hipStream_t st) {
+    StiffArgs a;
+    a.n = p.n;
+    a.side = p.side;
+    a.region = p.prob.d_region;
+    a.rkh = (const double*)(ws + p.off_rkh);
+    a.kt = (double*)(ws + p.lev[0].off_kt);
+    hipLaunchKernelGGL(k_fine_stiffness, dim3(grid_for(p.nodes)), dim3(kBlock), 0, st, a);
 }
 
 }  // namespace pt

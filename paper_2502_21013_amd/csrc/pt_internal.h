@@ -41,6 +41,7 @@ struct LevelDesc {
     int side;       // n + 1
     size_t nodes;   // side * side
     size_t off_mt;  // M stencil table, 4 * nodes doubles
+    size_t off_kt;  // Khat stencil table in the same layout (per-region Khat only, else 0)
     size_t off_r;   // slot vector: right-hand side at this level
     size_t off_x;   // slot vector: correction at this level
 };
@@ -134,7 +135,9 @@ struct Plan {
     pt_region regions[kMaxRegions];  // region mode: host copy of the regions
     double* h_regp;     // B x kMaxRegions x 4: law parameters of each region (see law_nu)
     double* h_rsj;      // kMaxRegions x 2: conductivity and current amplitude (region mode)
-    size_t off_regp, off_rsj;
+    double h_rkh[kMaxRegions];  // Khat coefficient of each region (nu_max where nu_hat is 0)
+    bool vk;            // Khat = S_nuhat with a per-region coefficient (stencil tables off_kt)
+    size_t off_regp, off_rsj, off_rkh;
     int target_slot, target_team;  // grid targets of the slot-vector and per-node kernels
     int target_down, target_up;    // grid targets of the restriction and up sweeps (all levels)
     Geom g_slot0;       // up sweep on level 0 (its dot partials: one row per workgroup)
@@ -158,6 +161,8 @@ Geom fwd_geom(int side, int S, int B, int target);
 // setup (k_setup.hip)
 void launch_setup_fine(const Plan& p, char* ws, hipStream_t st);
 void launch_galerkin(const Plan& p, char* ws, int l, hipStream_t st);
+void launch_galerkin_table(const Plan& p, char* ws, int l, bool khat, hipStream_t st);
+void launch_setup_stiffness(const Plan& p, char* ws, hipStream_t st);
 void launch_row_records(const Plan& p, char* ws, hipStream_t st);
 // time axis (k_time.hip)
 void launch_transpose_in(const Plan& p, const double* src, double* dst, hipStream_t st);

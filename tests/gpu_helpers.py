@@ -75,8 +75,9 @@ def vcycle_reference(d, omega, R, pre=1, post=1):
     written out from its definition on the interior nodes of each level: x1 = omega D^{-1} r
     (x1 = 0 without pre-smoothing), r_c = P^T (r - A x1), x_c = the cycle on the next level
     (exact on the 2 x 2-cell grid), x2 = x1 + P x_c, x3 = x2 + omega D^{-1} (r - A x2)
-    (x3 = x2 without post-smoothing), with A = Khat + z M, Khat = nu_max * (5-point stencil),
-    D = 4 nu_max + z diag(M), P the P1 interpolation and the coarse mass P^T M P.
+    (x3 = x2 without post-smoothing), with A = Khat + z M, D = diag(Khat) + z diag(M), P the P1
+    interpolation, and the coarse Khat and M the Galerkin products P^T Khat P, P^T M P (Khat =
+    nu_max * (5-point stencil) or the per-region stiffness of d.Khat).
     R: (nodes, S) complex; slot 0 holds the k = 0 system on the real part and k = N/2 on the
     imaginary part."""
     p = d.p
@@ -85,24 +86,28 @@ def vcycle_reference(d, omega, R, pre=1, post=1):
     levels = []
     n = p.n
     Mf = fem.mass_full(d.mesh, d.mat.sigma).tocsr()
+    Kf = (fem.stiffness_full(d.mesh, d.khat_coef) if d.khat_coef is not None
+          else nu * fem.stiffness_full(d.mesh)).tocsr()
     while True:
         m = fem.build_mesh(n)
         free = np.flatnonzero(m.free)
-        Kh = nu * fem.stiffness_full(m)[free][:, free].tocsr()
+        Kh = Kf[free][:, free].tocsr()
         M = Mf[free][:, free].tocsr()
-        lev = {"n": n, "free": free, "Kh": Kh, "M": M, "dM": M.diagonal(), "nodes": (n + 1) ** 2}
+        lev = {"n": n, "free": free, "Kh": Kh, "dK": Kh.diagonal(), "M": M, "dM": M.diagonal(),
+               "nodes": (n + 1) ** 2}
         levels.append(lev)
         if n == 2:
             break
         Pf = _prolongation(n // 2)               # coarse (n/2) -> this level
         lev["P"] = Pf[free][:, np.flatnonzero(fem.build_mesh(n // 2).free)].tocsr()
         Mf = (Pf.T @ Mf @ Pf).tocsr()
+        Kf = (Pf.T @ Kf @ Pf).tocsr()
         n //= 2
 
     def cycle(l, zz, r):
         L = levels[l]
         A = L["Kh"] + zz * L["M"]
-        D = 4 * nu + zz * L["dM"]
+        D = L["dK"] + zz * L["dM"]
         if L["n"] == 2:
             return r / D
         x1 = omega * r / D if pre else np.zeros_like(r)

@@ -56,3 +56,40 @@ def test_largest_batch_is_in_bounds(P):
     # 1024 instances of N = 128: 65536 slots per node, the ABI's limit
     probs = [dataclasses.replace(W.with_size(W.config1(), 8, 128), J0=1.0 + k) for k in range(512)]
     check(P, P.BatchPlan(probs, precision="fp32", inner="cocg"))
+
+
+def _region_plan_status(P, p, **opts):
+    """Create a region-mode plan through the ABI with a placeholder device pointer for the region
+    table (plan creation and the bounds walk never dereference it); returns (status, plan handle)."""
+    from paper_2502_21013_amd import _lib as L
+    lib = P.library()
+    ps = P.problem_struct(dataclasses.replace(p, regions=None))
+    arr = (L.Region * len(p.regions))(*[L.Region(r.sigma, r.a, r.b, r.c, r.d, r.j, r.nu_hat) for r in p.regions])
+    ps.law = {"rational": L.PT_NU_RATIONAL, "expcap": L.PT_NU_EXPCAP}[p.law]
+    ps.nregions, ps.regions, ps.d_region = len(p.regions), arr, 0x1000
+    o = P._options(lib, 1e-8, 100, 1, opts.pop("precision", "fp64"), opts.pop("inner", "galerkin1"), 1, 0.8, False,
+                   1e3, True, False, False, **opts)
+    h = C.c_void_p()
+    st = lib.pt_plan_create(C.byref(ps), C.byref(o), C.byref(h))
+    return st, h, arr
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,grid", [(16, 0), (64, 66), (512, 0)])
+def test_region_khat_plans_are_in_bounds(P, precision, n, grid):
+    # per-region Khat: the stiffness tables of every level join the workspace layout
+    st, h, _ = _region_plan_status(P, W.transformer(n, 8, khat_factor=1.2), precision=precision, grid_slot=grid)
+    assert st == 0, P.library().pt_last_error()
+    msg = C.create_string_buffer(512)
+    assert P.library().pt_plan_check_bounds(h, msg, 512) == 0, msg.value.decode()
+    P.library().pt_plan_destroy(h)
+
+
+def test_region_khat_needs_the_galerkin_v01_step(P):
+    p = W.transformer(16, 8, khat_factor=1.2)
+    for kw in (dict(inner="cocg"), dict(cycle="v11")):
+        st, h, _ = _region_plan_status(P, p, **kw)
+        assert st == -1 and b"nu_hat" in P.library().pt_last_error()
+    bad = dataclasses.replace(p, regions=(dataclasses.replace(p.regions[0], nu_hat=-1.0),) + p.regions[1:])
+    st, h, _ = _region_plan_status(P, bad)
+    assert st == -1 and b"nu_hat" in P.library().pt_last_error()

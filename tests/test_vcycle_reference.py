@@ -33,6 +33,53 @@ def test_galerkin_coarse_mass_is_the_coarse_assembly():
     assert abs(P.T @ Mf @ P - Mc).max() <= 1e-15 * abs(Mc).max()
 
 
+def _regions_problem(n, N):
+    # two regions with their own Khat coefficient, the inner one a union of triangles of every grid
+    # down to 8 x 8 cells (its edges on multiples of 1/8)
+    R = W.Region
+    regs = (R("outer", a=1.0, nu_hat=3.0), R("inner", sigma=2.0, a=2.0, b=1.0, nu_hat=7.0))
+    layout = ((W.Rect(0.0, 0.0, 1.0, 1.0), 0), (W.Rect(0.25, 0.25, 0.75, 0.625), 1))
+    return W.Problem(n=n, N=N, law="rational", regions=regs, layout=layout, nu_max=10.0)
+
+
+def test_region_khat_galerkin_coarse_is_the_coarse_assembly():
+    # P^T Khat_f P equals the per-region stiffness assembled on the coarse mesh when the regions
+    # are unions of coarse triangles; a constant coefficient gives nu_hat S
+    pf, pc = _regions_problem(16, 8), _regions_problem(8, 8)
+    df, dc = fem.discretise(pf), fem.discretise(pc)
+    Kf = fem.stiffness_full(df.mesh, df.khat_coef)
+    Kc = fem.stiffness_full(dc.mesh, dc.khat_coef)
+    P = _prolongation(8)
+    assert abs(P.T @ Kf @ P - Kc).max() <= 1e-13 * abs(Kc).max()
+    assert set(np.unique(df.khat_coef)) == {3.0, 7.0}
+    m = df.mesh
+    assert abs(fem.stiffness_full(m, np.full(m.area.shape, 3.0)) - 3.0 * fem.stiffness_full(m)).max() <= 1e-13
+
+
+def test_reference_cycle_with_region_khat():
+    # with a per-region Khat the V(0,1) and V(1,0) cycles are still transposes of each other, and
+    # the cycle is the exact solve on the 2 x 2-cell grid
+    d = fem.discretise(_regions_problem(16, 8))
+    rng = np.random.default_rng(9)
+    R1, R2 = (rng.standard_normal((d.mesh.nodes, 4)) + 1j * rng.standard_normal((d.mesh.nodes, 4)) for _ in range(2))
+    R1[~d.mesh.free] = 0
+    R2[~d.mesh.free] = 0
+    B01 = vcycle_reference(d, 0.8, R1, pre=0, post=1)
+    B10 = vcycle_reference(d, 0.8, R2, pre=1, post=0)
+    for s in range(1, 4):
+        a, b = np.sum(B01[:, s] * R2[:, s]), np.sum(R1[:, s] * B10[:, s])
+        assert abs(a - b) <= 1e-13 * abs(a)
+    d2 = fem.discretise(_regions_problem(2, 8))
+    R = rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4))
+    R[~d2.mesh.free] = 0
+    B = vcycle_reference(d2, 0.8, R, pre=0)
+    z = dft.shifts(8, d2.p.tau)
+    fi = d2.free_idx
+    for s in range(1, 4):
+        A = (d2.Khat + z[s] * d2.M).toarray()
+        assert np.allclose(A @ B[fi, s], R[fi, s], rtol=1e-13, atol=0)
+
+
 def _setup(n, N, seed):
     p = W.with_size(W.config2(seed), n, N)
     d = fem.discretise(p)

@@ -52,7 +52,9 @@ class Rect:
 @dataclass(frozen=True)
 class Region:
     """Material of one region of a cross-section (Sec. 4, table tab:coef): conductivity sigma,
-    parameters a, b, c, d of the reluctivity law and current-density amplitude j."""
+    parameters a, b, c, d of the reluctivity law and current-density amplitude j, and the
+    region's coefficient nu_hat of the iteration's linear operator Khat (0: the problem's
+    nu_max)."""
     name: str
     sigma: float = 0.0
     a: float = 0.0
@@ -60,6 +62,7 @@ class Region:
     c: float = 1.0
     d: float = 1.0
     j: float = 0.0
+    nu_hat: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -214,14 +217,17 @@ def _mm_rect(x0, y0, x1, y1) -> Rect:
 
 
 def transformer(n: int = 128, N: int = 64, law: str = "expcap", nu_max: Optional[float] = None,
-                j_scale: float = 1.0) -> Problem:
+                j_scale: float = 1.0, khat_factor: Optional[float] = None) -> Problem:
     """The transformer cross-section of Sec. 4 drawn on the unit square (each axis scaled onto
     [0, 1], so the grid stays uniform and square: a transformer-like geometry with the paper's
     layout and materials, not its exact aspect ratio), with the law nu = a min(exp(b s^2), c) + d
     of table tab:coef, T = 0.02 s, the cos source j_i cos(2 pi t / T) (j_i scaled by j_scale) and
     Khat = nu_max S, nu_max = max_i (a_i c_i + d_i) by default (the largest reluctivity the law
-    takes)."""
+    takes). khat_factor: Khat = S_nuhat with nu_hat_i = khat_factor (a_i + d_i) per region
+    instead (the law's value at zero field, scaled)."""
     regs = tuple(replace(r, j=r.j * j_scale) for r in TRANSFORMER_REGIONS)
+    if khat_factor is not None:
+        regs = tuple(replace(r, nu_hat=float(khat_factor) * (r.a + r.d)) for r in regs)
     layout = (
         (Rect(0.0, 0.0, 1.0, 1.0), 2),                 # steel tank wall ...
         (_mm_rect(10, 10, 345, 456), 0),               # ... around the air inside it
