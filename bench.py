@@ -31,7 +31,7 @@ FP64. It is compared with the plain FP64 path (each instance alone, eager launch
 after the other; plans, workspaces and fields built and warmed up before timing), with its
 own roofline (a serial pass with per-kernel events) and CPU baseline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c4|tr] [--paper-stop]
 """
 from __future__ import annotations
 
@@ -62,7 +62,14 @@ def workload(name, seed):
         return W.config2(seed), "256x256 cells, N=256, seeded materials"
     if name == "c1":
         return W.config1(), "32x32 cells, N=32"
+    if name == "tr":
+        return (W.transformer(256, 512, khat_factor=TR_KHAT),
+                f"transformer cross-section (Sec. 4 layout and exp-capped law on the unit square), 256x256 cells, "
+                f"N=512, per-region Khat {TR_KHAT} nu(0)")
     raise SystemExit(f"unknown workload {name}")
+
+
+TR_KHAT = 1.2   # the transformer workload's Khat coefficient per region, in units of the law at zero field
 
 
 def run_many(P, problems, mode, steps, warmup, tol, nstreams, graph, tuning, trace_gap=0.0, **opts):
@@ -296,7 +303,7 @@ def load_traffic(kernel, mode, wl):
     return ent.get("hbm_bytes_per_launch")
 
 
-def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inner=None):
+def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inner=None, extra=None):
     """Time `steps` solves after `warmup` untimed ones. Before them, one untimed solve with every
     kernel class bracketed by HIP events gives the per-class device times; the timed solves then
     bracket only the two classes with the most device time (two event records per launch of
@@ -304,6 +311,7 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inne
     import torch
     kw = dict(inner or {})
     kw.update(tuned or {})   # a tuning table entry overrides the inner method given on the command line
+    kw.update(extra or {})   # problem tables (region ids) and the stopping protocol
     plan = P.Plan(prob, tol=tol, precision=mode, timing=True, max_outer=max_outer, **kw)
     U = plan.new_time_field()
     plan.workspace()
@@ -320,13 +328,14 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inne
     for w in range(warmup):
         _, st = plan.solve(U, raise_on_error=max_outer >= 2000)
         log(f"{mode} warmup {w}: outer={st.outer_iters} rel={st.rel_residual:.3e} {st.time_ms:.1f} ms")
-    kms, kcnt, outer, dev_ms = {}, {}, [], []
+    kms, kcnt, outer, dev_ms, init = {}, {}, [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         _, st = plan.solve(U, raise_on_error=max_outer >= 2000)
         outer.append(st.outer_iters)
         dev_ms.append(st.time_ms)
+        init.append(st.init_iters)
         for name, v in st.kernel_ms.items():
             kms[name] = kms.get(name, 0.0) + v
             kcnt[name] = kcnt.get(name, 0) + st.kernel_launches[name]
@@ -337,7 +346,7 @@ def run_mode(P, prob, mode, steps, warmup, tol, max_outer=2000, tuned=None, inne
     del plan
     torch.cuda.empty_cache()
     return {"ms_per_step": 1e3 * wall / steps, "kernel_ms": kms, "kernel_launches": kcnt,
-            "kernel_ms_pass": all_ms, "kernel_launches_pass": all_n, "solve_ms_device": dev_ms,
+            "kernel_ms_pass": all_ms, "kernel_launches_pass": all_n, "solve_ms_device": dev_ms, "init_iters": init,
             "outer_iters": outer, "rel_residual": st.rel_residual, "U": U}
 
 
@@ -408,6 +417,8 @@ def _oracle_sample_worker(job):
     kind, seed, n, N, tol = job
     if kind == "c4":
         base = W.config4(seed)[0]
+    elif kind == "tr":
+        base = W.transformer(n, N, khat_factor=TR_KHAT)
     else:
         base = W.config3(seed)
     p = W.with_size(base, n, N)
@@ -439,7 +450,8 @@ def cpu_baseline(kind, seed, n=32, N=64, tol=1e-8):
         res = list(ex.map(_oracle_sample_worker, jobs))
     dofs = sum(r[0] for r in res)
     tmax = max(r[1] for r in res)
-    what = "config-4 instance 0's materials and source" if kind == "c4" else "the same seeded materials/source"
+    what = {"c4": "config-4 instance 0's materials and source",
+            "tr": "the same transformer cross-section and per-region Khat"}.get(kind, "the same seeded materials/source")
     return {"value": dofs / tmax, "unit": "space-time DoFs/s", "cores": cores, "kind": "oracle",
             "sample": f"{cores} concurrent copies (one per host core, one thread each) of {n}x{n} cells, N={N}, "
                       f"{what}, tol {tol:g}, {res[0][2]} outer steps, longest {tmax:.1f} s "
@@ -585,6 +597,9 @@ def main():
                     help="inner method of every periodic solve (default: the one-step Galerkin V-cycle)")
     ap.add_argument("--inner-iters", type=int, default=1, help="COCG steps per outer step (at most)")
     ap.add_argument("--inner-rtol", type=float, default=0.0, help="COCG per-frequency relative tolerance")
+    ap.add_argument("--paper-stop", action="store_true",
+                    help="the paper's protocol: start from the static solution, stop at --tol relative to its "
+                         "residual (tab:runtime: 1e-4)")
     ap.add_argument("--cycle", default="default", choices=["default", "v11", "v01"],
                     help="multigrid cycle (default: V(0,1) with the Galerkin step, V(1,1) with COCG)")
     ap.add_argument("--no-batching", action="store_true", help="skip the batching sub-record")
@@ -631,7 +646,7 @@ def main():
     if not args.no_cpu_baseline and not args.calibrate_copy:
         if args.workload != "c4":
             log("cpu baseline (oracle on a bounded sample, one copy per host core)")
-            cpu = cpu_baseline("c3", args.seed)
+            cpu = cpu_baseline("tr" if args.workload == "tr" else "c3", args.seed)
             log(f"cpu baseline {cpu['value']:.1f} DoFs/s on {cpu['cores']} cores")
         if want_batch:
             cpu4 = cpu_baseline("c4", args.seed)
@@ -648,6 +663,7 @@ def main():
     if args.workload == "c4":
         main_many(args, P, cpu4)
         return
+    import workloads as W
     prob, desc = workload(args.workload, args.seed)
     log(f"workload {args.workload}: {desc}, {prob.st_dofs} space-time DoFs")
 
@@ -656,12 +672,18 @@ def main():
     from paper_2502_21013_amd.batch import tune_key
     table = AT.load_table(args.tuning) if args.tuning else {}
     inner = {"inner": args.inner, "inner_iters": args.inner_iters, "inner_rtol": args.inner_rtol, "cycle": args.cycle}
+    extra = {}
+    if prob.regions is not None:
+        extra["region"] = torch.from_numpy(W.region_ids(prob)).to("cuda:0")
+    if args.paper_stop:
+        # Sec. 4: start from the static solution (sigma = 0) and stop relative to its residual
+        extra.update(init_static=True, stop_relative_initial=True)
     res = {}
     for m in modes:
         tuned = table.get(tune_key(prob, 1, m))
         if tuned:
             log(f"{m}: tuned setting {tuned}")
-        res[m] = run_mode(P, prob, m, args.steps, args.warmup, args.tol, args.max_outer, tuned, inner)
+        res[m] = run_mode(P, prob, m, args.steps, args.warmup, args.tol, args.max_outer, tuned, inner, extra)
         res[m]["tuned"] = tuned
         log(f"{m}: {res[m]['ms_per_step']:.1f} ms per solve")
     errors = {}
@@ -729,6 +751,7 @@ def main():
                       "median_solve_ms_device": statistics.median(res[m]["solve_ms_device"]),
                       "solve_ms_device": [round(x, 2) for x in res[m]["solve_ms_device"]],
                       "outer_iters": res[m]["outer_iters"], "rel_residual": res[m]["rel_residual"],
+                      **({"static_start_iters": res[m]["init_iters"]} if args.paper_stop else {}),
                       "tuned": res[m]["tuned"]} for m in modes},
         "errors": errors,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}

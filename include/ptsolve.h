@@ -105,9 +105,8 @@ typedef enum { PT_NU_RATIONAL = 0, PT_NU_EXPCAP = 1 } pt_nu_law;
  * Khat of the fixed-point iteration (eq. (iter1); Thm. thm:iter admits any Khat = S_nuhat with a
  * piecewise-constant coefficient bounding the law's range suitably): Khat is the P1 stiffness
  * with coefficient nu_hat on the region's triangles. nu_hat = 0 takes the problem's nu_max; when
- * every region has nu_hat = 0, Khat = nu_max S (a constant stencil). A per-region Khat needs the
- * Galerkin inner step with the V(0,1) cycle (options.inner = PT_INNER_GALERKIN1, vc_cycle
- * PT_VC_DEFAULT or PT_VC_V01). */
+ * every region has nu_hat = 0, Khat = nu_max S (a constant stencil). Every inner method and
+ * cycle shape takes the per-region Khat (on coarse levels its Galerkin products). */
 typedef struct {
     double sigma;          /* >= 0 */
     double a, b, c, d;     /* PT_NU_RATIONAL: a > 0, a + b > 0; PT_NU_EXPCAP: a, b >= 0, c >= 1, d > 0 */

@@ -175,9 +175,6 @@ static pt_status validate(const pt_problem* pr, const pt_options* o) {
                 !(g.nu_hat >= 0))
                 return fail(PT_ERR_INVALID, "region " + std::to_string(r) +
                                                 ": parameters must be finite, sigma >= 0 and nu_hat >= 0");
-            if (g.nu_hat > 0 && (o->inner != PT_INNER_GALERKIN1 || o->vc_cycle == PT_VC_V11))
-                return fail(PT_ERR_INVALID, "a per-region Khat (nu_hat > 0) needs the Galerkin inner step with the "
-                                            "V(0,1) cycle");
             const bool ok = pr->law == PT_NU_RATIONAL ? (g.a > 0 && g.a + g.b > 0)
                                                       : (g.a >= 0 && g.b >= 0 && g.c >= 1 && g.d > 0);
             if (!ok) return fail(PT_ERR_INVALID, "region " + std::to_string(r) + ": the law's parameters are out of range");

@@ -285,7 +285,7 @@ __device__ __forceinline__ void store_dot_partials(const double (*acc)[3], doubl
 // after the last one), and the mass rows of a uniform column come through the scalar unit,
 // so that the wait for a row's inputs never waits for the loads of the row after it. The
 // coarse residual is stored with streaming access (it is read back only by the next level).
-template <typename T, bool UNI>
+template <typename T, bool UNI, bool VK>
 __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_, void* rout_) {
     using W = SV<T>;
     const W* rin = (const W*)rin_;
@@ -317,6 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
 #pragma unroll
     for (int d = 0; d < 5; ++d) of[d] = (((unsigned)(c - 2 + d) << lgST) + L.s0) * E;
     // rows 2 cj0 - 2 .. 2 cj1 (all inside the grid, 0 <= R <= nF) are fetched
+    // mv[d]: diagonal mass of column c-2+d; mv[5+d]: its Khat diagonal (VK)
     auto fetch_row = [&](int R, W* rv, double* mv) {
         const W* fr = row_of(rin, R, sf, lgR);
         const long mr = (long)R * sf + (c - 2);
@@ -324,18 +325,25 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
         for (int d = 0; d < 5; ++d) {
             rv[d] = *cboff(fr, of[d]);
             mv[d] = uload<UNI>(F.mt, mr + d);
+            if constexpr (VK) mv[5 + d] = uload<UNI>(F.kt, mr + d);
         }
     };
     // x1 on a row: one branch per row (uniform) on whether any of its five diagonal mass
     // entries is nonzero, then five independent Jacobi steps
     auto eval_row = [&](const W* rv, const double* mv, W* xr, W* rr) {
+        T dd[5], idd[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            dd[d] = VK ? (T)mv[5 + d] : dl;
+            idd[d] = VK ? (T)1 / dd[d] : idl;
+        }
         const bool anym = mv[0] != 0.0 || mv[1] != 0.0 || mv[2] != 0.0 || mv[3] != 0.0 || mv[4] != 0.0;
         if (anym) {
 #pragma unroll
-            for (int d = 0; d < 5; ++d) xr[d] = jacobi_t<T, true>(dl, idl, om, mv[d], L.z, rv[d]);
+            for (int d = 0; d < 5; ++d) xr[d] = jacobi_t<T, true>(dd[d], idd[d], om, mv[d], L.z, rv[d]);
         } else {
 #pragma unroll
-            for (int d = 0; d < 5; ++d) xr[d] = jacobi_t<T, false>(dl, idl, om, mv[d], L.z, rv[d]);
+            for (int d = 0; d < 5; ++d) xr[d] = jacobi_t<T, false>(dd[d], idd[d], om, mv[d], L.z, rv[d]);
         }
 #pragma unroll
         for (int d = 1; d <= 3; ++d) rr[d - 1] = rv[d];
@@ -346,7 +354,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
     W X[3][5], Rr[3][3];
     {
         W rv[5];
-        double mv[5];
+        double mv[10];
         fetch_row(Rs - 1, rv, mv);
         eval_row(rv, mv, X[0], Rr[0]);
         fetch_row(Rs, rv, mv);
@@ -359,7 +367,7 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
         constexpr int u = decltype(u_)::value;  // (R - Rs) mod 3
         constexpr int ia = u, ib = (u + 1) % 3, iq = (u + 2) % 3;
         W nr[5];
-        double nm[5];
+        double nm[10];
         // next row's inputs, loaded before this row is computed (unused after the last row)
         fetch_row(R + 2 < nF ? R + 2 : nF, nr, nm);
         issue_fence();
@@ -371,20 +379,23 @@ __global__ void __launch_bounds__(kBlock) k_vc_down(SlotArgs sa, LvArgs F, LvArg
         // s = r - A x1 at (c-1+k, R), k = 0..2; rows: xa = R-1, xb = R, xq = R+1
         const long m0 = (long)R * sf + (c - 1);
         W sv[3];
-        MRow mr3[3];
+        MRow mr3[3], kr3[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) mr3[k] = mrow<UNI>(F, m0 + k);
+        for (int k = 0; k < 3; ++k) {
+            mr3[k] = mrow<UNI>(F, m0 + k);
+            if constexpr (VK) kr3[k] = krow<UNI>(F, m0 + k);
+        }
         // one branch per row on whether any of the three mass rows is nonzero
         if (mr3[0].any() || mr3[1].any() || mr3[2].any()) {
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                sv[k] = sv_sub(rb[k], apply_A_t<T, true>(mr3[k], nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1],
-                                                         xa[k + 1], xq[k + 2], xa[k]));
+                sv[k] = sv_sub(rb[k], apply_A_t<T, true, VK>(mr3[k], nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1],
+                                                             xa[k + 1], xq[k + 2], xa[k], kr3[k]));
         } else {
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                sv[k] = sv_sub(rb[k], apply_A_t<T, false>(mr3[k], nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1],
-                                                          xa[k + 1], xq[k + 2], xa[k]));
+                sv[k] = sv_sub(rb[k], apply_A_t<T, false, VK>(mr3[k], nu, L.z, xb[k + 1], xb[k + 2], xb[k], xq[k + 1],
+                                                              xa[k + 1], xq[k + 2], xa[k], kr3[k]));
         }
         if (R & 1) {
             if (R > Rs) {  // upper row of coarse row (R-1)/2: complete it
@@ -657,16 +668,18 @@ __global__ void __launch_bounds__(kBlock) k_vc_small(SlotArgs sa, SmallArgs sm, 
 // diagonal mass entry and the (one or two) coarse values its P1 interpolation uses.
 template <typename W> struct UpIn {
     W r, c0, c1;
-    double mc;
+    double mc, kc;  // diagonal mass and (per-region Khat) Khat diagonal
     int kind;  // 0: outside the grid rows, 1: coincides with a coarse node, 2: edge midpoint
 };
 
 // x2 at one fine point (the kind is uniform in a column walk); MASS as in jacobi_t; PRE: the
-// pre-smoothed omega D^{-1} r is part of x2 (V(1,1)), otherwise x2 = P x_c (V(0,1))
-template <typename T, bool MASS, bool PRE>
+// pre-smoothed omega D^{-1} r is part of x2 (V(1,1)), otherwise x2 = P x_c (V(0,1)); VK: D's
+// Khat part is the point's own Khat diagonal
+template <typename T, bool MASS, bool PRE, bool VK = false>
 __device__ __forceinline__ SV<T> up_eval_t(const UpIn<SV<T>>& u, T dl, T idl, T om, const GS<T>* z) {
     if (u.kind == 0) return sv_zero<T>();
-    const SV<T> v = PRE ? jacobi_t<T, MASS>(dl, idl, om, u.mc, z, u.r) : sv_zero<T>();
+    const T dlu = VK ? (T)u.kc : dl, idlu = VK ? (T)1 / dlu : idl;
+    const SV<T> v = PRE ? jacobi_t<T, MASS>(dlu, idlu, om, u.mc, z, u.r) : sv_zero<T>();
     if (u.kind == 1) return sv_add(v, u.c0);
     return sv_fma((T)0.5, sv_add(u.c0, u.c1), v);
 }
@@ -695,8 +708,7 @@ __device__ __forceinline__ SV<T> post_smooth_t(const MRow& m, T nu, T dl, T idl,
 template <typename T, bool UNI, bool PRE, bool VK>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) k_vc_up(SlotArgs sa, LvArgs F, LvArgs C, const void* rin_,
                                                   const void* xc_, void* xout_, int dotmode, double* part) {
-    static_assert(!(PRE && VK), "a per-region Khat runs the V(0,1) cycle");
-    using W = SV<T>;
+using W = SV<T>;
     constexpr int V = W::V;
     const W* rin = (const W*)rin_;
     const W* xc = (const W*)xc_;
@@ -731,6 +743,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
             const int bc = clampi(bj, 0, nF);
             u.r = (PRE || d == 1) ? *cboff(row_of(rin, bc, sf, lgR), ofn[d]) : sv_zero<T>();
             u.mc = PRE ? uload<UNI>(F.mt, (long)bc * sf + ai - 1 + d) : 0.0;
+            u.kc = (PRE && VK) ? uload<UNI>(F.kt, (long)bc * sf + ai - 1 + d) : 0.0;
             const int hj = bc >> 1, oj = bc & 1;
             u.c0 = *cboff(row_of(xc, hj, sc, lgR), och[d]);
             u.c1 = *cboff(row_of(xc, hj + oj, sc, lgR), ocq[d]);
@@ -742,13 +755,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         {
             const UpIn<W> q0 = load(0, j0 - 1), q1 = load(1, j0 - 1), q2 = load(0, j0), q3 = load(1, j0),
                           q4 = load(2, j0), q5 = load(1, j0 + 1), q6 = load(2, j0 + 1);
-            xsw = up_eval_t<T, true, PRE>(q0, dl, idl, om, L.z);
-            xs = up_eval_t<T, true, PRE>(q1, dl, idl, om, L.z);
-            xw = up_eval_t<T, true, PRE>(q2, dl, idl, om, L.z);
-            xcn = up_eval_t<T, true, PRE>(q3, dl, idl, om, L.z);
-            xe = up_eval_t<T, true, PRE>(q4, dl, idl, om, L.z);
-            xn = up_eval_t<T, true, PRE>(q5, dl, idl, om, L.z);
-            xne = up_eval_t<T, true, PRE>(q6, dl, idl, om, L.z);
+            xsw = up_eval_t<T, true, PRE, VK>(q0, dl, idl, om, L.z);
+            xs = up_eval_t<T, true, PRE, VK>(q1, dl, idl, om, L.z);
+            xw = up_eval_t<T, true, PRE, VK>(q2, dl, idl, om, L.z);
+            xcn = up_eval_t<T, true, PRE, VK>(q3, dl, idl, om, L.z);
+            xe = up_eval_t<T, true, PRE, VK>(q4, dl, idl, om, L.z);
+            xn = up_eval_t<T, true, PRE, VK>(q5, dl, idl, om, L.z);
+            xne = up_eval_t<T, true, PRE, VK>(q6, dl, idl, om, L.z);
             rc = q3.r;
             rn = q5.r;
         }
@@ -768,6 +781,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
         auto rload = [&](int d, int bj) -> W { return *cboff(row_of(rin, clampi(bj, 0, nF), sf, lgR), ofn[d]); };
         auto mload = [&](int d, int bj) -> double {
             return uload<UNI>(F.mt, (long)clampi(bj, 0, nF) * sf + ai - 1 + d);
+        };
+        auto kload = [&](int d, int bj) -> double {   // Khat diagonal (VK)
+            return uload<UNI>(F.kt, (long)clampi(bj, 0, nF) * sf + ai - 1 + d);
         };
         auto walk = [&](auto aodd_) {
             constexpr bool AODD = decltype(aodd_)::value;
@@ -798,11 +814,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 constexpr int e1 = ROWODD ? e + 1 : e;
                 return sv_scale((T)0.5, sv_add(a0, cw[d1][e1]));
             };
-            auto x2_at = [&](int bj, const W& r, double mc, const W& pxv, auto mass_) -> W {
+            auto x2_at = [&](int bj, const W& r, double mc, double kc, const W& pxv, auto mass_) -> W {
                 constexpr bool MASS = decltype(mass_)::value;
                 if (bj < 0 || bj > nF) return sv_zero<T>();
                 if constexpr (!PRE) return pxv;
-                return sv_add(jacobi_t<T, MASS>(dl, idl, om, mc, L.z, r), pxv);
+                const T dlk = VK ? (T)kc : dl, idlk = VK ? (T)1 / dlk : idl;
+                return sv_add(jacobi_t<T, MASS>(dlk, idlk, om, mc, L.z, r), pxv);
             };
             // one fine row aj < row1 (inside the chunk: computed and stored; past it: loads only)
             auto step = [&](int aj, auto ajodd_) {
@@ -819,6 +836,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                 const W r0 = PRE ? rload(0, aj + 1) : sv_zero<T>(), r2 = PRE ? rload(2, aj + 2) : sv_zero<T>();
                 const double m0 = PRE ? mload(0, aj + 1) : 0.0, m1 = PRE ? mload(1, aj + 2) : 0.0,
                              m2 = PRE ? mload(2, aj + 2) : 0.0;
+                const double k0 = (PRE && VK) ? kload(0, aj + 1) : 0.0, k1 = (PRE && VK) ? kload(1, aj + 2) : 0.0,
+                             k2 = (PRE && VK) ? kload(2, aj + 2) : 0.0;
                 issue_fence();
                 W out = sv_zero<T>();
                 if (here && aj > 0 && aj < nF) {
@@ -857,13 +876,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
                     const W p1 = px(std::integral_constant<int, 1>(), RCE(), ECE());
                     const W p2 = px(std::integral_constant<int, 2>(), RCE(), ECE());
                     if (PRE && (nzbits(m0) | nzbits(m1) | nzbits(m2)) != 0) {  // one branch per row
-                        xw = x2_at(aj + 1, r0, m0, p0, std::true_type());
-                        xn = x2_at(aj + 2, r1, m1, p1, std::true_type());
-                        xne = x2_at(aj + 2, r2, m2, p2, std::true_type());
+                        xw = x2_at(aj + 1, r0, m0, k0, p0, std::true_type());
+                        xn = x2_at(aj + 2, r1, m1, k1, p1, std::true_type());
+                        xne = x2_at(aj + 2, r2, m2, k2, p2, std::true_type());
                     } else {
-                        xw = x2_at(aj + 1, r0, m0, p0, std::false_type());
-                        xn = x2_at(aj + 2, r1, m1, p1, std::false_type());
-                        xne = x2_at(aj + 2, r2, m2, p2, std::false_type());
+                        xw = x2_at(aj + 1, r0, m0, k0, p0, std::false_type());
+                        xn = x2_at(aj + 2, r1, m1, k1, p1, std::false_type());
+                        xne = x2_at(aj + 2, r2, m2, k2, p2, std::false_type());
                     }
                 }
             };
@@ -1363,16 +1382,24 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
                     hipLaunchKernelGGL((k_vc_restrict<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin,
                                        rout);
             }
-        } else if (p.fp32) {
-            if (uni)
-                hipLaunchKernelGGL((k_vc_down<float, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
-            else
-                hipLaunchKernelGGL((k_vc_down<float, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
         } else {
-            if (uni)
-                hipLaunchKernelGGL((k_vc_down<double, true>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+            auto down = [&](auto t_, auto uni_, auto vk_) {
+                using T = decltype(t_);
+                constexpr bool U = decltype(uni_)::value, VK = decltype(vk_)::value;
+                hipLaunchKernelGGL((k_vc_down<T, U, VK>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+            };
+            auto down_u = [&](auto t_, auto uni_) {
+                if (p.vk) down(t_, uni_, std::true_type());
+                else down(t_, uni_, std::false_type());
+            };
+            auto down_t = [&](auto t_) {
+                if (uni) down_u(t_, std::true_type());
+                else down_u(t_, std::false_type());
+            };
+            if (p.fp32)
+                down_t(0.0f);
             else
-                hipLaunchKernelGGL((k_vc_down<double, false>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, rout);
+                down_t(0.0);
         }
         tm_end(p, kid, st);
     }
@@ -1436,13 +1463,16 @@ void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmod
             hipLaunchKernelGGL((k_vc_up<T, U, PRE, VK>), grid, dim3(kBlock), 0, st, sa, Fl, Cl, rin, xc, xout, dm,
                                part);
         };
-        // (a per-region Khat only with V(0,1): the plan validation guarantees !(p.vk && p.vc_pre))
         auto up_u = [&](auto t_, auto uni_) {
             using TT = std::true_type;
             using FF = std::false_type;
-            if (p.vc_pre) up(t_, uni_, TT(), FF());
-            else if (p.vk) up(t_, uni_, FF(), TT());
-            else up(t_, uni_, FF(), FF());
+            if (p.vc_pre) {
+                if (p.vk) up(t_, uni_, TT(), TT());
+                else up(t_, uni_, TT(), FF());
+            } else {
+                if (p.vk) up(t_, uni_, FF(), TT());
+                else up(t_, uni_, FF(), FF());
+            }
         };
         auto up_t = [&](auto t_) {
             if (uni) up_u(t_, std::true_type());

@@ -101,8 +101,10 @@ __device__ __forceinline__ double pweight(int fi, int fj, int ci, int cj) {
 
 // Galerkin coarse mass M_c = P^T M_f P with P the P1 interpolation of the nested
 // SW-NE grids: M_c[I, J] = sum_a P[a, I] sum_b M_f[a, b] P[b, J] over the fine
-// support of I and the 7-point neighbourhood of a.
-__global__ void __launch_bounds__(kBlock) k_galerkin(const double* mf, int sf, double* mc, int sc) {
+// support of I and the 7-point neighbourhood of a (the same for a Khat table). Boundary
+// nodes get the centre value bdiag and no couplings: 0 for the mass; 1 for Khat, whose
+// diagonal divides in the Jacobi step (the vector entries there are zero, so they stay zero).
+__global__ void __launch_bounds__(kBlock) k_galerkin(const double* mf, int sf, double* mc, int sc, double bdiag) {
     size_t nf = (size_t)sf * sf, ncn = (size_t)sc * sc;
     const int oxs[7] = {0, 1, -1, 0, 0, 1, -1};
     const int oys[7] = {0, 0, 0, 1, -1, 1, -1};
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(const double* mf, int sf, d
                 }
             }
         }
-        mc[id] = out[0];
+        mc[id] = interior ? out[0] : bdiag;
         mc[ncn + id] = out[1];
         mc[2 * ncn + id] = out[2];
         mc[3 * ncn + id] = out[3];
@@ -180,7 +182,7 @@ void launch_galerkin_table(const Plan& p, char* ws, int l, bool khat, hipStream_
     const LevelDesc& c = p.lev[l + 1];
     const size_t fo = khat ? f.off_kt : f.off_mt, co = khat ? c.off_kt : c.off_mt;
     hipLaunchKernelGGL(k_galerkin, dim3(grid_for(c.nodes)), dim3(kBlock), 0, st, (const double*)(ws + fo), f.side,
-                       (double*)(ws + co), c.side);
+                       (double*)(ws + co), c.side, khat ? 1.0 : 0.0);
 }
 
 void launch_galerkin(const Plan& p, char* ws, int l, hipStream_t st) { launch_galerkin_table(p, ws, l, false, st); }
@@ -212,7 +214,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_stiffness(StiffArgs a) {
         const double ww = 0.5 * (tri_khat(a, i - 1, j, 0) + tri_khat(a, i - 1, j - 1, 1));
         const double wn = 0.5 * (tri_khat(a, i, j, 1) + tri_khat(a, i - 1, j, 0));
         const double ws = 0.5 * (tri_khat(a, i, j - 1, 1) + tri_khat(a, i - 1, j - 1, 0));
-        a.kt[id] = we + ww + wn + ws;
+        const bool interior = i > 0 && j > 0 && i < a.n && j < a.n;
+        a.kt[id] = interior ? we + ww + wn + ws : 1.0;   // (boundary: as in k_galerkin)
         a.kt[nodes + id] = -we;
         a.kt[2 * nodes + id] = -wn;
         a.kt[3 * nodes + id] = 0.0;

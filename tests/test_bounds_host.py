@@ -85,11 +85,14 @@ def test_region_khat_plans_are_in_bounds(P, precision, n, grid):
     P.library().pt_plan_destroy(h)
 
 
-def test_region_khat_needs_the_galerkin_v01_step(P):
+def test_region_khat_validation_and_inner_methods(P):
     p = W.transformer(16, 8, khat_factor=1.2)
     for kw in (dict(inner="cocg"), dict(cycle="v11")):
         st, h, _ = _region_plan_status(P, p, **kw)
-        assert st == -1 and b"nu_hat" in P.library().pt_last_error()
+        assert st == 0, P.library().pt_last_error()
+        msg = C.create_string_buffer(512)
+        assert P.library().pt_plan_check_bounds(h, msg, 512) == 0, msg.value.decode()
+        P.library().pt_plan_destroy(h)
     bad = dataclasses.replace(p, regions=(dataclasses.replace(p.regions[0], nu_hat=-1.0),) + p.regions[1:])
     st, h, _ = _region_plan_status(P, bad)
     assert st == -1 and b"nu_hat" in P.library().pt_last_error()

@@ -171,20 +171,34 @@ def test_region_khat_shifted_operator_matches_oracle(gpu, P, precision):
 # per-level sweeps; grid 66: row chunks that start on odd rows
 @pytest.mark.parametrize("n,grid", [(16, 0), (64, 0), (64, 66)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_region_khat_vcycle_matches_its_definition(gpu, P, n, grid, precision):
+@pytest.mark.parametrize("cycle", ["v01", "v11"])
+def test_region_khat_vcycle_matches_its_definition(gpu, P, n, grid, precision, cycle):
     N = 8
-    say(f"region khat vcycle n={n} grid={grid} {precision}")
+    say(f"region khat vcycle n={n} grid={grid} {precision} {cycle}")
     p = W.transformer(n, N, khat_factor=1.2)
     d = fem.discretise(p)
     rng = np.random.default_rng(n + 7)
     R = rng.standard_normal((d.mesh.nodes, N // 2)) + 1j * rng.standard_normal((d.mesh.nodes, N // 2))
     R[~d.mesh.free] = 0
     cd = np.complex128 if precision == "fp64" else np.complex64
-    plan = plan_for(P, p, precision=precision, grid_slot=grid)
+    plan = plan_for(P, p, precision=precision, grid_slot=grid, cycle=cycle)
     B = plan.precond_apply(dev(R.astype(cd))).cpu().numpy().astype(np.complex128)
-    ref = vcycle_reference(d, 0.8, R.astype(cd).astype(np.complex128), pre=0)
+    ref = vcycle_reference(d, 0.8, R.astype(cd).astype(np.complex128), pre=1 if cycle == "v11" else 0)
     assert rel_err(B, ref) <= (1e-12 if precision == "fp64" else 5e-5)
     plan.close()
+
+
+def test_region_khat_cocg_solve_matches_oracle(gpu, P):
+    # COCG on the symmetric V(1,1) cycle with the per-region Khat: close to the exact inner solve,
+    # so the outer iteration takes about the oracle's step count
+    n, N = 32, 16
+    say("transformer region khat cocg")
+    p = W.transformer(n, N, khat_factor=1.2)
+    d = fem.discretise(p)
+    ref = pp.fixed_point(d, tol=1e-13, max_iter=500)
+    U, st = plan_for(P, p, tol=1e-12, max_outer=500, inner="cocg", inner_iters=16, inner_rtol=1e-6).solve()
+    assert st.rel_residual <= 1e-12 and st.outer_iters <= ref.iters + 5
+    assert rel_err(pp.to_free(d, U.cpu().numpy()), ref.U) <= 1e-9
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
