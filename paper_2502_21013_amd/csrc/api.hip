@@ -285,7 +285,7 @@ static void layout(Plan& p) {
     }
     p.off_flags = take(B * 2 * (size_t)p.n * p.n);
     p.off_b = take(B * p.nodes * sizeof(double));
-    p.off_rec = take(B * p.nodes * kRecDoubles * sizeof(double));
+    p.off_rec = take(B * p.nodes * (p.law == PT_NU_EXPCAP ? kRecDoublesExp : kRecDoubles) * sizeof(double));
     p.off_tw64 = take((size_t)p.N * 2 * sizeof(double));
     p.off_tw32 = take((size_t)p.N * 2 * sizeof(float));
     p.off_zs = take(S * 3 * sizeof(double));

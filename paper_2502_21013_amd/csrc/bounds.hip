@@ -61,7 +61,7 @@ std::vector<Buf> buffers(const Plan& p) {
     }
     v.push_back({"flags", p.off_flags, B * 2 * (size_t)p.n * p.n});
     v.push_back({"load", p.off_b, dbl(B * p.nodes)});
-    v.push_back({"records", p.off_rec, dbl(B * p.nodes * kRecDoubles)});
+    v.push_back({"records", p.off_rec, dbl(B * p.nodes * (p.law == PT_NU_EXPCAP ? kRecDoublesExp : kRecDoubles))});
     v.push_back({"twiddles64", p.off_tw64, dbl((size_t)p.N * 2)});
     v.push_back({"twiddles32", p.off_tw32, (size_t)p.N * 2 * sizeof(float)});
     v.push_back({"shifts", p.off_zs, dbl(S * 3)});
@@ -190,8 +190,6 @@ pt_status check_bounds(const Plan& p, std::string& msg) {
     check_team(c, "time DFT / inverse", p.g_team, (size_t)p.side * p.B, p.g_team.slot_chunk,
                2L * p.g_team.slot_chunk, p.S / 2, 0);
     if ((size_t)p.g_team.per_step * 2 * p.S * p.elem > kMaxDynLds) c.fail("time DFT: LDS request above 64 KiB");
-    // generic residual kernel (exp-capped law): at most 4096 pairs of partials
-    if (p.law == PT_NU_EXPCAP && part_doubles < 2 * 4096) c.fail("generic residual: partial buffer too small");
     // COCG vector kernels and their reduction
     if (p.has_cocg_vectors) {
         const int SC = p.ST < kBlock ? p.ST : kBlock;

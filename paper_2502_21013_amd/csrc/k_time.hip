@@ -247,26 +247,35 @@ struct Win {
 
 // Everything the residual sweep needs at node (i, j) besides u, in one record read through the
 // scalar unit: the seven mass-stencil coefficients (centre, E, W, N, S, NE, SW), the load
-// amplitude b, and for the triangles T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i-1,j) the pair (A, B)
-// of the rational reluctivity law nu = theta (a + b s^2/(1+s^2)) = A - B / (1 + s^2) of the
-// triangle's region: A = theta (a + b), B = theta b (rectangle problems: a = nu_a, b = nu_b in
-// nu_rect, a = nu_out, b = 0 elsewhere). The exp-capped law takes the generic residual kernel.
-struct NodeRec {
+// amplitude b, and for the triangles T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i-1,j) the parameters
+// of the reluctivity law of the triangle's region, times its theta:
+//  - rational law nu = theta (a + b s^2/(1+s^2)) = A - B / (1 + s^2): (A, B) = theta (a + b, b)
+//    (rectangle problems: a = nu_a, b = nu_b in nu_rect, a = nu_out, b = 0 elsewhere);
+//  - exp-capped law nu = theta (a min(exp(b s^2), c) + d) = A exp(b min(s^2, z)) + D, z = ln(c)/b:
+//    (A, b, z, D) = (theta a, b, z, theta d), and (0, 0, inf, theta (a + d)) where the law is
+//    constant (a = 0 or b = 0).
+// In both, the law is nonlinear exactly where the second (rational) / first (exp-capped) entry
+// is nonzero.
+template <int LAW> struct NodeRecT {
+    static constexpr int P = LAW == PT_NU_EXPCAP ? 4 : 2;   // law parameters per triangle
     double m[7];
     double bl;
-    double law[4][2];
+    double law[4][P];
 };
-static_assert(sizeof(NodeRec) == kRecDoubles * sizeof(double), "record size");
+template <int LAW> constexpr int rec_doubles() { return 8 + 4 * NodeRecT<LAW>::P; }
+static_assert(sizeof(NodeRecT<PT_NU_RATIONAL>) == kRecDoubles * sizeof(double), "record size");
+static_assert(sizeof(NodeRecT<PT_NU_EXPCAP>) == kRecDoublesExp * sizeof(double), "record size");
+using NodeRec = NodeRecT<PT_NU_RATIONAL>;
 
 // Record idx of a table (through the scalar unit when UNI: adjacent words, merged into wide
 // scalar loads).
-template <bool UNI>
-__device__ __forceinline__ NodeRec load_rec(const NodeRec* base, size_t idx) {
+template <bool UNI, int LAW>
+__device__ __forceinline__ NodeRecT<LAW> load_rec(const NodeRecT<LAW>* base, size_t idx) {
     const double* p = reinterpret_cast<const double*>(base + idx);
-    NodeRec r;
+    NodeRecT<LAW> r;
     double* o = &r.m[0];
 #pragma unroll
-    for (int k = 0; k < kRecDoubles; ++k) o[k] = uload<UNI>(p, (size_t)k);
+    for (int k = 0; k < rec_doubles<LAW>(); ++k) o[k] = uload<UNI>(p, (size_t)k);
     return r;
 }
 
@@ -277,17 +286,19 @@ struct RecArgs {
     const double* bload;   // [B][nodes]
     const uint8_t* flags;  // [B][2 n^2]
     const double* theta;   // [2 n^2] or null (one instance)
-    const double4* regp;   // [B][kMaxRegions] law parameters of each region (rational law)
-    NodeRec* rec;          // [B][nodes]
+    const double4* regp;   // [B][kMaxRegions] law parameters of each region (law_nu)
+    void* rec;             // [B][nodes] NodeRecT<LAW>
 };
 
+template <int LAW>
 __global__ void __launch_bounds__(kBlock) k_row_records(RecArgs a) {
     const size_t total = (size_t)a.B * a.nodes, nt = 2 * (size_t)a.n * a.n;
+    NodeRecT<LAW>* rec = (NodeRecT<LAW>*)a.rec;
     for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
         const int b = (int)(id / a.nodes);
         const size_t node = id - (size_t)b * a.nodes;
         const int i = (int)(node % a.side), j = (int)(node / a.side);
-        NodeRec r;
+        NodeRecT<LAW> r;
         const bool interior = i > 0 && j > 0 && i < a.n && j < a.n;
         const size_t nd = a.nodes, sd = a.side;
         if (interior) {
@@ -304,18 +315,25 @@ __global__ void __launch_bounds__(kBlock) k_row_records(RecArgs a) {
         r.bl = a.bload[id];
         for (int t = 0; t < 4; ++t) {
             const int ci = i - (t >> 1), typ = t & 1;   // cells (i, j), (i, j), (i-1, j), (i-1, j)
-            double A = 0.0, Bv = 0.0;
+            double th = 0.0;
+            double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
             if (ci >= 0 && ci < a.n && j < a.n) {
                 const size_t tri = 2 * ((size_t)j * a.n + ci) + typ;
-                const double th = a.theta ? a.theta[tri] : 1.0;
-                const double4 q = a.regp[(size_t)b * kMaxRegions + a.flags[(size_t)b * nt + tri]];
-                A = th * (q.x + q.y);   // nu = q.x + q.y s^2/(1+s^2) = A - B / (1 + s^2)
-                Bv = th * q.y;
+                th = a.theta ? a.theta[tri] : 1.0;
+                q = a.regp[(size_t)b * kMaxRegions + a.flags[(size_t)b * nt + tri]];
             }
-            r.law[t][0] = A;
-            r.law[t][1] = Bv;
+            if constexpr (LAW == PT_NU_RATIONAL) {
+                r.law[t][0] = th * (q.x + q.y);   // nu = q.x + q.y s^2/(1+s^2) = A - B / (1 + s^2)
+                r.law[t][1] = th * q.y;
+            } else {
+                const bool nl = q.x != 0.0 && q.y != 0.0;
+                r.law[t][0] = nl ? th * q.x : 0.0;
+                r.law[t][1] = nl ? q.y : 0.0;
+                r.law[t][2] = nl ? q.z : 1e300;
+                r.law[t][3] = nl ? th * q.w : th * (q.x + q.w);
+            }
         }
-        a.rec[id] = r;
+        rec[id] = r;
     }
 }
 
@@ -330,47 +348,59 @@ void launch_row_records(const Plan& p, char* ws, hipStream_t st) {
     a.flags = (const uint8_t*)(ws + p.off_flags);
     a.theta = p.prob.d_theta;
     a.regp = (const double4*)(ws + p.off_regp);
-    a.rec = (NodeRec*)(ws + p.off_rec);
+    a.rec = ws + p.off_rec;
     size_t g = ((size_t)p.B * p.nodes + kBlock - 1) / kBlock;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_row_records, dim3((unsigned)g), dim3(kBlock), 0, st, a);
+    if (p.law == PT_NU_EXPCAP)
+        hipLaunchKernelGGL(k_row_records<PT_NU_EXPCAP>, dim3((unsigned)g), dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_row_records<PT_NU_RATIONAL>, dim3((unsigned)g), dim3(kBlock), 0, st, a);
 }
 
-// Reluctivity from a record pair (A, B): nu = A - B / (1 + s^2), s^2 = n^2 |G|^2. NL: the
-// law is evaluated without a branch (exactly A where B = 0, since 1 / (1 + s^2) is finite), so
-// that the laws of all triangles of a row form independent chains; otherwise every B is 0.
-template <bool NL>
-__device__ __forceinline__ double nu_law(double gx, double gy, double n2, const double law[2]) {
-    if constexpr (!NL) return law[0];
-    return law[0] - law[1] * rcp_ge1_1(1.0 + n2 * (gx * gx + gy * gy));
+// Reluctivity of a triangle from its record entries, s^2 = n^2 |G|^2. NL: the law is evaluated
+// without a branch (rational: exactly A where B = 0, since 1 / (1 + s^2) is finite; exp-capped:
+// exactly D where A = 0), so that the laws of all triangles of a row form independent chains;
+// otherwise every triangle of the row has a constant law (A, resp. D).
+template <bool NL, int LAW = PT_NU_RATIONAL>
+__device__ __forceinline__ double nu_law(double gx, double gy, double n2, const double* law) {
+    if constexpr (LAW == PT_NU_RATIONAL) {
+        if constexpr (!NL) return law[0];
+        return law[0] - law[1] * rcp_ge1_1(1.0 + n2 * (gx * gx + gy * gy));
+    } else {
+        if constexpr (!NL) return law[3];
+        return law[0] * exp(law[1] * fmin(n2 * (gx * gx + gy * gy), law[2])) + law[3];
+    }
 }
 
 // lower_three / upper_four with the reluctivity laws of a record: the record of node
 // (i, j-1) holds T_b(i,j-1), T_a(i-1,j-1), T_b(i-1,j-1) as its laws 1, 2, 3; the record of
 // node (i, j) holds T_a(i,j), T_b(i,j), T_a(i-1,j), T_b(i-1,j) as laws 0..3.
-__device__ __forceinline__ double lower_three_rec(const Win& v, double n2, const NodeRec& rs) {
+template <int LAW>
+__device__ __forceinline__ double lower_three_rec(const Win& v, double n2, const NodeRecT<LAW>& rs) {
     double g4x = v.e - v.c, g4y = v.c - v.s;
     double g5x = v.s - v.sw, g5y = v.c - v.s;
     double g6x = v.c - v.w, g6y = v.w - v.sw;
-    return 0.5 * (nu_law<true>(g4x, g4y, n2, rs.law[1]) * (g4y - g4x) + nu_law<true>(g5x, g5y, n2, rs.law[2]) * g5y +
-                  nu_law<true>(g6x, g6y, n2, rs.law[3]) * g6x);
+    return 0.5 * (nu_law<true, LAW>(g4x, g4y, n2, rs.law[1]) * (g4y - g4x) +
+                  nu_law<true, LAW>(g5x, g5y, n2, rs.law[2]) * g5y + nu_law<true, LAW>(g6x, g6y, n2, rs.law[3]) * g6x);
 }
 
 // whether any of the four laws of a record is nonlinear (uniform per row in a column walk)
-__device__ __forceinline__ bool rec_nonlinear(const NodeRec& r) {
-    return (nzbits(r.law[0][1]) | nzbits(r.law[1][1]) | nzbits(r.law[2][1]) | nzbits(r.law[3][1])) != 0;
+template <int LAW>
+__device__ __forceinline__ bool rec_nonlinear(const NodeRecT<LAW>& r) {
+    constexpr int q = LAW == PT_NU_RATIONAL ? 1 : 0;
+    return (nzbits(r.law[0][q]) | nzbits(r.law[1][q]) | nzbits(r.law[2][q]) | nzbits(r.law[3][q])) != 0;
 }
 
-template <bool NL>
-__device__ __forceinline__ double upper_four_rec(const Win& v, double n2, const NodeRec& rc, double& carry_up) {
+template <bool NL, int LAW>
+__device__ __forceinline__ double upper_four_rec(const Win& v, double n2, const NodeRecT<LAW>& rc, double& carry_up) {
     double g1x = v.e - v.c, g1y = v.ne - v.e;    // T_a(i,j)
     double g2x = v.ne - v.n, g2y = v.n - v.c;    // T_b(i,j)
     double g3x = v.c - v.w, g3y = v.n - v.c;     // T_a(i-1,j)
     double g4x = v.n - v.nw, g4y = v.nw - v.w;   // T_b(i-1,j)
-    double nu1 = nu_law<NL>(g1x, g1y, n2, rc.law[0]);
-    double nu2 = nu_law<NL>(g2x, g2y, n2, rc.law[1]);
-    double nu3 = nu_law<NL>(g3x, g3y, n2, rc.law[2]);
-    double nu4 = nu_law<NL>(g4x, g4y, n2, rc.law[3]);
+    double nu1 = nu_law<NL, LAW>(g1x, g1y, n2, rc.law[0]);
+    double nu2 = nu_law<NL, LAW>(g2x, g2y, n2, rc.law[1]);
+    double nu3 = nu_law<NL, LAW>(g3x, g3y, n2, rc.law[2]);
+    double nu4 = nu_law<NL, LAW>(g4x, g4y, n2, rc.law[3]);
     carry_up = 0.5 * (nu2 * (g2y - g2x) + nu3 * g3y + nu4 * g4x);
     return 0.5 * (nu1 * (-g1x) + nu2 * (-g2y) + nu3 * (g3x - g3y)) + v.carry;
 }
@@ -394,7 +424,7 @@ __device__ __forceinline__ double upper_four_rec(const Win& v, double n2, const 
 constexpr int kRowBatch = 4;
 enum ResKind { RK_WAVE = 0, RK_LOAD = 1, RK_SIGNAL = 2 };
 
-template <typename T, bool UNI, int KP, int RK, bool FUSE>
+template <typename T, bool UNI, int KP, int RK, bool FUSE, int LAW = PT_NU_RATIONAL>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FUSE && UNI ? 4 : 1)))
 k_residual(FwdArgs a, void* rt_) {
     constexpr bool SIG = RK == RK_SIGNAL;
@@ -473,9 +503,10 @@ k_residual(FwdArgs a, void* rt_) {
         return Win{g(Wv[k][s0]), g(Cv[k][s0]), g(Wv[k][s1]), g(Cv[k][s1]), g(Ev[k][s1]),
                    g(Wv[k][s2]), g(Cv[k][s2]), g(Ev[k][s2]), cy};
     };
-    const NodeRec* recb = (const NodeRec*)a.rec + (colvalid ? (size_t)bi * a.nodes : 0);
+    using Rec = NodeRecT<LAW>;
+    const Rec* recb = (const Rec*)a.rec + (colvalid ? (size_t)bi * a.nodes : 0);
     if (!SIG && colint && jin < sr.row1 && jin < n) {
-        const NodeRec rs = load_rec<UNI>(recb, (size_t)(jin - 1) * side + i);
+        const Rec rs = load_rec<UNI, LAW>(recb, (size_t)(jin - 1) * side + i);
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             Wv[k][0] = ldd(0, jin - 1, k);
@@ -551,7 +582,7 @@ k_residual(FwdArgs a, void* rt_) {
                 }
                 if (interior) {
                     // mass row, load and reluctivity laws of the row: one record
-                    const NodeRec rc = load_rec<UNI>(recb, (size_t)node);
+                    const Rec rc = load_rec<UNI, LAW>(recb, (size_t)node);
                     issue_fence();   // both halves of the record requested before either is used
                     const double mc = rc.m[0], mE = rc.m[1], mW = rc.m[2], mN = rc.m[3], mS = rc.m[4],
                                  mNE = rc.m[5], mSW = rc.m[6];
@@ -851,65 +882,6 @@ __global__ void __launch_bounds__(kBlock) k_apply_K(FwdArgs a, int nslices, doub
     }
 }
 
-// Residual R^n = f^n - M (u^n - u^{n-1}) / tau - K(u^n) (eq. (disc1), u^0 = u^N) of a single
-// instance, one thread per node and time level on the node-major layout, for any law (the
-// exp-capped law of Sec. 4 takes this path: the record sweep holds the rational law only).
-// Writes R in double (rout, if non-null) and in the solver precision (rt, if non-null), and the
-// FP64 norm partials of R and F over interior nodes, two per workgroup.
-template <typename T, int LAW, bool LOAD>
-__global__ void __launch_bounds__(kBlock) k_residual_gen(FwdArgs a, T* rt) {
-    const size_t total = a.nodes * (size_t)a.N;
-    const size_t sd = a.side;
-    const size_t NN = a.N;
-    double rr = 0.0, ff = 0.0;
-    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
-        const size_t node = id / NN;
-        const int t = (int)(id - node * NN);
-        const int i = (int)(node % sd), j = (int)(node / sd);
-        double R = 0.0;
-        if (i > 0 && j > 0 && i < a.n && j < a.n) {
-            const double* u = a.U + id;
-            const long s = (long)sd * (long)NN, e = (long)NN;
-            const double uc = u[0], ue = u[e], uw = u[-e], un = u[s], us = u[-s], une = u[s + e], usw = u[-s - e];
-            const Six g = six_triangles(a.n, i, j, uc, ue, uw, un, us, une, usw);
-            const double K = k_six<LAW>(g, a, a.regp);
-            const double f = LOAD ? a.F[id] : a.bload[node] * a.wave[t];
-            // mass stencil (centre, E, W, N, S, NE, SW) applied to u^n - u^{n-1}
-            const long pt = t == 0 ? (long)NN - 1 : -1;   // offset of u^{n-1} (cyclic: u^0 = u^N)
-            const size_t nd = a.nodes;
-            const double mc = a.mt[node], mE = a.mt[nd + node], mW = a.mt[nd + node - 1], mN = a.mt[2 * nd + node],
-                         mS = a.mt[2 * nd + node - sd], mNE = a.mt[3 * nd + node], mSW = a.mt[3 * nd + node - sd - 1];
-            double Mu = 0.0;
-            if (mc != 0.0 || mE != 0.0 || mW != 0.0 || mN != 0.0 || mS != 0.0 || mNE != 0.0 || mSW != 0.0) {
-                const double* v = u + pt;
-                Mu = mc * (uc - v[0]) + mE * (ue - v[e]) + mW * (uw - v[-e]) + mN * (un - v[s]) + mS * (us - v[-s]) +
-                     mNE * (une - v[s + e]) + mSW * (usw - v[-s - e]);
-            }
-            R = f - Mu * a.inv_tau - K;
-            rr += R * R;
-            ff += f * f;
-        }
-        if (a.rout) a.rout[id] = R;
-        if (rt) rt[id] = (T)R;
-    }
-    __shared__ double red[2][kBlock];
-    red[0][threadIdx.x] = rr;
-    red[1][threadIdx.x] = ff;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + w];
-            red[1][threadIdx.x] += red[1][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        a.part[2 * (size_t)blockIdx.x] = red[0][0];
-        a.part[2 * (size_t)blockIdx.x + 1] = red[1][0];
-    }
-}
-
-constexpr int kGenBlocks = 4096;  // workgroups of the generic residual kernel, at most
 
 int launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* out, double* rout, double* part,
                    hipStream_t st) {
@@ -958,71 +930,65 @@ int launch_forward(const Plan& p, char* ws, int mode, const double* Uw, void* ou
     void* rt = out ? (void*)(ws + p.off_P) : nullptr;  // R in solver precision, node-major
     tm_begin(p, KID_RESIDUAL, st);
     const int rk = mode == TM_SIGNAL ? RK_SIGNAL : (a.F ? RK_LOAD : RK_WAVE);
-    if (p.law == PT_NU_EXPCAP && rk != RK_SIGNAL) {
-        // the exp-capped law: generic residual kernel (single instance), then the DFT
-        size_t g = (p.nodes * (size_t)p.N + kBlock - 1) / kBlock;
-        if (g > (size_t)kGenBlocks) g = kGenBlocks;
-        const bool ld = rk == RK_LOAD;
-#define PT_GEN(TT) \
-    do { \
-        if (ld) hipLaunchKernelGGL((k_residual_gen<TT, PT_NU_EXPCAP, true>), dim3(g), dim3(kBlock), 0, st, a, (TT*)rt); \
-        else hipLaunchKernelGGL((k_residual_gen<TT, PT_NU_EXPCAP, false>), dim3(g), dim3(kBlock), 0, st, a, (TT*)rt); \
-    } while (0)
-        if (p.fp32) PT_GEN(float);
-        else PT_GEN(double);
-#undef PT_GEN
-        tm_end(p, KID_RESIDUAL, st);
-        if (out) launch_rfft(p, ws, rt, out, 0, st);
-        return (int)g;
-    }
+    // the law of the records (the field-copy mode reads none)
+    const bool expcap = p.law == PT_NU_EXPCAP && rk != RK_SIGNAL;
     // residual spectrum in one pass: transform fused into the sweep (see k_residual); its
     // S/4 lanes per node must lie in one wavefront, so S <= 256
     if (out && !rout && rk != RK_SIGNAL && KP == 1 && p.S >= 4 && p.S <= 256) {
         a.out = out;
         shm += (size_t)p.N * p.elem;  // twiddle table
-#define PT_RESF(TT, U, G) hipLaunchKernelGGL((k_residual<TT, U, 1, G, true>), dim3(gf.blocks), blk, shm, st, a, nullptr)
-        if (p.fp32) {
-            if (uni) {
-                if (rk == RK_LOAD) PT_RESF(float, true, RK_LOAD);
-                else PT_RESF(float, true, RK_WAVE);
-            } else {
-                if (rk == RK_LOAD) PT_RESF(float, false, RK_LOAD);
-                else PT_RESF(float, false, RK_WAVE);
-            }
-        } else {
-            if (uni) {
-                if (rk == RK_LOAD) PT_RESF(double, true, RK_LOAD);
-                else PT_RESF(double, true, RK_WAVE);
-            } else {
-                if (rk == RK_LOAD) PT_RESF(double, false, RK_LOAD);
-                else PT_RESF(double, false, RK_WAVE);
-            }
-        }
-#undef PT_RESF
+        auto fused = [&](auto t_, auto uni_, auto rk_, auto law_) {
+            using TT = decltype(t_);
+            constexpr bool U = decltype(uni_)::value;
+            constexpr int G = decltype(rk_)::value, LW = decltype(law_)::value;
+            hipLaunchKernelGGL((k_residual<TT, U, 1, G, true, LW>), dim3(gf.blocks), blk, shm, st, a, nullptr);
+        };
+        auto fused_law = [&](auto t_, auto uni_, auto rk_) {
+            if (expcap) fused(t_, uni_, rk_, std::integral_constant<int, PT_NU_EXPCAP>());
+            else fused(t_, uni_, rk_, std::integral_constant<int, PT_NU_RATIONAL>());
+        };
+        auto fused_rk = [&](auto t_, auto uni_) {
+            if (rk == RK_LOAD) fused_law(t_, uni_, std::integral_constant<int, RK_LOAD>());
+            else fused_law(t_, uni_, std::integral_constant<int, RK_WAVE>());
+        };
+        auto fused_t = [&](auto t_) {
+            if (uni) fused_rk(t_, std::true_type());
+            else fused_rk(t_, std::false_type());
+        };
+        if (p.fp32)
+            fused_t(0.0f);
+        else
+            fused_t(0.0);
         tm_end(p, KID_RESIDUAL, st);
         return 0;
     }
-#define PT_RES(TT, U, K, G) hipLaunchKernelGGL((k_residual<TT, U, K, G, false>), dim3(gf.blocks), blk, shm, st, a, rt)
-#define PT_RES_MODE(TT, U, K)               \
-    do {                                    \
-        if (rk == RK_SIGNAL)                \
-            PT_RES(TT, U, K, RK_SIGNAL);    \
-        else if (rk == RK_LOAD)             \
-            PT_RES(TT, U, K, RK_LOAD);      \
-        else                                \
-            PT_RES(TT, U, K, RK_WAVE);      \
-    } while (0)
-    if (p.fp32) {
-        if (KP == 2) PT_RES_MODE(float, true, 2);
-        else if (uni) PT_RES_MODE(float, true, 1);
-        else PT_RES_MODE(float, false, 1);
-    } else {
-        if (KP == 2) PT_RES_MODE(double, true, 2);
-        else if (uni) PT_RES_MODE(double, true, 1);
-        else PT_RES_MODE(double, false, 1);
-    }
-#undef PT_RES_MODE
-#undef PT_RES
+    auto sweep = [&](auto t_, auto uni_, auto kp_, auto rk_, auto law_) {
+        using TT = decltype(t_);
+        constexpr bool U = decltype(uni_)::value;
+        constexpr int K = decltype(kp_)::value, G = decltype(rk_)::value, LW = decltype(law_)::value;
+        hipLaunchKernelGGL((k_residual<TT, U, K, G, false, LW>), dim3(gf.blocks), blk, shm, st, a, rt);
+    };
+    auto sweep_rk = [&](auto t_, auto uni_, auto kp_) {
+        using RAT = std::integral_constant<int, PT_NU_RATIONAL>;
+        using EXP = std::integral_constant<int, PT_NU_EXPCAP>;
+        if (rk == RK_SIGNAL) sweep(t_, uni_, kp_, std::integral_constant<int, RK_SIGNAL>(), RAT());
+        else if (rk == RK_LOAD) {
+            if (expcap) sweep(t_, uni_, kp_, std::integral_constant<int, RK_LOAD>(), EXP());
+            else sweep(t_, uni_, kp_, std::integral_constant<int, RK_LOAD>(), RAT());
+        } else {
+            if (expcap) sweep(t_, uni_, kp_, std::integral_constant<int, RK_WAVE>(), EXP());
+            else sweep(t_, uni_, kp_, std::integral_constant<int, RK_WAVE>(), RAT());
+        }
+    };
+    auto sweep_t = [&](auto t_) {
+        if (KP == 2) sweep_rk(t_, std::true_type(), std::integral_constant<int, 2>());
+        else if (uni) sweep_rk(t_, std::true_type(), std::integral_constant<int, 1>());
+        else sweep_rk(t_, std::false_type(), std::integral_constant<int, 1>());
+    };
+    if (p.fp32)
+        sweep_t(0.0f);
+    else
+        sweep_t(0.0);
     tm_end(p, KID_RESIDUAL, st);
     if (out) launch_rfft(p, ws, rt, out, 0, st);
     return 0;

@@ -28,6 +28,7 @@ constexpr int kReduceBatch = 8;      // partials whose loads a reduction thread 
 constexpr int kAdjBlocks = 8192;     // workgroups of the grid-stride adjoint kernels
 constexpr int kCocgRows = 4096;      // workgroups along the nodes of the COCG vector kernels, at most
 constexpr int kRecDoubles = 16;      // residual-sweep record per node: mass row, load, reluctivity laws
+constexpr int kRecDoublesExp = 24;   // the same with the exp-capped law (four parameters per triangle)
 constexpr int kMaxRegions = 16;      // material regions of a problem (the triangles' region ids)
 
 // Per-slot scalar in "generic" form: for slot s >= 1 a complex number (x + i y);
@@ -111,7 +112,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t off_U, off_F, off_P, off_cx, off_cr, off_cq, off_cp;
     size_t off_flags, off_b, off_tw64, off_tw32, off_zs, off_wave;
-    size_t off_rec;     // per-instance, per-node records of the residual sweep (kRecDoubles doubles)
+    size_t off_rec;     // per-instance, per-node records of the residual sweep (rec_doubles(law) doubles)
     size_t off_npart, off_caux;  // COCG plans: r^H r partials, per-slot scalars and counter
     int inner_done;              // inner steps of the last inner solve
     int inner_max;               // most inner steps of one outer step in the current call
