@@ -202,6 +202,20 @@ __device__ __forceinline__ void rfft_split(const T2* z, int S, int q, const T2 p
     }
 }
 
+// Packed real DFT split for a mirror pair of slots: from z_k and z_{S-k} of the half-length
+// transform (index mod S) and w = exp(-2 pi i k / N), the values X_k and X_{S-k} of the real
+// series' spectrum. With E = z_k + conj z_{S-k} and O = -i (z_k - conj z_{S-k}), X_k = (E + w O)/2;
+// since E and O of slot S-k are the conjugates of those of slot k and w^(S-k) = -conj w^k,
+// X_{S-k} = conj(E - w O)/2. At k = 0 the two are X_0 and X_{N/2}, both real.
+template <typename T, typename T2>
+__device__ __forceinline__ void rfft_mirror(T2 zk, T2 zm, T2 w, T2& Xk, T2& Xm) {
+    const T2 zc = conj2(zm);
+    const T2 E = add2(zk, zc);
+    const T2 t = cmul(w, mul_mi(sub2(zk, zc)));
+    Xk = scale2((T)0.5, add2(E, t));
+    Xm = conj2(scale2((T)0.5, sub2(E, t)));
+}
+
 // Two consecutive slot values (one 16-byte access in FP32).
 template <typename T2> struct alignas(16) Pair {
     T2 a, b;
@@ -664,35 +678,34 @@ k_residual(FwdArgs a, void* rt_) {
             }
             __syncthreads();
         } else {
-            // Node fid = (team fc, row fq) of the batch on the S/4 lanes fl of one wavefront
-            // (S/4 <= 64 divides the wavefront): each lane forms the residual, mass difference
-            // included, at the four time pairs m = fl + c S/4 that the first radix-4 stage takes
-            // from it, so the series goes straight from the row buffers into the butterflies.
-            // The node's buffers are touched by its wavefront only, which needs no workgroup
-            // barrier between the stages. The lanes of node (fc, fq) are lanes of team fc
-            // (TS = S), so the team's mass bits are in their registers. (The lane index is made opaque so that the transform's
-            // addresses and twiddles are formed per batch instead of being kept live across the
-            // row walk.)
+            // Node (team, row fq) of the batch on the S/4 lanes fl of one wavefront (S/4 <= 64
+            // divides the wavefront): each lane forms the residual, mass difference included,
+            // at the four time pairs m = fl + c S/4 that the first radix-4 stage takes from it,
+            // so the series goes straight from the row buffers into the butterflies. The node's
+            // buffers are touched by its wavefront only, which needs no workgroup barrier
+            // between the stages. With TS = S the RB S/4 lanes of a team's RB nodes are the
+            // team's own lanes (lane tid: node (tid / S, (tid / (S/4)) % RB)), so the column,
+            // instance and mass bits of the node are those of the team. (The lane index is made
+            // opaque so that the transform's addresses and twiddles are formed per batch
+            // instead of being kept live across the row walk.)
             int tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
-            const int F4 = S >> 2, H = S >> 1;
-            const int fid = tid >> (a.lgS - 2), fl = tid & (F4 - 1);
-            const int fc = fid / RB, fq = fid - fc * RB;
-            const int fvcol = sr.col0 + fc, fj = jb + fq;
-            const bool fvalid = fvcol < side * a.B && fj < sr.row1;
-            const int fbi = (a.B == 1 || !fvalid) ? 0 : fvcol / side, fi = fvcol - fbi * side;
-            const bool fint = fvalid && fi > 0 && fi < n && fj > 0 && fj < n;
+            const int F4 = S >> 2;
+            const int fq = (tid >> (a.lgS - 2)) & (RB - 1), fl = tid & (F4 - 1);
+            const int fj = jb + fq;
+            const bool fvalid = colvalid && fj < sr.row1;
+            const bool fint = fvalid && colint && fj > 0 && fj < n;
             const bool fmass = (mass_bits >> fq) & 1u;
-            const double2* rs = RSp(fc, fq);
-            const double* me = MEp(fc, fq);
-            const double* xo = XOp(fc, fq);
+            const double2* rs = RSp(team, fq);
+            const double* me = MEp(team, fq);
+            const double* xo = XOp(team, fq);
             T2 z[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int m = fl + c * F4;
                 double2 rv = rs[m];
                 if (fmass) {
-                    const double mue = me[m], muo = xo[m], prev = xo[m == 0 ? S - 1 : m - 1];
+                    const double mue = me[m], muo = xo[m], prev = xo[(m - 1) & (S - 1)];
                     rv.x -= (mue - prev) * a.inv_tau;
                     rv.y -= (muo - mue) * a.inv_tau;
                 }
@@ -700,22 +713,25 @@ k_residual(FwdArgs a, void* rt_) {
                 z[c] = mk2<T>((T)rv.x, (T)rv.y);
             }
             const T2* tw = twl;
-            const T2* res = fft_wave_tab<T2>(z, (T2*)RSp(fc, fq), (T2*)MEp(fc, fq), S, a.lgS, fl, tw);
+            const T2* res = fft_wave_tab<T2>(z, (T2*)RSp(team, fq), (T2*)MEp(team, fq), S, a.lgS, fl, tw);
             if (fvalid) {
-                const size_t chunk = ((size_t)fj * side + fi) * a.ST + (size_t)fbi * S;  // even
-                Pair<T2>* outp = (Pair<T2>*)a.out + chunk / 2;
+                // slots k = fl and fl + S/4 (k < S/2) with their mirrors S - k; the lane with
+                // k = 0 stores the packed slot 0 (X_0, X_{N/2}) and slot S/2, its own mirror,
+                // X_{N/4} = conj z_{S/2}
+                T2* outp = (T2*)a.out + ((size_t)fj * side + i) * a.ST + (size_t)bi * S;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int qq = fl + h * F4;
-                    if (qq < H) {
-                        const T2 pw[2] = {tw[2 * qq], tw[2 * qq + 1]};
-                        T2 X[2];
-                        rfft_split<T>(res, S, qq, pw, 0, X);
-                        Pair<T2> o;
-                        o.a = X[0];
-                        o.b = X[1];
-                        outp[qq] = o;
+                    const int k = fl + h * F4;
+                    T2 Xk, Xm;
+                    rfft_mirror<T>(res[k], res[(S - k) & (S - 1)], tw[k], Xk, Xm);
+                    int km = S - k;
+                    if (h == 0 && k == 0) {
+                        Xk = mk2<T>(Xk.x, Xm.x);
+                        Xm = conj2(res[S >> 1]);
+                        km = S >> 1;
                     }
+                    outp[k] = Xk;
+                    outp[km] = Xm;
                 }
             }
             __syncthreads();
