@@ -322,6 +322,14 @@ pt_status pt_residual_spectrum(pt_plan* plan, void* d_ws, size_t ws_bytes, const
 pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_u,
                      double* d_ku, int32_t nslices, void* stream);
 
+/* Device check of the two FP64 reciprocals the kernels use in place of a divide (no plan): for
+ * 0 <= i < n, d_y[2i] = the residual sweep's 1/x (hardware estimate refined by one Newton step;
+ * the law's 1 / (1 + s^2), so x >= 1) and d_y[2i+1] = the V-cycle's 1/x (two Newton steps; the
+ * Jacobi inverse, x > 0). d_x: n doubles, d_y: 2n doubles, both device memory owned by the
+ * caller. PT_ERR_INVALID for n < 0 or NULL buffers with n > 0; n = 0 does nothing. Enqueued on
+ * stream, does not block. */
+pt_status pt_device_reciprocals(const double* d_x, double* d_y, int64_t n, void* stream);
+
 /* Packed real DFT along time: time field (double) -> frequency field (plan precision). */
 pt_status pt_time_rfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_x,
                        void* d_xhat, void* stream);

@@ -76,6 +76,24 @@ def _ptr(t, name, numel):
     return t.data_ptr()
 
 
+def device_reciprocals(x):
+    """The kernels' two FP64 reciprocals of a contiguous float64 device tensor x: (the residual
+    sweep's, one Newton step, for x >= 1; the V-cycle's, two Newton steps, for x > 0), each a
+    tensor like x (pt_device_reciprocals). Synchronises the current stream."""
+    import torch
+    if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float64 device tensor")
+    y = torch.empty(2 * x.numel(), dtype=torch.float64, device=x.device)
+    lib = L.load()
+    st = lib.pt_device_reciprocals(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), x.numel(),
+                                   C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != 0:
+        raise PTError(st, "pt_device_reciprocals")
+    torch.cuda.current_stream().synchronize()
+    y = y.view(-1, 2)
+    return y[:, 0].reshape(x.shape), y[:, 1].reshape(x.shape)
+
+
 @dataclass
 class SolveStats:
     status: int

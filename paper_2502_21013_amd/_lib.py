@@ -110,6 +110,7 @@ def load():
         "pt_residual_spectrum": (i32, [vp, vp, sz, vp, vp, vp, dp, dp]),
         "pt_apply_K": (i32, [vp, vp, sz, vp, vp, i32, vp]),
         "pt_time_rfft": (i32, [vp, vp, sz, vp, vp, vp]),
+        "pt_device_reciprocals": (i32, [vp, vp, C.c_int64, vp]),
         "pt_time_irfft": (i32, [vp, vp, sz, vp, vp, vp]),
         "pt_shifted_apply": (i32, [vp, vp, sz, vp, vp, vp]),
         "pt_precond_apply": (i32, [vp, vp, sz, vp, vp, vp]),

@@ -1342,6 +1342,15 @@ pt_status pt_apply_K(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d
     return PT_OK;
 }
 
+pt_status pt_device_reciprocals(const double* d_x, double* d_y, int64_t n, void* stream) {
+    if (n < 0) return fail(PT_ERR_INVALID, "n must be >= 0");
+    if (n == 0) return PT_OK;
+    if (!d_x || !d_y) return fail(PT_ERR_INVALID, "d_x and d_y must not be NULL");
+    launch_reciprocals(d_x, d_y, (long)n, (hipStream_t)stream);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
 pt_status pt_time_rfft(pt_plan* plan, void* d_ws, size_t ws_bytes, const double* d_x, void* d_xhat, void* stream) {
     if (!plan || !d_x || !d_xhat) return fail(PT_ERR_INVALID, "plan, d_x and d_xhat must not be NULL");
     Plan& p = plan->p;

@@ -200,6 +200,7 @@ int launch_tdot(const Plan& p, const double* a, const double* b, double* part, h
 void launch_taxpby(const Plan& p, double alpha, const double* x, double beta, double* y, hipStream_t st);
 void launch_apply_K(const Plan& p, char* ws, const double* u, double* ku, int nslices,
                     hipStream_t st);
+void launch_reciprocals(const double* x, double* y, long n, hipStream_t st);
 // frequency (k_freq.hip)
 void launch_vcycle(const Plan& p, char* ws, const void* r0, void* x0, int dotmode, double* part,
                    hipStream_t st);
