@@ -9,7 +9,8 @@
  *     M     = sigma-weighted consistent P1 mass (sigma may vanish: degenerate, (A2)),
  *     f^n   = J0 w(2 pi t_n / T) b,  t_n = n tau, tau = T / N.
  * The solver is the fixed-point iteration of Sec. 3, eqs. (iter1)-(iter2), with
- * the linear operator Khat = nu_max * (P1 stiffness), run in correction form
+ * the linear operator Khat = nu_max * (P1 stiffness) (or a P1 stiffness with a
+ * coefficient per region, pt_region.nu_hat), run in correction form
  *     U^{k+1} = U^k + P^{-1}(F - A(U^k)),  P = I (x) (M/tau + Khat) - C_N (x) M/tau,
  * whose fixed point is A(U) = F however P^{-1} is approximated. Each P^{-1} is
  * applied by a DFT along time (remark rem:parallel: the periodic time-invariant
@@ -80,7 +81,8 @@ typedef enum { PT_FP64 = 0, PT_FP32_REFINE = 1 } pt_precision;
 typedef enum { PT_INNER_GALERKIN1 = 0, PT_INNER_COCG = 1 } pt_inner;
 
 /* Shape of the multigrid cycle B_k (P1 interpolation P, restriction P^T, damped Jacobi with
- * D = 4 nu_max + z_k diag(M), exact solve on the 2 x 2-cell grid), the same on every level:
+ * D = diag(Khat) + z_k diag(M), i.e. 4 nu_max + z_k diag(M) for Khat = nu_max S, exact solve on
+ * the 2 x 2-cell grid), the same on every level:
  *  PT_VC_V11: V(1,1): x1 = omega D^{-1} r, coarse cycle on P^T (r - A x1), x2 = x1 + P x_c,
  *             x3 = x2 + omega D^{-1} (r - A x2). Symmetric in the bilinear form x^T y, as
  *             COCG requires.
@@ -128,7 +130,7 @@ typedef struct {
     double J0;            /* source amplitude on coil_rect */
     pt_rect coil_rect;
     int32_t waveform;     /* pt_waveform: w = sin or cos */
-    double nu_max;        /* Khat = nu_max * stiffness; > 0 */
+    double nu_max;        /* Khat = nu_max * stiffness (region mode: per region, see nu_hat); > 0 */
     const double* d_theta; /* optional device [2 n^2] per-triangle nu scale (> 0), NULL = 1 */
     const double* d_sigma; /* optional device [2 n^2] per-triangle conductivity (>= 0),
                               NULL = sigma_in on sigma_rect */
