@@ -237,6 +237,83 @@ def main_many(args, P, cpu=None):
     print(json.dumps(out), flush=True)
 
 
+def main_adjoint(args, P, cpu=None):
+    """Config 5 (differentiation mode, 256^2 x 256, log-normal per-cell nu scale): one evaluation of the
+    eddy-current loss and its gradients with respect to the per-cell nu scale and the conductivity is a
+    forward solve, an adjoint solve (both to --tol) and the gradient kernels. Per mode: a per-kernel pass
+    (every launch of both solves bracketed by HIP events), then --steps timed evaluations after --warmup.
+    The roofline is taken on the adjoint residual sweep: U, lambda and dl/dU read (8 B each per DoF), the
+    residual written in the solver precision."""
+    import torch
+    import workloads as W
+    prob = W.config5(args.seed)
+    theta = torch.from_numpy(prob.theta).to("cuda:0")
+    nodes, N = (prob.n + 1) ** 2, prob.N
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    rec, grads = {}, {}
+    for m in modes:
+        plan = P.Plan(prob, theta=theta, tol=args.tol, precision=m, adjoint=True, timing=True,
+                      max_outer=args.max_outer)
+        U, sf = plan.solve()
+        Lam, sa = plan.adjoint_solve(U)
+        adj_ms, adj_n = dict(sa.kernel_ms), dict(sa.kernel_launches)
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+        plan = P.Plan(prob, theta=theta, tol=args.tol, precision=m, adjoint=True, max_outer=args.max_outer)
+        U = plan.new_time_field()
+        Lam = plan.new_time_field()
+        def evaluate():
+            _, f = plan.solve(U)
+            _, a = plan.adjoint_solve(U, Lam)
+            loss, gt, gs = plan.loss_gradients(U, Lam, per_cell=True)
+            return f, a, loss, gt, gs
+        for _ in range(args.warmup):
+            evaluate()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            f, a, loss, gt, gs = evaluate()
+            torch.cuda.synchronize()
+            log(f"{m} evaluation {k}: forward {f.outer_iters} steps {f.time_ms:.1f} ms, adjoint {a.outer_iters} "
+                f"steps {a.time_ms:.1f} ms, loss {loss:.6e}")
+        wall = (time.perf_counter() - t0) / args.steps
+        e = 8 if m == "fp32" else 16
+        alg = nodes * N * (24 + e // 2)
+        avg = adj_ms["residual_sweep"] / adj_n["residual_sweep"]
+        rec[m] = {"value": prob.st_dofs / wall, "ms_per_step": 1e3 * wall, "forward_ms": f.time_ms,
+                  "adjoint_ms": a.time_ms, "forward_outer_iters": f.outer_iters, "adjoint_outer_iters": a.outer_iters,
+                  "rel_residual": f.rel_residual, "adjoint_rel_residual": a.rel_residual, "loss": loss,
+                  "adjoint_kernel_ms_pass": adj_ms,
+                  "roofline": {"bound": "hbm", "achieved": round(alg / (avg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "traffic": None, "kernel": "adjoint residual sweep (k_adj_residual)",
+                               "alg_bytes_per_launch": alg, "avg_launch_ms": round(avg, 4)}}
+        grads[m] = (gt.clone(), gs.clone(), loss)
+        plan.close()
+        del plan, U, Lam
+        torch.cuda.empty_cache()
+    errors = {}
+    if "fp32" in grads and "fp64" in grads:
+        (t32, s32, l32), (t64, s64, l64) = grads["fp32"], grads["fp64"]
+        errors = {"loss_rel": abs(l32 - l64) / abs(l64),
+                  "dl_dtheta_rel_l2": float((t32 - t64).norm() / t64.norm()),
+                  "dl_dsigma_rel_l2": float((s32 - s64).norm() / s64.norm())}
+    primary = modes[0]
+    r0 = rec[primary]
+    out = {
+        "metric": "space-time DoFs/s of one loss-gradient evaluation (forward + adjoint solve to rel. residual "
+                  "tol, then dl/dtheta and dl/dsigma per cell)",
+        "value": r0["value"], "unit": "space-time DoFs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r0["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if primary == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": f"adjoint gradients: {prob.n}x{prob.n} cells, N={N}, log-normal per-cell nu scale "
+                               f"(sd 0.1), seed {args.seed}", "st_dofs": prob.st_dofs, "tol": args.tol},
+        "roofline": r0["roofline"], "cpu_baseline": cpu, "modes": rec, "errors": errors,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def algorithmic_bytes(p, elem, count=1):
     """Bytes each dominant kernel must move per launch (all (n+1)^2 grid nodes, `count`
     instances of the grid and period of p stacked in one batch plan).
@@ -422,13 +499,18 @@ def _oracle_sample_worker(job):
         base = W.config4(seed)[0]
     elif kind == "tr":
         base = W.transformer(n, N, khat_factor=TR_KHAT)
+    elif kind == "c5":
+        base = W.config5(seed, n, N)
     else:
         base = W.config3(seed)
-    p = W.with_size(base, n, N)
+    p = W.with_size(base, n, N) if kind != "c5" else base
     with threadpool_limits(1):
         t0 = time.perf_counter()
         d = fem.discretise(p)
         r = pp.fixed_point(d, tol=tol, max_iter=2000)
+        if kind == "c5":
+            from oracle import adjoint as AD
+            AD.gradients(d, r.U)     # the adjoint state by sparse LU, then both gradients
         dt = time.perf_counter() - t0
     return p.st_dofs, dt, r.iters
 
@@ -454,7 +536,9 @@ def cpu_baseline(kind, seed, n=32, N=64, tol=1e-8):
     dofs = sum(r[0] for r in res)
     tmax = max(r[1] for r in res)
     what = {"c4": "config-4 instance 0's materials and source",
-            "tr": "the same transformer cross-section and per-region Khat"}.get(kind, "the same seeded materials/source")
+            "tr": "the same transformer cross-section and per-region Khat",
+            "c5": "a log-normal per-cell nu scale (the same recipe), forward solve + adjoint state + gradients"
+            }.get(kind, "the same seeded materials/source")
     return {"value": dofs / tmax, "unit": "space-time DoFs/s", "cores": cores, "kind": "oracle",
             "sample": f"{cores} concurrent copies (one per host core, one thread each) of {n}x{n} cells, N={N}, "
                       f"{what}, tol {tol:g}, {res[0][2]} outer steps, longest {tmax:.1f} s "
@@ -649,7 +733,8 @@ def main():
     if not args.no_cpu_baseline and not args.calibrate_copy:
         if args.workload != "c4":
             log("cpu baseline (oracle on a bounded sample, one copy per host core)")
-            cpu = cpu_baseline("tr" if args.workload == "tr" else "c3", args.seed)
+            kind = args.workload if args.workload in ("tr", "c5") else "c3"
+            cpu = cpu_baseline(kind, args.seed, N=32 if kind == "c5" else 64)
             log(f"cpu baseline {cpu['value']:.1f} DoFs/s on {cpu['cores']} cores")
         if want_batch:
             cpu4 = cpu_baseline("c4", args.seed)
@@ -665,6 +750,9 @@ def main():
     P.library()
     if args.workload == "c4":
         main_many(args, P, cpu4)
+        return
+    if args.workload == "c5":
+        main_adjoint(args, P, cpu)
         return
     import workloads as W
     prob, desc = workload(args.workload, args.seed)

@@ -40,13 +40,30 @@ struct Law {
 };
 
 template <int LAW>
-__device__ __forceinline__ Law tri_law(const AdjArgs& a, int region, double th, double gx, double gy) {
+__device__ __forceinline__ Law tri_law_q(const double4 q, double n2, double th, double gx, double gy) {
     Law L;
-    const double s2 = a.n2 * (gx * gx + gy * gy);
+    const double s2 = n2 * (gx * gx + gy * gy);
     double dn;
-    L.nu = th * law_nu_dn<LAW>(a.regp[region], s2, dn);
-    L.dn = 2.0 * a.n2 * th * dn;
+    L.nu = th * law_nu_dn<LAW>(q, s2, dn);
+    L.dn = 2.0 * n2 * th * dn;
     return L;
+}
+template <int LAW>
+__device__ __forceinline__ Law tri_law(const AdjArgs& a, int region, double th, double gx, double gy) {
+    return tri_law_q<LAW>(a.regp[region], a.n2, th, gx, gy);
+}
+
+// Per-triangle tables at an index that is the same on every lane when UNI (read through the
+// scalar unit; the region byte from the aligned word that holds it: the table has 2 n^2 bytes,
+// a multiple of 4).
+template <bool UNI>
+__device__ __forceinline__ int region_of(const AdjArgs& a, size_t tri) {
+    if constexpr (UNI) {
+        const uint32_t w = uload<true>((const uint32_t*)a.flags, tri >> 2);
+        return (int)((w >> (8 * (tri & 3))) & 0xffu);
+    } else {
+        return a.flags[tri];
+    }
 }
 
 // Contribution of one triangle to (K'(u) lambda)_i / 1: half of
@@ -80,16 +97,17 @@ struct MassRow {
     bool any;
 };
 
+template <bool UNI = false>
 __device__ __forceinline__ MassRow mass_row(const AdjArgs& a, size_t node) {
     const size_t nd = a.nodes, sd = a.side;
     MassRow m;
-    m.c = a.mt[node];
-    m.e = a.mt[nd + node];
-    m.w = a.mt[nd + node - 1];
-    m.nn = a.mt[2 * nd + node];
-    m.s = a.mt[2 * nd + node - sd];
-    m.ne = a.mt[3 * nd + node];
-    m.sw = a.mt[3 * nd + node - sd - 1];
+    m.c = uload<UNI>(a.mt, node);
+    m.e = uload<UNI>(a.mt, nd + node);
+    m.w = uload<UNI>(a.mt, nd + node - 1);
+    m.nn = uload<UNI>(a.mt, 2 * nd + node);
+    m.s = uload<UNI>(a.mt, 2 * nd + node - sd);
+    m.ne = uload<UNI>(a.mt, 3 * nd + node);
+    m.sw = uload<UNI>(a.mt, 3 * nd + node - sd - 1);
     m.any = (m.c != 0.0) || (m.e != 0.0) || (m.w != 0.0) || (m.nn != 0.0) || (m.s != 0.0) || (m.ne != 0.0) ||
             (m.sw != 0.0);
     return m;
@@ -121,7 +139,8 @@ __device__ __forceinline__ void block_pair_sum(double x, double y, double* out) 
 __global__ void __launch_bounds__(kBlock) k_adj_source(AdjArgs a, double* g) {
     const size_t total = a.nodes * (size_t)a.N;
     const size_t sd = a.side;
-    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
+    for (size_t id = (size_t)virtual_block_of(blockIdx.x, gridDim.x, 1) * kBlock + threadIdx.x; id < total;
+         id += (size_t)gridDim.x * kBlock) {
         const size_t node = id >> a.lgN;
         const int t = (int)(id & (size_t)(a.N - 1));
         const int i = (int)(node % sd), j = (int)(node / sd);
@@ -142,13 +161,18 @@ __global__ void __launch_bounds__(kBlock) k_adj_source(AdjArgs a, double* g) {
 
 // R^n = g^n - (M/tau)(lambda^n - lambda^{n+1}) - K'(u^n) lambda^n at interior nodes (0 on the
 // boundary), written in the solver precision T for the time DFT; norm partials of R and g.
-template <typename T, int LAW>
+// UNI (N >= 64): the 64 lanes of a wavefront hold 64 consecutive time levels of one node (every
+// wavefront starts at a multiple of 64 and N is a multiple of 64), so the node's tables are read
+// through the scalar unit.
+template <typename T, int LAW, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_adj_residual(AdjArgs a, T* rt) {
     const size_t total = a.nodes * (size_t)a.N;
     const size_t sd = a.side;
     double rr = 0.0, gg = 0.0;
-    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
-        const size_t node = id >> a.lgN;
+    for (size_t id = (size_t)virtual_block_of(blockIdx.x, gridDim.x, 1) * kBlock + threadIdx.x; id < total;
+         id += (size_t)gridDim.x * kBlock) {
+        size_t node = id >> a.lgN;
+        if constexpr (UNI) node = (size_t)__builtin_amdgcn_readfirstlane((int)node);
         const int t = (int)(id & (size_t)(a.N - 1));
         const int i = (int)(node % sd), j = (int)(node / sd);
         double R = 0.0;
@@ -168,12 +192,16 @@ __global__ void __launch_bounds__(kBlock) k_adj_residual(AdjArgs a, T* rt) {
             double Kl = 0.0;
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const double th = a.theta ? a.theta[tri[k]] : 1.0;
-                const Law L = tri_law<LAW>(a, a.flags[tri[k]], th, gux[k], guy[k]);
+                const double th = a.theta ? uload<UNI>(a.theta, tri[k]) : 1.0;
+                const size_t rq = 4 * (size_t)region_of<UNI>(a, tri[k]);
+                const double* rp = (const double*)a.regp;
+                const double4 q = make_double4(uload<UNI>(rp, rq), uload<UNI>(rp, rq + 1), uload<UNI>(rp, rq + 2),
+                                               uload<UNI>(rp, rq + 3));
+                const Law L = tri_law_q<LAW>(q, a.n2, th, gux[k], guy[k]);
                 Kl += tri_lin(L, gux[k], guy[k], glx[k], gly[k], px[k], py[k]);
             }
             R = g - Kl;
-            const MassRow m = mass_row(a, node);
+            const MassRow m = mass_row<UNI>(a, node);
             if (m.any) {
                 const int tn = t + 1 == a.N ? 0 : t + 1;
                 const Stencil ln = load_stencil(a.L, node, sd, a.N, tn);
@@ -196,7 +224,8 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(AdjArgs a, const double* v
                                                       int dir) {
     const size_t total = a.nodes * (size_t)a.N;
     const size_t sd = a.side;
-    for (size_t id = blockIdx.x * (size_t)kBlock + threadIdx.x; id < total; id += (size_t)gridDim.x * kBlock) {
+    for (size_t id = (size_t)virtual_block_of(blockIdx.x, gridDim.x, 1) * kBlock + threadIdx.x; id < total;
+         id += (size_t)gridDim.x * kBlock) {
         const size_t node = id >> a.lgN;
         const int t = (int)(id & (size_t)(a.N - 1));
         const int i = (int)(node % sd), j = (int)(node / sd);
@@ -329,10 +358,14 @@ static AdjArgs mk_adj(const Plan& p, char* ws) {
     return a;
 }
 
+// Grid of the grid-stride kernels over [nodes][N]: a multiple of kNumXcd workgroups, remapped
+// (virtual_block_of) so that every XCD walks contiguous node ranges and finds the stencil
+// neighbours of its nodes in its own L2.
+static_assert(kAdjBlocks % kNumXcd == 0, "the adjoint grid is a multiple of the XCD count");
 static int adj_grid(size_t total) {
     size_t g = (total + kBlock - 1) / kBlock;
+    g = (g + kNumXcd - 1) / kNumXcd * kNumXcd;
     if (g > (size_t)kAdjBlocks) g = kAdjBlocks;
-    if (g < 1) g = 1;
     return (int)g;
 }
 
@@ -341,17 +374,29 @@ void launch_adj_source(const Plan& p, char* ws, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_source, dim3(adj_grid(p.nodes * p.N)), dim3(kBlock), 0, st, a, (double*)(ws + p.off_G));
 }
 
+template <typename X> struct AdjTag {
+    using type = X;
+};
+
 int launch_adj_residual(const Plan& p, char* ws, void* rt, hipStream_t st) {
     AdjArgs a = mk_adj(p, ws);
     const int grid = adj_grid(p.nodes * p.N);
     const bool ex = p.law == PT_NU_EXPCAP;
+    auto go = [&](auto t_, auto uni_) {
+        using T = typename decltype(t_)::type;
+        constexpr bool U = decltype(uni_)::value;
+        if (ex)
+            hipLaunchKernelGGL((k_adj_residual<T, PT_NU_EXPCAP, U>), dim3(grid), dim3(kBlock), 0, st, a, (T*)rt);
+        else
+            hipLaunchKernelGGL((k_adj_residual<T, PT_NU_RATIONAL, U>), dim3(grid), dim3(kBlock), 0, st, a, (T*)rt);
+    };
+    const bool uni = p.N >= 64;   // one node per wavefront
     if (p.fp32) {
-        if (ex) hipLaunchKernelGGL((k_adj_residual<float, PT_NU_EXPCAP>), dim3(grid), dim3(kBlock), 0, st, a, (float*)rt);
-        else hipLaunchKernelGGL((k_adj_residual<float, PT_NU_RATIONAL>), dim3(grid), dim3(kBlock), 0, st, a, (float*)rt);
+        if (uni) go(AdjTag<float>(), std::true_type());
+        else go(AdjTag<float>(), std::false_type());
     } else {
-        if (ex) hipLaunchKernelGGL((k_adj_residual<double, PT_NU_EXPCAP>), dim3(grid), dim3(kBlock), 0, st, a, (double*)rt);
-        else hipLaunchKernelGGL((k_adj_residual<double, PT_NU_RATIONAL>), dim3(grid), dim3(kBlock), 0, st, a,
-                                (double*)rt);
+        if (uni) go(AdjTag<double>(), std::true_type());
+        else go(AdjTag<double>(), std::false_type());
     }
     return grid;
 }

@@ -234,7 +234,7 @@ template <int LAW> __device__ __forceinline__ double law_nu(const double4 q, dou
 
 template <int LAW> __device__ __forceinline__ double law_nu_dn(const double4 q, double s2, double& dn) {
     if constexpr (LAW == PT_NU_RATIONAL) {
-        const double r = 1.0 / (1.0 + s2);
+        const double r = fast_rcp<double>(1.0 + s2);
         dn = q.y * r * r;
         return (q.x + q.y) - q.y * r;
     } else {
