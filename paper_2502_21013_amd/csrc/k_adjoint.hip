@@ -218,15 +218,16 @@ __global__ void __launch_bounds__(kBlock) k_adj_residual(AdjArgs a, T* rt) {
 // The linearised operator at the state U: (J v)^n = (M/tau)(v^n - v^{n-dir}) + K'(u^n) v^n with
 // dir = +1 (J, eqs. (disc1)-(disc2) linearised) or -1 (J^T: the time coupling runs the other
 // way, K' being symmetric). Writes out = J v when b is null and out = b - J v otherwise;
-// boundary entries are 0. FP64 throughout.
-template <int LAW>
+// boundary entries are 0. FP64 throughout. UNI as in k_adj_residual.
+template <int LAW, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_jac_apply(AdjArgs a, const double* v, const double* b, double* out,
                                                       int dir) {
     const size_t total = a.nodes * (size_t)a.N;
     const size_t sd = a.side;
     for (size_t id = (size_t)virtual_block_of(blockIdx.x, gridDim.x, 1) * kBlock + threadIdx.x; id < total;
          id += (size_t)gridDim.x * kBlock) {
-        const size_t node = id >> a.lgN;
+        size_t node = id >> a.lgN;
+        if constexpr (UNI) node = (size_t)__builtin_amdgcn_readfirstlane((int)node);
         const int t = (int)(id & (size_t)(a.N - 1));
         const int i = (int)(node % sd), j = (int)(node / sd);
         double Jv = 0.0;
@@ -244,11 +245,15 @@ __global__ void __launch_bounds__(kBlock) k_jac_apply(AdjArgs a, const double* v
             const int py[6] = {0, -1, -1, 1, 1, 0};
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const double th = a.theta ? a.theta[tri[k]] : 1.0;
-                const Law L = tri_law<LAW>(a, a.flags[tri[k]], th, gux[k], guy[k]);
+                const double th = a.theta ? uload<UNI>(a.theta, tri[k]) : 1.0;
+                const size_t rq = 4 * (size_t)region_of<UNI>(a, tri[k]);
+                const double* rp = (const double*)a.regp;
+                const double4 q = make_double4(uload<UNI>(rp, rq), uload<UNI>(rp, rq + 1), uload<UNI>(rp, rq + 2),
+                                               uload<UNI>(rp, rq + 3));
+                const Law L = tri_law_q<LAW>(q, a.n2, th, gux[k], guy[k]);
                 Jv += tri_lin(L, gux[k], guy[k], glx[k], gly[k], px[k], py[k]);
             }
-            const MassRow m = mass_row(a, node);
+            const MassRow m = mass_row<UNI>(a, node);
             if (m.any) {
                 const int to = dir > 0 ? (t == 0 ? a.N - 1 : t - 1) : (t + 1 == a.N ? 0 : t + 1);
                 const Stencil lo = load_stencil(v, node, sd, a.N, to);
@@ -416,10 +421,15 @@ void launch_jac_apply(const Plan& p, char* ws, const double* v, const double* b,
                       hipStream_t st) {
     AdjArgs a = mk_adj(p, ws);
     const dim3 grid(adj_grid(p.nodes * p.N));
-    if (p.law == PT_NU_EXPCAP)
-        hipLaunchKernelGGL(k_jac_apply<PT_NU_EXPCAP>, grid, dim3(kBlock), 0, st, a, v, b, out, dir);
+    const bool ex = p.law == PT_NU_EXPCAP, uni = p.N >= 64;
+    if (ex && uni)
+        hipLaunchKernelGGL((k_jac_apply<PT_NU_EXPCAP, true>), grid, dim3(kBlock), 0, st, a, v, b, out, dir);
+    else if (ex)
+        hipLaunchKernelGGL((k_jac_apply<PT_NU_EXPCAP, false>), grid, dim3(kBlock), 0, st, a, v, b, out, dir);
+    else if (uni)
+        hipLaunchKernelGGL((k_jac_apply<PT_NU_RATIONAL, true>), grid, dim3(kBlock), 0, st, a, v, b, out, dir);
     else
-        hipLaunchKernelGGL(k_jac_apply<PT_NU_RATIONAL>, grid, dim3(kBlock), 0, st, a, v, b, out, dir);
+        hipLaunchKernelGGL((k_jac_apply<PT_NU_RATIONAL, false>), grid, dim3(kBlock), 0, st, a, v, b, out, dir);
 }
 
 }  // namespace pt
