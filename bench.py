@@ -31,7 +31,12 @@ FP64. It is compared with the plain FP64 path (each instance alone, eager launch
 after the other; plans, workspaces and fields built and warmed up before timing), with its
 own roofline (a serial pass with per-kernel events) and CPU baseline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c4|tr] [--paper-stop]
+Loss-gradient workload (--workload c5): the differentiation-mode instance (256 x 256 cells, N = 256, a
+log-normal per-cell nu scale); one step is one evaluation of the eddy-current loss and its per-cell
+gradients (forward solve, adjoint solve, gradient kernels), with the roofline of the adjoint residual
+sweep and the oracle's adjoint as the CPU baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|tr] [--paper-stop]
 """
 from __future__ import annotations
 
